@@ -1,0 +1,289 @@
+"""Seeded synthetic problem generator shared by the FP64 oracle and the HIP path.
+
+This module only draws random numbers and lays out mesh / network data.  It
+holds none of the method's arithmetic: no rest-shape matrices, masses,
+derivatives, forces or solves (each side computes those itself).
+
+Random numbers come from one counter-based generator, SplitMix64 (Steele,
+Lea and Flood, "Fast splittable pseudorandom number generators", OOPSLA
+2014), turned into 53-bit uniforms and then into normals by the Box-Muller
+transform.  Every named sub-stream (``dec/3``, ``q0/0`` ...) gets its own
+64-bit key, so adding a stream never shifts another one.
+
+Workloads follow the paper's setting (Sec. 3.6 system, Sec. 6 experiments):
+tet-meshed solids, a decoder MLP ``q -> u``, a cubature subset of elements
+with weights that may come from a small weight-prediction MLP (Sec. 5.2),
+implicit Euler with a fixed number of Newton iterations per step.  The
+paper's meshes and trained networks are not available; regular grids split
+into 5 tets and Xavier-initialised networks stand in for them.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+MASTER_SEED = 2102
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+# --------------------------------------------------------------------------
+# counter-based generator
+# --------------------------------------------------------------------------
+def _fnv1a64(text: str) -> np.uint64:
+    h = 0xCBF29CE484222325
+    for b in text.encode():
+        h ^= b
+        h = (h * 0x100000001B3) & 0xFFFFFFFFFFFFFFFF
+    return np.uint64(h)
+
+
+def _mix(z: np.ndarray) -> np.ndarray:
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def stream_key(name: str, seed: int = MASTER_SEED) -> np.uint64:
+    """64-bit key of a named sub-stream."""
+    with np.errstate(over="ignore"):
+        return _mix(np.array([np.uint64(seed) ^ _fnv1a64(name)], dtype=np.uint64))[0]
+
+
+def raw64(name: str, count: int, seed: int = MASTER_SEED) -> np.ndarray:
+    """SplitMix64 outputs 1..count of stream ``name`` (counter form)."""
+    key = stream_key(name, seed)
+    ctr = np.arange(1, count + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        return _mix(key + ctr * _GAMMA)
+
+
+def uniform(name: str, count: int, seed: int = MASTER_SEED) -> np.ndarray:
+    """Uniforms in (0, 1]: top 53 bits of each draw, plus one ulp."""
+    r = raw64(name, count, seed)
+    return ((r >> np.uint64(11)).astype(np.float64) + 1.0) * (1.0 / 9007199254740992.0)
+
+
+def normal(name: str, count: int, seed: int = MASTER_SEED) -> np.ndarray:
+    """Standard normals by Box-Muller on consecutive uniform pairs."""
+    pairs = (count + 1) // 2
+    u = uniform(name, 2 * pairs, seed)
+    u1, u2 = u[0::2], u[1::2]
+    rad = np.sqrt(-2.0 * np.log(u1))
+    z = np.empty(2 * pairs)
+    z[0::2] = rad * np.cos(2.0 * np.pi * u2)
+    z[1::2] = rad * np.sin(2.0 * np.pi * u2)
+    return z[:count]
+
+
+def permutation(name: str, n: int, seed: int = MASTER_SEED) -> np.ndarray:
+    """Uniform random permutation of range(n) (argsort of 64-bit draws)."""
+    return np.argsort(raw64(name, n, seed), kind="stable")
+
+
+# --------------------------------------------------------------------------
+# meshes
+# --------------------------------------------------------------------------
+# 5-tet split of a unit cube.  Corners are named by (dx, dy, dz) bits.  The
+# "even" split keeps corner 000 with its three neighbours; the "odd" one is
+# its mirror, so the face diagonals of neighbouring cubes agree.
+_EVEN = [(0b000, 0b001, 0b010, 0b100), (0b011, 0b010, 0b001, 0b111),
+         (0b101, 0b001, 0b100, 0b111), (0b110, 0b100, 0b010, 0b111),
+         (0b001, 0b010, 0b100, 0b111)]
+_ODD = [(0b001, 0b000, 0b011, 0b101), (0b010, 0b000, 0b011, 0b110),
+        (0b100, 0b000, 0b101, 0b110), (0b111, 0b011, 0b101, 0b110),
+        (0b000, 0b011, 0b101, 0b110)]
+
+
+def grid_mesh(nx: int, ny: int, nz: int, spacing: float = 0.1):
+    """Regular vertex grid split into 5 tets per cube.
+
+    Vertex (i, j, k) sits at (i, j, k) * spacing with index i + nx*(j + ny*k).
+    Returns (X (n,3) float64, tets (m,4) int32) with every tet positively
+    oriented (vertex order swapped where needed).
+    """
+    ii, jj, kk = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    idx = lambda i, j, k: i + nx * (j + ny * k)
+    n = nx * ny * nz
+    X = np.zeros((n, 3))
+    X[idx(ii, jj, kk).ravel(), 0] = ii.ravel() * spacing
+    X[idx(ii, jj, kk).ravel(), 1] = jj.ravel() * spacing
+    X[idx(ii, jj, kk).ravel(), 2] = kk.ravel() * spacing
+    # cubes in k, j, i loop order (i fastest)
+    ck, cj, ci = (a.ravel() for a in np.meshgrid(np.arange(nz - 1), np.arange(ny - 1), np.arange(nx - 1),
+                                                 indexing="ij"))
+    even = ((ci + cj + ck) % 2 == 0)[:, None, None]
+    pat = np.where(even, np.asarray(_EVEN)[None], np.asarray(_ODD)[None])  # (cubes, 5, 4)
+    tets = idx(ci[:, None, None] + (pat & 1), cj[:, None, None] + ((pat >> 1) & 1),
+               ck[:, None, None] + ((pat >> 2) & 1)).reshape(-1, 4).astype(np.int32)
+    # orientation: signed volume of the corner offsets
+    e = X[tets[:, 1:]] - X[tets[:, :1]]
+    s = np.einsum("ij,ij->i", e[:, 0], np.cross(e[:, 1], e[:, 2]))
+    neg = s < 0
+    tets[neg, 1], tets[neg, 2] = tets[neg, 2].copy(), tets[neg, 1].copy()
+    return X, tets
+
+
+# --------------------------------------------------------------------------
+# problem bundle
+# --------------------------------------------------------------------------
+@dataclass
+class Problem:
+    """One simulated object.  All arrays float64 / int32, host memory."""
+    name: str
+    X: np.ndarray              # (n, 3) rest positions [m]
+    tets: np.ndarray           # (m, 4) vertex ids, positive orientation
+    pinned: np.ndarray         # (n,) uint8, 1 = Dirichlet vertex
+    E: float
+    nu: float
+    rho: float
+    gravity: np.ndarray        # (3,)
+    dt: float
+    U: np.ndarray              # (N, n_p) orthonormal, zero rows at pinned DOFs
+    weights: List[np.ndarray]  # decoder W_l, (out, in)
+    biases: List[np.ndarray]   # decoder b_l, (out,)
+    act: str                   # hidden activation: tanh | elu | sin | identity
+    cub_ids: np.ndarray        # (|C|,) tet ids
+    cub_w: Optional[np.ndarray]            # fixed weights, or None -> W-net
+    wnet_weights: Optional[List[np.ndarray]] = None
+    wnet_biases: Optional[List[np.ndarray]] = None
+    wnet_scale: float = 1.0
+    r0: np.ndarray = None      # (R,) initial generalized coordinate [p; q]
+    rdot0: np.ndarray = None   # (R,)
+    steps: int = 1
+    newton_iters: int = 1
+    out_rows: int = 0          # rows of the output layer (>= N; prefix used)
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def n(self) -> int:
+        return self.X.shape[0]
+
+    @property
+    def N(self) -> int:
+        return 3 * self.X.shape[0]
+
+    @property
+    def n_p(self) -> int:
+        return self.U.shape[1]
+
+    @property
+    def n_q(self) -> int:
+        return self.weights[0].shape[1]
+
+    @property
+    def R(self) -> int:
+        return self.n_p + self.n_q
+
+    def replace(self, **kw) -> "Problem":
+        return dataclasses.replace(self, **kw)
+
+
+def xavier_mlp(widths, stream: str, seed: int = MASTER_SEED):
+    """Xavier-normal weights (gain 1, std sqrt(2/(fan_in+fan_out))), zero biases."""
+    Ws, bs = [], []
+    for l in range(len(widths) - 1):
+        fi, fo = widths[l], widths[l + 1]
+        std = np.sqrt(2.0 / (fi + fo))
+        Ws.append(normal(f"{stream}/{l}", fo * fi, seed).reshape(fo, fi) * std)
+        bs.append(np.zeros(fo))
+    return Ws, bs
+
+
+def random_orthonormal(N: int, n_p: int, pinned_dof: np.ndarray, stream: str,
+                       seed: int = MASTER_SEED) -> np.ndarray:
+    """Orthonormal N x n_p basis supported on the free DOFs (QR of a Gaussian)."""
+    if n_p == 0:
+        return np.zeros((N, 0))
+    free = np.flatnonzero(pinned_dof == 0)
+    G = normal(stream, free.size * n_p, seed).reshape(free.size, n_p)
+    Q, _ = np.linalg.qr(G)
+    U = np.zeros((N, n_p))
+    U[free] = Q
+    return U
+
+
+def _pins_k0(n: int, nx: int, ny: int) -> np.ndarray:
+    p = np.zeros(n, dtype=np.uint8)
+    p[: nx * ny] = 1  # vertices with k == 0
+    return p
+
+
+MATERIAL = dict(E=1.0e5, nu=0.45, rho=1000.0)
+GRAVITY = np.array([0.0, -9.81, 0.0])
+DT = 1.0 / 60.0
+
+
+def bar_problem(name: str, grid, widths, act: str, *, n_p: int = 0, n_cub: int = 0,
+                wnet_hidden=(64, 64), steps: int = 1, newton_iters: int = 1,
+                q_std: float = 0.1, out_scale: float = 1.0, seed: int = MASTER_SEED,
+                stream_prefix: str = "", instance: int = 0) -> Problem:
+    """A bar on a regular grid pinned at its k = 0 face.
+
+    ``widths`` are the decoder widths from n_q to the output size (3n).
+    ``n_cub == 0`` means full quadrature (every tet, weight 1); otherwise a
+    uniform sample of ``n_cub`` tets with weights from a softplus W-net
+    evaluated on r (scaled so each weight is m/|C| at zero pre-activation).
+    """
+    nx, ny, nz = grid
+    X, tets = grid_mesh(nx, ny, nz)
+    n = X.shape[0]
+    N = 3 * n
+    assert widths[-1] >= N, "decoder output must cover every DOF"
+    pinned = _pins_k0(n, nx, ny)
+    pin_dof = np.repeat(pinned, 3)
+    sp = stream_prefix
+    Ws, bs = xavier_mlp(widths, sp + "dec", seed)
+    Ws[-1] = Ws[-1] * out_scale
+    U = random_orthonormal(N, n_p, pin_dof, f"{sp}U/{instance}", seed)
+    n_q = widths[0]
+    R = n_p + n_q
+    m = tets.shape[0]
+    if n_cub == 0:
+        cub_ids = np.arange(m, dtype=np.int32)
+        cub_w = np.ones(m)
+        wW = wb = None
+        wscale = 1.0
+    else:
+        cub_ids = np.sort(permutation(sp + "cub", m, seed)[:n_cub]).astype(np.int32)
+        cub_w = None
+        wW, wb = xavier_mlp([R, *wnet_hidden, n_cub], sp + "wnet", seed)
+        wscale = (m / n_cub) / np.log(2.0)
+    r0 = np.zeros(R)
+    r0[n_p:] = q_std * normal(f"{sp}q0/{instance}", n_q, seed)
+    return Problem(name=name, X=X, tets=tets, pinned=pinned, gravity=GRAVITY.copy(), dt=DT,
+                   U=U, weights=Ws, biases=bs, act=act, cub_ids=cub_ids, cub_w=cub_w,
+                   wnet_weights=wW, wnet_biases=wb, wnet_scale=wscale, r0=r0,
+                   rdot0=np.zeros(R), steps=steps, newton_iters=newton_iters,
+                   out_rows=widths[-1], meta=dict(grid=tuple(grid), widths=list(widths)),
+                   **MATERIAL)
+
+
+# Workload recipes ----------------------------------------------------------
+C2_WIDTHS = [15, 64, 128, 256, 512, 512, 512, 512, 512, 256, 30000]
+
+
+def config_plain_fp64() -> Problem:
+    """192-vertex bar, r = 3, tanh decoder [3,32,64,128,576], full quadrature,
+    20 steps x 3 Newton iterations."""
+    return bar_problem("bar192_r3", (4, 4, 12), [3, 32, 64, 128, 576], "tanh",
+                       steps=20, newton_iters=3)
+
+
+def config_single_10k(instance: int = 0) -> Problem:
+    """10,000-vertex bar (20x20x25, 43,320 tets), r = 15, 10-layer ELU decoder,
+    500 cubature tets weighted by a 15->64->64->500 softplus W-net,
+    100 steps x 4 Newton iterations."""
+    return bar_problem("bar10k_r15", (20, 20, 25), C2_WIDTHS, "elu", n_cub=500,
+                       steps=100, newton_iters=4, instance=instance)
+
+
+def tiny_problem(grid=(2, 2, 3), widths=(2, 4, 4, 36), act="tanh", n_p=0, n_cub=0,
+                 q_std=0.1, name="tiny", instance=0, out_scale=1.0) -> Problem:
+    return bar_problem(name, grid, list(widths), act, n_p=n_p, n_cub=n_cub, q_std=q_std,
+                       instance=instance, out_scale=out_scale, stream_prefix=name + "/")
