@@ -1,0 +1,180 @@
+/*
+ * nmr.h - C ABI of libnmr: the reduced implicit-Euler Newton iteration of a
+ * deep-autoencoder subspace simulator on AMD MI355X (gfx950).
+ *
+ * Method (High-order Differentiable Autoencoder for Nonlinear Model
+ * Reduction): full-space displacement u = U p + D(q) (Sec. 3.6,
+ * eq. our_subspace) with D a decoder MLP followed by the fixed filtering
+ * layer I - U U^T (Sec. 3.5) and the Dirichlet mask P of pinned DOFs.  Each
+ * implicit-Euler step (Sec. 3.2) solves phi(r) = 0 (eq. our_equation_of_motion)
+ * for r = [p; q] by Newton's method with the matrix of eq. system_mat, whose
+ * third-order term dJ is eq. delta_j.  Decoder derivatives are collective
+ * complex-step right contractions (Sec. 4.3) and complex-step
+ * backpropagation (Sec. 4.4); force and stiffness are integrated over a
+ * weighted cubature set of tets (Sec. 5) with weights from a
+ * weight-prediction MLP evaluated once per step (Sec. 5.2).
+ *
+ * Conventions for every call:
+ *   - Return value: NMR_OK (0) or a negative nmr_status.  No C++ exception
+ *     crosses this ABI.  nmr_last_error() gives a text for the last failure
+ *     on the calling thread.
+ *   - Ownership: the caller owns every array argument.  The library owns only
+ *     what lives inside a handle (device copies of the problem, state,
+ *     workspaces) and frees it in the matching destroy call.
+ *   - Device vs host: arguments documented "device" are device pointers on the
+ *     context's GPU (for example torch tensors' data pointers); "host" ones are
+ *     ordinary host memory.  Every call is ordered on the context's stream
+ *     and returns without waiting unless it writes a host output, in which
+ *     case it synchronizes that stream first.
+ *   - Layouts: row-major; the DOF index of vertex v, coordinate c is 3 v + c;
+ *     r = [p; q] with the n_p linear coordinates first (Sec. 3.6).
+ *   - Element type "real": double for an instance created with NMR_PREC_FP64,
+ *     float for NMR_PREC_FP32 and NMR_PREC_BF16.
+ */
+#ifndef NMR_H
+#define NMR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nmr_ctx nmr_ctx;         /* one GPU + one stream + HBM budget   */
+typedef struct nmr_decoder nmr_decoder; /* device copy of a decoder MLP        */
+typedef struct nmr_inst nmr_inst;       /* one simulated object and its state  */
+
+typedef enum {
+  NMR_OK = 0,
+  NMR_ERR_ARG = -1,       /* invalid argument or shape                        */
+  NMR_ERR_BUDGET = -2,    /* instance does not fit the context's HBM budget    */
+  NMR_ERR_OOM = -3,       /* device allocation failed                          */
+  NMR_ERR_INVERTED = -4,  /* a cubature tet has det F <= 0                     */
+  NMR_ERR_SINGULAR = -5,  /* LU pivot below 1e-300 * max |A_ij|                */
+  NMR_ERR_NONFINITE = -6, /* non-finite residual or Newton matrix              */
+  NMR_ERR_DEVICE = -7     /* HIP runtime error                                 */
+} nmr_status;
+
+typedef enum { NMR_ACT_IDENTITY = 0, NMR_ACT_TANH = 1, NMR_ACT_ELU = 2, NMR_ACT_SIN = 3 } nmr_act;
+typedef enum { NMR_PREC_FP64 = 0, NMR_PREC_FP32 = 1, NMR_PREC_BF16 = 2 } nmr_prec;
+
+/* A fully connected MLP: z_0 = x, z_l = act(W_l z_{l-1} + b_l) for l < L and
+ * a linear last layer (the decoder of Sec. 3.5).  Host pointers, read only
+ * during the create call. */
+typedef struct {
+  int n_layers;             /* L >= 1                                          */
+  const int* widths;        /* L + 1 entries: input size ... output size       */
+  int act;                  /* nmr_act of the hidden layers                    */
+  const double* const* W;   /* L pointers, W[l]: widths[l+1] x widths[l]       */
+  const double* const* b;   /* L pointers, b[l]: widths[l+1]                   */
+} nmr_mlp_desc;
+
+/* One simulated object (host pointers, copied to the device by
+ * nmr_instance_create).  N = 3 * n_vertices, R = n_p + n_q. */
+typedef struct {
+  int n_vertices;
+  const double* X;          /* n_vertices x 3 rest positions                   */
+  int n_tets;
+  const int32_t* tets;      /* n_tets x 4, positively oriented                  */
+  const uint8_t* pinned;    /* n_vertices, 1 = Dirichlet vertex (mask P)        */
+  double E, nu, rho;        /* neo-Hookean Young's modulus, Poisson, density    */
+  double gravity[3];        /* f_ext = M (1 (x) gravity)                        */
+  double dt;                /* implicit-Euler time step                         */
+  int n_p;                  /* linear (PCA) subspace size, may be 0             */
+  const double* U;          /* N x n_p, orthonormal, zero at pinned DOFs        */
+  const nmr_mlp_desc* decoder;   /* decoder (n_q = widths[0], widths[L] >= N)  */
+  nmr_decoder* shared_decoder;   /* if non-NULL, used instead of `decoder`;    */
+                                 /* the first N output rows are used           */
+  int n_cub;                /* cubature set size |C|                            */
+  const int32_t* cub_ids;   /* |C| tet ids                                      */
+  const double* cub_w;      /* |C| fixed weights, or NULL: weight net below     */
+  const nmr_mlp_desc* wnet; /* R -> ... -> |C|, softplus after every layer      */
+  double wnet_scale;        /* w = wnet_scale * wnet(rbar)                      */
+  const double* r0;         /* R initial generalized coordinate                 */
+  const double* rdot0;      /* R initial generalized velocity                   */
+} nmr_problem;
+
+/* ---- lifecycle ---------------------------------------------------------- */
+
+/* Context on GPU `device`; `hip_stream` is a hipStream_t (NULL = a stream the
+ * library creates at default priority).  hbm_budget_bytes = 0: no limit. */
+int nmr_create(int device, void* hip_stream, size_t hbm_budget_bytes, nmr_ctx** out);
+int nmr_destroy(nmr_ctx* ctx);
+const char* nmr_last_error(void);
+
+/* Device copy of a decoder in precision `prec` (nmr_prec), shareable by many
+ * instances (one trained net reused across identical domains, Sec. 6.8).
+ * Destroying it while instances still use it is deferred until the last one
+ * is destroyed. */
+int nmr_decoder_create(nmr_ctx* ctx, const nmr_mlp_desc* desc, int prec, nmr_decoder** out);
+int nmr_decoder_destroy(nmr_decoder* dec);
+
+/* Copies the problem to the device, precomputes rest-shape matrices, volumes
+ * and the lumped mass (Sec. 3.1), and sets the state (rbar, rdot_bar) =
+ * (r0, rdot0).  Charges the context budget: NMR_ERR_BUDGET if it does not
+ * fit, NMR_ERR_OOM if allocation fails. */
+int nmr_instance_create(nmr_ctx* ctx, const nmr_problem* prob, int prec, nmr_inst** out);
+int nmr_instance_destroy(nmr_inst* inst);
+/* Device bytes charged to the budget for this instance (host output). */
+int nmr_instance_bytes(const nmr_inst* inst, size_t* bytes);
+/* Host buffers: r and rdot (R doubles each) of the last completed step; u
+ * (N reals, may be NULL) is the full-space displacement u = U p + D(q).
+ * Synchronizes. */
+int nmr_instance_get_state(nmr_inst* inst, double* r, double* rdot, void* u_or_null);
+/* Host buffers: sets (rbar, rdot_bar) and clears a failed status. */
+int nmr_instance_set_state(nmr_inst* inst, const double* r, const double* rdot);
+/* Status of the last step (nmr_status); synchronizes. */
+int nmr_instance_status(nmr_inst* inst);
+
+/* ---- hot path ----------------------------------------------------------- */
+
+/* Decoder value and contracted derivatives (Sec. 4.3, 4.4, eq. delta_j).
+ * Device inputs, n_q doubles each: q, dq = q - qbar, qdot_bar.
+ * Device outputs (reals): u = D(q) [N], J = dD/dq [N x n_q],
+ * dJ = (S.dq).dq + H.(3 dq - dt qdot_bar) [N x n_q], Hdd = H(dq, dq) [N].
+ * If a_or_null (device, N reals) is given, also the left contractions of
+ * D through complex-step backpropagation: B = sum_i a_i H_i [n_q x n_q
+ * doubles, column j from the perturbation of q_j] and JTa = J^T a [n_q
+ * doubles]; both may be NULL otherwise.  D includes the filter and mask. */
+int decoder_jacobian_hessian(nmr_inst* inst, const double* q, const double* dq,
+                             const double* qdot_bar, const void* a_or_null,
+                             void* u, void* J, void* dJ, void* Hdd,
+                             double* B_or_null, double* JTa_or_null);
+
+/* Cubature force and reduced stiffness (Sec. 5, neo-Hookean tets).  Device
+ * inputs: u [N reals], Jt = [U, J] [N x R reals], w [|C| reals] or NULL for
+ * the instance's current weights.  Device outputs: f_int [N reals] or NULL,
+ * fr = sum_e w_e Jt_e^T f_e [R doubles], Kr = sum_e w_e Jt_e^T K_e Jt_e
+ * [R x R doubles].  NMR_ERR_INVERTED if a cubature tet has det F <= 0
+ * (checked after a synchronization). */
+int cubature_force_stiffness(nmr_inst* inst, const void* u, const void* Jt, const void* w_or_null,
+                             void* f_int_or_null, double* fr, double* Kr);
+
+/* Newton system at iterate r (device, R doubles) of the step that starts from
+ * the instance state: phi (eq. our_equation_of_motion) [R doubles] and its
+ * Jacobian A = dphi/dr (eq. system_mat) [R x R doubles], both device.  Uses
+ * the cubature weights of that step. */
+int reduced_newton_system(nmr_inst* inst, const double* r, double* A, double* phi);
+
+/* One implicit-Euler step with n_iters full Newton iterations starting from
+ * r = rbar, then rdot = (r - rbar) / dt, rbar = r.  resid_norms_or_null:
+ * host, n_iters doubles of ||phi|| per iteration (synchronizes).  A failure
+ * leaves the state of the previous step in place and is returned here (if
+ * synchronized) or by nmr_instance_status. */
+int reduced_newton_step(nmr_inst* inst, int n_iters, double* resid_norms_or_null);
+
+/* Advances n_inst instances (same context) n_steps steps of n_iters Newton
+ * iterations each, all instances together: instances that share a decoder
+ * run their decoder passes as one batched launch per layer, and every phase
+ * is one launch for the whole set, captured in a HIP graph per step.  Host
+ * outputs: status [n_inst] (nmr_status of each instance; a failed instance is
+ * frozen at its last good state, the others continue) and step_ms_or_null
+ * [n_steps] (device time of each step). */
+int step_many(nmr_ctx* ctx, nmr_inst* const* insts, int n_inst, int n_steps, int n_iters,
+              int* status, float* step_ms_or_null);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NMR_H */

@@ -1,0 +1,962 @@
+// C ABI of libnmr (include/nmr.h): contexts, decoders, instances, HIP-graph
+// capture of whole time steps, and the hot-path entry points.  The per-step
+// work is a fixed sequence of kernel launches (decoder jets, output layer,
+// cubature, mass terms, sums, backpropagation, solve), captured once per
+// (instance set, Newton iteration count) and replayed with one
+// hipGraphLaunch per step.
+#include "nmr_internal.h"
+#include "nmr.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace nmr;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                                  \
+  do {                                                                                             \
+    hipError_t e_ = (x);                                                                           \
+    if (e_ != hipSuccess) return fail(NMR_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHK(x)                 \
+  do {                         \
+    int c_ = (x);              \
+    if (c_ != NMR_OK) return c_; \
+  } while (0)
+
+namespace {
+
+struct DevMem {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+};
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+int dalloc(DevMem& m, size_t bytes, void** out) {
+  *out = nullptr;
+  if (bytes == 0) return NMR_OK;
+  void* p = nullptr;
+  if (hipMalloc(&p, round256(bytes)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(NMR_ERR_OOM, "hipMalloc failed");
+  }
+  if (hipMemset(p, 0, round256(bytes)) != hipSuccess) {
+    (void)hipFree(p);
+    return fail(NMR_ERR_DEVICE, "hipMemset failed");
+  }
+  m.ptrs.push_back(p);
+  m.bytes += round256(bytes);
+  *out = p;
+  return NMR_OK;
+}
+
+template <typename P>
+int dalloc_t(DevMem& m, size_t count, P** out) {
+  void* p;
+  int rc = dalloc(m, count * sizeof(P), &p);
+  *out = static_cast<P*>(p);
+  return rc;
+}
+
+uint16_t f2bf(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x7fffffu)) return 0x7fc0;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  std::vector<void*> tabs;  // device tables owned by this entry
+};
+
+}  // namespace
+
+struct nmr_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  hipStream_t cap = nullptr;
+  size_t budget = 0;
+  size_t used = 0;
+  std::map<std::vector<nmr_inst*>, std::map<int, GraphEntry>> many_graphs;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+struct nmr_decoder {
+  nmr_ctx* ctx = nullptr;
+  DecoderDev d{};
+  DevMem mem;
+  int refs = 1;  // the creator's reference
+  bool charged = false;
+};
+
+struct nmr_inst {
+  nmr_ctx* ctx = nullptr;
+  nmr_decoder* dec = nullptr;
+  int prec = PREC_FP32;
+  int N = 0, n = 0, n_p = 0, n_q = 0, R = 0, n_cub = 0;
+  int Cp = 0, Cb = 0, Cf = 0, n_mblk = 0, n_cblk = 0, n_bblk = 0;
+  size_t bytes = 0;
+  DevMem mem;
+  void* tab = nullptr;      // Inst<T> on the device
+  void* api_tab = nullptr;  // scratch Inst<T> for the caller-array entry points
+  std::vector<unsigned char> host;  // host copy of the Inst<T>
+  std::map<int, hipGraphExec_t> step_graphs;
+  double* A_scratch = nullptr;
+};
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+static const int kMaxIters = 64;
+
+static int set_device(nmr_ctx* c) {
+  HIPCHK(hipSetDevice(c->device));
+  return NMR_OK;
+}
+
+template <typename T>
+static Inst<T>& host_inst(nmr_inst* in) {
+  return *reinterpret_cast<Inst<T>*>(in->host.data());
+}
+
+static bool is_f64(const nmr_inst* in) { return in->prec == PREC_FP64; }
+
+static void drop_many_graphs(nmr_ctx* c, nmr_inst* in) {
+  for (auto it = c->many_graphs.begin(); it != c->many_graphs.end();) {
+    if (in == nullptr || std::find(it->first.begin(), it->first.end(), in) != it->first.end()) {
+      for (auto& kv : it->second) {
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+        for (void* p : kv.second.tabs) (void)hipFree(p);
+      }
+      it = c->many_graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+static int check_mlp(const nmr_mlp_desc* d, int min_layers, const char* what) {
+  if (!d) return fail(NMR_ERR_ARG, std::string(what) + ": missing description");
+  if (d->n_layers < min_layers || d->n_layers > NMR_MAX_LAYERS)
+    return fail(NMR_ERR_ARG, std::string(what) + ": layer count out of range");
+  if (!d->widths || !d->W || !d->b) return fail(NMR_ERR_ARG, std::string(what) + ": null arrays");
+  for (int l = 0; l <= d->n_layers; ++l)
+    if (d->widths[l] <= 0) return fail(NMR_ERR_ARG, std::string(what) + ": non-positive width");
+  for (int l = 0; l < d->n_layers; ++l)
+    if (!d->W[l] || !d->b[l]) return fail(NMR_ERR_ARG, std::string(what) + ": null layer");
+  return NMR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" int nmr_create(int device, void* hip_stream, size_t hbm_budget_bytes, nmr_ctx** out) {
+  if (!out) return fail(NMR_ERR_ARG, "null out");
+  *out = nullptr;
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(NMR_ERR_ARG, "no such device");
+  nmr_ctx* c = new nmr_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return fail(NMR_ERR_DEVICE, "hipSetDevice failed");
+  }
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(NMR_ERR_DEVICE, "stream create failed");
+    }
+    c->own_stream = true;
+  }
+  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
+    delete c;
+    return fail(NMR_ERR_DEVICE, "stream/event create failed");
+  }
+  *out = c;
+  return NMR_OK;
+}
+
+extern "C" int nmr_destroy(nmr_ctx* c) {
+  if (!c) return fail(NMR_ERR_ARG, "null ctx");
+  CHK(set_device(c));
+  (void)hipStreamSynchronize(c->stream);
+  drop_many_graphs(c, nullptr);
+  (void)hipStreamDestroy(c->cap);
+  (void)hipEventDestroy(c->ev[0]);
+  (void)hipEventDestroy(c->ev[1]);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+  return NMR_OK;
+}
+
+extern "C" const char* nmr_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// decoder
+// ---------------------------------------------------------------------------
+static int decoder_bytes(const nmr_mlp_desc* desc, int prec, size_t* bytes) {
+  const int L = desc->n_layers;
+  const size_t tw = prec == PREC_FP64 ? 8 : (prec == PREC_BF16 ? 2 : 4);
+  const size_t tb = prec == PREC_FP64 ? 8 : 4;
+  size_t b = 0;
+  for (int l = 0; l < L; ++l) {
+    const size_t ip = pad_to(desc->widths[l], NMR_WPAD), op = pad_to(desc->widths[l + 1], NMR_WPAD);
+    b += round256(ip * op * tw) + round256(op * tb);
+    if (l < L - 1) b += round256(ip * op * tw);
+  }
+  *bytes = b;
+  return NMR_OK;
+}
+
+static int decoder_build(nmr_ctx* ctx, const nmr_mlp_desc* desc, int prec, nmr_decoder** out) {
+  CHK(check_mlp(desc, 2, "decoder"));
+  if (prec < PREC_FP64 || prec > PREC_BF16) return fail(NMR_ERR_ARG, "bad precision");
+  if (desc->act < ACT_IDENTITY || desc->act > ACT_SIN) return fail(NMR_ERR_ARG, "bad activation");
+  const int L = desc->n_layers;
+  if (1 + desc->widths[0] > 64 || 4 + 4 * desc->widths[0] > 128)
+    return fail(NMR_ERR_ARG, "decoder input size n_q must be <= 31");
+  nmr_decoder* d = new nmr_decoder();
+  d->ctx = ctx;
+  d->d.L = L;
+  d->d.act = desc->act;
+  d->d.prec = prec;
+  for (int l = 0; l <= L; ++l) {
+    d->d.w[l] = desc->widths[l];
+    d->d.wp[l] = pad_to(desc->widths[l], NMR_WPAD);
+  }
+  const size_t tw = prec == PREC_FP64 ? 8 : (prec == PREC_BF16 ? 2 : 4);
+  const size_t tb = prec == PREC_FP64 ? 8 : 4;
+  for (int l = 0; l < L; ++l) {
+    const int in = d->d.w[l], outw = d->d.w[l + 1], ip = d->d.wp[l], op = d->d.wp[l + 1];
+    std::vector<unsigned char> hw((size_t)ip * op * tw, 0), hb((size_t)op * tb, 0), ht;
+    if (l < L - 1) ht.assign((size_t)ip * op * tw, 0);
+    auto put = [&](std::vector<unsigned char>& v, size_t idx, double x) {
+      if (prec == PREC_FP64) std::memcpy(&v[idx * 8], &x, 8);
+      else if (prec == PREC_FP32) {
+        float f = (float)x;
+        std::memcpy(&v[idx * 4], &f, 4);
+      } else {
+        uint16_t h = f2bf((float)x);
+        std::memcpy(&v[idx * 2], &h, 2);
+      }
+    };
+    for (int o = 0; o < outw; ++o)
+      for (int i = 0; i < in; ++i) {
+        const double x = desc->W[l][(size_t)o * in + i];
+        put(hw, (size_t)o * ip + i, x);
+        if (l < L - 1) put(ht, (size_t)i * op + o, x);
+      }
+    for (int o = 0; o < outw; ++o) {
+      const double x = desc->b[l][o];
+      if (prec == PREC_FP64) std::memcpy(&hb[o * 8], &x, 8);
+      else {
+        float f = (float)x;
+        std::memcpy(&hb[o * 4], &f, 4);
+      }
+    }
+    void *pw, *pb, *pt = nullptr;
+    int rc = dalloc(d->mem, hw.size(), &pw);
+    if (rc == NMR_OK) rc = dalloc(d->mem, hb.size(), &pb);
+    if (rc == NMR_OK && l < L - 1) rc = dalloc(d->mem, ht.size(), &pt);
+    if (rc != NMR_OK) {
+      d->mem.release();
+      delete d;
+      return rc;
+    }
+    if (hipMemcpy(pw, hw.data(), hw.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(pb, hb.data(), hb.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        (pt && hipMemcpy(pt, ht.data(), ht.size(), hipMemcpyHostToDevice) != hipSuccess)) {
+      d->mem.release();
+      delete d;
+      return fail(NMR_ERR_DEVICE, "decoder upload failed");
+    }
+    d->d.W[l] = pw;
+    d->d.b[l] = pb;
+    d->d.WT[l] = pt;
+  }
+  *out = d;
+  return NMR_OK;
+}
+
+static void decoder_unref(nmr_decoder* d) {
+  if (--d->refs == 0) {
+    if (d->charged) d->ctx->used -= d->mem.bytes;
+    d->mem.release();
+    delete d;
+  }
+}
+
+extern "C" int nmr_decoder_create(nmr_ctx* ctx, const nmr_mlp_desc* desc, int prec, nmr_decoder** out) {
+  if (!ctx || !out) return fail(NMR_ERR_ARG, "null argument");
+  *out = nullptr;
+  CHK(set_device(ctx));
+  CHK(check_mlp(desc, 2, "decoder"));
+  size_t bytes;
+  decoder_bytes(desc, prec, &bytes);
+  if (ctx->budget && ctx->used + bytes > ctx->budget) return fail(NMR_ERR_BUDGET, "decoder exceeds HBM budget");
+  nmr_decoder* d;
+  CHK(decoder_build(ctx, desc, prec, &d));
+  d->charged = true;
+  ctx->used += d->mem.bytes;
+  *out = d;
+  return NMR_OK;
+}
+
+extern "C" int nmr_decoder_destroy(nmr_decoder* d) {
+  if (!d) return fail(NMR_ERR_ARG, "null decoder");
+  CHK(set_device(d->ctx));
+  (void)hipStreamSynchronize(d->ctx->stream);
+  decoder_unref(d);
+  return NMR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// instance
+// ---------------------------------------------------------------------------
+struct Sizes {
+  int N, n, m, n_p, n_q, R, n_cub, L, Cp, Cb, Cf, Wmax, n_mblk, n_cblk, n_bblk, cub_per_blk;
+  int wn_L, wn_maxw;
+};
+
+template <typename T>
+static size_t instance_bytes(const Sizes& s, const DecoderDev& d) {
+  size_t b = 0;
+  auto add = [&](size_t bytes) { b += round256(bytes); };
+  const size_t t = sizeof(T);
+  add(s.R * 8); add(s.R * 8); add(s.R * 8); add(3 * s.n_q * 8); add(kMaxIters * 8); add(4);
+  add(s.N * t); add(s.N * t); add(s.N * t); add((size_t)s.N * s.n_p * t);
+  add(s.n_cub * 16); add(s.n_cub * 9 * t); add(s.n_cub * t); add((s.n + 1) * 4); add(s.n_cub * 16);
+  add(s.n_cub * t);
+  add((size_t)s.Cp * s.Wmax * t); add((size_t)s.Cp * s.Wmax * t);
+  for (int l = 0; l < s.L - 1; ++l) add((size_t)s.Cb * d.wp[l + 1] * t);
+  add((size_t)s.Cf * d.wp[s.L - 1] * t);
+  add((size_t)s.N * s.Cf * t); add(s.N * t);
+  add((size_t)s.Cb * s.Wmax * t); add((size_t)s.Cb * s.Wmax * t);
+  add((size_t)s.n_cub * 12 * t);
+  add((size_t)s.n_cblk * (s.R * s.R + s.R) * 8);
+  add((size_t)s.n_mblk * (s.R * s.R + s.R * s.n_q + s.R + s.n_p) * 8);
+  add((size_t)s.n_bblk * d.wp[s.L - 1] * 8);
+  add((s.R * s.R + s.R) * 8); add((s.R * s.R + s.R * s.n_q + s.R + s.n_p) * 8);
+  add(s.n_q * s.n_q * 8); add(s.n_q * 8);
+  add(s.R * s.R * 8);
+  return b;
+}
+
+template <typename T>
+static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_decoder* dec, nmr_inst* in) {
+  const DecoderDev& d = dec->d;
+  Sizes s{};
+  s.n = p->n_vertices;
+  s.N = 3 * s.n;
+  s.m = p->n_tets;
+  s.n_p = p->n_p;
+  s.n_q = d.w[0];
+  s.R = s.n_p + s.n_q;
+  s.n_cub = p->n_cub;
+  s.L = d.L;
+  s.Cp = pad_to(4 + 4 * s.n_q, 16);
+  s.Cb = pad_to(1 + s.n_q, 16);
+  s.Cf = pad_to(2 + 2 * s.n_q, 16);
+  s.Wmax = 0;
+  for (int l = 1; l < d.L; ++l) s.Wmax = std::max(s.Wmax, d.wp[l]);
+  s.cub_per_blk = 4;
+  s.n_mblk = (s.N + 255) / 256;
+  s.n_cblk = (s.n_cub + s.cub_per_blk - 1) / s.cub_per_blk;
+  s.n_bblk = (s.N + 127) / 128;
+  if (s.R > NMR_MAX_R) return fail(NMR_ERR_ARG, "n_p + n_q must be <= 32");
+  if (d.w[d.L] < s.N) return fail(NMR_ERR_ARG, "decoder output smaller than 3 * n_vertices");
+  if (s.Cf > 64) return fail(NMR_ERR_ARG, "n_q too large for the output layer");
+  s.wn_L = 0;
+  s.wn_maxw = 0;
+  if (!p->cub_w) {
+    CHK(check_mlp(p->wnet, 1, "weight net"));
+    if (p->wnet->widths[0] != s.R || p->wnet->widths[p->wnet->n_layers] != s.n_cub)
+      return fail(NMR_ERR_ARG, "weight net must map R -> n_cub");
+    s.wn_L = p->wnet->n_layers;
+    for (int l = 0; l <= s.wn_L; ++l) s.wn_maxw = std::max(s.wn_maxw, p->wnet->widths[l]);
+  }
+  size_t bytes = instance_bytes<T>(s, d);
+  size_t wn_bytes = 0;
+  if (s.wn_L)
+    for (int l = 0; l < s.wn_L; ++l)
+      wn_bytes += round256((size_t)p->wnet->widths[l] * p->wnet->widths[l + 1] * sizeof(T)) +
+                  round256(p->wnet->widths[l + 1] * sizeof(T));
+  bytes += wn_bytes + round256(2 * s.wn_maxw * sizeof(T)) + 2 * round256(sizeof(Inst<T>));
+  if (!dec->charged) bytes += dec->mem.bytes;
+  if (ctx->budget && ctx->used + bytes > ctx->budget) return fail(NMR_ERR_BUDGET, "instance exceeds HBM budget");
+
+  in->N = s.N; in->n = s.n; in->n_p = s.n_p; in->n_q = s.n_q; in->R = s.R; in->n_cub = s.n_cub;
+  in->Cp = s.Cp; in->Cb = s.Cb; in->Cf = s.Cf;
+  in->n_mblk = s.n_mblk; in->n_cblk = s.n_cblk; in->n_bblk = s.n_bblk;
+  in->host.assign(sizeof(Inst<T>), 0);
+  Inst<T>& I = host_inst<T>(in);
+  I.N = s.N; I.n = s.n; I.n_p = s.n_p; I.n_q = s.n_q; I.R = s.R; I.n_cub = s.n_cub;
+  I.Cp = s.Cp; I.Cb = s.Cb; I.Cf = s.Cf; I.Np = pad_to(s.N, NMR_WPAD);
+  I.n_mblk = s.n_mblk; I.n_cblk = s.n_cblk; I.n_bblk = s.n_bblk; I.cub_per_blk = s.cub_per_blk;
+  I.dt = p->dt;
+  I.mu = p->E / (2.0 * (1.0 + p->nu));
+  I.lam = p->E * p->nu / ((1.0 + p->nu) * (1.0 - 2.0 * p->nu));
+  for (int c = 0; c < 3; ++c) I.g[c] = p->gravity[c];
+
+  DevMem& M = in->mem;
+  CHK(dalloc_t(M, s.R, &I.r));
+  CHK(dalloc_t(M, s.R, &I.rbar));
+  CHK(dalloc_t(M, s.R, &I.rdot));
+  CHK(dalloc_t(M, 3 * s.n_q, &I.dec_in));
+  CHK(dalloc_t(M, kMaxIters, &I.resid));
+  CHK(dalloc_t(M, 1, &I.status));
+  T *X, *mass, *keep, *U = nullptr, *Bm, *Ve;
+  int *cub_v, *csr_ptr, *csr_ent;
+  CHK(dalloc_t(M, s.N, &X));
+  CHK(dalloc_t(M, s.N, &mass));
+  CHK(dalloc_t(M, s.N, &keep));
+  CHK(dalloc_t(M, (size_t)s.N * s.n_p, &U));
+  CHK(dalloc_t(M, 4 * s.n_cub, &cub_v));
+  CHK(dalloc_t(M, 9 * s.n_cub, &Bm));
+  CHK(dalloc_t(M, s.n_cub, &Ve));
+  CHK(dalloc_t(M, s.n + 1, &csr_ptr));
+  CHK(dalloc_t(M, 4 * s.n_cub, &csr_ent));
+  CHK(dalloc_t(M, s.n_cub, &I.cub_w));
+  I.X = X; I.mass = mass; I.keep = keep; I.U = U; I.cub_v = cub_v; I.cub_Bm = Bm; I.cub_Ve = Ve;
+  I.csr_ptr = csr_ptr; I.csr_ent = csr_ent;
+  CHK(dalloc_t(M, (size_t)s.Cp * s.Wmax, &I.act0));
+  CHK(dalloc_t(M, (size_t)s.Cp * s.Wmax, &I.act1));
+  for (int l = 0; l < s.L - 1; ++l) CHK(dalloc_t(M, (size_t)s.Cb * d.wp[l + 1], &I.pre[l]));
+  CHK(dalloc_t(M, (size_t)s.Cf * d.wp[s.L - 1], &I.fold));
+  CHK(dalloc_t(M, (size_t)s.N * s.Cf, &I.rec));
+  CHK(dalloc_t(M, s.N, &I.seed));
+  CHK(dalloc_t(M, (size_t)s.Cb * s.Wmax, &I.zb0));
+  CHK(dalloc_t(M, (size_t)s.Cb * s.Wmax, &I.zb1));
+  CHK(dalloc_t(M, (size_t)s.n_cub * 12, &I.fe));
+  CHK(dalloc_t(M, (size_t)s.n_cblk * (s.R * s.R + s.R), &I.part_cub));
+  CHK(dalloc_t(M, (size_t)s.n_mblk * (s.R * s.R + s.R * s.n_q + s.R + s.n_p), &I.part_mass));
+  CHK(dalloc_t(M, (size_t)s.n_bblk * d.wp[s.L - 1], &I.part_bwd));
+  CHK(dalloc_t(M, s.R * s.R + s.R, &I.sum_cub));
+  CHK(dalloc_t(M, s.R * s.R + s.R * s.n_q + s.R + s.n_p, &I.sum_mass));
+  CHK(dalloc_t(M, s.n_q * s.n_q, &I.Bq));
+  CHK(dalloc_t(M, s.n_q, &I.JTa));
+  CHK(dalloc_t(M, s.R * s.R, &in->A_scratch));
+  // cubature sources: the Newton path reads the decoder records
+  I.cu_u = I.rec; I.cu_u_ld = s.Cf;
+  I.cu_Ja = U; I.cu_Ja_ld = s.n_p; I.cu_na = s.n_p;
+  I.cu_Jb = I.rec + 1; I.cu_Jb_ld = s.Cf; I.cu_nb = s.n_q;
+  I.cu_w = I.cub_w;
+  // weight net
+  I.wn_L = s.wn_L;
+  I.wn_scale = p->wnet_scale;
+  I.wn_maxw = s.wn_maxw;
+  for (int l = 0; l < s.wn_L; ++l) {
+    const int wi = p->wnet->widths[l], wo = p->wnet->widths[l + 1];
+    I.wn_w[l] = wi;
+    I.wn_w[l + 1] = wo;
+    std::vector<T> hw((size_t)wi * wo), hb(wo);
+    for (size_t k = 0; k < hw.size(); ++k) hw[k] = (T)p->wnet->W[l][k];
+    for (int o = 0; o < wo; ++o) hb[o] = (T)p->wnet->b[l][o];
+    T *pw, *pb;
+    CHK(dalloc_t(M, hw.size(), &pw));
+    CHK(dalloc_t(M, hb.size(), &pb));
+    HIPCHK(hipMemcpy(pw, hw.data(), hw.size() * sizeof(T), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(pb, hb.data(), hb.size() * sizeof(T), hipMemcpyHostToDevice));
+    I.wn_W[l] = pw;
+    I.wn_b[l] = pb;
+  }
+  if (s.wn_L) CHK(dalloc_t(M, 2 * (size_t)s.wn_maxw, &I.wn_buf));
+
+  // host-side index bookkeeping and constant uploads
+  {
+    std::vector<T> hX(s.N), hkeep(s.N), hU((size_t)s.N * s.n_p);
+    for (int i = 0; i < s.N; ++i) {
+      hX[i] = (T)p->X[i];
+      hkeep[i] = p->pinned[i / 3] ? T(0) : T(1);
+    }
+    for (size_t k = 0; k < hU.size(); ++k) hU[k] = (T)p->U[k];
+    std::vector<int> hcv(4 * s.n_cub);
+    for (int c = 0; c < s.n_cub; ++c) {
+      const int e = p->cub_ids[c];
+      if (e < 0 || e >= s.m) return fail(NMR_ERR_ARG, "cubature id out of range");
+      for (int a = 0; a < 4; ++a) hcv[4 * c + a] = p->tets[4 * e + a];
+    }
+    for (int k = 0; k < 4 * s.m; ++k)
+      if (p->tets[k] < 0 || p->tets[k] >= s.n) return fail(NMR_ERR_ARG, "tet vertex out of range");
+    // vertex -> (cubature slot, corner), slots in increasing order
+    std::vector<int> cnt(s.n + 1, 0), ent(4 * s.n_cub);
+    for (int c = 0; c < s.n_cub; ++c)
+      for (int a = 0; a < 4; ++a) cnt[hcv[4 * c + a] + 1]++;
+    for (int v = 0; v < s.n; ++v) cnt[v + 1] += cnt[v];
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    for (int c = 0; c < s.n_cub; ++c)
+      for (int a = 0; a < 4; ++a) ent[fill[hcv[4 * c + a]]++] = 4 * c + a;
+    HIPCHK(hipMemcpy(X, hX.data(), s.N * sizeof(T), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(keep, hkeep.data(), s.N * sizeof(T), hipMemcpyHostToDevice));
+    if (s.n_p) HIPCHK(hipMemcpy(U, hU.data(), hU.size() * sizeof(T), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(cub_v, hcv.data(), hcv.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(csr_ptr, cnt.data(), (s.n + 1) * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(csr_ent, ent.data(), ent.size() * 4, hipMemcpyHostToDevice));
+    if (p->cub_w) {
+      std::vector<T> hw(s.n_cub);
+      for (int c = 0; c < s.n_cub; ++c) hw[c] = (T)p->cub_w[c];
+      HIPCHK(hipMemcpy(I.cub_w, hw.data(), s.n_cub * sizeof(T), hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemcpy(I.rbar, p->r0, s.R * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(I.r, p->r0, s.R * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(I.rdot, p->rdot0, s.R * 8, hipMemcpyHostToDevice));
+    // rest shape and lumped mass on the device (temporaries not charged)
+    std::vector<int> vcnt(s.n + 1, 0), vent(4 * s.m);
+    for (int e = 0; e < s.m; ++e)
+      for (int a = 0; a < 4; ++a) vcnt[p->tets[4 * e + a] + 1]++;
+    for (int v = 0; v < s.n; ++v) vcnt[v + 1] += vcnt[v];
+    std::vector<int> vf(vcnt.begin(), vcnt.end() - 1);
+    for (int e = 0; e < s.m; ++e)
+      for (int a = 0; a < 4; ++a) vent[vf[p->tets[4 * e + a]]++] = e;
+    DevMem tmp;
+    double *dX, *dVe;
+    int *dT, *dcub, *dvp, *dve;
+    int rc = NMR_OK;
+    if (rc == NMR_OK) rc = dalloc_t(tmp, s.N, &dX);
+    if (rc == NMR_OK) rc = dalloc_t(tmp, s.m, &dVe);
+    if (rc == NMR_OK) rc = dalloc_t(tmp, 4 * s.m, &dT);
+    if (rc == NMR_OK) rc = dalloc_t(tmp, s.n_cub, &dcub);
+    if (rc == NMR_OK) rc = dalloc_t(tmp, s.n + 1, &dvp);
+    if (rc == NMR_OK) rc = dalloc_t(tmp, 4 * s.m, &dve);
+    if (rc != NMR_OK) {
+      tmp.release();
+      return rc;
+    }
+    (void)hipMemcpy(dX, p->X, s.N * 8, hipMemcpyHostToDevice);
+    (void)hipMemcpy(dT, p->tets, 16 * (size_t)s.m, hipMemcpyHostToDevice);
+    (void)hipMemcpy(dcub, p->cub_ids, 4 * (size_t)s.n_cub, hipMemcpyHostToDevice);
+    (void)hipMemcpy(dvp, vcnt.data(), 4 * (size_t)(s.n + 1), hipMemcpyHostToDevice);
+    (void)hipMemcpy(dve, vent.data(), 4 * (size_t)(4 * s.m), hipMemcpyHostToDevice);
+    launch_rest_shape<T>(dX, dT, s.m, dcub, s.n_cub, dvp, dve, s.n, p->rho, Bm, Ve, mass, dVe, ctx->stream);
+    hipError_t e1 = hipGetLastError();
+    hipError_t e2 = hipStreamSynchronize(ctx->stream);
+    tmp.release();
+    if (e1 != hipSuccess || e2 != hipSuccess) return fail(NMR_ERR_DEVICE, "rest-shape setup failed");
+  }
+  // device copies of the instance table
+  CHK(dalloc(M, sizeof(Inst<T>), &in->tab));
+  CHK(dalloc(M, sizeof(Inst<T>), &in->api_tab));
+  HIPCHK(hipMemcpy(in->tab, &I, sizeof(Inst<T>), hipMemcpyHostToDevice));
+  in->bytes = M.bytes + (dec->charged ? 0 : dec->mem.bytes);
+  return NMR_OK;
+}
+
+extern "C" int nmr_instance_create(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_inst** out) {
+  if (!ctx || !p || !out) return fail(NMR_ERR_ARG, "null argument");
+  *out = nullptr;
+  CHK(set_device(ctx));
+  if (prec < PREC_FP64 || prec > PREC_BF16) return fail(NMR_ERR_ARG, "bad precision");
+  if (p->n_vertices <= 0 || !p->X || p->n_tets <= 0 || !p->tets || !p->pinned || p->n_cub <= 0 || !p->cub_ids ||
+      !p->r0 || !p->rdot0 || p->n_p < 0 || (p->n_p > 0 && !p->U) || !(p->dt > 0))
+    return fail(NMR_ERR_ARG, "incomplete problem");
+  nmr_decoder* dec = p->shared_decoder;
+  bool own = false;
+  if (dec) {
+    if (dec->ctx != ctx) return fail(NMR_ERR_ARG, "shared decoder belongs to another context");
+    if (dec->d.prec != prec) return fail(NMR_ERR_ARG, "shared decoder precision differs");
+  } else {
+    size_t db;
+    CHK(check_mlp(p->decoder, 2, "decoder"));
+    decoder_bytes(p->decoder, prec, &db);
+    if (ctx->budget && ctx->used + db > ctx->budget) return fail(NMR_ERR_BUDGET, "decoder exceeds HBM budget");
+    CHK(decoder_build(ctx, p->decoder, prec, &dec));
+    own = true;
+  }
+  nmr_inst* in = new nmr_inst();
+  in->ctx = ctx;
+  in->dec = dec;
+  in->prec = prec;
+  if (!own) dec->refs++;
+  int rc = (prec == PREC_FP64) ? build_instance<double>(ctx, p, prec, dec, in)
+                               : build_instance<float>(ctx, p, prec, dec, in);
+  if (rc != NMR_OK) {
+    std::string msg = g_err;
+    in->mem.release();
+    decoder_unref(dec);
+    delete in;
+    g_err = msg;
+    return rc;
+  }
+  ctx->used += in->bytes;
+  *out = in;
+  return NMR_OK;
+}
+
+extern "C" int nmr_instance_destroy(nmr_inst* in) {
+  if (!in) return fail(NMR_ERR_ARG, "null instance");
+  nmr_ctx* c = in->ctx;
+  CHK(set_device(c));
+  (void)hipStreamSynchronize(c->stream);
+  drop_many_graphs(c, in);
+  for (auto& kv : in->step_graphs) (void)hipGraphExecDestroy(kv.second);
+  c->used -= in->bytes;
+  in->mem.release();
+  decoder_unref(in->dec);
+  delete in;
+  return NMR_OK;
+}
+
+extern "C" int nmr_instance_bytes(const nmr_inst* in, size_t* bytes) {
+  if (!in || !bytes) return fail(NMR_ERR_ARG, "null argument");
+  *bytes = in->bytes;
+  return NMR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch sequences
+// ---------------------------------------------------------------------------
+struct Group {
+  nmr_decoder* dec;
+  bool f64;
+  void* tab;  // device array of Inst<T>
+  int nb, Cp, Cb, Cf, maxN, maxR, n_q, max_mblk, max_cblk, max_bblk, max_entries;
+  bool any_np;
+};
+
+static Group group_of(const std::vector<nmr_inst*>& v, void* tab) {
+  Group g{};
+  g.dec = v[0]->dec;
+  g.f64 = is_f64(v[0]);
+  g.tab = tab;
+  g.nb = (int)v.size();
+  g.Cp = v[0]->Cp; g.Cb = v[0]->Cb; g.Cf = v[0]->Cf; g.n_q = v[0]->n_q;
+  for (nmr_inst* in : v) {
+    g.maxN = std::max(g.maxN, in->N);
+    g.maxR = std::max(g.maxR, in->R);
+    g.max_mblk = std::max(g.max_mblk, in->n_mblk);
+    g.max_cblk = std::max(g.max_cblk, in->n_cblk);
+    g.max_bblk = std::max(g.max_bblk, in->n_bblk);
+    g.max_entries = std::max(g.max_entries, 2 * in->R * in->R + in->R * in->n_q + 2 * in->R + in->n_p);
+    g.any_np = g.any_np || in->n_p > 0;
+  }
+  return g;
+}
+
+template <typename T>
+static void enqueue_decoder_fwd(const Group& g, hipStream_t s, int add_up) {
+  const DecoderDev& d = g.dec->d;
+  const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
+  for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, s);
+  launch_fwd_out<T>(d, tab, g.nb, g.maxN, g.Cf, s);
+  if (g.any_np) launch_filter<T>(tab, g.nb, add_up, s);
+}
+
+template <typename T>
+static void enqueue_decoder_bwd(const Group& g, hipStream_t s) {
+  const DecoderDev& d = g.dec->d;
+  const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
+  launch_bwd_out<T>(d, tab, g.nb, g.max_bblk, s);
+  launch_bwd_reduce<T>(d, tab, g.nb, s);
+  for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, s);
+}
+
+template <typename T>
+static void enqueue_iteration(const Group& g, int iter, int mode, double* A_out, double* phi_out, hipStream_t s) {
+  const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
+  enqueue_decoder_fwd<T>(g, s, 1);
+  launch_cubature<T>(tab, g.nb, g.max_cblk, s);
+  launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
+  launch_sums<T>(tab, g.nb, g.max_entries, s);
+  enqueue_decoder_bwd<T>(g, s);
+  launch_solve<T>(tab, g.nb, iter, mode, A_out, phi_out, s);
+}
+
+static void enqueue_step(const Group& g, int K, hipStream_t s) {
+  for (int it = -1; it < K; ++it) {
+    if (g.f64) {
+      if (it < 0) launch_step_begin<double>(static_cast<const Inst<double>*>(g.tab), g.nb, BEGIN_STEP, s);
+      else enqueue_iteration<double>(g, it, SOLVE_UPDATE | (it == K - 1 ? SOLVE_FINISH : 0), nullptr, nullptr, s);
+    } else {
+      if (it < 0) launch_step_begin<float>(static_cast<const Inst<float>*>(g.tab), g.nb, BEGIN_STEP, s);
+      else enqueue_iteration<float>(g, it, SOLVE_UPDATE | (it == K - 1 ? SOLVE_FINISH : 0), nullptr, nullptr, s);
+    }
+  }
+}
+
+static int capture(nmr_ctx* c, const std::vector<Group>& groups, int K, hipGraphExec_t* exec) {
+  hipGraph_t graph;
+  HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+  for (const Group& g : groups) enqueue_step(g, K, c->cap);
+  HIPCHK(hipStreamEndCapture(c->cap, &graph));
+  hipError_t e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(NMR_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return NMR_OK;
+}
+
+static int map_status(int st) {
+  if (st & ST_INVERTED) return NMR_ERR_INVERTED;
+  if (st & ST_NONFINITE) return NMR_ERR_NONFINITE;
+  if (st & ST_SINGULAR) return NMR_ERR_SINGULAR;
+  return NMR_OK;
+}
+
+static int read_status(nmr_inst* in, int* st) {
+  const int* dst = is_f64(in) ? host_inst<double>(in).status : host_inst<float>(in).status;
+  HIPCHK(hipStreamSynchronize(in->ctx->stream));
+  HIPCHK(hipMemcpy(st, dst, sizeof(int), hipMemcpyDeviceToHost));
+  return NMR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// entry points
+// ---------------------------------------------------------------------------
+extern "C" int reduced_newton_step(nmr_inst* in, int n_iters, double* resid_norms_or_null) {
+  if (!in) return fail(NMR_ERR_ARG, "null instance");
+  if (n_iters < 1 || n_iters > kMaxIters) return fail(NMR_ERR_ARG, "n_iters must be in [1, 64]");
+  nmr_ctx* c = in->ctx;
+  CHK(set_device(c));
+  auto it = in->step_graphs.find(n_iters);
+  if (it == in->step_graphs.end()) {
+    std::vector<nmr_inst*> v{in};
+    hipGraphExec_t ex;
+    CHK(capture(c, {group_of(v, in->tab)}, n_iters, &ex));
+    it = in->step_graphs.emplace(n_iters, ex).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, c->stream));
+  if (resid_norms_or_null) {
+    const double* dres = is_f64(in) ? host_inst<double>(in).resid : host_inst<float>(in).resid;
+    HIPCHK(hipMemcpyAsync(resid_norms_or_null, dres, n_iters * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    int st;
+    CHK(read_status(in, &st));
+    const int rc = map_status(st);
+    if (rc != NMR_OK) return fail(rc, "instance failed during the step");
+  }
+  return NMR_OK;
+}
+
+extern "C" int step_many(nmr_ctx* c, nmr_inst* const* insts, int n_inst, int n_steps, int n_iters, int* status,
+                         float* step_ms_or_null) {
+  if (!c || !insts || n_inst <= 0 || n_steps < 0 || !status) return fail(NMR_ERR_ARG, "bad argument");
+  if (n_iters < 1 || n_iters > kMaxIters) return fail(NMR_ERR_ARG, "n_iters must be in [1, 64]");
+  CHK(set_device(c));
+  std::vector<nmr_inst*> key(insts, insts + n_inst);
+  for (nmr_inst* in : key)
+    if (!in || in->ctx != c) return fail(NMR_ERR_ARG, "instance of another context");
+  auto& per_k = c->many_graphs[key];
+  auto git = per_k.find(n_iters);
+  if (git == per_k.end()) {
+    // group by decoder (instances sharing weights run as one batched launch)
+    std::vector<std::pair<nmr_decoder*, std::vector<nmr_inst*>>> byd;
+    for (nmr_inst* in : key) {
+      auto f = std::find_if(byd.begin(), byd.end(), [&](auto& pr) { return pr.first == in->dec; });
+      if (f == byd.end()) byd.push_back({in->dec, {in}});
+      else f->second.push_back(in);
+    }
+    GraphEntry ge;
+    std::vector<Group> groups;
+    for (auto& pr : byd) {
+      const size_t isz = is_f64(pr.second[0]) ? sizeof(Inst<double>) : sizeof(Inst<float>);
+      std::vector<unsigned char> host(isz * pr.second.size());
+      for (size_t k = 0; k < pr.second.size(); ++k) std::memcpy(&host[k * isz], pr.second[k]->host.data(), isz);
+      void* tab;
+      HIPCHK(hipMalloc(&tab, host.size()));
+      ge.tabs.push_back(tab);
+      HIPCHK(hipMemcpy(tab, host.data(), host.size(), hipMemcpyHostToDevice));
+      groups.push_back(group_of(pr.second, tab));
+    }
+    int rc = capture(c, groups, n_iters, &ge.exec);
+    if (rc != NMR_OK) {
+      for (void* p : ge.tabs) (void)hipFree(p);
+      return rc;
+    }
+    git = per_k.emplace(n_iters, ge).first;
+  }
+  std::vector<hipEvent_t> ev;
+  if (step_ms_or_null) {
+    ev.resize(n_steps + 1);
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(ev[0], c->stream));
+  }
+  for (int s = 0; s < n_steps; ++s) {
+    HIPCHK(hipGraphLaunch(git->second.exec, c->stream));
+    if (step_ms_or_null) HIPCHK(hipEventRecord(ev[s + 1], c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (step_ms_or_null) {
+    for (int s = 0; s < n_steps; ++s) HIPCHK(hipEventElapsedTime(&step_ms_or_null[s], ev[s], ev[s + 1]));
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+  for (int k = 0; k < n_inst; ++k) {
+    int st;
+    CHK(read_status(key[k], &st));
+    status[k] = map_status(st);
+  }
+  return NMR_OK;
+}
+
+template <typename T>
+static int djh_impl(nmr_inst* in, const double* q, const double* dq, const double* qdot, const void* a, void* u,
+                    void* J, void* dJ, void* Hdd, double* B, double* JTa) {
+  nmr_ctx* c = in->ctx;
+  Inst<T>& I = host_inst<T>(in);
+  const size_t nqb = in->n_q * sizeof(double);
+  HIPCHK(hipMemcpyAsync(I.dec_in, q, nqb, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(I.dec_in + in->n_q, dq, nqb, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(I.dec_in + 2 * in->n_q, qdot, nqb, hipMemcpyDeviceToDevice, c->stream));
+  std::vector<nmr_inst*> v{in};
+  Group g = group_of(v, in->tab);
+  enqueue_decoder_fwd<T>(g, c->stream, 0);
+  launch_unpack<T>(static_cast<const Inst<T>*>(in->tab), (T*)u, (T*)J, (T*)dJ, (T*)Hdd, in->N, c->stream);
+  if (a) {
+    launch_seed_from_a<T>(static_cast<const Inst<T>*>(in->tab), static_cast<const T*>(a), 1, in->n_mblk, c->stream);
+    launch_sums<T>(static_cast<const Inst<T>*>(in->tab), 1, g.max_entries, c->stream);
+    enqueue_decoder_bwd<T>(g, c->stream);
+    if (B) HIPCHK(hipMemcpyAsync(B, I.Bq, in->n_q * nqb, hipMemcpyDeviceToDevice, c->stream));
+    if (JTa) HIPCHK(hipMemcpyAsync(JTa, I.JTa, nqb, hipMemcpyDeviceToDevice, c->stream));
+  }
+  HIPCHK(hipGetLastError());
+  return NMR_OK;
+}
+
+extern "C" int decoder_jacobian_hessian(nmr_inst* in, const double* q, const double* dq, const double* qdot_bar,
+                                        const void* a_or_null, void* u, void* J, void* dJ, void* Hdd,
+                                        double* B_or_null, double* JTa_or_null) {
+  if (!in || !q || !dq || !qdot_bar || !u || !J || !dJ || !Hdd) return fail(NMR_ERR_ARG, "null argument");
+  CHK(set_device(in->ctx));
+  return is_f64(in) ? djh_impl<double>(in, q, dq, qdot_bar, a_or_null, u, J, dJ, Hdd, B_or_null, JTa_or_null)
+                    : djh_impl<float>(in, q, dq, qdot_bar, a_or_null, u, J, dJ, Hdd, B_or_null, JTa_or_null);
+}
+
+template <typename T>
+static int cfs_impl(nmr_inst* in, const void* u, const void* Jt, const void* w, void* f_int, double* fr, double* Kr) {
+  nmr_ctx* c = in->ctx;
+  int st0;
+  CHK(read_status(in, &st0));
+  Inst<T> I = host_inst<T>(in);
+  I.cu_u = static_cast<const T*>(u);
+  I.cu_u_ld = 1;
+  I.cu_Ja = static_cast<const T*>(Jt);
+  I.cu_Ja_ld = in->R;
+  I.cu_na = in->R;
+  I.cu_Jb = nullptr;
+  I.cu_Jb_ld = 0;
+  I.cu_nb = 0;
+  if (w) I.cu_w = static_cast<const T*>(w);
+  HIPCHK(hipMemcpy(in->api_tab, &I, sizeof(Inst<T>), hipMemcpyHostToDevice));
+  const Inst<T>* tab = static_cast<const Inst<T>*>(in->api_tab);
+  launch_cubature<T>(tab, 1, in->n_cblk, c->stream);
+  std::vector<nmr_inst*> v{in};
+  Group g = group_of(v, in->api_tab);
+  launch_sums<T>(tab, 1, g.max_entries, c->stream);
+  HIPCHK(hipMemcpyAsync(Kr, I.sum_cub, in->R * in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(fr, I.sum_cub + in->R * in->R, in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (f_int) launch_fint<T>(tab, static_cast<T*>(f_int), in->N, c->stream);
+  HIPCHK(hipGetLastError());
+  int st;
+  CHK(read_status(in, &st));
+  if ((st & ST_INVERTED) && !(st0 & ST_INVERTED)) {
+    HIPCHK(hipMemcpy(I.status, &st0, sizeof(int), hipMemcpyHostToDevice));
+    return fail(NMR_ERR_INVERTED, "a cubature tet has det F <= 0");
+  }
+  return NMR_OK;
+}
+
+extern "C" int cubature_force_stiffness(nmr_inst* in, const void* u, const void* Jt, const void* w_or_null,
+                                        void* f_int_or_null, double* fr, double* Kr) {
+  if (!in || !u || !Jt || !fr || !Kr) return fail(NMR_ERR_ARG, "null argument");
+  CHK(set_device(in->ctx));
+  return is_f64(in) ? cfs_impl<double>(in, u, Jt, w_or_null, f_int_or_null, fr, Kr)
+                    : cfs_impl<float>(in, u, Jt, w_or_null, f_int_or_null, fr, Kr);
+}
+
+template <typename T>
+static int sys_impl(nmr_inst* in, const double* r, double* A, double* phi) {
+  nmr_ctx* c = in->ctx;
+  Inst<T>& I = host_inst<T>(in);
+  HIPCHK(hipMemcpyAsync(I.r, r, in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  std::vector<nmr_inst*> v{in};
+  Group g = group_of(v, in->tab);
+  launch_step_begin<T>(static_cast<const Inst<T>*>(in->tab), 1, BEGIN_SYSTEM, c->stream);
+  enqueue_iteration<T>(g, 0, SOLVE_WRITE_SYSTEM, A, phi, c->stream);
+  HIPCHK(hipGetLastError());
+  return NMR_OK;
+}
+
+extern "C" int reduced_newton_system(nmr_inst* in, const double* r, double* A, double* phi) {
+  if (!in || !r || !A || !phi) return fail(NMR_ERR_ARG, "null argument");
+  CHK(set_device(in->ctx));
+  return is_f64(in) ? sys_impl<double>(in, r, A, phi) : sys_impl<float>(in, r, A, phi);
+}
+
+template <typename T>
+static int get_state_impl(nmr_inst* in, double* r, double* rdot, void* u) {
+  nmr_ctx* c = in->ctx;
+  Inst<T>& I = host_inst<T>(in);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (r) HIPCHK(hipMemcpy(r, I.rbar, in->R * sizeof(double), hipMemcpyDeviceToHost));
+  if (rdot) HIPCHK(hipMemcpy(rdot, I.rdot, in->R * sizeof(double), hipMemcpyDeviceToHost));
+  if (u) {
+    // decode at rbar: r <- rbar, decoder input (qbar, 0, rdot_bar), u = U p + D(q)
+    HIPCHK(hipMemcpyAsync(I.r, I.rbar, in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    launch_step_begin<T>(static_cast<const Inst<T>*>(in->tab), 1, BEGIN_SYSTEM, c->stream);
+    std::vector<nmr_inst*> v{in};
+    Group g = group_of(v, in->tab);
+    enqueue_decoder_fwd<T>(g, c->stream, 1);
+    T* du;
+    HIPCHK(hipMalloc(&du, in->N * sizeof(T)));
+    launch_unpack<T>(static_cast<const Inst<T>*>(in->tab), du, nullptr, nullptr, nullptr, in->N, c->stream);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(u, du, in->N * sizeof(T), hipMemcpyDeviceToHost);
+    (void)hipFree(du);
+    if (e != hipSuccess) return fail(NMR_ERR_DEVICE, hipGetErrorString(e));
+  }
+  return NMR_OK;
+}
+
+extern "C" int nmr_instance_get_state(nmr_inst* in, double* r, double* rdot, void* u_or_null) {
+  if (!in) return fail(NMR_ERR_ARG, "null instance");
+  CHK(set_device(in->ctx));
+  return is_f64(in) ? get_state_impl<double>(in, r, rdot, u_or_null) : get_state_impl<float>(in, r, rdot, u_or_null);
+}
+
+extern "C" int nmr_instance_set_state(nmr_inst* in, const double* r, const double* rdot) {
+  if (!in || !r || !rdot) return fail(NMR_ERR_ARG, "null argument");
+  CHK(set_device(in->ctx));
+  double *rb, *rd;
+  int* st;
+  if (is_f64(in)) {
+    rb = host_inst<double>(in).rbar; rd = host_inst<double>(in).rdot; st = host_inst<double>(in).status;
+  } else {
+    rb = host_inst<float>(in).rbar; rd = host_inst<float>(in).rdot; st = host_inst<float>(in).status;
+  }
+  HIPCHK(hipStreamSynchronize(in->ctx->stream));
+  HIPCHK(hipMemcpy(rb, r, in->R * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(rd, rdot, in->R * sizeof(double), hipMemcpyHostToDevice));
+  const int zero = 0;
+  HIPCHK(hipMemcpy(st, &zero, sizeof(int), hipMemcpyHostToDevice));
+  return NMR_OK;
+}
+
+extern "C" int nmr_instance_status(nmr_inst* in) {
+  if (!in) return fail(NMR_ERR_ARG, "null instance");
+  CHK(set_device(in->ctx));
+  int st;
+  CHK(read_status(in, &st));
+  return map_status(st);
+}

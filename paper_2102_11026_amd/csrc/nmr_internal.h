@@ -1,0 +1,158 @@
+// Internal declarations of libnmr (not part of the C ABI).
+//
+// Data layout in HBM, per instance (all row-major):
+//   dec_in  [3][n_q] f64     q, dq = q - qbar, qdot_bar fed to the decoder
+//   act     [2][Cp][Wmax]    post-activation jets, channel-major, ping-pong
+//   pre[l]  [Cb][m_l]        hidden pre-activations kept for backpropagation:
+//                            channel 0 = value, 1 + j = tangent along e_j
+//   fold    [Cf][m_{L-1}]    last hidden layer folded to output channels
+//   rec     [N][Cf]          one record per DOF: u, J (n_q), dJ (n_q), Hdd
+//   seed    [N]              P a, the backpropagation seed
+//   zb      [2][Cb][Wmax]    adjoints of the hidden layers, ping-pong
+// Jet channels of the forward pass (multicomplex units taken to the h -> 0
+// limit, i.e. each component stored divided by h^order):
+//   0 value, 1 along dq (i2 = i3), 2 along qdot_bar (i4), 3 along (dq, dq),
+//   4 + j along e_j (i1), 4 + n_q + j (e_j, dq), 4 + 2 n_q + j (e_j, qdot_bar),
+//   4 + 3 n_q + j (e_j, dq, dq).
+// Output channels (rec and fold): 0 value, 1 + j  J e_j,
+//   1 + n_q + j  dJ e_j = S(e_j,dq,dq) + 3 H(e_j,dq) - dt H(e_j,qdot_bar),
+//   1 + 2 n_q  Hdd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#define NMR_MAX_LAYERS 16
+#define NMR_MAX_R 32
+#define NMR_WPAD 32  // every layer width is padded to a multiple of this
+
+typedef __hip_bfloat16 bf16_t;
+
+namespace nmr {
+
+enum { ACT_IDENTITY = 0, ACT_TANH = 1, ACT_ELU = 2, ACT_SIN = 3 };
+enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
+enum { ST_OK = 0, ST_INVERTED = 1, ST_SINGULAR = 2, ST_NONFINITE = 4 };
+
+inline int pad_to(int x, int m) { return (x + m - 1) / m * m; }
+
+// Device copy of a decoder.  Weights are zero-padded to [out_p][in_p]
+// (widths padded to NMR_WPAD) in the decoder's weight type; biases in the
+// activation type.
+struct DecoderDev {
+  int L;
+  int act;
+  int prec;
+  int w[NMR_MAX_LAYERS + 1];   // true widths
+  int wp[NMR_MAX_LAYERS + 1];  // padded widths
+  const void* W[NMR_MAX_LAYERS];
+  const void* b[NMR_MAX_LAYERS];
+  const void* WT[NMR_MAX_LAYERS];  // hidden layers: W^T, [in_p][out_p]
+};
+
+// Everything a kernel needs to know about one instance.  T = float for the
+// FP32 / BF16 forms, double for the FP64 form.  One copy lives in device
+// memory per instance; batched launches take an array of them and select
+// the instance with blockIdx.y.
+template <typename T>
+struct Inst {
+  int N, n, n_p, n_q, R, n_cub;
+  int Cp, Cb, Cf;          // padded channel counts: forward, backward, output
+  int Np;                  // N padded to NMR_WPAD
+  int n_mblk, n_cblk, n_bblk;  // partial-sum blocks: mass, cubature, bwd-out
+  int cub_per_blk;
+  double dt, mu, lam, g[3];
+  // state
+  double* r;
+  double* rbar;
+  double* rdot;
+  double* dec_in;          // [3][n_q]
+  double* resid;           // [max_iters]
+  int* status;             // sticky failure bits
+  // mesh and problem constants
+  const T* X;              // [N] rest positions per DOF
+  const T* mass;           // [N]
+  const T* keep;           // [N] 1 - pinned
+  const T* U;              // [N][n_p]
+  const int* cub_v;        // [n_cub][4]
+  const T* cub_Bm;         // [n_cub][9]
+  const T* cub_Ve;         // [n_cub]
+  const int* csr_ptr;      // [n + 1] vertex -> (slot, corner) of cubature tets
+  const int* csr_ent;      // [4 n_cub], value = 4 * slot + corner
+  T* cub_w;                // [n_cub] current weights
+  // cubature sources (Newton path: rec / U; API path: caller arrays)
+  const T* cu_u; int cu_u_ld;
+  const T* cu_Ja; int cu_Ja_ld; int cu_na;
+  const T* cu_Jb; int cu_Jb_ld; int cu_nb;
+  const T* cu_w;
+  // decoder workspaces
+  T* act0;
+  T* act1;
+  T* pre[NMR_MAX_LAYERS];
+  T* fold;
+  T* rec;
+  T* seed;
+  T* zb0;
+  T* zb1;
+  T* fe;                   // [n_cub][12] weighted element forces
+  double* part_cub;        // [n_cblk][R*R + R]
+  double* part_mass;       // [n_mblk][R*R + R*n_q + R + n_p]
+  double* part_bwd;        // [n_bblk][K_last]
+  double* sum_cub;         // [R*R + R]
+  double* sum_mass;        // [R*R + R*n_q + R + n_p]
+  double* Bq;              // [n_q][n_q] a . H, column j from perturbation j
+  double* JTa;             // [n_q]
+  // weight net (optional)
+  int wn_L;
+  int wn_w[NMR_MAX_LAYERS + 1];
+  const T* wn_W[NMR_MAX_LAYERS];
+  const T* wn_b[NMR_MAX_LAYERS];
+  double wn_scale;
+  T* wn_buf;               // [2][max width]
+  int wn_maxw;
+};
+
+// ---- launchers (decoder.hip) -------------------------------------------
+template <typename T>
+void launch_fwd_hidden(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int max_cp, hipStream_t s);
+template <typename T>
+void launch_fwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_np, int max_cf, hipStream_t s);
+template <typename T>
+void launch_filter(const Inst<T>* tab, int nb, int add_up, hipStream_t s);
+template <typename T>
+void launch_bwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_bblk, hipStream_t s);
+template <typename T>
+void launch_bwd_reduce(const DecoderDev& d, const Inst<T>* tab, int nb, hipStream_t s);
+template <typename T>
+void launch_bwd_hidden(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cb, hipStream_t s);
+template <typename T>
+void launch_unpack(const Inst<T>* tab, T* u, T* J, T* dJ, T* Hdd, int N, hipStream_t s);
+
+// ---- launchers (sim.hip) -----------------------------------------------
+template <typename T>
+void launch_rest_shape(const double* X, const int* tets, int m, const int* cub_ids, int n_cub,
+                       const int* vt_ptr, const int* vt_ent, int n, double rho,
+                       T* cub_Bm, T* cub_Ve, T* mass, double* Ve_tmp, hipStream_t s);
+template <typename T>
+void launch_step_begin(const Inst<T>* tab, int nb, int mode, hipStream_t s);
+template <typename T>
+void launch_cubature(const Inst<T>* tab, int nb, int max_cblk, hipStream_t s);
+template <typename T>
+void launch_mass(const Inst<T>* tab, int nb, int max_mblk, int R, int nq, hipStream_t s);
+template <typename T>
+void launch_seed_from_a(const Inst<T>* tab, const T* a, int nb, int max_mblk, hipStream_t s);
+template <typename T>
+void launch_sums(const Inst<T>* tab, int nb, int max_entries, hipStream_t s);
+template <typename T>
+void launch_solve(const Inst<T>* tab, int nb, int iter, int mode, double* A_out, double* phi_out,
+                  hipStream_t s);
+template <typename T>
+void launch_fint(const Inst<T>* tab, T* f_int, int N, hipStream_t s);
+
+// solve modes
+enum { SOLVE_UPDATE = 1, SOLVE_FINISH = 2, SOLVE_WRITE_SYSTEM = 4 };
+// step-begin modes
+enum { BEGIN_STEP = 0, BEGIN_SYSTEM = 1 };
+
+}  // namespace nmr

@@ -1,0 +1,281 @@
+"""Thin ctypes binding of libnmr (the C ABI in include/nmr.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  PyTorch supplies device memory and the stream.  Importing this
+module does not load the library; ``lib()`` does, and raises if the HIP
+library has not been built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnmr.so")
+
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+ACT = {"identity": 0, "tanh": 1, "elu": 2, "sin": 3}
+STATUS = {0: "ok", -1: "arg", -2: "budget", -3: "oom", -4: "inverted", -5: "singular", -6: "nonfinite",
+          -7: "device"}
+
+_dp = C.POINTER(C.c_double)
+
+
+class MlpDesc(C.Structure):
+    _fields_ = [("n_layers", C.c_int), ("widths", C.POINTER(C.c_int)), ("act", C.c_int),
+                ("W", C.POINTER(_dp)), ("b", C.POINTER(_dp))]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("n_vertices", C.c_int), ("X", _dp), ("n_tets", C.c_int), ("tets", C.POINTER(C.c_int32)),
+                ("pinned", C.POINTER(C.c_uint8)), ("E", C.c_double), ("nu", C.c_double), ("rho", C.c_double),
+                ("gravity", C.c_double * 3), ("dt", C.c_double), ("n_p", C.c_int), ("U", _dp),
+                ("decoder", C.POINTER(MlpDesc)), ("shared_decoder", C.c_void_p), ("n_cub", C.c_int),
+                ("cub_ids", C.POINTER(C.c_int32)), ("cub_w", _dp), ("wnet", C.POINTER(MlpDesc)),
+                ("wnet_scale", C.c_double), ("r0", _dp), ("rdot0", _dp)]
+
+
+class NmrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+_LIB = None
+
+
+def lib():
+    """Load libnmr.so; raise if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run paper_2102_11026_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        vp, ip, i = C.c_void_p, C.POINTER(C.c_int), C.c_int
+        sig = {
+            "nmr_create": (i, [i, vp, C.c_size_t, C.POINTER(vp)]),
+            "nmr_destroy": (i, [vp]),
+            "nmr_last_error": (C.c_char_p, []),
+            "nmr_decoder_create": (i, [vp, C.POINTER(MlpDesc), i, C.POINTER(vp)]),
+            "nmr_decoder_destroy": (i, [vp]),
+            "nmr_instance_create": (i, [vp, C.POINTER(ProblemDesc), i, C.POINTER(vp)]),
+            "nmr_instance_destroy": (i, [vp]),
+            "nmr_instance_bytes": (i, [vp, C.POINTER(C.c_size_t)]),
+            "nmr_instance_get_state": (i, [vp, _dp, _dp, vp]),
+            "nmr_instance_set_state": (i, [vp, _dp, _dp]),
+            "nmr_instance_status": (i, [vp]),
+            "decoder_jacobian_hessian": (i, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "cubature_force_stiffness": (i, [vp, vp, vp, vp, vp, vp, vp]),
+            "reduced_newton_system": (i, [vp, vp, vp, vp]),
+            "reduced_newton_step": (i, [vp, i, _dp]),
+            "step_many": (i, [vp, C.POINTER(vp), i, i, i, ip, C.POINTER(C.c_float)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise NmrError(rc, lib().nmr_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+class _Mlp:
+    """Keeps the host arrays of an MLP description alive."""
+
+    def __init__(self, Ws, bs, act: str):
+        self.W = [np.ascontiguousarray(W, dtype=np.float64) for W in Ws]
+        self.b = [np.ascontiguousarray(b, dtype=np.float64) for b in bs]
+        widths = [self.W[0].shape[1]] + [W.shape[0] for W in self.W]
+        self.widths = (C.c_int * len(widths))(*widths)
+        self.Wp = (_dp * len(self.W))(*[W.ctypes.data_as(_dp) for W in self.W])
+        self.bp = (_dp * len(self.b))(*[b.ctypes.data_as(_dp) for b in self.b])
+        self.desc = MlpDesc(len(self.W), self.widths, ACT[act], self.Wp, self.bp)
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None, budget_bytes: int = 0):
+        import torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib().nmr_create(device, C.c_void_p(stream.cuda_stream), budget_bytes, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _check(lib().nmr_destroy(self.h))
+            self.h = None
+
+
+class Decoder:
+    """A device decoder shared by several instances."""
+
+    def __init__(self, ctx: Context, weights, biases, act: str, prec: str = "fp32"):
+        m = _Mlp(weights, biases, act)
+        h = C.c_void_p()
+        _check(lib().nmr_decoder_create(ctx.h, C.byref(m.desc), PREC[prec], C.byref(h)))
+        self.h, self.ctx, self.prec = h, ctx, prec
+
+    def close(self):
+        if self.h:
+            _check(lib().nmr_decoder_destroy(self.h))
+            self.h = None
+
+
+class Instance:
+    def __init__(self, ctx: Context, prob, prec: str = "fp32", shared: Optional[Decoder] = None):
+        import torch
+        self.ctx, self.prob, self.prec = ctx, prob, prec
+        self.N, self.n_p, self.n_q, self.R = prob.N, prob.n_p, prob.n_q, prob.R
+        self.n_cub = int(prob.cub_ids.size)
+        self.rdtype = torch.float64 if prec == "fp64" else torch.float32
+        self.dev = torch.device("cuda", ctx.device)
+        keep = []
+        X = np.ascontiguousarray(prob.X, np.float64)
+        T = np.ascontiguousarray(prob.tets, np.int32)
+        pin = np.ascontiguousarray(prob.pinned, np.uint8)
+        U = np.ascontiguousarray(prob.U, np.float64)
+        ids = np.ascontiguousarray(prob.cub_ids, np.int32)
+        r0 = np.ascontiguousarray(prob.r0, np.float64)
+        rd0 = np.ascontiguousarray(prob.rdot0, np.float64)
+        keep += [X, T, pin, U, ids, r0, rd0]
+        d = ProblemDesc()
+        d.n_vertices, d.X = prob.n, X.ctypes.data_as(_dp)
+        d.n_tets, d.tets = T.shape[0], T.ctypes.data_as(C.POINTER(C.c_int32))
+        d.pinned = pin.ctypes.data_as(C.POINTER(C.c_uint8))
+        d.E, d.nu, d.rho = prob.E, prob.nu, prob.rho
+        d.gravity = (C.c_double * 3)(*prob.gravity)
+        d.dt = prob.dt
+        d.n_p = prob.n_p
+        d.U = U.ctypes.data_as(_dp) if prob.n_p else None
+        if shared is None:
+            dm = _Mlp(prob.weights, prob.biases, prob.act)
+            keep.append(dm)
+            d.decoder = C.pointer(dm.desc)
+            d.shared_decoder = None
+        else:
+            d.decoder = None
+            d.shared_decoder = shared.h
+        d.n_cub, d.cub_ids = ids.size, ids.ctypes.data_as(C.POINTER(C.c_int32))
+        if prob.cub_w is not None:
+            w = np.ascontiguousarray(prob.cub_w, np.float64)
+            keep.append(w)
+            d.cub_w = w.ctypes.data_as(_dp)
+            d.wnet = None
+        else:
+            d.cub_w = None
+            wm = _Mlp(prob.wnet_weights, prob.wnet_biases, "identity")
+            keep.append(wm)
+            d.wnet = C.pointer(wm.desc)
+        d.wnet_scale = prob.wnet_scale
+        d.r0, d.rdot0 = r0.ctypes.data_as(_dp), rd0.ctypes.data_as(_dp)
+        h = C.c_void_p()
+        _check(lib().nmr_instance_create(ctx.h, C.byref(d), PREC[prec], C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            _check(lib().nmr_instance_destroy(self.h))
+            self.h = None
+
+    @property
+    def nbytes(self) -> int:
+        b = C.c_size_t()
+        _check(lib().nmr_instance_bytes(self.h, C.byref(b)))
+        return b.value
+
+    # -- state ---------------------------------------------------------------
+    def get_state(self, with_u: bool = False):
+        r = np.zeros(self.R)
+        rd = np.zeros(self.R)
+        u = np.zeros(self.N, dtype=np.float64 if self.prec == "fp64" else np.float32) if with_u else None
+        _check(lib().nmr_instance_get_state(self.h, r.ctypes.data_as(_dp), rd.ctypes.data_as(_dp),
+                                            None if u is None else u.ctypes.data))
+        return (r, rd, u) if with_u else (r, rd)
+
+    def set_state(self, r, rdot):
+        r = np.ascontiguousarray(r, np.float64)
+        rd = np.ascontiguousarray(rdot, np.float64)
+        _check(lib().nmr_instance_set_state(self.h, r.ctypes.data_as(_dp), rd.ctypes.data_as(_dp)))
+
+    def status(self) -> int:
+        return lib().nmr_instance_status(self.h)
+
+    # -- hot path --------------------------------------------------------------
+    def step(self, n_iters: int, resid: bool = True):
+        """One implicit-Euler step; returns ||phi|| per Newton iteration if resid."""
+        if resid:
+            out = np.zeros(n_iters)
+            _check(lib().reduced_newton_step(self.h, n_iters, out.ctypes.data_as(_dp)))
+            return out
+        _check(lib().reduced_newton_step(self.h, n_iters, None))
+        return None
+
+    def decoder_jacobian_hessian(self, q, dq, qdot, a=None):
+        import torch
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        rt = dict(dtype=self.rdtype, device=self.dev)
+        q, dq, qdot = (torch.as_tensor(np.asarray(x, np.float64), **f64).contiguous() for x in (q, dq, qdot))
+        out = dict(u=torch.empty(self.N, **rt), J=torch.empty(self.N, self.n_q, **rt),
+                   dJ=torch.empty(self.N, self.n_q, **rt), Hdd=torch.empty(self.N, **rt))
+        B = JTa = at = None
+        if a is not None:
+            at = torch.as_tensor(np.asarray(a), **rt).contiguous() if not torch.is_tensor(a) else a.to(**rt).contiguous()
+            B = torch.empty(self.n_q, self.n_q, **f64)
+            JTa = torch.empty(self.n_q, **f64)
+        torch.cuda.synchronize(self.dev)
+        _check(lib().decoder_jacobian_hessian(self.h, _ptr(q), _ptr(dq), _ptr(qdot), _ptr(at), _ptr(out["u"]),
+                                              _ptr(out["J"]), _ptr(out["dJ"]), _ptr(out["Hdd"]), _ptr(B),
+                                              _ptr(JTa)))
+        torch.cuda.synchronize(self.dev)
+        if a is not None:
+            out["B"], out["JTa"] = B, JTa
+        return out
+
+    def cubature_force_stiffness(self, u, Jt, w=None, want_fint: bool = True):
+        import torch
+        rt = dict(dtype=self.rdtype, device=self.dev)
+        ut = torch.as_tensor(np.asarray(u), **rt).contiguous()
+        Jtt = torch.as_tensor(np.asarray(Jt), **rt).contiguous()
+        wt = None if w is None else torch.as_tensor(np.asarray(w), **rt).contiguous()
+        fint = torch.empty(self.N, **rt) if want_fint else None
+        fr = torch.empty(self.R, dtype=torch.float64, device=self.dev)
+        Kr = torch.empty(self.R, self.R, dtype=torch.float64, device=self.dev)
+        torch.cuda.synchronize(self.dev)
+        _check(lib().cubature_force_stiffness(self.h, _ptr(ut), _ptr(Jtt), _ptr(wt), _ptr(fint), _ptr(fr),
+                                              _ptr(Kr)))
+        torch.cuda.synchronize(self.dev)
+        return dict(f_int=fint, fr=fr, Kr=Kr)
+
+    def newton_system(self, r):
+        import torch
+        rt = torch.as_tensor(np.asarray(r, np.float64), dtype=torch.float64, device=self.dev).contiguous()
+        A = torch.empty(self.R, self.R, dtype=torch.float64, device=self.dev)
+        phi = torch.empty(self.R, dtype=torch.float64, device=self.dev)
+        torch.cuda.synchronize(self.dev)
+        _check(lib().reduced_newton_system(self.h, _ptr(rt), _ptr(A), _ptr(phi)))
+        torch.cuda.synchronize(self.dev)
+        return A, phi
+
+
+def step_many(ctx: Context, insts: Sequence[Instance], n_steps: int, n_iters: int, timings: bool = True):
+    """Advance all instances together; returns (status per instance, ms per step)."""
+    n = len(insts)
+    hs = (C.c_void_p * n)(*[x.h.value for x in insts])
+    st = (C.c_int * n)()
+    ms = (C.c_float * max(n_steps, 1))() if timings else None
+    _check(lib().step_many(ctx.h, hs, n, n_steps, n_iters, st, ms))
+    return list(st), (list(ms)[:n_steps] if timings else None)

@@ -1,0 +1,158 @@
+"""GPU parity of every hot-path call against the FP64 oracle (through the C ABI).
+
+Tolerances (relative Frobenius norms) follow the arithmetic: FP64 mode is
+exact CSFD up to rounding; the FP32 form accumulates ~1e-7 per operation over
+K <= 512-term dot products chained through ten layers, and the third-order
+channel is a difference of products, so it carries the loosest bound.
+"""
+import numpy as np
+import pytest
+
+from oracle import decoder as odec
+from oracle.newton import Instance as OInst
+from paper_2102_11026_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {
+    "fp64": dict(u=1e-12, J=1e-11, dJ=1e-10, Hdd=1e-10, B=1e-10, JTa=1e-11, fint=1e-12, fr=1e-12, Kr=1e-11,
+                 A=1e-10, phi=1e-10),
+    "fp32": dict(u=1e-5, J=1e-4, dJ=1e-3, Hdd=1e-3, B=1e-3, JTa=1e-4, fint=1e-5, fr=1e-5, Kr=1e-4,
+                 A=1e-4, phi=1e-4),
+}
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def nmr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2102_11026_amd import nmr as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(nmr):
+    c = nmr.Context(0)
+    yield c
+    c.close()
+
+
+def problems():
+    return {
+        "bar192": synth.config_plain_fp64(),
+        "tiny_elu_np": synth.tiny_problem(grid=(3, 3, 5), widths=(4, 24, 40, 135), act="elu", n_p=3,
+                                          name="t1", q_std=0.3, out_scale=0.1),
+        "tiny_sin_wnet": synth.tiny_problem(grid=(3, 4, 6), widths=(5, 33, 70, 216), act="sin", n_cub=17,
+                                            name="t2", q_std=0.3, out_scale=0.1),
+    }
+
+
+PROBS = problems()
+
+
+def random_inputs(p, seed=0):
+    rng = np.random.default_rng(seed)
+    nq = p.n_q
+    q = p.r0[p.n_p:] + rng.normal(size=nq) * 0.05
+    dq = rng.normal(size=nq) * 0.02
+    qdot = rng.normal(size=nq) * 0.5
+    a = rng.normal(size=p.N)
+    return q, dq, qdot, a
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(PROBS))
+def test_decoder_jacobian_hessian(nmr, ctx, name, prec):
+    p = PROBS[name]
+    inst = nmr.Instance(ctx, p, prec)
+    try:
+        q, dq, qdot, a = random_inputs(p)
+        got = inst.decoder_jacobian_hessian(q, dq, qdot, a)
+        oi = OInst(p)
+        ref = oi.decode(q, dq, qdot)
+        JTa, B = oi.left(q, a)
+        t = TOL[prec]
+        print(name, prec, {k: rel(got[k].cpu().numpy(), ref[kk]) for k, kk in
+                           [("u", "m"), ("J", "J"), ("dJ", "dJ"), ("Hdd", "Hdd")]})
+        assert rel(got["u"].cpu().numpy(), ref["m"]) < t["u"]
+        assert rel(got["J"].cpu().numpy(), ref["J"]) < t["J"]
+        assert rel(got["dJ"].cpu().numpy(), ref["dJ"]) < t["dJ"]
+        assert rel(got["Hdd"].cpu().numpy(), ref["Hdd"]) < t["Hdd"]
+        assert rel(got["JTa"].cpu().numpy(), JTa) < t["JTa"]
+        assert rel(got["B"].cpu().numpy(), B) < t["B"]
+    finally:
+        inst.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(PROBS))
+def test_cubature_force_stiffness(nmr, ctx, name, prec):
+    from oracle import fem
+    p = PROBS[name]
+    inst = nmr.Instance(ctx, p, prec)
+    try:
+        rng = np.random.default_rng(1)
+        u = rng.normal(size=p.N) * 0.004 * np.repeat(1 - p.pinned, 3)
+        Jt = rng.normal(size=(p.N, p.R)) * 0.1
+        w = rng.uniform(0.5, 2.0, size=p.cub_ids.size)
+        got = inst.cubature_force_stiffness(u, Jt, w)
+        oi = OInst(p)
+        f_int, fr, Kr = fem.cubature_force_stiffness(p.X, p.tets, u, Jt, p.cub_ids, w, oi.Bm, oi.Ve, oi.mu, oi.lam)
+        t = TOL[prec]
+        assert rel(got["f_int"].cpu().numpy(), f_int) < t["fint"]
+        assert rel(got["fr"].cpu().numpy(), fr) < t["fr"]
+        assert rel(got["Kr"].cpu().numpy(), Kr) < t["Kr"]
+    finally:
+        inst.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(PROBS))
+def test_newton_system(nmr, ctx, name, prec):
+    p = PROBS[name]
+    rng = np.random.default_rng(2)
+    rdot = rng.normal(size=p.R) * 0.3
+    inst = nmr.Instance(ctx, p.replace(rdot0=rdot), prec)
+    try:
+        oi = OInst(p)
+        r = p.r0 + rng.normal(size=p.R) * 0.01
+        A, phi = inst.newton_system(r)
+        sysd = oi.system(r, p.r0, rdot, oi.cubature_weights(p.r0))
+        t = TOL[prec]
+        assert rel(phi.cpu().numpy(), sysd["phi"]) < t["phi"]
+        assert rel(A.cpu().numpy(), sysd["A"]) < t["A"]
+    finally:
+        inst.close()
+
+
+def test_trajectory_plain_fp64(nmr, ctx):
+    """20 steps x 3 Newton iterations of the 192-vertex bar in FP64 mode."""
+    p = PROBS["bar192"]
+    inst = nmr.Instance(ctx, p, "fp64")
+    try:
+        oi = OInst(p)
+        st = oi.initial_state()
+        scale = vscale = None
+        for s in range(p.steps):
+            norms = inst.step(p.newton_iters)
+            st, onorms = oi.step(st, p.newton_iters)
+            r, rd = inst.get_state()
+            assert rel(r, st.rbar) < 1e-9, s
+            # once the bar is at rest rdot = (r - rbar)/dt cancels, so compare it
+            # against the velocity scale of the first step
+            vscale = vscale or np.linalg.norm(st.rdot_bar)
+            assert np.linalg.norm(rd - st.rdot_bar) < 1e-9 * vscale, s
+            scale = scale or onorms[0]
+            np.testing.assert_allclose(norms, onorms, rtol=1e-6, atol=1e-11 * scale)
+        r, rd, u = inst.get_state(with_u=True)
+        assert rel(u, oi.displacement(st.rbar)) < 1e-9
+    finally:
+        inst.close()
