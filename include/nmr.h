@@ -174,6 +174,28 @@ int reduced_newton_step(nmr_inst* inst, int n_iters, double* resid_norms_or_null
 int step_many(nmr_ctx* ctx, nmr_inst* const* insts, int n_inst, int n_steps, int n_iters,
               int* status, float* step_ms_or_null);
 
+/* ---- measurement -------------------------------------------------------- */
+
+/* Phases of one Newton iteration, in launch order. */
+typedef enum {
+  NMR_PHASE_DEC_HIDDEN = 0, /* forward jet GEMMs of the hidden layers         */
+  NMR_PHASE_DEC_OUT = 1,    /* output-layer GEMM (+ filter when n_p > 0)      */
+  NMR_PHASE_CUBATURE = 2,   /* cubature force / reduced stiffness             */
+  NMR_PHASE_MASS = 3,       /* mass terms, residual pieces, BP seed           */
+  NMR_PHASE_SUMS = 4,       /* fixed-order sums of the partials               */
+  NMR_PHASE_BWD_OUT = 5,    /* backpropagation through the output layer       */
+  NMR_PHASE_BWD_HIDDEN = 6, /* partial-sum reduce + hidden-layer complex BP   */
+  NMR_PHASE_SOLVE = 7,      /* assemble, LU solve, update                     */
+  NMR_PHASE_COUNT = 8
+} nmr_phase;
+
+/* Replays one phase of a Newton iteration of `inst` `reps` times on the
+ * context stream between two HIP events (after one untimed replay) and
+ * writes the mean device time per replay in microseconds to *avg_us (host).
+ * The instance state is saved before and restored after, so the call does
+ * not change the trajectory.  Synchronizes. */
+int nmr_time_phase(nmr_inst* inst, int phase, int reps, float* avg_us);
+
 #ifdef __cplusplus
 }
 #endif

@@ -240,6 +240,10 @@ static int decoder_build(nmr_ctx* ctx, const nmr_mlp_desc* desc, int prec, nmr_d
   const int L = desc->n_layers;
   if (1 + desc->widths[0] > 64 || 4 + 4 * desc->widths[0] > 128)
     return fail(NMR_ERR_ARG, "decoder input size n_q must be <= 31");
+  if (prec == PREC_FP64 && 4 + 4 * desc->widths[0] > 64)
+    return fail(NMR_ERR_ARG, "FP64 decoders take n_q <= 15");
+  if (prec != PREC_FP64 && pad_to(desc->widths[L - 1], NMR_WPAD) > 256)
+    return fail(NMR_ERR_ARG, "the last hidden layer must be at most 256 wide");
   nmr_decoder* d = new nmr_decoder();
   d->ctx = ctx;
   d->d.L = L;
@@ -384,7 +388,7 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   s.Cf = pad_to(2 + 2 * s.n_q, 16);
   s.Wmax = 0;
   for (int l = 1; l < d.L; ++l) s.Wmax = std::max(s.Wmax, d.wp[l]);
-  s.cub_per_blk = 4;
+  s.cub_per_blk = 4;  // one tet per wave of a 4-wave block
   s.n_mblk = (s.N + 255) / 256;
   s.n_cblk = (s.n_cub + s.cub_per_blk - 1) / s.cub_per_blk;
   s.n_bblk = (s.N + 127) / 128;
@@ -399,6 +403,8 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
       return fail(NMR_ERR_ARG, "weight net must map R -> n_cub");
     s.wn_L = p->wnet->n_layers;
     for (int l = 0; l <= s.wn_L; ++l) s.wn_maxw = std::max(s.wn_maxw, p->wnet->widths[l]);
+    for (int l = 0; l < s.wn_L; ++l)
+      if (p->wnet->widths[l] > 1024) return fail(NMR_ERR_ARG, "weight-net hidden widths must be <= 1024");
   }
   size_t bytes = instance_bytes<T>(s, d);
   size_t wn_bytes = 0;
@@ -634,7 +640,7 @@ struct Group {
   nmr_decoder* dec;
   bool f64;
   void* tab;  // device array of Inst<T>
-  int nb, Cp, Cb, Cf, maxN, maxR, n_q, max_mblk, max_cblk, max_bblk, max_entries;
+  int nb, Cp, Cb, Cf, maxN, maxR, n_q, max_mblk, max_cblk, max_bblk, max_entries, max_cub;
   bool any_np;
 };
 
@@ -651,6 +657,7 @@ static Group group_of(const std::vector<nmr_inst*>& v, void* tab) {
     g.max_mblk = std::max(g.max_mblk, in->n_mblk);
     g.max_cblk = std::max(g.max_cblk, in->n_cblk);
     g.max_bblk = std::max(g.max_bblk, in->n_bblk);
+    g.max_cub = std::max(g.max_cub, in->n_cub);
     g.max_entries = std::max(g.max_entries, 2 * in->R * in->R + in->R * in->n_q + 2 * in->R + in->n_p);
     g.any_np = g.any_np || in->n_p > 0;
   }
@@ -689,10 +696,10 @@ static void enqueue_iteration(const Group& g, int iter, int mode, double* A_out,
 static void enqueue_step(const Group& g, int K, hipStream_t s) {
   for (int it = -1; it < K; ++it) {
     if (g.f64) {
-      if (it < 0) launch_step_begin<double>(static_cast<const Inst<double>*>(g.tab), g.nb, BEGIN_STEP, s);
+      if (it < 0) launch_step_begin<double>(static_cast<const Inst<double>*>(g.tab), g.nb, BEGIN_STEP, g.max_cub, s);
       else enqueue_iteration<double>(g, it, SOLVE_UPDATE | (it == K - 1 ? SOLVE_FINISH : 0), nullptr, nullptr, s);
     } else {
-      if (it < 0) launch_step_begin<float>(static_cast<const Inst<float>*>(g.tab), g.nb, BEGIN_STEP, s);
+      if (it < 0) launch_step_begin<float>(static_cast<const Inst<float>*>(g.tab), g.nb, BEGIN_STEP, g.max_cub, s);
       else enqueue_iteration<float>(g, it, SOLVE_UPDATE | (it == K - 1 ? SOLVE_FINISH : 0), nullptr, nullptr, s);
     }
   }
@@ -892,7 +899,7 @@ static int sys_impl(nmr_inst* in, const double* r, double* A, double* phi) {
   HIPCHK(hipMemcpyAsync(I.r, r, in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   std::vector<nmr_inst*> v{in};
   Group g = group_of(v, in->tab);
-  launch_step_begin<T>(static_cast<const Inst<T>*>(in->tab), 1, BEGIN_SYSTEM, c->stream);
+  launch_step_begin<T>(static_cast<const Inst<T>*>(in->tab), 1, BEGIN_SYSTEM, in->n_cub, c->stream);
   enqueue_iteration<T>(g, 0, SOLVE_WRITE_SYSTEM, A, phi, c->stream);
   HIPCHK(hipGetLastError());
   return NMR_OK;
@@ -914,7 +921,7 @@ static int get_state_impl(nmr_inst* in, double* r, double* rdot, void* u) {
   if (u) {
     // decode at rbar: r <- rbar, decoder input (qbar, 0, rdot_bar), u = U p + D(q)
     HIPCHK(hipMemcpyAsync(I.r, I.rbar, in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    launch_step_begin<T>(static_cast<const Inst<T>*>(in->tab), 1, BEGIN_SYSTEM, c->stream);
+    launch_step_begin<T>(static_cast<const Inst<T>*>(in->tab), 1, BEGIN_SYSTEM, in->n_cub, c->stream);
     std::vector<nmr_inst*> v{in};
     Group g = group_of(v, in->tab);
     enqueue_decoder_fwd<T>(g, c->stream, 1);
@@ -959,4 +966,69 @@ extern "C" int nmr_instance_status(nmr_inst* in) {
   int st;
   CHK(read_status(in, &st));
   return map_status(st);
+}
+
+// ---------------------------------------------------------------------------
+// measurement: replay one phase between events (state saved and restored)
+// ---------------------------------------------------------------------------
+template <typename T>
+static void enqueue_phase(const Group& g, int phase, hipStream_t s) {
+  const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
+  const DecoderDev& d = g.dec->d;
+  switch (phase) {
+    case NMR_PHASE_DEC_HIDDEN:
+      for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, s);
+      break;
+    case NMR_PHASE_DEC_OUT:
+      launch_fwd_out<T>(d, tab, g.nb, g.maxN, g.Cf, s);
+      if (g.any_np) launch_filter<T>(tab, g.nb, 1, s);
+      break;
+    case NMR_PHASE_CUBATURE: launch_cubature<T>(tab, g.nb, g.max_cblk, s); break;
+    case NMR_PHASE_MASS: launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s); break;
+    case NMR_PHASE_SUMS: launch_sums<T>(tab, g.nb, g.max_entries, s); break;
+    case NMR_PHASE_BWD_OUT: launch_bwd_out<T>(d, tab, g.nb, g.max_bblk, s); break;
+    case NMR_PHASE_BWD_HIDDEN:
+      launch_bwd_reduce<T>(d, tab, g.nb, s);
+      for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, s);
+      break;
+    case NMR_PHASE_SOLVE: launch_solve<T>(tab, g.nb, 0, SOLVE_UPDATE, nullptr, nullptr, s); break;
+    default: break;
+  }
+}
+
+template <typename T>
+static int time_phase_impl(nmr_inst* in, int phase, int reps, float* avg_us) {
+  nmr_ctx* c = in->ctx;
+  Inst<T>& I = host_inst<T>(in);
+  const int R = in->R, nq = in->n_q;
+  std::vector<double> save(3 * R + 3 * nq);
+  int st = 0;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(save.data(), I.r, R * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(save.data() + R, I.rbar, R * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(save.data() + 2 * R, I.rdot, R * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(save.data() + 3 * R, I.dec_in, 3 * nq * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&st, I.status, sizeof(int), hipMemcpyDeviceToHost));
+  std::vector<nmr_inst*> v{in};
+  Group g = group_of(v, in->tab);
+  enqueue_phase<T>(g, phase, c->stream);
+  HIPCHK(hipEventRecord(c->ev[0], c->stream));
+  for (int k = 0; k < reps; ++k) enqueue_phase<T>(g, phase, c->stream);
+  HIPCHK(hipEventRecord(c->ev[1], c->stream));
+  HIPCHK(hipEventSynchronize(c->ev[1]));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+  *avg_us = 1000.f * ms / reps;
+  HIPCHK(hipMemcpy(I.r, save.data(), R * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(I.rbar, save.data() + R, R * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(I.rdot, save.data() + 2 * R, R * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(I.dec_in, save.data() + 3 * R, 3 * nq * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(I.status, &st, sizeof(int), hipMemcpyHostToDevice));
+  return NMR_OK;
+}
+
+extern "C" int nmr_time_phase(nmr_inst* in, int phase, int reps, float* avg_us) {
+  if (!in || !avg_us || phase < 0 || phase >= NMR_PHASE_COUNT || reps < 1) return fail(NMR_ERR_ARG, "bad argument");
+  CHK(set_device(in->ctx));
+  return is_f64(in) ? time_phase_impl<double>(in, phase, reps, avg_us) : time_phase_impl<float>(in, phase, reps, avg_us);
 }

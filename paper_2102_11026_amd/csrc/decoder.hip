@@ -25,6 +25,15 @@
 // multiplies the adjoint by sigma'(x0 + h x1 i) = s1 + h s2 x1 i, so with the
 // adjoint zb0 + h zb1_j i:  xb0 = s1 zb0,  xb1_j = s1 zb1_j + s2 x1_j zb0.
 // At the input Re = m_q^T s and Im/h = column j of s . H.
+//
+// GEMM tiling for gfx950.  The hidden layers are small (<= 1024 x 1024, 16..128
+// channel columns), so a launch is latency-bound: each 16-row output tile is
+// owned by one block of NW wavefronts that split the K dimension, each wave
+// issuing its loads for up to four K-steps before its MFMAs, and the NW
+// partial tiles are added in LDS in wave order (deterministic).  The output
+// layer (N x K with N up to 1.5e5) is bandwidth-bound: every wave owns 16
+// rows, issues all of its weight loads first and reads the folded
+// activations from LDS.
 #include "nmr_internal.h"
 
 #include <type_traits>
@@ -33,6 +42,7 @@ namespace nmr {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 __device__ inline void act_jet(int act, T x, T& y, T& d1, T& d2, T& d3) {
@@ -63,111 +73,167 @@ __device__ inline void act_d12(int act, T x, T& d1, T& d2) {
   act_jet(act, x, y, d1, d2, d3);
 }
 
+template <typename T> struct vec4;
+template <> struct vec4<float> { typedef float4 type; };
+template <> struct vec4<double> { typedef double4 type; };
+
+template <typename TW> struct kstep { static constexpr int v = 16; };
+template <> struct kstep<__bf16> { static constexpr int v = 32; };
+template <> struct kstep<double> { static constexpr int v = 4; };
+
+// waves per split-K block: keep the partial tiles within 32 KB of LDS
+template <typename T, int NCB>
+struct splitk_waves { static constexpr int v = (NCB * (int)sizeof(T) <= 16) ? 8 : 4; };
+
 // ---------------------------------------------------------------------------
-// One wave computes a 16-row x (NCB*16)-column tile of D = A B with
-// A [rows][K] row-major (K contiguous) and B given as Bt [cols][K] (K
-// contiguous).  Result: acc[cb][i] = D[4*(lane/16) + i][cb*16 + lane%16].
-// K must be a multiple of 32.  B is read through `bload(col, k)` returning
-// 4 (or 8) consecutive K entries.
+// One wave: partial 16 x (NCB*16) tile over k in [kb, ke).  A is [16][lda]
+// (K contiguous), B is read as 4 consecutive K entries of column c through
+// bload(c, k).  acc[cb][i] = D[4*(lane/16) + i][cb*16 + lane%16].
 // ---------------------------------------------------------------------------
 template <int NCB, typename BL>
-__device__ inline void gemm_tile_f32(const float* __restrict__ A, int lda, int K, BL bload,
-                                     f32x4 (&acc)[NCB]) {
+__device__ inline void mfma_range(const float* __restrict__ A, int lda, int kb, int ke, BL bload,
+                                  f32x4 (&acc)[NCB]) {
+  constexpr int PF = NCB <= 4 ? 4 : 2;  // K-steps whose loads are issued together
   const int lane = threadIdx.x & 63;
   const int rA = lane & 15, g = lane >> 4;
   const float* ap = A + (size_t)rA * lda + 4 * g;
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    const float4 a = *reinterpret_cast<const float4*>(ap + k0);
+  for (int k0 = kb; k0 < ke; k0 += 16 * PF) {
+    float4 a[PF];
+    float4 b[PF][NCB];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      const float4 b = bload(cb * 16 + rA, k0 + 4 * g);
-      acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[cb], 0, 0, 0);
-      acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[cb], 0, 0, 0);
-      acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc[cb], 0, 0, 0);
-      acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc[cb], 0, 0, 0);
+    for (int t = 0; t < PF; ++t) {
+      const int k = k0 + 16 * t;
+      if (k < ke) {
+        a[t] = *reinterpret_cast<const float4*>(ap + k);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) b[t][cb] = bload(cb * 16 + rA, k + 4 * g);
+      } else {
+        a[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) b[t][cb] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
     }
+#pragma unroll
+    for (int t = 0; t < PF; ++t)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].x, b[t][cb].x, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].y, b[t][cb].y, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].z, b[t][cb].z, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].w, b[t][cb].w, acc[cb], 0, 0, 0);
+      }
   }
+}
+
+__device__ inline bf16x8 to_bf16x8(float4 lo, float4 hi) {
+  bf16x8 b;
+  b[0] = (__bf16)lo.x; b[1] = (__bf16)lo.y; b[2] = (__bf16)lo.z; b[3] = (__bf16)lo.w;
+  b[4] = (__bf16)hi.x; b[5] = (__bf16)hi.y; b[6] = (__bf16)hi.z; b[7] = (__bf16)hi.w;
+  return b;
 }
 
 template <int NCB, typename BL>
-__device__ inline void gemm_tile_bf16(const __bf16* __restrict__ A, int lda, int K, BL bload,
-                                      f32x4 (&acc)[NCB]) {
+__device__ inline void mfma_range(const __bf16* __restrict__ A, int lda, int kb, int ke, BL bload,
+                                  f32x4 (&acc)[NCB]) {
+  constexpr int PF = NCB <= 4 ? 4 : 2;
   const int lane = threadIdx.x & 63;
   const int rA = lane & 15, g = lane >> 4;
   const __bf16* ap = A + (size_t)rA * lda + 8 * g;
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    const bf16x8 a = *reinterpret_cast<const bf16x8*>(ap + k0);
+  for (int k0 = kb; k0 < ke; k0 += 32 * PF) {
+    bf16x8 a[PF];
+    bf16x8 b[PF][NCB];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      const float4 b0 = bload(cb * 16 + rA, k0 + 8 * g);
-      const float4 b1 = bload(cb * 16 + rA, k0 + 8 * g + 4);
-      bf16x8 b;
-      b[0] = (__bf16)b0.x; b[1] = (__bf16)b0.y; b[2] = (__bf16)b0.z; b[3] = (__bf16)b0.w;
-      b[4] = (__bf16)b1.x; b[5] = (__bf16)b1.y; b[6] = (__bf16)b1.z; b[7] = (__bf16)b1.w;
-      acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[cb], 0, 0, 0);
+    for (int t = 0; t < PF; ++t) {
+      const int k = k0 + 32 * t;
+      if (k < ke) {
+        a[t] = *reinterpret_cast<const bf16x8*>(ap + k);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          b[t][cb] = to_bf16x8(bload(cb * 16 + rA, k + 8 * g), bload(cb * 16 + rA, k + 8 * g + 4));
+      } else {
+        const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+        a[t] = to_bf16x8(z, z);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) b[t][cb] = to_bf16x8(z, z);
+      }
     }
+#pragma unroll
+    for (int t = 0; t < PF; ++t)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b[t][cb], acc[cb], 0, 0, 0);
   }
 }
 
-// Generic tile: MFMA for float / bf16 weights, plain FMA for double.  Writes
-// the 16 x (NCB*16) tile into S[col][row] (row stride 17).
-template <typename T, typename TW, int NCB, typename BL>
-__device__ inline void gemm_tile_to_lds(const TW* __restrict__ A, int lda, int K, BL bload,
-                                        T (*S)[17]) {
-  const int lane = threadIdx.x & 63;
+// Split-K tile: NW waves each take a slice of K; the partial tiles are added
+// in wave order into S[c][r] (c = column < NCB*16, r = row < 16).
+template <typename T, typename TW, int NCB, int NW, typename BL>
+__device__ inline void gemm_splitk(const TW* __restrict__ A, int lda, int K, BL bload, T (*S)[17],
+                                   T (*red)[NCB * 16][16]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int KS = kstep<TW>::v;
+  const int nks = K / KS;
+  const int per = (nks + NW - 1) / NW;
+  const int kb = min(K, wave * per * KS), ke = min(K, kb + per * KS);
   if constexpr (std::is_same<TW, double>::value) {
     for (int o = lane; o < NCB * 16 * 16; o += 64) {
       const int c = o >> 4, r = o & 15;
       double acc = 0.0;
       const double* ar = A + (size_t)r * lda;
-      for (int k = 0; k < K; k += 4) {
+      for (int k = kb; k < ke; k += 4) {
         const double4 b = bload(c, k);
         acc = fma(ar[k], b.x, acc);
         acc = fma(ar[k + 1], b.y, acc);
         acc = fma(ar[k + 2], b.z, acc);
         acc = fma(ar[k + 3], b.w, acc);
       }
-      S[c][r] = acc;
+      red[wave][c][r] = acc;
     }
   } else {
     f32x4 acc[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if constexpr (std::is_same<TW, float>::value)
-      gemm_tile_f32<NCB>(A, lda, K, bload, acc);
-    else
-      gemm_tile_bf16<NCB>(A, lda, K, bload, acc);
+    mfma_range<NCB>(A, lda, kb, ke, bload, acc);
     const int rA = lane & 15, g = lane >> 4;
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) S[cb * 16 + rA][4 * g + i] = acc[cb][i];
+      for (int i = 0; i < 4; ++i) red[wave][cb * 16 + rA][4 * g + i] = acc[cb][i];
   }
+  __syncthreads();
+  for (int p = threadIdx.x; p < NCB * 16 * 16; p += NW * 64) {
+    const int c = p >> 4, r = p & 15;
+    T v = red[0][c][r];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) v += red[w][c][r];
+    S[c][r] = v;
+  }
+  __syncthreads();
 }
 
-template <typename T> struct vec4;
-template <> struct vec4<float> { typedef float4 type; };
-template <> struct vec4<double> { typedef double4 type; };
-
 // ---------------------------------------------------------------------------
-// Forward hidden layer l with the jet activation.  One wave per 16 rows.
+// Forward hidden layer l with the jet activation.  One block per 16 rows.
 // ---------------------------------------------------------------------------
 template <typename T, typename TW, int NCB>
-__global__ __launch_bounds__(64) void k_fwd_hidden(DecoderDev d, int l, const Inst<T>* __restrict__ tab) {
+__global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const Inst<T>* __restrict__ tab) {
+  constexpr int NW = splitk_waves<T, NCB>::v;
   const Inst<T>& I = tab[blockIdx.y];
   const int m_inp = d.wp[l], m_out = d.w[l + 1], m_outp = d.wp[l + 1];
   const int row0 = blockIdx.x * 16;
   if (row0 >= m_outp) return;
   const int nq = I.n_q;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, nthr = NW * 64;
   const TW* W = reinterpret_cast<const TW*>(d.W[l]) + (size_t)row0 * m_inp;
   const T* bias = reinterpret_cast<const T*>(d.b[l]);
   __shared__ T S[NCB * 16][17];
+  __shared__ T red[NW][NCB * 16][16];
   __shared__ T sd1[16], sd2[16], sd3[16], sx2[16], sx4[16], sx23[16];
   typedef typename vec4<T>::type V4;
 
   const T* X = (l & 1) ? I.act0 : I.act1;
   const double* din = I.dec_in;
+  // the bias of this tile is loaded before the GEMM (no dependent round trip)
+  const T bias_v = (tid < 16 && row0 + tid < m_out) ? bias[row0 + tid] : T(0);
   auto bload = [&](int c, int k) -> V4 {
     if (l == 0) {
       // input jets: value q, tangents dq (i2) and qdot (i4), unit e_j (i1)
@@ -188,27 +254,26 @@ __global__ __launch_bounds__(64) void k_fwd_hidden(DecoderDev d, int l, const In
     }
     return *reinterpret_cast<const V4*>(X + (size_t)c * m_inp + k);
   };
-  gemm_tile_to_lds<T, TW, NCB>(W, m_inp, m_inp, bload, S);
-  __syncthreads();
+  gemm_splitk<T, TW, NCB, NW>(W, m_inp, m_inp, bload, S, red);
 
   T* pre = I.pre[l];
-  if (lane < 16) {
-    const int row = row0 + lane;
+  if (tid < 16) {
+    const int row = row0 + tid;
     const bool valid = row < m_out;
-    const T x0 = S[0][lane] + (valid ? bias[row] : T(0));
-    const T x2 = S[1][lane], x4 = S[2][lane], x23 = S[3][lane];
+    const T x0 = S[0][tid] + bias_v;
+    const T x2 = S[1][tid], x4 = S[2][tid], x23 = S[3][tid];
     T y, d1, d2, d3;
     act_jet(d.act, x0, y, d1, d2, d3);
-    sd1[lane] = d1; sd2[lane] = d2; sd3[lane] = d3;
-    sx2[lane] = x2; sx4[lane] = x4; sx23[lane] = x23;
+    sd1[tid] = d1; sd2[tid] = d2; sd3[tid] = d3;
+    sx2[tid] = x2; sx4[tid] = x4; sx23[tid] = x23;
     pre[row] = valid ? x0 : T(0);
-    S[0][lane] = valid ? y : T(0);
-    S[1][lane] = valid ? d1 * x2 : T(0);
-    S[2][lane] = valid ? d1 * x4 : T(0);
-    S[3][lane] = valid ? d1 * x23 + d2 * x2 * x2 : T(0);
+    S[0][tid] = valid ? y : T(0);
+    S[1][tid] = valid ? d1 * x2 : T(0);
+    S[2][tid] = valid ? d1 * x4 : T(0);
+    S[3][tid] = valid ? d1 * x23 + d2 * x2 * x2 : T(0);
   }
   __syncthreads();
-  for (int p = lane; p < 16 * nq; p += 64) {
+  for (int p = tid; p < 16 * nq; p += nthr) {
     const int r = p & 15, j = p >> 4;
     const bool valid = row0 + r < m_out;
     const T x1 = S[4 + j][r], x12 = S[4 + nq + j][r], x14 = S[4 + 2 * nq + j][r],
@@ -224,7 +289,7 @@ __global__ __launch_bounds__(64) void k_fwd_hidden(DecoderDev d, int l, const In
   if (l + 2 < d.L) {
     T* out = (l & 1) ? I.act1 : I.act0;
     const int C = 4 + 4 * nq;
-    for (int p = lane; p < C * 16; p += 64) {
+    for (int p = tid; p < C * 16; p += nthr) {
       const int c = p >> 4, r = p & 15;
       out[(size_t)c * m_outp + row0 + r] = S[c][r];
     }
@@ -233,7 +298,7 @@ __global__ __launch_bounds__(64) void k_fwd_hidden(DecoderDev d, int l, const In
     // linear, so eq. delta_j can be combined before it)
     const T dt = (T)I.dt;
     const int C = 2 + 2 * nq;
-    for (int p = lane; p < C * 16; p += 64) {
+    for (int p = tid; p < C * 16; p += nthr) {
       const int c = p >> 4, r = p & 15;
       T v;
       if (c == 0) v = S[0][r];
@@ -248,50 +313,98 @@ __global__ __launch_bounds__(64) void k_fwd_hidden(DecoderDev d, int l, const In
 }
 
 // ---------------------------------------------------------------------------
-// Output layer: rec[i][c] = keep_i (W_L fold + b_L e_0)[i][c].  4 waves per
-// block, each wave RT tiles of 16 rows; the folded activations are staged in
-// LDS once per block.
+// Output layer: rec[i][c] = keep_i (W_L fold + b_L e_0)[i][c].  8 waves per
+// block, one 16-row tile per wave; each wave loads its whole weight tile
+// before staging of the folded activations into LDS completes.
 // ---------------------------------------------------------------------------
-template <typename T, typename TW, int NCB, int RT>
-__global__ __launch_bounds__(256) void k_fwd_out(DecoderDev d, const Inst<T>* __restrict__ tab) {
-  const Inst<T>& I = tab[blockIdx.y];
+#define OUT_WAVES 8
+#define OUT_KMAX 256  // weight tile held in registers: K <= 256
+
+template <typename TW, int NCB>
+__global__ __launch_bounds__(512) void k_fwd_out(DecoderDev d, const Inst<float>* __restrict__ tab) {
+  const Inst<float>& I = tab[blockIdx.y];
   const int l = d.L - 1;
   const int K = d.wp[l];
-  const int rows_per_blk = 4 * 16 * RT;
-  const int blk_row0 = blockIdx.x * rows_per_blk;
+  const int blk_row0 = blockIdx.x * (OUT_WAVES * 16);
   if (blk_row0 >= I.N) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rA = lane & 15, g = lane >> 4;
+  const int row0 = blk_row0 + wave * 16;
+  const bool active = row0 < I.N;
+  const TW* W = reinterpret_cast<const TW*>(d.W[l]);
+  constexpr int KS = kstep<TW>::v;
+  constexpr int NKS = OUT_KMAX / KS;
+  // 1) weight tile into registers
+  typedef typename std::conditional<std::is_same<TW, float>::value, float4, bf16x8>::type AF;
+  AF a[NKS];
+  if (active) {
+    const TW* ap = W + (size_t)(row0 + rA) * K + (KS / 4) * g;
+#pragma unroll
+    for (int t = 0; t < NKS; ++t)
+      if (t * KS < K) a[t] = *reinterpret_cast<const AF*>(ap + t * KS);
+  }
+  // 2) folded activations into LDS
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* F = reinterpret_cast<T*>(smem_raw);  // [NCB*16][K + 4]
+  float* F = reinterpret_cast<float*>(smem_raw);  // [NCB*16][K + 4]
   const int ldf = K + 4;
-  for (int p = threadIdx.x; p < NCB * 16 * K; p += 256) {
-    const int c = p / K, k = p - c * K;
-    F[c * ldf + k] = I.fold[(size_t)c * K + k];
+  for (int p = threadIdx.x; p < NCB * 16 * (K / 4); p += OUT_WAVES * 64) {
+    const int c = p / (K / 4), k4 = p - c * (K / 4);
+    *reinterpret_cast<float4*>(F + c * ldf + 4 * k4) = *reinterpret_cast<const float4*>(I.fold + (size_t)c * K + 4 * k4);
   }
   __syncthreads();
-  typedef typename vec4<T>::type V4;
-  auto bload = [&](int c, int k) -> V4 { return *reinterpret_cast<const V4*>(F + c * ldf + k); };
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const TW* W = reinterpret_cast<const TW*>(d.W[l]);
-  const T* bias = reinterpret_cast<const T*>(d.b[l]);
-  __shared__ T S[4][NCB * 16][17];
-  const int Cf = I.Cf;
-  for (int t = 0; t < RT; ++t) {
-    const int row0 = blk_row0 + (t * 4 + wave) * 16;
-    if (row0 < I.N) {
-      gemm_tile_to_lds<T, TW, NCB>(W + (size_t)row0 * K, K, K, bload, S[wave]);
-    }
-    __syncthreads();
-    if (row0 < I.N) {
-      for (int p = lane; p < 16 * Cf; p += 64) {
-        const int r = p / Cf, c = p - r * Cf;
-        const int row = row0 + r;
-        if (row < I.N) {
-          T v = S[wave][c][r] + (c == 0 ? bias[row] : T(0));
-          I.rec[(size_t)row * Cf + c] = v * I.keep[row];
-        }
+  if (!active) return;
+  f32x4 acc[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < NKS; ++t) {
+    if (t * KS >= K) break;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const float* fp = F + (cb * 16 + rA) * ldf + t * KS + (KS / 4) * g;
+      if constexpr (std::is_same<TW, float>::value) {
+        const float4 b = *reinterpret_cast<const float4*>(fp);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].x, b.x, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].y, b.y, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].z, b.z, acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].w, b.w, acc[cb], 0, 0, 0);
+      } else {
+        const bf16x8 b = to_bf16x8(*reinterpret_cast<const float4*>(fp), *reinterpret_cast<const float4*>(fp + 4));
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b, acc[cb], 0, 0, 0);
       }
     }
-    __syncthreads();
+  }
+  const float* bias = reinterpret_cast<const float*>(d.b[l]);
+  const int Cf = I.Cf;
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = row0 + 4 * g + i, c = cb * 16 + rA;
+      if (row < I.N && c < Cf) {
+        const float v = acc[cb][i] + (c == 0 ? bias[row] : 0.f);
+        I.rec[(size_t)row * Cf + c] = v * I.keep[row];
+      }
+    }
+}
+
+// FP64 form of the output layer (plain FMA; correctness configurations)
+__global__ __launch_bounds__(256) void k_fwd_out_f64(DecoderDev d, const Inst<double>* __restrict__ tab) {
+  const Inst<double>& I = tab[blockIdx.y];
+  const int l = d.L - 1;
+  const int K = d.wp[l];
+  const int Cf = I.Cf;
+  const int row = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int c0 = threadIdx.x & 15;
+  if (row >= I.N) return;
+  const double* W = reinterpret_cast<const double*>(d.W[l]) + (size_t)row * K;
+  const double* bias = reinterpret_cast<const double*>(d.b[l]);
+  for (int c = c0; c < Cf; c += 16) {
+    double acc = 0.0;
+    const double* f = I.fold + (size_t)c * K;
+    for (int k = 0; k < K; ++k) acc = fma(W[k], f[k], acc);
+    if (c == 0) acc += bias[row];
+    I.rec[(size_t)row * Cf + c] = acc * I.keep[row];
   }
 }
 
@@ -325,13 +438,24 @@ __global__ __launch_bounds__(256) void k_filter(const Inst<T>* __restrict__ tab,
 }
 
 // ---------------------------------------------------------------------------
-// Backward through the output layer: partial sums of W_L^T s over row chunks.
-// s_i = seed_i - sum_k U_ik (U^T P a)_k (the filter's transpose).
+// Backward through the output layer: partial sums of W_L^T s over 128-row
+// chunks, s_i = seed_i - sum_k U_ik (U^T P a)_k (the filter's transpose).
+// 64 column groups of 4 x 4 row slices per block; slices added in order.
 // ---------------------------------------------------------------------------
 #define BWD_ROWS 128
-__device__ inline double wval(double w) { return w; }
-__device__ inline double wval(float w) { return (double)w; }
-__device__ inline double wval(__bf16 w) { return (double)(float)w; }
+__device__ inline void load4(const float* p, double (&w)[4]) {
+  const float4 v = *reinterpret_cast<const float4*>(p);
+  w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+}
+__device__ inline void load4(const double* p, double (&w)[4]) {
+  const double4 v = *reinterpret_cast<const double4*>(p);
+  w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+}
+__device__ inline void load4(const __bf16* p, double (&w)[4]) {
+  const bf16x4 v = *reinterpret_cast<const bf16x4*>(p);
+  w[0] = (float)v[0]; w[1] = (float)v[1]; w[2] = (float)v[2]; w[3] = (float)v[3];
+}
+
 template <typename T, typename TW>
 __global__ __launch_bounds__(256) void k_bwd_out(DecoderDev d, const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
@@ -341,6 +465,7 @@ __global__ __launch_bounds__(256) void k_bwd_out(DecoderDev d, const Inst<T>* __
   const int i0 = blockIdx.x * BWD_ROWS;
   const int i1 = min(i0 + BWD_ROWS, I.N);
   __shared__ double s[BWD_ROWS];
+  __shared__ double red[4][256];
   const int np = I.n_p;
   const double* uta = I.sum_mass + I.R * I.R + I.R * I.n_q + I.R;
   for (int i = i0 + threadIdx.x; i < i1; i += 256) {
@@ -350,10 +475,28 @@ __global__ __launch_bounds__(256) void k_bwd_out(DecoderDev d, const Inst<T>* __
   }
   __syncthreads();
   const TW* W = reinterpret_cast<const TW*>(d.W[l]);
-  for (int k = threadIdx.x; k < K; k += 256) {
-    double acc = 0.0;
-    for (int i = i0; i < i1; ++i) acc = fma(wval(W[(size_t)i * K + k]), s[i - i0], acc);
-    I.part_bwd[(size_t)blockIdx.x * K + k] = acc;
+  const int cg = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < K; c0 += 256) {
+    const int col = c0 + 4 * cg;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (col < K) {
+#pragma unroll 8
+      for (int i = i0 + sl; i < i1; i += 4) {
+        double w[4];
+        load4(W + (size_t)i * K + col, w);
+        const double si = s[i - i0];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = fma(w[t], si, acc[t]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) red[sl][4 * cg + t] = acc[t];
+    __syncthreads();
+    const int c = c0 + threadIdx.x;
+    if (c < K)
+      I.part_bwd[(size_t)blockIdx.x * K + c] =
+          ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    __syncthreads();
   }
 }
 
@@ -366,16 +509,20 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(DecoderDev d, const Inst<T>*
   const Inst<T>& I = tab[blockIdx.y];
   const int l = d.L - 1;  // output layer; its input is hidden layer l-1
   const int K = d.wp[l];
-  const int kk = threadIdx.x & 63, sl = threadIdx.x >> 6;
-  const int k = blockIdx.x * 64 + kk;
-  __shared__ double part[4][64];
+  const int kk = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int k = blockIdx.x * 16 + kk;
+  __shared__ double part[16][17];
   double acc = 0.0;
-  if (k < K)
-    for (int b = sl; b < I.n_bblk; b += 4) acc += I.part_bwd[(size_t)b * K + k];
+  if (k < K) {
+    const double* src = I.part_bwd + k;
+#pragma unroll 4
+    for (int b = sl; b < I.n_bblk; b += 16) acc += src[(size_t)b * K];
+  }
   part[sl][kk] = acc;
   __syncthreads();
   if (sl == 0 && k < K) {
-    const double zb0 = ((part[0][kk] + part[1][kk]) + part[2][kk]) + part[3][kk];
+    double zb0 = part[0][kk];
+    for (int q = 1; q < 16; ++q) zb0 += part[q][kk];
     const T* pre = I.pre[l - 1];
     const T x0 = pre[k];
     T d1, d2;
@@ -388,46 +535,61 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(DecoderDev d, const Inst<T>*
 }
 
 // ---------------------------------------------------------------------------
-// Backward through hidden layer l: zb_prev = W_l^T xb_l (a GEMM with the
+// Backward through hidden layer l: zb_prev = W_l^T xb_l (split-K GEMM with the
 // transposed weights stored row-major), then either sigma' of layer l-1 or,
 // at the input, J^T a and a . H.
 // ---------------------------------------------------------------------------
 template <typename T, typename TW, int NCB>
-__global__ __launch_bounds__(64) void k_bwd_hidden(DecoderDev d, const void* WT_, int l,
-                                                   const Inst<T>* __restrict__ tab) {
+__global__ __launch_bounds__(512) void k_bwd_hidden(DecoderDev d, const void* WT_, int l,
+                                                    const Inst<T>* __restrict__ tab) {
+  constexpr int NW = splitk_waves<T, NCB>::v;
   const Inst<T>& I = tab[blockIdx.y];
-  const int K = d.wp[l + 1];     // reduction over the outputs of layer l
+  const int K = d.wp[l + 1];  // reduction over the outputs of layer l
   const int m_in = d.w[l], m_inp = d.wp[l];
   const int row0 = blockIdx.x * 16;
   if (row0 >= m_inp) return;
   const int nq = I.n_q;
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, nthr = NW * 64;
   const int step = d.L - 2 - l;  // 0 for the last hidden layer
   const T* xb = (step & 1) ? I.zb1 : I.zb0;
   T* xb_out = (step & 1) ? I.zb0 : I.zb1;
   const TW* WT = reinterpret_cast<const TW*>(WT_) + (size_t)row0 * K;
   __shared__ T S[NCB * 16][17];
+  __shared__ T red[NW][NCB * 16][16];
   typedef typename vec4<T>::type V4;
-  auto bload = [&](int c, int k) -> V4 {
-    return *reinterpret_cast<const V4*>(xb + (size_t)c * K + k);
-  };
-  gemm_tile_to_lds<T, TW, NCB>(WT, K, K, bload, S);
-  __syncthreads();
-  if (l > 0) {
-    const T* pre = I.pre[l - 1];
-    for (int p = lane; p < 16 * (1 + nq); p += 64) {
+  auto bload = [&](int c, int k) -> V4 { return *reinterpret_cast<const V4*>(xb + (size_t)c * K + k); };
+  // pre-activations of layer l-1 used by the epilogue, loaded before the GEMM
+  constexpr int PP = (16 * 32 + 255) / 256;  // items per thread (16 rows x (1 + n_q <= 32) / >= 256 threads)
+  T px0[PP], px1[PP];
+  const T* pre = (l > 0) ? I.pre[l - 1] : nullptr;
+#pragma unroll
+  for (int t = 0; t < PP; ++t) {
+    const int p = tid + t * nthr;
+    px0[t] = px1[t] = T(0);
+    if (l > 0 && p < 16 * (1 + nq)) {
       const int r = p & 15, c = p >> 4;
-      const int row = row0 + r;
-      const T x0 = pre[row];
-      T d1, d2;
-      act_d12(d.act, x0, d1, d2);
-      T v;
-      if (c == 0) v = d1 * S[0][r];
-      else v = d1 * S[c][r] + d2 * pre[(size_t)c * m_inp + row] * S[0][r];
-      xb_out[(size_t)c * m_inp + row] = (row < m_in) ? v : T(0);
+      px0[t] = pre[row0 + r];
+      if (c > 0) px1[t] = pre[(size_t)c * m_inp + row0 + r];
+    }
+  }
+  gemm_splitk<T, TW, NCB, NW>(WT, K, K, bload, S, red);
+  if (l > 0) {
+#pragma unroll
+    for (int t = 0; t < PP; ++t) {
+      const int p = tid + t * nthr;
+      if (p < 16 * (1 + nq)) {
+        const int r = p & 15, c = p >> 4;
+        const int row = row0 + r;
+        T d1, d2;
+        act_d12(d.act, px0[t], d1, d2);
+        T v;
+        if (c == 0) v = d1 * S[0][r];
+        else v = d1 * S[c][r] + d2 * px1[t] * S[0][r];
+        xb_out[(size_t)c * m_inp + row] = (row < m_in) ? v : T(0);
+      }
     }
   } else {
-    for (int p = lane; p < 16 * (1 + nq); p += 64) {
+    for (int p = tid; p < 16 * (1 + nq); p += nthr) {
       const int r = p & 15, c = p >> 4;
       const int row = row0 + r;
       if (row < nq) {
@@ -457,20 +619,25 @@ __global__ void k_unpack(const Inst<T>* __restrict__ tab, T* u, T* J, T* dJ, T* 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+#define NCB_SWITCH(ncb, CALL) \
+  switch (ncb) {              \
+    case 1: CALL(1); break;   \
+    case 2: CALL(2); break;   \
+    case 3: CALL(3); break;   \
+    case 4: CALL(4); break;   \
+    case 5: CALL(5); break;   \
+    case 6: CALL(6); break;   \
+    case 7: CALL(7); break;   \
+    case 8: CALL(8); break;   \
+    default: break;           \
+  }
+
 template <typename T, typename TW>
 static void fwd_hidden_dispatch(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cp, hipStream_t s) {
   dim3 grid(d.wp[l + 1] / 16, nb);
-  switch (cp / 16) {
-    case 1: k_fwd_hidden<T, TW, 1><<<grid, 64, 0, s>>>(d, l, tab); break;
-    case 2: k_fwd_hidden<T, TW, 2><<<grid, 64, 0, s>>>(d, l, tab); break;
-    case 3: k_fwd_hidden<T, TW, 3><<<grid, 64, 0, s>>>(d, l, tab); break;
-    case 4: k_fwd_hidden<T, TW, 4><<<grid, 64, 0, s>>>(d, l, tab); break;
-    case 5: k_fwd_hidden<T, TW, 5><<<grid, 64, 0, s>>>(d, l, tab); break;
-    case 6: k_fwd_hidden<T, TW, 6><<<grid, 64, 0, s>>>(d, l, tab); break;
-    case 7: k_fwd_hidden<T, TW, 7><<<grid, 64, 0, s>>>(d, l, tab); break;
-    case 8: k_fwd_hidden<T, TW, 8><<<grid, 64, 0, s>>>(d, l, tab); break;
-    default: break;
-  }
+#define FWD_H(n) k_fwd_hidden<T, TW, n><<<grid, 64 * splitk_waves<T, n>::v, 0, s>>>(d, l, tab)
+  NCB_SWITCH(cp / 16, FWD_H)
+#undef FWD_H
 }
 
 template <>
@@ -480,33 +647,44 @@ void launch_fwd_hidden<float>(const DecoderDev& d, int l, const Inst<float>* tab
 }
 template <>
 void launch_fwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* tab, int nb, int cp, hipStream_t s) {
-  fwd_hidden_dispatch<double, double>(d, l, tab, nb, cp, s);
-}
-
-template <typename T, typename TW>
-static void fwd_out_dispatch(const DecoderDev& d, const Inst<T>* tab, int nb, int max_n, int cf, hipStream_t s) {
-  constexpr int RT = 2;
-  const int rows = 4 * 16 * RT;
-  dim3 grid((max_n + rows - 1) / rows, nb);
-  const int K = d.wp[d.L - 1];
-  const size_t lds = (size_t)cf * (K + 4) * sizeof(T);
-  switch (cf / 16) {
-    case 1: k_fwd_out<T, TW, 1, RT><<<grid, 256, lds, s>>>(d, tab); break;
-    case 2: k_fwd_out<T, TW, 2, RT><<<grid, 256, lds, s>>>(d, tab); break;
-    case 3: k_fwd_out<T, TW, 3, RT><<<grid, 256, lds, s>>>(d, tab); break;
-    case 4: k_fwd_out<T, TW, 4, RT><<<grid, 256, lds, s>>>(d, tab); break;
+  // FP64 decoders take n_q <= 15, i.e. at most 4 column blocks
+  dim3 grid(d.wp[l + 1] / 16, nb);
+#define FWD_H64(n) k_fwd_hidden<double, double, n><<<grid, 64 * splitk_waves<double, n>::v, 0, s>>>(d, l, tab)
+  switch (cp / 16) {
+    case 1: FWD_H64(1); break;
+    case 2: FWD_H64(2); break;
+    case 3: FWD_H64(3); break;
+    case 4: FWD_H64(4); break;
     default: break;
   }
+#undef FWD_H64
+}
+
+template <typename TW>
+static void fwd_out_dispatch(const DecoderDev& d, const Inst<float>* tab, int nb, int max_n, int cf, hipStream_t s) {
+  const int rows = OUT_WAVES * 16;
+  dim3 grid((max_n + rows - 1) / rows, nb);
+  const int K = d.wp[d.L - 1];
+  const size_t lds = (size_t)cf * (K + 4) * sizeof(float);
+#define FWD_O(n) k_fwd_out<TW, n><<<grid, OUT_WAVES * 64, lds, s>>>(d, tab)
+  switch (cf / 16) {
+    case 1: FWD_O(1); break;
+    case 2: FWD_O(2); break;
+    case 3: FWD_O(3); break;
+    case 4: FWD_O(4); break;
+    default: break;
+  }
+#undef FWD_O
 }
 
 template <>
 void launch_fwd_out<float>(const DecoderDev& d, const Inst<float>* tab, int nb, int max_n, int cf, hipStream_t s) {
-  if (d.prec == PREC_BF16) fwd_out_dispatch<float, __bf16>(d, tab, nb, max_n, cf, s);
-  else fwd_out_dispatch<float, float>(d, tab, nb, max_n, cf, s);
+  if (d.prec == PREC_BF16) fwd_out_dispatch<__bf16>(d, tab, nb, max_n, cf, s);
+  else fwd_out_dispatch<float>(d, tab, nb, max_n, cf, s);
 }
 template <>
 void launch_fwd_out<double>(const DecoderDev& d, const Inst<double>* tab, int nb, int max_n, int cf, hipStream_t s) {
-  fwd_out_dispatch<double, double>(d, tab, nb, max_n, cf, s);
+  k_fwd_out_f64<<<dim3((max_n + 15) / 16, nb), 256, 0, s>>>(d, tab);
 }
 
 template <typename T>
@@ -531,7 +709,7 @@ void launch_bwd_out<double>(const DecoderDev& d, const Inst<double>* tab, int nb
 template <typename T>
 void launch_bwd_reduce(const DecoderDev& d, const Inst<T>* tab, int nb, hipStream_t s) {
   const int K = d.wp[d.L - 1];
-  k_bwd_reduce<T><<<dim3((K + 63) / 64, nb), 256, 0, s>>>(d, tab);
+  k_bwd_reduce<T><<<dim3((K + 15) / 16, nb), 256, 0, s>>>(d, tab);
 }
 template void launch_bwd_reduce<float>(const DecoderDev&, const Inst<float>*, int, hipStream_t);
 template void launch_bwd_reduce<double>(const DecoderDev&, const Inst<double>*, int, hipStream_t);
@@ -540,13 +718,15 @@ template <typename T, typename TW>
 static void bwd_hidden_dispatch(const DecoderDev& d, const void* WT, int l, const Inst<T>* tab, int nb, int cb,
                                 hipStream_t s) {
   dim3 grid(d.wp[l] / 16, nb);
+#define BWD_H(n) k_bwd_hidden<T, TW, n><<<grid, 64 * splitk_waves<T, n>::v, 0, s>>>(d, WT, l, tab)
   switch (cb / 16) {
-    case 1: k_bwd_hidden<T, TW, 1><<<grid, 64, 0, s>>>(d, WT, l, tab); break;
-    case 2: k_bwd_hidden<T, TW, 2><<<grid, 64, 0, s>>>(d, WT, l, tab); break;
-    case 3: k_bwd_hidden<T, TW, 3><<<grid, 64, 0, s>>>(d, WT, l, tab); break;
-    case 4: k_bwd_hidden<T, TW, 4><<<grid, 64, 0, s>>>(d, WT, l, tab); break;
+    case 1: BWD_H(1); break;
+    case 2: BWD_H(2); break;
+    case 3: BWD_H(3); break;
+    case 4: BWD_H(4); break;
     default: break;
   }
+#undef BWD_H
 }
 
 template <>

@@ -135,7 +135,7 @@ void launch_rest_shape(const double* X, const int* tets, int m, const int* cub_i
                        const int* vt_ptr, const int* vt_ent, int n, double rho,
                        T* cub_Bm, T* cub_Ve, T* mass, double* Ve_tmp, hipStream_t s);
 template <typename T>
-void launch_step_begin(const Inst<T>* tab, int nb, int mode, hipStream_t s);
+void launch_step_begin(const Inst<T>* tab, int nb, int mode, int max_cub, hipStream_t s);
 template <typename T>
 void launch_cubature(const Inst<T>* tab, int nb, int max_cblk, hipStream_t s);
 template <typename T>

@@ -79,79 +79,101 @@ template void launch_rest_shape<float>(const double*, const int*, int, const int
 template void launch_rest_shape<double>(const double*, const int*, int, const int*, int, const int*, const int*, int,
                                         double, double*, double*, double*, double*, hipStream_t);
 
+
 // ---------------------------------------------------------------------------
 // step begin: cubature weights from the weight net at rbar (softplus after
 // every layer, scaled), the Newton start r = rbar and the decoder input.
 // mode BEGIN_SYSTEM keeps r and only refreshes weights and decoder input.
+// Every block recomputes the small hidden layers of the weight net and then
+// produces 256 of the |C| outputs.
 // ---------------------------------------------------------------------------
 __device__ inline double softplus(double x) { return x > 0.0 ? x + log1p(exp(-x)) : log1p(exp(x)); }
 
 template <typename T>
+__device__ inline double dot_unrolled(const T* __restrict__ w, const double* __restrict__ z, int n) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int k = 0;
+  for (; k + 4 <= n; k += 4) {
+    a0 += (double)w[k] * z[k];
+    a1 += (double)w[k + 1] * z[k + 1];
+    a2 += (double)w[k + 2] * z[k + 2];
+    a3 += (double)w[k + 3] * z[k + 3];
+  }
+  for (; k < n; ++k) a0 += (double)w[k] * z[k];
+  return (a0 + a1) + (a2 + a3);
+}
+
+#define WN_MAXW 1024
+template <typename T>
 __global__ __launch_bounds__(256) void k_step_begin(const Inst<T>* __restrict__ tab, int mode) {
   const Inst<T>& I = tab[blockIdx.y];
   const int R = I.R, np = I.n_p, nq = I.n_q;
-  if (mode == BEGIN_STEP)
-    for (int k = threadIdx.x; k < R; k += 256) I.r[k] = I.rbar[k];
-  if (I.wn_L > 0) {
-    T* buf0 = I.wn_buf;
-    T* buf1 = I.wn_buf + I.wn_maxw;
-    const int W0 = I.wn_w[0];
-    for (int k = threadIdx.x; k < W0; k += 256) buf0[k] = (T)I.rbar[k];
-    __syncthreads();
-    for (int l = 0; l < I.wn_L; ++l) {
-      const T* in = (l & 1) ? buf1 : buf0;
-      T* out = (l & 1) ? buf0 : buf1;
-      const int wi = I.wn_w[l], wo = I.wn_w[l + 1];
-      const bool last = (l == I.wn_L - 1);
-      for (int o = threadIdx.x; o < wo; o += 256) {
-        double acc = (double)I.wn_b[l][o];
-        const T* Wr = I.wn_W[l] + (size_t)o * wi;
-        for (int k = 0; k < wi; ++k) acc += (double)Wr[k] * (double)in[k];
-        const double z = softplus(acc);
-        if (last) I.cub_w[o] = (T)(I.wn_scale * z);
-        else out[o] = (T)z;
-      }
-      __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int k = threadIdx.x; k < nq; k += 256) {
+      const double q = (mode == BEGIN_STEP) ? I.rbar[np + k] : I.r[np + k];
+      I.dec_in[k] = q;
+      I.dec_in[nq + k] = q - I.rbar[np + k];
+      I.dec_in[2 * nq + k] = I.rdot[np + k];
     }
+    if (mode == BEGIN_STEP)
+      for (int k = threadIdx.x; k < R; k += 256) I.r[k] = I.rbar[k];
   }
+  if (I.wn_L == 0) return;
+  const int last = I.wn_L - 1;
+  const int o0 = blockIdx.x * 256;
+  if (o0 >= I.wn_w[I.wn_L]) return;
+  __shared__ double z[2][WN_MAXW];
+  for (int k = threadIdx.x; k < I.wn_w[0]; k += 256) z[0][k] = I.rbar[k];
   __syncthreads();
-  for (int k = threadIdx.x; k < nq; k += 256) {
-    const double q = I.r[np + k];
-    I.dec_in[k] = q;
-    I.dec_in[nq + k] = q - I.rbar[np + k];
-    I.dec_in[2 * nq + k] = I.rdot[np + k];
+  for (int l = 0; l < last; ++l) {
+    const double* in = z[l & 1];
+    double* out = z[(l + 1) & 1];
+    const int wi = I.wn_w[l], wo = I.wn_w[l + 1];
+    for (int o = threadIdx.x; o < wo; o += 256)
+      out[o] = softplus((double)I.wn_b[l][o] + dot_unrolled(I.wn_W[l] + (size_t)o * wi, in, wi));
+    __syncthreads();
   }
+  const double* in = z[last & 1];
+  const int wi = I.wn_w[last], wo = I.wn_w[last + 1];
+  const int o = o0 + threadIdx.x;
+  if (o < wo)
+    I.cub_w[o] = (T)(I.wn_scale * softplus((double)I.wn_b[last][o] + dot_unrolled(I.wn_W[last] + (size_t)o * wi, in, wi)));
 }
 
 template <typename T>
-void launch_step_begin(const Inst<T>* tab, int nb, int mode, hipStream_t s) {
-  k_step_begin<T><<<dim3(1, nb), 256, 0, s>>>(tab, mode);
+void launch_step_begin(const Inst<T>* tab, int nb, int mode, int max_cub, hipStream_t s) {
+  k_step_begin<T><<<dim3((max_cub + 255) / 256, nb), 256, 0, s>>>(tab, mode);
 }
-template void launch_step_begin<float>(const Inst<float>*, int, int, hipStream_t);
-template void launch_step_begin<double>(const Inst<double>*, int, int, hipStream_t);
+template void launch_step_begin<float>(const Inst<float>*, int, int, int, hipStream_t);
+template void launch_step_begin<double>(const Inst<double>*, int, int, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Cubature: one wave handles cub_per_blk tets.  Per tet e with deformation
-// gradient F = D_s B_m, first Piola stress P and its tangent dP:
+// Cubature: 4 waves per block, each wave takes every fourth tet of the
+// block's range.  Per tet e with deformation gradient F = D_s B_m, first Piola
+// stress P and its tangent dP:
 //   dF_r = dF/dr_r = sum_a Jt_{a,r} (x) g_a,   g_a = gradient of hat fn a,
 //   fr_r += w V P : dF_r,   Kr_rs += w V dP[dF_r] : dF_s,
-//   f_a   = w V P g_a (element force, scattered later by gather),
+//   f_a   = w V P g_a (element force, gathered per DOF later),
 // which equals Jt_e^T f_e and Jt_e^T K_e Jt_e without forming the 12 x 12
 // K_e.  Neo-Hookean: P = mu (F - F^-T) + lam ln J F^-T,
 //   dP[dF] = mu dF + (mu - lam ln J) F^-T dF^T F^-T + lam tr(F^-1 dF) F^-T.
-// Element math in T, accumulation in FP64.
+// Element math in T, accumulation in FP64; the four wave sums are added in
+// wave order.
 // ---------------------------------------------------------------------------
+#define CUB_WAVES 4
 template <typename T>
-__global__ __launch_bounds__(64) void k_cubature(const Inst<T>* __restrict__ tab) {
+__global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
   if ((int)blockIdx.x >= I.n_cblk) return;
-  const int R = I.R, lane = threadIdx.x;
+  const int R = I.R;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int na = I.cu_na;
   const T mu = (T)I.mu, lam = (T)I.lam;
-  __shared__ T xs[12];
-  __shared__ T J12[12][NMR_MAX_R + 1];
-  __shared__ T dFs[NMR_MAX_R][9];
-  __shared__ T dPs[NMR_MAX_R][9];
+  __shared__ T xs[CUB_WAVES][12];
+  __shared__ T J12[CUB_WAVES][12][NMR_MAX_R + 1];
+  __shared__ T dFs[CUB_WAVES][NMR_MAX_R][9];
+  __shared__ T dPs[CUB_WAVES][NMR_MAX_R][9];
+  __shared__ double red[NMR_MAX_R * NMR_MAX_R + NMR_MAX_R];
   constexpr int KT = (NMR_MAX_R * NMR_MAX_R + 63) / 64;
   double kacc[KT];
 #pragma unroll
@@ -159,19 +181,20 @@ __global__ __launch_bounds__(64) void k_cubature(const Inst<T>* __restrict__ tab
   double facc = 0.0;
   const int e0 = blockIdx.x * I.cub_per_blk;
   const int e1 = min(e0 + I.cub_per_blk, I.n_cub);
-  for (int e = e0; e < e1; ++e) {
+  for (int e = e0 + wave; e < e1; e += CUB_WAVES) {
     const int* tv = I.cub_v + 4 * e;
     if (lane < 12) {
       const int dof = 3 * tv[lane / 3] + lane % 3;
-      xs[lane] = I.X[dof] + I.cu_u[(size_t)dof * I.cu_u_ld];
+      xs[wave][lane] = I.X[dof] + I.cu_u[(size_t)dof * I.cu_u_ld];
     }
     for (int p = lane; p < 12 * R; p += 64) {
       const int ac = p / R, r = p - ac * R;
       const int dof = 3 * tv[ac / 3] + ac % 3;
-      J12[ac][r] = (r < na) ? I.cu_Ja[(size_t)dof * I.cu_Ja_ld + r] : I.cu_Jb[(size_t)dof * I.cu_Jb_ld + (r - na)];
+      J12[wave][ac][r] =
+          (r < na) ? I.cu_Ja[(size_t)dof * I.cu_Ja_ld + r] : I.cu_Jb[(size_t)dof * I.cu_Jb_ld + (r - na)];
     }
-    __syncthreads();
-    // every lane: F, its inverse, P (uniform work, no divergence)
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
     const T* Bm = I.cub_Bm + 9 * e;
     T G[4][3];
     for (int j = 0; j < 3; ++j) {
@@ -184,7 +207,7 @@ __global__ __launch_bounds__(64) void k_cubature(const Inst<T>* __restrict__ tab
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
         T acc = T(0);
-        for (int a = 1; a < 4; ++a) acc += (xs[3 * a + i] - xs[i]) * G[a][j];
+        for (int a = 1; a < 4; ++a) acc += (xs[wave][3 * a + i] - xs[wave][i]) * G[a][j];
         F[i][j] = acc;
       }
     const T det = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
@@ -213,23 +236,21 @@ __global__ __launch_bounds__(64) void k_cubature(const Inst<T>* __restrict__ tab
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
           T acc = T(0);
-          for (int a = 0; a < 4; ++a) acc += J12[3 * a + i][r] * G[a][j];
+          for (int a = 0; a < 4; ++a) acc += J12[wave][3 * a + i][r] * G[a][j];
           dF[i][j] = acc;
         }
-      // tr(F^-1 dF) = A : dF
       T tr = T(0);
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) tr += A[i][j] * dF[i][j];
-      // M = dF^T A, then A M = A dF^T A
-      T M[3][3];
+      T M[3][3];  // dF^T A
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) M[i][j] = dF[0][i] * A[0][j] + dF[1][i] * A[1][j] + dF[2][i] * A[2][j];
       T fr = T(0);
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
           const T ADA = A[i][0] * M[0][j] + A[i][1] * M[1][j] + A[i][2] * M[2][j];
-          dPs[r][3 * i + j] = mu * dF[i][j] + c2 * ADA + lam * tr * A[i][j];
-          dFs[r][3 * i + j] = dF[i][j];
+          dPs[wave][r][3 * i + j] = mu * dF[i][j] + c2 * ADA + lam * tr * A[i][j];
+          dFs[wave][r][3 * i + j] = dF[i][j];
           fr += P[i][j] * dF[i][j];
         }
       facc += (double)wV * (double)fr;
@@ -240,32 +261,41 @@ __global__ __launch_bounds__(64) void k_cubature(const Inst<T>* __restrict__ tab
       for (int j = 0; j < 3; ++j) f += P[i][j] * G[a][j];
       I.fe[(size_t)e * 12 + lane] = wV * f;
     }
-    __syncthreads();
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
       const int p = lane + 64 * t;
       if (p < R * R) {
         const int r = p / R, s = p - r * R;
         T acc = T(0);
-        for (int k = 0; k < 9; ++k) acc += dPs[r][k] * dFs[s][k];
+        for (int k = 0; k < 9; ++k) acc += dPs[wave][r][k] * dFs[wave][s][k];
         kacc[t] += (double)wV * (double)acc;
       }
     }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+  }
+  // wave sums added in wave order
+  const int E = R * R + R;
+  for (int w = 0; w < CUB_WAVES; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int t = 0; t < KT; ++t) {
+        const int p = lane + 64 * t;
+        if (p < R * R) red[p] = (w == 0 ? 0.0 : red[p]) + kacc[t];
+      }
+      if (lane < R) red[R * R + lane] = (w == 0 ? 0.0 : red[R * R + lane]) + facc;
+    }
     __syncthreads();
   }
-  const int E = R * R + R;
   double* out = I.part_cub + (size_t)blockIdx.x * E;
-#pragma unroll
-  for (int t = 0; t < KT; ++t) {
-    const int p = lane + 64 * t;
-    if (p < R * R) out[p] = kacc[t];
-  }
-  if (lane < R) out[R * R + lane] = facc;
+  for (int p = threadIdx.x; p < E; p += 256) out[p] = red[p];
 }
 
 template <typename T>
 void launch_cubature(const Inst<T>* tab, int nb, int max_cblk, hipStream_t s) {
-  k_cubature<T><<<dim3(max_cblk, nb), 64, 0, s>>>(tab);
+  k_cubature<T><<<dim3(max_cblk, nb), 64 * CUB_WAVES, 0, s>>>(tab);
 }
 template void launch_cubature<float>(const Inst<float>*, int, int, hipStream_t);
 template void launch_cubature<double>(const Inst<double>*, int, int, hipStream_t);
@@ -295,6 +325,7 @@ void launch_fint(const Inst<T>* tab, T* f_int, int N, hipStream_t s) {
 template void launch_fint<float>(const Inst<float>*, float*, int, hipStream_t);
 template void launch_fint<double>(const Inst<double>*, double*, int, hipStream_t);
 
+
 // ---------------------------------------------------------------------------
 // Mass terms over 256-DOF chunks.  With Jt_i = [U_i, J_i], w_r = r - rbar -
 // dt rdot_bar, v_i = m_i (Jt_i . w_r + Hdd_i) - dt^2 m_i g_c:
@@ -303,87 +334,134 @@ template void launch_fint<double>(const Inst<double>*, double*, int, hipStream_t
 //   E_kj    += m_i Jt_ik dJ_ij             (Jt^T M [0, dJ])
 //   phim_k  += Jt_ik v_i                   (phi without dt^2 Jt^T f_int)
 //   uta_k   += U_ik (P a)_i                (filter transpose of the seed)
-// and the backpropagation seed P a.  FP64 accumulation, one partial per
-// block.
+// i.e. one product Jt^T Y with Y_i = [m_i Jt_i, m_i dJ_i, v_i, (P a)_i],
+// computed on the FP64 matrix cores (v_mfma_f64_16x16x4: A = Jt^T over four
+// DOFs, B = four rows of Y), one partial per block, the four wave partials
+// added in wave order.
 // ---------------------------------------------------------------------------
 #define MASS_ROWS 256
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_mass(const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
   if ((int)blockIdx.x >= I.n_mblk) return;
-  const int R = I.R, np = I.n_p, nq = I.n_q, Cf = I.Cf;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* sm = reinterpret_cast<double*>(smem_raw);      // [MASS_ROWS]
-  double* sv = sm + MASS_ROWS;                            // [MASS_ROWS]
-  double* ss = sv + MASS_ROWS;                            // [MASS_ROWS]
+  const int R = I.R, np = I.n_p, nq = I.n_q, Cf = I.Cf, N = I.N;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   __shared__ double wr[NMR_MAX_R];
-  T* sJ = reinterpret_cast<T*>(ss + MASS_ROWS);           // [MASS_ROWS][R]
-  T* sdJ = sJ + MASS_ROWS * R;                            // [MASS_ROWS][nq]
+  __shared__ double sm[MASS_ROWS], sv[MASS_ROWS], ss[MASS_ROWS];
+  __shared__ double tile[2 * 16][5 * 16];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sJ = reinterpret_cast<T*>(smem_raw);  // [MASS_ROWS][R]
+  T* sdJ = sJ + MASS_ROWS * R;               // [MASS_ROWS][nq]
   const double dt = I.dt;
   if (threadIdx.x < R) wr[threadIdx.x] = I.r[threadIdx.x] - I.rbar[threadIdx.x] - dt * I.rdot[threadIdx.x];
   __syncthreads();
-  const int t = threadIdx.x;
-  const int i = blockIdx.x * MASS_ROWS + t;
-  if (i < I.N) {
-    const T* rr = I.rec + (size_t)i * Cf;
-    const double m = (double)I.mass[i];
-    double jw = 0.0;
-    for (int k = 0; k < np; ++k) {
-      const T u = I.U[(size_t)i * np + k];
-      sJ[t * R + k] = u;
-      jw += (double)u * wr[k];
+  const int i0 = blockIdx.x * MASS_ROWS;
+  {
+    // one DOF per thread: stage Jt_i and dJ_i, form v_i, a_i and the seed
+    const int t = threadIdx.x;
+    const int i = i0 + t;
+    double m = 0.0, v = 0.0, s = 0.0;
+    if (i < N) {
+      const T* rr = I.rec + (size_t)i * Cf;
+      m = (double)I.mass[i];
+      const double fi = fint_at(I, i);
+      double jw = 0.0;
+      for (int k = 0; k < np; ++k) {
+        const T u = I.U[(size_t)i * np + k];
+        sJ[t * R + k] = u;
+        jw += (double)u * wr[k];
+      }
+      for (int j = 0; j < nq; ++j) {
+        const T Jv = rr[1 + j];
+        sJ[t * R + np + j] = Jv;
+        sdJ[t * nq + j] = rr[1 + nq + j];
+        jw += (double)Jv * wr[np + j];
+      }
+      v = m * (jw + (double)rr[1 + 2 * nq]) - dt * dt * m * I.g[i % 3];
+      const double a = v + dt * dt * fi;
+      s = (double)I.keep[i] * a;
+      I.seed[i] = (T)s;
+    } else {
+      for (int k = 0; k < R; ++k) sJ[t * R + k] = T(0);
+      for (int j = 0; j < nq; ++j) sdJ[t * nq + j] = T(0);
     }
-    for (int j = 0; j < nq; ++j) {
-      const T Jv = rr[1 + j];
-      sJ[t * R + np + j] = Jv;
-      sdJ[t * nq + j] = rr[1 + nq + j];
-      jw += (double)Jv * wr[np + j];
-    }
-    const double v = m * (jw + (double)rr[1 + 2 * nq]) - dt * dt * m * I.g[i % 3];
-    const double a = v + dt * dt * fint_at(I, i);
-    const double s = (double)I.keep[i] * a;
-    I.seed[i] = (T)s;
     sm[t] = m;
     sv[t] = v;
     ss[t] = s;
-  } else {
-    for (int k = 0; k < R; ++k) sJ[t * R + k] = T(0);
-    for (int j = 0; j < nq; ++j) sdJ[t * nq + j] = T(0);
-    sm[t] = 0.0;
-    sv[t] = 0.0;
-    ss[t] = 0.0;
   }
   __syncthreads();
+  // Jt^T Y on the FP64 matrix cores: each wave takes 64 DOFs, 4 per MFMA
+  const int nrb = (R + 15) / 16;
+  const int ny = R + nq + 2;
+  const int ncb = (ny + 15) / 16;
+  const int col = lane & 15, kk = lane >> 4;
+  f64x4 acc[2][5];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 5; ++cb) acc[rb][cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  auto jt = [&](int lrow, int c) -> double { return c < R ? (double)sJ[lrow * R + c] : 0.0; };
+  for (int step = 0; step < 16; ++step) {
+    const int lrow = wave * 64 + step * 4 + kk;
+    double a[2], b[5];
+    const double m = sm[lrow];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) a[rb] = (rb < nrb) ? jt(lrow, rb * 16 + col) : 0.0;
+#pragma unroll
+    for (int cb = 0; cb < 5; ++cb) {
+      const int n = cb * 16 + col;
+      double y = 0.0;
+      if (cb < ncb) {
+        if (n < R) y = m * jt(lrow, n);
+        else if (n < R + nq) y = m * (double)sdJ[lrow * nq + (n - R)];
+        else if (n == R + nq) y = sv[lrow];
+        else if (n == R + nq + 1) y = ss[lrow];
+      }
+      b[cb] = y;
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 5; ++cb)
+        if (rb < nrb && cb < ncb) acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], b[cb], acc[rb][cb], 0, 0, 0);
+  }
+  // wave partial tiles added in wave order; the f64 16x16x4 result layout is
+  // row-interleaved: item q of lane l is D[4*q + l/16][l%16]
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 5; ++cb)
+          if (rb < nrb && cb < ncb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int rr = rb * 16 + 4 * q + kk, cc = cb * 16 + col;
+              tile[rr][cc] = (w == 0 ? 0.0 : tile[rr][cc]) + acc[rb][cb][q];
+            }
+    }
+    __syncthreads();
+  }
   const int E = R * R + R * nq + R + np;
   double* out = I.part_mass + (size_t)blockIdx.x * E;
   for (int e = threadIdx.x; e < E; e += 256) {
-    double acc = 0.0;
-    if (e < R * R) {
-      const int k = e / R, l = e - k * R;
-      for (int q = 0; q < MASS_ROWS; ++q) acc += sm[q] * (double)sJ[q * R + k] * (double)sJ[q * R + l];
-    } else if (e < R * R + R * nq) {
+    double v;
+    if (e < R * R) v = tile[e / R][e % R];
+    else if (e < R * R + R * nq) {
       const int e2 = e - R * R;
-      const int k = e2 / nq, j = e2 - k * nq;
-      for (int q = 0; q < MASS_ROWS; ++q) acc += sm[q] * (double)sJ[q * R + k] * (double)sdJ[q * nq + j];
-    } else if (e < R * R + R * nq + R) {
-      const int k = e - R * R - R * nq;
-      for (int q = 0; q < MASS_ROWS; ++q) acc += (double)sJ[q * R + k] * sv[q];
-    } else {
-      const int k = e - R * R - R * nq - R;
-      for (int q = 0; q < MASS_ROWS; ++q) acc += (double)sJ[q * R + k] * ss[q];
-    }
-    out[e] = acc;
+      v = tile[e2 / nq][R + e2 % nq];
+    } else if (e < R * R + R * nq + R) v = tile[e - R * R - R * nq][R + nq];
+    else v = tile[e - R * R - R * nq - R][R + nq + 1];
+    out[e] = v;
   }
-}
-
-template <typename T>
-static size_t mass_lds(int R, int nq) {
-  return 3 * MASS_ROWS * sizeof(double) + (size_t)MASS_ROWS * (R + nq) * sizeof(T);
 }
 
 template <typename T>
 void launch_mass(const Inst<T>* tab, int nb, int max_mblk, int R, int nq, hipStream_t s) {
-  k_mass<T><<<dim3(max_mblk, nb), 256, mass_lds<T>(R, nq), s>>>(tab);
+  const size_t lds = (size_t)MASS_ROWS * (R + nq) * sizeof(T);
+  k_mass<T><<<dim3(max_mblk, nb), 256, lds, s>>>(tab);
 }
 template void launch_mass<float>(const Inst<float>*, int, int, int, int, hipStream_t);
 template void launch_mass<double>(const Inst<double>*, int, int, int, int, hipStream_t);
@@ -427,10 +505,11 @@ void launch_seed_from_a(const Inst<T>* tab, const T* a, int nb, int max_mblk, hi
 template void launch_seed_from_a<float>(const Inst<float>*, const float*, int, int, hipStream_t);
 template void launch_seed_from_a<double>(const Inst<double>*, const double*, int, int, hipStream_t);
 
+
 // ---------------------------------------------------------------------------
-// Fixed-order sums of the cubature and mass partials.  Each block takes 64
-// entries; four slices of 64 threads add every fourth block, then the four
-// slice sums are added in order.
+// Fixed-order sums of the cubature and mass partials.  Each block takes 16
+// entries; 16 slices of 16 threads add every sixteenth partial, then the 16
+// slice sums are added in slice order.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_sums(const Inst<T>* __restrict__ tab) {
@@ -438,20 +517,24 @@ __global__ __launch_bounds__(256) void k_sums(const Inst<T>* __restrict__ tab) {
   const int R = I.R;
   const int Ec = R * R + R;
   const int Em = R * R + R * I.n_q + R + I.n_p;
-  const int kk = threadIdx.x & 63, sl = threadIdx.x >> 6;
-  const int e = blockIdx.x * 64 + kk;
-  __shared__ double part[4][64];
+  const int kk = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int e = blockIdx.x * 16 + kk;
+  __shared__ double part[16][17];
   double acc = 0.0;
   if (e < Ec) {
-    for (int b = sl; b < I.n_cblk; b += 4) acc += I.part_cub[(size_t)b * Ec + e];
+    const double* src = I.part_cub + e;
+#pragma unroll 4
+    for (int b = sl; b < I.n_cblk; b += 16) acc += src[(size_t)b * Ec];
   } else if (e < Ec + Em) {
-    const int e2 = e - Ec;
-    for (int b = sl; b < I.n_mblk; b += 4) acc += I.part_mass[(size_t)b * Em + e2];
+    const double* src = I.part_mass + (e - Ec);
+#pragma unroll 4
+    for (int b = sl; b < I.n_mblk; b += 16) acc += src[(size_t)b * Em];
   }
   part[sl][kk] = acc;
   __syncthreads();
   if (sl == 0) {
-    const double v = ((part[0][kk] + part[1][kk]) + part[2][kk]) + part[3][kk];
+    double v = part[0][kk];
+    for (int q = 1; q < 16; ++q) v += part[q][kk];
     if (e < Ec) I.sum_cub[e] = v;
     else if (e < Ec + Em) I.sum_mass[e - Ec] = v;
   }
@@ -459,7 +542,7 @@ __global__ __launch_bounds__(256) void k_sums(const Inst<T>* __restrict__ tab) {
 
 template <typename T>
 void launch_sums(const Inst<T>* tab, int nb, int max_entries, hipStream_t s) {
-  k_sums<T><<<dim3((max_entries + 63) / 64, nb), 256, 0, s>>>(tab);
+  k_sums<T><<<dim3((max_entries + 15) / 16, nb), 256, 0, s>>>(tab);
 }
 template void launch_sums<float>(const Inst<float>*, int, int, hipStream_t);
 template void launch_sums<double>(const Inst<double>*, int, int, hipStream_t);
@@ -467,10 +550,28 @@ template void launch_sums<double>(const Inst<double>*, int, int, hipStream_t);
 // ---------------------------------------------------------------------------
 // Assemble A = Jt^T M [U, J + dJ] + dt^2 Kr + diag(0, a . H) and
 // phi = phim + dt^2 fr (eq. system_mat with the sign differentiation gives),
-// record ||phi||, LU with partial pivoting (one lane per row) and r += delta
-// with A delta = -phi.  On the last iteration of a step: rdot = (r-rbar)/dt,
-// rbar = r.  A failed instance keeps its last good (rbar, rdot).
+// record ||phi||, solve A delta = -phi by LU with partial pivoting and update
+// r += delta.  One wavefront; lane i keeps row i in registers.  Rows are not
+// moved: the pivot of column k is the largest |a_ik| among the rows not yet
+// used as pivots (ties to the lower index), which is partial pivoting with the
+// row exchanges kept as a permutation.  On the last iteration of a step:
+// rdot = (r - rbar)/dt, rbar = r.  A failed instance keeps its last good
+// (rbar, rdot).
 // ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ inline double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  return v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(64) void k_solve(const Inst<T>* __restrict__ tab, int iter, int mode, double* A_out,
                                               double* phi_out) {
@@ -479,113 +580,152 @@ __global__ __launch_bounds__(64) void k_solve(const Inst<T>* __restrict__ tab, i
   const double dt = I.dt;
   __shared__ double A[NMR_MAX_R][NMR_MAX_R + 1];
   __shared__ double b[NMR_MAX_R];
-  __shared__ double x[NMR_MAX_R];
-  __shared__ int flag;
-  __shared__ int st;
+  __shared__ double xs[NMR_MAX_R];
+  __shared__ int piv[NMR_MAX_R];
   const double* G = I.sum_mass;
   const double* E = G + R * R;
   const double* phim = E + R * nq;
   const double* Kr = I.sum_cub;
   const double* fr = Kr + R * R;
-  for (int p = lane; p < R * R; p += 64) {
-    const int k = p / R, l = p - k * R;
-    double v = G[p] + dt * dt * Kr[p];
-    if (l >= np) v += E[k * nq + (l - np)];
-    if (k >= np && l >= np) v += I.Bq[(k - np) * nq + (l - np)];
-    A[k][l] = v;
+  const bool row = lane < R;
+  // every global load of the kernel is issued here, in one round trip
+  const int st0 = *I.status;
+  double r_l = 0.0, rbar_l = 0.0, rdot_l = 0.0, phi_l = 0.0;
+  if (row) {
+    r_l = I.r[lane];
+    rbar_l = I.rbar[lane];
+    rdot_l = I.rdot[lane];
+    phi_l = phim[lane] + dt * dt * fr[lane];
   }
-  if (lane < R) b[lane] = phim[lane] + dt * dt * fr[lane];
-  if (lane == 0) {
-    flag = 0;
-    st = __atomic_load_n(I.status, __ATOMIC_RELAXED);
-  }
-  __syncthreads();
-  if (lane == 0) {
-    double nrm = 0.0, amax = 0.0;
-    bool finite = true;
-    for (int k = 0; k < R; ++k) {
-      nrm += b[k] * b[k];
-      finite = finite && isfinite(b[k]);
-      for (int l = 0; l < R; ++l) {
-        finite = finite && isfinite(A[k][l]);
-        amax = fmax(amax, fabs(A[k][l]));
-      }
+  constexpr int NE = (NMR_MAX_R * NMR_MAX_R + 63) / 64;
+  double ent[NE];
+#pragma unroll
+  for (int t = 0; t < NE; ++t) {
+    const int p = lane + 64 * t;
+    double v = 0.0;
+    if (p < R * R) {
+      const int k = p / R, j = p - k * R;
+      v = G[p] + dt * dt * Kr[p];
+      if (j >= np) v += E[k * nq + (j - np)];
+      if (k >= np && j >= np) v += I.Bq[(k - np) * nq + (j - np)];
     }
-    I.resid[iter] = sqrt(nrm);
-    if (!finite && st == 0) {
-      atomicOr(I.status, ST_NONFINITE);
-      st |= ST_NONFINITE;
-    }
-    x[0] = amax;
+    ent[t] = v;
   }
+#pragma unroll
+  for (int t = 0; t < NE; ++t) {
+    const int p = lane + 64 * t;
+    if (p < R * R) A[p / R][p % R] = ent[t];
+  }
+  if (row) b[lane] = phi_l;
   __syncthreads();
-  const double amax = x[0];
+  double bb = row ? b[lane] : 0.0;
+  bool finite = isfinite(bb);
+  double amax = 0.0;
+  if (row)
+    for (int j = 0; j < R; ++j) {
+      finite = finite && isfinite(A[lane][j]);
+      amax = fmax(amax, fabs(A[lane][j]));
+    }
+  const double nrm2 = wave_sum(bb * bb);
+  amax = wave_max(amax);
+  const bool all_finite = __all(finite);
+  int st = st0;
+  if (!all_finite && st == 0) st = ST_NONFINITE;
+  if (lane == 0) {
+    I.resid[iter] = sqrt(nrm2);
+    if (st != st0) atomicOr(I.status, st);
+  }
   if (mode & SOLVE_WRITE_SYSTEM) {
     for (int p = lane; p < R * R; p += 64) A_out[p] = A[p / R][p % R];
-    if (lane < R) phi_out[lane] = b[lane];
+    if (row) phi_out[lane] = bb;
   }
-  if (!(mode & SOLVE_UPDATE)) return;
-  if (st != 0) return;  // frozen: keep the last good state
-  // LU with partial pivoting on [A | -phi]
-  if (lane < R) b[lane] = -b[lane];
-  __syncthreads();
+  if (!(mode & SOLVE_UPDATE) || st != 0) return;
+  // LU with partial pivoting in registers: lane i holds row i; the pivot row
+  // is broadcast with readlane, the pivot search is one LDS exchange.
+  double a[NMR_MAX_R];
+#pragma unroll
+  for (int j = 0; j < NMR_MAX_R; ++j) a[j] = (row && j < R) ? A[lane][j] : 0.0;
+  double bl = -bb;
+  bool used = !row;
+  bool singular = false;
+  __shared__ double colk[64];
   for (int k = 0; k < R; ++k) {
-    double v = (lane >= k && lane < R) ? fabs(A[lane][k]) : -1.0;
-    int idx = lane;
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(v, off);
-      const int oi = __shfl_xor(idx, off);
-      if (ov > v || (ov == v && oi < idx)) {
-        v = ov;
-        idx = oi;
-      }
-    }
-    const int p = idx;
-    if (!(v > 1e-300 * amax)) {
-      if (lane == 0) flag = 1;
-    }
-    if (p != k) {
-      if (lane < R) {
-        const double t0 = A[k][lane];
-        A[k][lane] = A[p][lane];
-        A[p][lane] = t0;
-      }
-      if (lane == 0) {
-        const double t1 = b[k];
-        b[k] = b[p];
-        b[p] = t1;
-      }
-    }
+    double ak = 0.0;
+#pragma unroll
+    for (int j = 0; j < NMR_MAX_R; ++j) ak = (j == k) ? a[j] : ak;
+    colk[lane] = used ? -1.0 : fabs(ak);
     __syncthreads();
-    if (lane > k && lane < R) {
-      const double f = A[lane][k] / A[k][k];
-      for (int j = k + 1; j < R; ++j) A[lane][j] -= f * A[k][j];
-      b[lane] -= f * b[k];
+    double best = -1.0;
+    int p = 0;
+    for (int i = 0; i < R; ++i) {
+      const double v = colk[i];
+      if (v > best) {
+        best = v;
+        p = i;
+      }
     }
+    p = __builtin_amdgcn_readfirstlane(p);
+    if (!(best > 1e-300 * amax)) singular = true;
+    if (lane == 0) piv[k] = p;
+    if (lane == p) used = true;
+    const double pk = readlane_f64(ak, p);
+    const double f = used ? 0.0 : ak / pk;
+#pragma unroll
+    for (int j = 0; j < NMR_MAX_R; ++j) {
+      const double pj = readlane_f64(a[j], p);
+      a[j] = (j > k) ? fma(-f, pj, a[j]) : a[j];
+    }
+    bl = fma(-f, readlane_f64(bl, p), bl);
     __syncthreads();
   }
-  if (flag) {
+  if (singular) {
     if (lane == 0) atomicOr(I.status, ST_SINGULAR);
     return;
   }
+  // back substitution in pivot order: the pivot row of step k holds U_kj, j >= k
+  double x[NMR_MAX_R];
+#pragma unroll
+  for (int j = 0; j < NMR_MAX_R; ++j) x[j] = 0.0;
   for (int k = R - 1; k >= 0; --k) {
-    if (lane == 0) x[k] = b[k] / A[k][k];
-    __syncthreads();
-    if (lane < k) b[lane] -= A[lane][k] * x[k];
-    __syncthreads();
+    const int p = __builtin_amdgcn_readfirstlane(piv[k]);
+    double acc = bl, akk = 1.0;
+#pragma unroll
+    for (int j = 0; j < NMR_MAX_R; ++j) {
+      acc = (j > k) ? fma(-a[j], x[j], acc) : acc;
+      akk = (j == k) ? a[j] : akk;
+    }
+    const double xk = readlane_f64(acc / akk, p);
+#pragma unroll
+    for (int j = 0; j < NMR_MAX_R; ++j) x[j] = (j == k) ? xk : x[j];
   }
-  if (lane < R) I.r[lane] += x[lane];
+  double xl = 0.0;
+#pragma unroll
+  for (int j = 0; j < NMR_MAX_R; ++j) xl = (j == lane) ? x[j] : xl;
+  if (row) xs[lane] = xl;
+  // new state from registers; the decoder input of the next iteration is
+  // taken from the lanes of the q block (exchange through LDS)
+  const double rn = r_l + (row ? xs[lane] : 0.0);
+  const bool fin = mode & SOLVE_FINISH;
+  const double rbar_n = fin ? rn : rbar_l;
+  const double rdot_n = fin ? (rn - rbar_l) / dt : rdot_l;
+  __shared__ double sq[3][NMR_MAX_R];
+  if (row) {
+    I.r[lane] = rn;
+    if (fin) {
+      I.rdot[lane] = rdot_n;
+      I.rbar[lane] = rbar_n;
+    }
+    if (lane >= np) {
+      sq[0][lane - np] = rn;
+      sq[1][lane - np] = rn - rbar_n;
+      sq[2][lane - np] = rdot_n;
+    }
+  }
   __syncthreads();
   if (lane < nq) {
-    const double q = I.r[np + lane];
-    I.dec_in[lane] = q;
-    I.dec_in[nq + lane] = q - I.rbar[np + lane];
-    I.dec_in[2 * nq + lane] = I.rdot[np + lane];
-  }
-  if ((mode & SOLVE_FINISH) && lane < R) {
-    const double rn = I.r[lane];
-    I.rdot[lane] = (rn - I.rbar[lane]) / dt;
-    I.rbar[lane] = rn;
+    I.dec_in[lane] = sq[0][lane];
+    I.dec_in[nq + lane] = sq[1][lane];
+    I.dec_in[2 * nq + lane] = sq[2][lane];
   }
 }
 

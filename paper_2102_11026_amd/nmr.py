@@ -17,6 +17,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnmr.so")
 
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+PHASES = ["dec_hidden", "dec_out", "cubature", "mass", "sums", "bwd_out", "bwd_hidden", "solve"]
+# kernels of each phase, as rocprofv3 names them
+PHASE_KERNELS = {"dec_hidden": "k_fwd_hidden", "dec_out": "k_fwd_out", "cubature": "k_cubature", "mass": "k_mass",
+                 "sums": "k_sums", "bwd_out": "k_bwd_out", "bwd_hidden": "k_bwd_hidden", "solve": "k_solve"}
 ACT = {"identity": 0, "tanh": 1, "elu": 2, "sin": 3}
 STATUS = {0: "ok", -1: "arg", -2: "budget", -3: "oom", -4: "inverted", -5: "singular", -6: "nonfinite",
           -7: "device"}
@@ -72,6 +76,7 @@ def lib():
             "reduced_newton_system": (i, [vp, vp, vp, vp]),
             "reduced_newton_step": (i, [vp, i, _dp]),
             "step_many": (i, [vp, C.POINTER(vp), i, i, i, ip, C.POINTER(C.c_float)]),
+            "nmr_time_phase": (i, [vp, i, i, C.POINTER(C.c_float)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -259,6 +264,12 @@ class Instance:
                                               _ptr(Kr)))
         torch.cuda.synchronize(self.dev)
         return dict(f_int=fint, fr=fr, Kr=Kr)
+
+    def time_phase(self, phase: int, reps: int = 20) -> float:
+        """Mean device microseconds of one phase of a Newton iteration."""
+        us = C.c_float()
+        _check(lib().nmr_time_phase(self.h, phase, reps, C.byref(us)))
+        return us.value
 
     def newton_system(self, r):
         import torch
