@@ -34,47 +34,93 @@ HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 FRAME_BUDGET_MS = 1000.0 / 60.0
+PHASE_KERNEL = dict(dec_hidden="k_fwd_hidden", dec_out="k_fwd_out", bwd_out="k_bwd_out", bwd_hidden="k_bwd_hidden")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def phase_roofline(p, inst, phase: str, us: float, prec: str):
-    """Algorithmic bytes / flops of one launch of a phase's kernel.
+def cubature_dofs(p) -> int:
+    """DOFs of the cubature tets: the rows the Gram-folded path decodes."""
+    v = np.unique(np.asarray(p.tets)[np.asarray(p.cub_ids)].ravel())
+    return 3 * v.size
 
-    dec_out  (k_fwd_out): reads W_L [N x K] once, the folded activations
-             [Cf x K], bias and mask [N]; writes the DOF records [N x Cf];
-             2 N K Cf flops with Cf = 2 n_q + 2.
-    bwd_out  (k_bwd_out): reads W_L [N x K] and the seed [N]; writes one
-             K-vector partial per 128 rows; 2 N K flops.
+
+def phase_work(p, phase: str, prec: str, gram: bool):
+    """(algorithmic bytes, algorithmic flops, launches) of one pass of a phase.
+
+    Widths are the decoder's own (unpadded); C = 4 + 4 n_q jet channels
+    forward, 1 + n_q channels backward, Cf = 2 + 2 n_q folded channels.
+    dec_hidden (k_fwd_hidden, one launch per hidden layer): reads W_l, b_l and
+        the input jets [C x m_in], writes the output jets [C x m_out] (the
+        folded channels [Cf x m_out] after the last hidden layer) and the
+        pre-activation jets [(1 + n_q) x m_out]; 2 m_out m_in C flops.
+    bwd_hidden (k_bwd_hidden, one launch per hidden layer): reads W_l, the
+        seed [(1 + n_q) x m_out] and the pre-activations, writes the seed of
+        the layer below [(1 + n_q) x m_in]; 2 m_out m_in (1 + n_q) flops.
+    dec_out (k_fwd_out): reads the rows of W_L that are decoded (all N, or
+        the cubature DOFs on the Gram-folded path), the folded activations
+        [Cf x K], bias and mask of those rows, writes their records [rows x
+        Cf]; 2 rows K Cf flops.
+    bwd_out (k_bwd_out): reads the same rows of W_L and their seeds, writes
+        one K-vector partial per 128 rows for each of the 1 + n_q channels;
+        2 rows K (1 + n_q) flops.
     """
-    N = p.N
-    K = p.weights[-1].shape[1]
     nq = p.n_q
-    cf = 2 * nq + 2
     sw = 2 if prec == "bf16" else 4
+    Ws = p.weights
+    L = len(Ws)
+    C, Cb, Cf = 4 + 4 * nq, 1 + nq, 2 + 2 * nq
+    if phase == "dec_hidden":
+        byts = flops = 0.0
+        for l in range(L - 1):
+            mo, mi = Ws[l].shape
+            cout = Cf if l == L - 2 else C
+            byts += mo * mi * sw + mo * 4 + C * mi * 4 + cout * mo * 4 + Cb * mo * 4
+            flops += 2.0 * mo * mi * C
+        return byts, flops, L - 1
+    if phase == "bwd_hidden":
+        byts = flops = 0.0
+        for l in range(L - 1):
+            mo, mi = Ws[l].shape
+            byts += mo * mi * sw + 2 * Cb * mo * 4 + Cb * mi * 4
+            flops += 2.0 * mo * mi * Cb
+        return byts, flops, L - 1
+    K = Ws[-1].shape[1]
+    rows = cubature_dofs(p) if gram else p.N
     if phase == "dec_out":
-        byts = N * K * sw + cf * K * 4 + 2 * N * 4 + N * cf * 4
-        flops = 2.0 * N * K * cf
-    elif phase == "bwd_out":
-        nblk = (N + 127) // 128
-        byts = N * K * sw + N * 4 + nblk * K * 8
-        flops = 2.0 * N * K
-    else:
+        return rows * K * sw + Cf * K * 4 + 2 * rows * 4 + rows * Cf * 4, 2.0 * rows * K * Cf, 1
+    if phase == "bwd_out":
+        nblk = (rows + 127) // 128
+        return rows * K * sw + rows * 4 + nblk * K * Cb * 4, 2.0 * rows * K * Cb, 1
+    return None
+
+
+def phase_roofline(p, phase: str, us: float, prec: str, gram: bool):
+    """Roofline of one launch of a phase's kernel, `us` being the phase's
+    device time (all its launches).  The bound follows the arithmetic
+    intensity against the ridge point of the MFMA peak of the phase's dtype."""
+    w = phase_work(p, phase, prec, gram)
+    if w is None:
         return None
-    ai = flops / byts
-    ridge = (BF16_MFMA_PEAK_TFLOPS if prec == "bf16" else FP32_MFMA_PEAK_TFLOPS) * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if ai < ridge:
-        ach = byts / (us * 1e-6) / 1e9
+    byts, flops, launches = w
+    byts /= launches
+    flops /= launches
+    us_l = us / launches
+    peak_tf = BF16_MFMA_PEAK_TFLOPS if prec == "bf16" else FP32_MFMA_PEAK_TFLOPS
+    ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
+    common = dict(traffic=None, kernel=PHASE_KERNEL[phase], phase=phase, launches_per_pass=launches,
+                  us_per_launch=round(us_l, 3), algorithmic_bytes_per_launch=int(byts),
+                  algorithmic_flops_per_launch=int(flops), arithmetic_intensity=round(flops / byts, 2),
+                  ridge=round(ridge, 2))
+    if flops / byts < ridge:
+        ach = byts / (us_l * 1e-6) / 1e9
         return dict(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, kernel=phase, us_per_launch=round(us, 3),
-                    algorithmic_bytes_per_launch=int(byts), algorithmic_flops_per_launch=int(flops))
-    peak = BF16_MFMA_PEAK_TFLOPS if prec == "bf16" else FP32_MFMA_PEAK_TFLOPS
-    ach = flops / (us * 1e-6) / 1e12
-    return dict(bound="mfma", achieved=round(ach, 3), peak=peak, unit="TFLOP/s", frac=round(ach / peak, 4),
-                traffic=None, kernel=phase, us_per_launch=round(us, 3),
-                algorithmic_bytes_per_launch=int(byts), algorithmic_flops_per_launch=int(flops))
+                    frac=round(ach / HBM_PEAK_GBS, 4), **common)
+    ach = flops / (us_l * 1e-6) / 1e12
+    return dict(bound="mfma", achieved=round(ach, 3), peak=peak_tf, unit="TFLOP/s", frac=round(ach / peak_tf, 4),
+                **common)
 
 
 def run_steps(nmr, ctx, insts, steps: int, warmup: int):
@@ -120,7 +166,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--batch", type=int, nargs="*", default=[16])
+    ap.add_argument("--batch", type=int, nargs="*", default=[16, 64])
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the served form (0: skip)")
+    ap.add_argument("--serve-slots", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the path has no multi-GPU form (instances would shard "
@@ -157,9 +205,12 @@ def main():
     for k, name in enumerate(nmr.PHASES):
         phases[name] = round(inst.time_phase(k, reps=50), 3)
     out["phase_us"] = phases
-    cand = {k: v for k, v in phases.items() if k in ("dec_out", "bwd_out")}
+    gram = inst.gram
+    cand = {k: v for k, v in phases.items() if k in PHASE_KERNEL}
     dom = max(cand, key=cand.get)
-    out["roofline"] = phase_roofline(p, inst, dom, phases[dom], "fp32")
+    out["roofline"] = phase_roofline(p, dom, phases[dom], "fp32", gram)
+    out["phase_rooflines"] = {k: phase_roofline(p, k, phases[k], "fp32", gram) for k in PHASE_KERNEL}
+    out["newton_path"] = "gram-folded" if gram else "direct"
     log("phases (us):", phases)
 
     if not args.no_variants:
@@ -189,6 +240,39 @@ def main():
                 for x in insts:
                     x.close()
             dec.close()
+        # batched ragged rods: 320 rods sharing one decoder, one launch sequence
+        rods = synth.config_rods(320)
+        for prec in ("fp32", "bf16"):
+            dec = nmr.Decoder(ctx, rods[0].weights, rods[0].biases, rods[0].act, prec)
+            insts = [nmr.Instance(ctx, q, prec, shared=dec) for q in rods]
+            t0 = time.perf_counter()
+            st, ms_r = nmr.step_many(ctx, insts, 2, 3, timings=True)
+            torch.cuda.synchronize()
+            st, ms_r = nmr.step_many(ctx, insts, 20, 3, timings=True)
+            torch.cuda.synchronize()
+            sec = float(np.sum(ms_r)) / 1000.0
+            assert all(s == 0 for s in st), st
+            var[f"rods320_{prec}"] = dict(rod_newton_iters_per_s=round(320 * 3 * 20 / sec, 1),
+                                          p99_step_ms=round(float(np.percentile(ms_r, 99)), 4),
+                                          steps=20, newton_iters_per_step=3)
+            for x in insts:
+                x.close()
+            dec.close()
+        if args.serve_seconds > 0:
+            from paper_2102_11026_amd import serve
+            probs = {"A": synth.config_serve_a(), "B": synth.config_serve_b(), "C": synth.config_serve_c()}
+            for prec in ("fp32", "bf16"):
+                sctx = nmr.Context(0, budget_bytes=200 * (1 << 30))
+                classes = [serve.RequestClass(k, v, capacity=args.serve_slots) for k, v in probs.items()]
+                srv = serve.Server(sctx, classes, prec, n_iters=ITERS)
+                reqs = serve.poisson_arrivals(200.0, args.serve_seconds, list(probs), 120, probs)
+                stats = srv.run(reqs, max_seconds=args.serve_seconds + 60.0, log=log)
+                srv.close()
+                sctx.close()
+                stats.update(rate_req_s=200.0, horizon_s=args.serve_seconds, steps_per_request=120,
+                             budget_gb=200, slots_per_class=args.serve_slots)
+                var[f"served_{prec}"] = stats
+                log(f"served {prec}:", stats)
         out["variants"] = var
         log("variants:", var)
     inst.close()

@@ -71,7 +71,7 @@ typedef struct {
 } nmr_mlp_desc;
 
 /* One simulated object (host pointers, copied to the device by
- * nmr_instance_create).  N = 3 * n_vertices, R = n_p + n_q. */
+ * nmr_instance_create).  N = 3 * n_vertices, R = n_p + n_q <= 31. */
 typedef struct {
   int n_vertices;
   const double* X;          /* n_vertices x 3 rest positions                   */
@@ -93,6 +93,11 @@ typedef struct {
   double wnet_scale;        /* w = wnet_scale * wnet(rbar)                      */
   const double* r0;         /* R initial generalized coordinate                 */
   const double* rdot0;      /* R initial generalized velocity                   */
+  int newton_path;          /* 0: automatic -- Gram-folded mass terms when      */
+                            /*    n_p == 0 (the output layer is linear and M    */
+                            /*    constant, so Jt^T M Jt = F^T (W^T M W) F and  */
+                            /*    only cubature DOFs are decoded per iteration); */
+                            /* 1: direct (every DOF decoded each iteration)     */
 } nmr_problem;
 
 /* ---- lifecycle ---------------------------------------------------------- */
@@ -118,6 +123,9 @@ int nmr_instance_create(nmr_ctx* ctx, const nmr_problem* prob, int prec, nmr_ins
 int nmr_instance_destroy(nmr_inst* inst);
 /* Device bytes charged to the budget for this instance (host output). */
 int nmr_instance_bytes(const nmr_inst* inst, size_t* bytes);
+/* Newton path the instance runs (host output): 0 = Gram-folded mass terms
+ * (only the DOFs of cubature tets decoded per iteration), 1 = direct. */
+int nmr_instance_newton_path(const nmr_inst* inst, int* path);
 /* Host buffers: r and rdot (R doubles each) of the last completed step; u
  * (N reals, may be NULL) is the full-space displacement u = U p + D(q).
  * Synchronizes. */
@@ -173,6 +181,29 @@ int reduced_newton_step(nmr_inst* inst, int n_iters, double* resid_norms_or_null
  * [n_steps] (device time of each step). */
 int step_many(nmr_ctx* ctx, nmr_inst* const* insts, int n_inst, int n_steps, int n_iters,
               int* status, float* step_ms_or_null);
+
+/* ---- served form: slot pools (continuous batching) ---------------------- */
+
+typedef struct nmr_pool nmr_pool;
+
+/* A pool of `capacity` slots whose time step is captured once as a HIP graph
+ * over all slots; instances attach to free slots and detach between steps
+ * without a new capture (empty slots return at once).  Every attached
+ * instance must share the first one's decoder, precision and sizes (N, n_p,
+ * n_q, |C|, weight net), i.e. one request class. */
+int nmr_pool_create(nmr_ctx* ctx, int capacity, nmr_pool** out);
+int nmr_pool_destroy(nmr_pool* pool);
+/* Attaches `inst` to a free slot (host output *slot).  NMR_ERR_BUDGET if the
+ * pool is full, NMR_ERR_ARG if the instance does not match the pool's class.
+ * The instance keeps its own state and buffers; it must stay alive until it is
+ * detached. */
+int nmr_pool_attach(nmr_pool* pool, nmr_inst* inst, int* slot);
+int nmr_pool_detach(nmr_pool* pool, int slot);
+/* One implicit-Euler step (n_iters Newton iterations) of every attached
+ * instance, one graph launch.  status_or_null: host, `capacity` ints
+ * (nmr_status per slot, 0 for empty slots; synchronizes); *ms_or_null: device
+ * time of the step (synchronizes). */
+int nmr_pool_step(nmr_pool* pool, int n_iters, int* status_or_null, float* ms_or_null);
 
 /* ---- measurement -------------------------------------------------------- */
 

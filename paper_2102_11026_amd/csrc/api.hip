@@ -115,6 +115,7 @@ struct nmr_inst {
   int prec = PREC_FP32;
   int N = 0, n = 0, n_p = 0, n_q = 0, R = 0, n_cub = 0;
   int Cp = 0, Cb = 0, Cf = 0, n_mblk = 0, n_cblk = 0, n_bblk = 0;
+  int gram = 0, n_cdofs = 0, n_sblk = 0;
   size_t bytes = 0;
   DevMem mem;
   void* tab = nullptr;      // Inst<T> on the device
@@ -345,6 +346,8 @@ extern "C" int nmr_decoder_destroy(nmr_decoder* d) {
 struct Sizes {
   int N, n, m, n_p, n_q, R, n_cub, L, Cp, Cb, Cf, Wmax, n_mblk, n_cblk, n_bblk, cub_per_blk;
   int wn_L, wn_maxw;
+  int gram, K, n_cdofs, n_gblk, n_sblk, mblk_alloc, bblk_alloc;
+  std::vector<int> cdofs;
 };
 
 template <typename T>
@@ -363,8 +366,13 @@ static size_t instance_bytes(const Sizes& s, const DecoderDev& d) {
   add((size_t)s.Cb * s.Wmax * t); add((size_t)s.Cb * s.Wmax * t);
   add((size_t)s.n_cub * 12 * t);
   add((size_t)s.n_cblk * (s.R * s.R + s.R) * 8);
-  add((size_t)s.n_mblk * (s.R * s.R + s.R * s.n_q + s.R + s.n_p) * 8);
-  add((size_t)s.n_bblk * d.wp[s.L - 1] * 8);
+  add((size_t)s.mblk_alloc * (s.R * s.R + s.R * s.n_q + s.R + s.n_p) * 8);
+  add((size_t)s.bblk_alloc * d.wp[s.L - 1] * 8);
+  if (s.gram) {
+    add((size_t)s.n_cdofs * 4);
+    add((size_t)s.K * s.K * 8);
+    add((size_t)s.K * 8);
+  }
   add((s.R * s.R + s.R) * 8); add((s.R * s.R + s.R * s.n_q + s.R + s.n_p) * 8);
   add(s.n_q * s.n_q * 8); add(s.n_q * 8);
   add(s.R * s.R * 8);
@@ -392,7 +400,31 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   s.n_mblk = (s.N + 255) / 256;
   s.n_cblk = (s.n_cub + s.cub_per_blk - 1) / s.cub_per_blk;
   s.n_bblk = (s.N + 127) / 128;
-  if (s.R > NMR_MAX_R) return fail(NMR_ERR_ARG, "n_p + n_q must be <= 32");
+  // Gram-folded path: no linear subspace, last hidden layer <= 256
+  s.K = d.wp[d.L - 1];
+  s.gram = (p->newton_path == 0 && s.n_p == 0 && s.K <= 256) ? 1 : 0;
+  s.n_cdofs = 0;
+  s.n_gblk = s.K / 16;
+  s.n_sblk = 0;
+  if (s.gram) {
+    std::vector<char> hit(s.N, 0);
+    for (int c = 0; c < s.n_cub; ++c) {
+      const int e = p->cub_ids[c];
+      if (e < 0 || e >= p->n_tets) return fail(NMR_ERR_ARG, "cubature id out of range");
+      for (int a = 0; a < 4; ++a) {
+        const int v = p->tets[4 * e + a];
+        if (v < 0 || v >= s.n) return fail(NMR_ERR_ARG, "tet vertex out of range");
+        for (int k = 0; k < 3; ++k) hit[3 * v + k] = 1;
+      }
+    }
+    for (int i = 0; i < s.N; ++i)
+      if (hit[i]) s.cdofs.push_back(i);
+    s.n_cdofs = (int)s.cdofs.size();
+    s.n_sblk = (s.n_cdofs + 127) / 128;
+  }
+  s.mblk_alloc = std::max(s.n_mblk, s.n_gblk);
+  s.bblk_alloc = std::max(s.n_bblk, s.n_sblk + 1);
+  if (s.R > NMR_MAX_R - 1) return fail(NMR_ERR_ARG, "n_p + n_q must be <= 31");
   if (d.w[d.L] < s.N) return fail(NMR_ERR_ARG, "decoder output smaller than 3 * n_vertices");
   if (s.Cf > 64) return fail(NMR_ERR_ARG, "n_q too large for the output layer");
   s.wn_L = 0;
@@ -419,8 +451,10 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   in->N = s.N; in->n = s.n; in->n_p = s.n_p; in->n_q = s.n_q; in->R = s.R; in->n_cub = s.n_cub;
   in->Cp = s.Cp; in->Cb = s.Cb; in->Cf = s.Cf;
   in->n_mblk = s.n_mblk; in->n_cblk = s.n_cblk; in->n_bblk = s.n_bblk;
+  in->gram = s.gram; in->n_cdofs = s.n_cdofs; in->n_sblk = s.n_sblk;
   in->host.assign(sizeof(Inst<T>), 0);
   Inst<T>& I = host_inst<T>(in);
+  I.active = 1;
   I.N = s.N; I.n = s.n; I.n_p = s.n_p; I.n_q = s.n_q; I.R = s.R; I.n_cub = s.n_cub;
   I.Cp = s.Cp; I.Cb = s.Cb; I.Cf = s.Cf; I.Np = pad_to(s.N, NMR_WPAD);
   I.n_mblk = s.n_mblk; I.n_cblk = s.n_cblk; I.n_bblk = s.n_bblk; I.cub_per_blk = s.cub_per_blk;
@@ -460,8 +494,23 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   CHK(dalloc_t(M, (size_t)s.Cb * s.Wmax, &I.zb1));
   CHK(dalloc_t(M, (size_t)s.n_cub * 12, &I.fe));
   CHK(dalloc_t(M, (size_t)s.n_cblk * (s.R * s.R + s.R), &I.part_cub));
-  CHK(dalloc_t(M, (size_t)s.n_mblk * (s.R * s.R + s.R * s.n_q + s.R + s.n_p), &I.part_mass));
-  CHK(dalloc_t(M, (size_t)s.n_bblk * d.wp[s.L - 1], &I.part_bwd));
+  CHK(dalloc_t(M, (size_t)s.mblk_alloc * (s.R * s.R + s.R * s.n_q + s.R + s.n_p), &I.part_mass));
+  CHK(dalloc_t(M, (size_t)s.bblk_alloc * d.wp[s.L - 1], &I.part_bwd));
+  I.gram = s.gram;
+  I.n_gblk = s.n_gblk;
+  I.n_cdofs = s.n_cdofs;
+  I.n_sblk = s.n_sblk;
+  if (s.gram) {
+    int* cd;
+    double *Gm, *gm;
+    CHK(dalloc_t(M, s.n_cdofs, &cd));
+    CHK(dalloc_t(M, (size_t)s.K * s.K, &Gm));
+    CHK(dalloc_t(M, s.K, &gm));
+    HIPCHK(hipMemcpy(cd, s.cdofs.data(), s.n_cdofs * sizeof(int), hipMemcpyHostToDevice));
+    I.cdofs = cd;
+    I.Gam = Gm;
+    I.gam = gm;
+  }
   CHK(dalloc_t(M, s.R * s.R + s.R, &I.sum_cub));
   CHK(dalloc_t(M, s.R * s.R + s.R * s.n_q + s.R + s.n_p, &I.sum_mass));
   CHK(dalloc_t(M, s.n_q * s.n_q, &I.Bq));
@@ -559,6 +608,9 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
     (void)hipMemcpy(dvp, vcnt.data(), 4 * (size_t)(s.n + 1), hipMemcpyHostToDevice);
     (void)hipMemcpy(dve, vent.data(), 4 * (size_t)(4 * s.m), hipMemcpyHostToDevice);
     launch_rest_shape<T>(dX, dT, s.m, dcub, s.n_cub, dvp, dve, s.n, p->rho, Bm, Ve, mass, dVe, ctx->stream);
+    if (s.gram)
+      launch_gram_setup<T>(d.W[d.L - 1], d.prec, s.K, mass, keep, s.N, p->dt, p->gravity, const_cast<double*>(I.Gam),
+                           const_cast<double*>(I.gam), ctx->stream);
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize(ctx->stream);
     tmp.release();
@@ -633,6 +685,12 @@ extern "C" int nmr_instance_bytes(const nmr_inst* in, size_t* bytes) {
   return NMR_OK;
 }
 
+extern "C" int nmr_instance_newton_path(const nmr_inst* in, int* path) {
+  if (!in || !path) return fail(NMR_ERR_ARG, "null argument");
+  *path = in->gram ? 0 : 1;
+  return NMR_OK;
+}
+
 // ---------------------------------------------------------------------------
 // launch sequences
 // ---------------------------------------------------------------------------
@@ -642,6 +700,8 @@ struct Group {
   void* tab;  // device array of Inst<T>
   int nb, Cp, Cb, Cf, maxN, maxR, n_q, max_mblk, max_cblk, max_bblk, max_entries, max_cub;
   bool any_np;
+  bool gram;  // every table entry runs the Gram-folded path
+  int max_cdofs, max_sblk, n_gblk, K;
 };
 
 static Group group_of(const std::vector<nmr_inst*>& v, void* tab) {
@@ -651,7 +711,13 @@ static Group group_of(const std::vector<nmr_inst*>& v, void* tab) {
   g.tab = tab;
   g.nb = (int)v.size();
   g.Cp = v[0]->Cp; g.Cb = v[0]->Cb; g.Cf = v[0]->Cf; g.n_q = v[0]->n_q;
+  g.K = g.dec->d.wp[g.dec->d.L - 1];
+  g.n_gblk = g.K / 16;
+  g.gram = true;
   for (nmr_inst* in : v) {
+    g.gram = g.gram && in->gram;
+    g.max_cdofs = std::max(g.max_cdofs, in->n_cdofs);
+    g.max_sblk = std::max(g.max_sblk, in->n_sblk);
     g.maxN = std::max(g.maxN, in->N);
     g.maxR = std::max(g.maxR, in->R);
     g.max_mblk = std::max(g.max_mblk, in->n_mblk);
@@ -669,7 +735,7 @@ static void enqueue_decoder_fwd(const Group& g, hipStream_t s, int add_up) {
   const DecoderDev& d = g.dec->d;
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
   for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, s);
-  launch_fwd_out<T>(d, tab, g.nb, g.maxN, g.Cf, s);
+  launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, s);
   if (g.any_np) launch_filter<T>(tab, g.nb, add_up, s);
 }
 
@@ -677,7 +743,7 @@ template <typename T>
 static void enqueue_decoder_bwd(const Group& g, hipStream_t s) {
   const DecoderDev& d = g.dec->d;
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
-  launch_bwd_out<T>(d, tab, g.nb, g.max_bblk, s);
+  launch_bwd_out<T>(d, tab, g.nb, g.gram ? g.max_sblk : g.max_bblk, s);
   launch_bwd_reduce<T>(d, tab, g.nb, s);
   for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, s);
 }
@@ -687,7 +753,8 @@ static void enqueue_iteration(const Group& g, int iter, int mode, double* A_out,
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
   enqueue_decoder_fwd<T>(g, s, 1);
   launch_cubature<T>(tab, g.nb, g.max_cblk, s);
-  launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
+  if (g.gram) launch_gram<T>(tab, g.nb, g.n_gblk, g.K, s);
+  else launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
   launch_sums<T>(tab, g.nb, g.max_entries, s);
   enqueue_decoder_bwd<T>(g, s);
   launch_solve<T>(tab, g.nb, iter, mode, A_out, phi_out, s);
@@ -780,7 +847,13 @@ extern "C" int step_many(nmr_ctx* c, nmr_inst* const* insts, int n_inst, int n_s
     for (auto& pr : byd) {
       const size_t isz = is_f64(pr.second[0]) ? sizeof(Inst<double>) : sizeof(Inst<float>);
       std::vector<unsigned char> host(isz * pr.second.size());
-      for (size_t k = 0; k < pr.second.size(); ++k) std::memcpy(&host[k * isz], pr.second[k]->host.data(), isz);
+      bool all_gram = true;
+      for (nmr_inst* x : pr.second) all_gram = all_gram && x->gram;
+      for (size_t k = 0; k < pr.second.size(); ++k) {
+        std::memcpy(&host[k * isz], pr.second[k]->host.data(), isz);
+        // a group runs one path: the direct one unless every member can fold
+        if (!all_gram) std::memset(&host[k * isz] + offsetof(Inst<float>, gram), 0, sizeof(int));
+      }
       void* tab;
       HIPCHK(hipMalloc(&tab, host.size()));
       ge.tabs.push_back(tab);
@@ -817,6 +890,18 @@ extern "C" int step_many(nmr_ctx* c, nmr_inst* const* insts, int n_inst, int n_s
   return NMR_OK;
 }
 
+// the instance table with the direct (all-DOF) output layer, in the scratch
+// slot: used by the calls that return full-space arrays
+template <typename T>
+static int direct_tab(nmr_inst* in, void** out) {
+  Inst<T> I = host_inst<T>(in);
+  I.gram = 0;
+  HIPCHK(hipStreamSynchronize(in->ctx->stream));
+  HIPCHK(hipMemcpy(in->api_tab, &I, sizeof(Inst<T>), hipMemcpyHostToDevice));
+  *out = in->api_tab;
+  return NMR_OK;
+}
+
 template <typename T>
 static int djh_impl(nmr_inst* in, const double* q, const double* dq, const double* qdot, const void* a, void* u,
                     void* J, void* dJ, void* Hdd, double* B, double* JTa) {
@@ -826,13 +911,17 @@ static int djh_impl(nmr_inst* in, const double* q, const double* dq, const doubl
   HIPCHK(hipMemcpyAsync(I.dec_in, q, nqb, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(I.dec_in + in->n_q, dq, nqb, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(I.dec_in + 2 * in->n_q, qdot, nqb, hipMemcpyDeviceToDevice, c->stream));
+  void* dt_tab;
+  CHK(direct_tab<T>(in, &dt_tab));
+  const Inst<T>* tab = static_cast<const Inst<T>*>(dt_tab);
   std::vector<nmr_inst*> v{in};
-  Group g = group_of(v, in->tab);
+  Group g = group_of(v, dt_tab);
+  g.gram = false;
   enqueue_decoder_fwd<T>(g, c->stream, 0);
-  launch_unpack<T>(static_cast<const Inst<T>*>(in->tab), (T*)u, (T*)J, (T*)dJ, (T*)Hdd, in->N, c->stream);
+  launch_unpack<T>(tab, (T*)u, (T*)J, (T*)dJ, (T*)Hdd, in->N, c->stream);
   if (a) {
-    launch_seed_from_a<T>(static_cast<const Inst<T>*>(in->tab), static_cast<const T*>(a), 1, in->n_mblk, c->stream);
-    launch_sums<T>(static_cast<const Inst<T>*>(in->tab), 1, g.max_entries, c->stream);
+    launch_seed_from_a<T>(tab, static_cast<const T*>(a), 1, in->n_mblk, c->stream);
+    launch_sums<T>(tab, 1, g.max_entries, c->stream);
     enqueue_decoder_bwd<T>(g, c->stream);
     if (B) HIPCHK(hipMemcpyAsync(B, I.Bq, in->n_q * nqb, hipMemcpyDeviceToDevice, c->stream));
     if (JTa) HIPCHK(hipMemcpyAsync(JTa, I.JTa, nqb, hipMemcpyDeviceToDevice, c->stream));
@@ -865,6 +954,7 @@ static int cfs_impl(nmr_inst* in, const void* u, const void* Jt, const void* w, 
   I.cu_Jb_ld = 0;
   I.cu_nb = 0;
   if (w) I.cu_w = static_cast<const T*>(w);
+  I.gram = 0;
   HIPCHK(hipMemcpy(in->api_tab, &I, sizeof(Inst<T>), hipMemcpyHostToDevice));
   const Inst<T>* tab = static_cast<const Inst<T>*>(in->api_tab);
   launch_cubature<T>(tab, 1, in->n_cblk, c->stream);
@@ -921,13 +1011,16 @@ static int get_state_impl(nmr_inst* in, double* r, double* rdot, void* u) {
   if (u) {
     // decode at rbar: r <- rbar, decoder input (qbar, 0, rdot_bar), u = U p + D(q)
     HIPCHK(hipMemcpyAsync(I.r, I.rbar, in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    launch_step_begin<T>(static_cast<const Inst<T>*>(in->tab), 1, BEGIN_SYSTEM, in->n_cub, c->stream);
+    void* dt_tab;
+    CHK(direct_tab<T>(in, &dt_tab));
+    launch_step_begin<T>(static_cast<const Inst<T>*>(dt_tab), 1, BEGIN_SYSTEM, in->n_cub, c->stream);
     std::vector<nmr_inst*> v{in};
-    Group g = group_of(v, in->tab);
+    Group g = group_of(v, dt_tab);
+    g.gram = false;
     enqueue_decoder_fwd<T>(g, c->stream, 1);
     T* du;
     HIPCHK(hipMalloc(&du, in->N * sizeof(T)));
-    launch_unpack<T>(static_cast<const Inst<T>*>(in->tab), du, nullptr, nullptr, nullptr, in->N, c->stream);
+    launch_unpack<T>(static_cast<const Inst<T>*>(dt_tab), du, nullptr, nullptr, nullptr, in->N, c->stream);
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = hipMemcpy(u, du, in->N * sizeof(T), hipMemcpyDeviceToHost);
     (void)hipFree(du);
@@ -960,6 +1053,126 @@ extern "C" int nmr_instance_set_state(nmr_inst* in, const double* r, const doubl
   return NMR_OK;
 }
 
+// ---------------------------------------------------------------------------
+// slot pools: one graph over `capacity` table entries; attach / detach rewrite
+// one entry of the device table between steps
+// ---------------------------------------------------------------------------
+struct nmr_pool {
+  nmr_ctx* ctx = nullptr;
+  int capacity = 0;
+  std::vector<nmr_inst*> slots;
+  nmr_inst proto_copy;        // class representative (sizes, decoder), a copy
+  nmr_inst* proto = nullptr;  // &proto_copy once the first instance attached
+  void* tab = nullptr;        // device table of capacity Inst<T>
+  size_t isz = 0;
+  std::map<int, hipGraphExec_t> graphs;
+};
+
+extern "C" int nmr_pool_create(nmr_ctx* c, int capacity, nmr_pool** out) {
+  if (!c || !out || capacity < 1) return fail(NMR_ERR_ARG, "bad argument");
+  CHK(set_device(c));
+  nmr_pool* p = new nmr_pool();
+  p->ctx = c;
+  p->capacity = capacity;
+  p->slots.assign(capacity, nullptr);
+  *out = p;
+  return NMR_OK;
+}
+
+static void pool_drop_graphs(nmr_pool* p) {
+  for (auto& kv : p->graphs) (void)hipGraphExecDestroy(kv.second);
+  p->graphs.clear();
+}
+
+extern "C" int nmr_pool_destroy(nmr_pool* p) {
+  if (!p) return fail(NMR_ERR_ARG, "null pool");
+  CHK(set_device(p->ctx));
+  (void)hipStreamSynchronize(p->ctx->stream);
+  pool_drop_graphs(p);
+  if (p->tab) (void)hipFree(p->tab);
+  if (p->proto) decoder_unref(p->proto->dec);
+  delete p;
+  return NMR_OK;
+}
+
+static bool same_class(const nmr_inst* a, const nmr_inst* b) {
+  return a->dec == b->dec && a->prec == b->prec && a->N == b->N && a->n_p == b->n_p && a->n_q == b->n_q &&
+         a->n_cub == b->n_cub && a->n_mblk == b->n_mblk && a->n_cblk == b->n_cblk && a->n_bblk == b->n_bblk;
+}
+
+extern "C" int nmr_pool_attach(nmr_pool* p, nmr_inst* in, int* slot) {
+  if (!p || !in || !slot || in->ctx != p->ctx) return fail(NMR_ERR_ARG, "bad argument");
+  CHK(set_device(p->ctx));
+  if (p->proto && !same_class(p->proto, in)) return fail(NMR_ERR_ARG, "instance does not match the pool's class");
+  int s = -1;
+  for (int k = 0; k < p->capacity; ++k)
+    if (!p->slots[k]) {
+      s = k;
+      break;
+    }
+  if (s < 0) return fail(NMR_ERR_BUDGET, "pool is full");
+  if (!p->proto) {
+    p->proto_copy = *in;
+    p->proto_copy.step_graphs.clear();
+    p->proto = &p->proto_copy;
+    p->proto->dec->refs++;  // the pool's graph references the decoder's weights
+    p->isz = is_f64(in) ? sizeof(Inst<double>) : sizeof(Inst<float>);
+    std::vector<unsigned char> zero(p->isz * p->capacity, 0);  // active = 0 everywhere
+    HIPCHK(hipMalloc(&p->tab, zero.size()));
+    HIPCHK(hipMemcpy(p->tab, zero.data(), zero.size(), hipMemcpyHostToDevice));
+  }
+  HIPCHK(hipStreamSynchronize(p->ctx->stream));
+  HIPCHK(hipMemcpy(static_cast<unsigned char*>(p->tab) + s * p->isz, in->host.data(), p->isz,
+                   hipMemcpyHostToDevice));
+  p->slots[s] = in;
+  *slot = s;
+  return NMR_OK;
+}
+
+extern "C" int nmr_pool_detach(nmr_pool* p, int s) {
+  if (!p || s < 0 || s >= p->capacity || !p->slots[s]) return fail(NMR_ERR_ARG, "bad slot");
+  CHK(set_device(p->ctx));
+  HIPCHK(hipStreamSynchronize(p->ctx->stream));
+  const int zero = 0;  // Inst<T>::active is the first member
+  HIPCHK(hipMemcpy(static_cast<unsigned char*>(p->tab) + s * p->isz, &zero, sizeof(int), hipMemcpyHostToDevice));
+  p->slots[s] = nullptr;
+  return NMR_OK;
+}
+
+extern "C" int nmr_pool_step(nmr_pool* p, int n_iters, int* status, float* ms) {
+  if (!p) return fail(NMR_ERR_ARG, "null pool");
+  if (n_iters < 1 || n_iters > kMaxIters) return fail(NMR_ERR_ARG, "n_iters must be in [1, 64]");
+  if (!p->proto) return NMR_OK;  // nothing ever attached
+  nmr_ctx* c = p->ctx;
+  CHK(set_device(c));
+  auto it = p->graphs.find(n_iters);
+  if (it == p->graphs.end()) {
+    Group g = group_of({p->proto}, p->tab);
+    g.nb = p->capacity;
+    hipGraphExec_t ex;
+    CHK(capture(c, {g}, n_iters, &ex));
+    it = p->graphs.emplace(n_iters, ex).first;
+  }
+  if (ms) HIPCHK(hipEventRecord(c->ev[0], c->stream));
+  HIPCHK(hipGraphLaunch(it->second, c->stream));
+  if (ms) {
+    HIPCHK(hipEventRecord(c->ev[1], c->stream));
+    HIPCHK(hipEventSynchronize(c->ev[1]));
+    HIPCHK(hipEventElapsedTime(ms, c->ev[0], c->ev[1]));
+  }
+  if (status) {
+    for (int k = 0; k < p->capacity; ++k) {
+      status[k] = 0;
+      if (p->slots[k]) {
+        int st;
+        CHK(read_status(p->slots[k], &st));
+        status[k] = map_status(st);
+      }
+    }
+  }
+  return NMR_OK;
+}
+
 extern "C" int nmr_instance_status(nmr_inst* in) {
   if (!in) return fail(NMR_ERR_ARG, "null instance");
   CHK(set_device(in->ctx));
@@ -984,7 +1197,10 @@ static void enqueue_phase(const Group& g, int phase, hipStream_t s) {
       if (g.any_np) launch_filter<T>(tab, g.nb, 1, s);
       break;
     case NMR_PHASE_CUBATURE: launch_cubature<T>(tab, g.nb, g.max_cblk, s); break;
-    case NMR_PHASE_MASS: launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s); break;
+    case NMR_PHASE_MASS:
+      if (g.gram) launch_gram<T>(tab, g.nb, g.n_gblk, g.K, s);
+      else launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
+      break;
     case NMR_PHASE_SUMS: launch_sums<T>(tab, g.nb, g.max_entries, s); break;
     case NMR_PHASE_BWD_OUT: launch_bwd_out<T>(d, tab, g.nb, g.max_bblk, s); break;
     case NMR_PHASE_BWD_HIDDEN:

@@ -218,6 +218,7 @@ template <typename T, typename TW, int NCB>
 __global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const Inst<T>* __restrict__ tab) {
   constexpr int NW = splitk_waves<T, NCB>::v;
   const Inst<T>& I = tab[blockIdx.y];
+  if (!I.active) return;
   const int m_inp = d.wp[l], m_out = d.w[l + 1], m_outp = d.wp[l + 1];
   const int row0 = blockIdx.x * 16;
   if (row0 >= m_outp) return;
@@ -323,14 +324,18 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const I
 template <typename TW, int NCB>
 __global__ __launch_bounds__(512) void k_fwd_out(DecoderDev d, const Inst<float>* __restrict__ tab) {
   const Inst<float>& I = tab[blockIdx.y];
+  if (!I.active) return;
   const int l = d.L - 1;
   const int K = d.wp[l];
+  // rows of the output layer this launch decodes: all N DOFs, or on the Gram
+  // path only the DOFs of cubature tets (positions map through cdofs)
+  const int nrows = I.gram ? I.n_cdofs : I.N;
   const int blk_row0 = blockIdx.x * (OUT_WAVES * 16);
-  if (blk_row0 >= I.N) return;
+  if (blk_row0 >= nrows) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rA = lane & 15, g = lane >> 4;
   const int row0 = blk_row0 + wave * 16;
-  const bool active = row0 < I.N;
+  const bool active = row0 < nrows;
   const TW* W = reinterpret_cast<const TW*>(d.W[l]);
   constexpr int KS = kstep<TW>::v;
   constexpr int NKS = OUT_KMAX / KS;
@@ -338,7 +343,10 @@ __global__ __launch_bounds__(512) void k_fwd_out(DecoderDev d, const Inst<float>
   typedef typename std::conditional<std::is_same<TW, float>::value, float4, bf16x8>::type AF;
   AF a[NKS];
   if (active) {
-    const TW* ap = W + (size_t)(row0 + rA) * K + (KS / 4) * g;
+    const int pos = row0 + rA;
+    // past the end: a padded zero row (direct path) or the last listed row
+    const int wrow = I.gram ? I.cdofs[min(pos, nrows - 1)] : pos;
+    const TW* ap = W + (size_t)wrow * K + (KS / 4) * g;
 #pragma unroll
     for (int t = 0; t < NKS; ++t)
       if (t * KS < K) a[t] = *reinterpret_cast<const AF*>(ap + t * KS);
@@ -380,8 +388,9 @@ __global__ __launch_bounds__(512) void k_fwd_out(DecoderDev d, const Inst<float>
   for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row = row0 + 4 * g + i, c = cb * 16 + rA;
-      if (row < I.N && c < Cf) {
+      const int pos = row0 + 4 * g + i, c = cb * 16 + rA;
+      if (pos < nrows && c < Cf) {
+        const int row = I.gram ? I.cdofs[pos] : pos;
         const float v = acc[cb][i] + (c == 0 ? bias[row] : 0.f);
         I.rec[(size_t)row * Cf + c] = v * I.keep[row];
       }
@@ -391,12 +400,15 @@ __global__ __launch_bounds__(512) void k_fwd_out(DecoderDev d, const Inst<float>
 // FP64 form of the output layer (plain FMA; correctness configurations)
 __global__ __launch_bounds__(256) void k_fwd_out_f64(DecoderDev d, const Inst<double>* __restrict__ tab) {
   const Inst<double>& I = tab[blockIdx.y];
+  if (!I.active) return;
   const int l = d.L - 1;
   const int K = d.wp[l];
   const int Cf = I.Cf;
-  const int row = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int nrows = I.gram ? I.n_cdofs : I.N;
+  const int pos = blockIdx.x * 16 + (threadIdx.x >> 4);
   const int c0 = threadIdx.x & 15;
-  if (row >= I.N) return;
+  if (pos >= nrows) return;
+  const int row = I.gram ? I.cdofs[pos] : pos;
   const double* W = reinterpret_cast<const double*>(d.W[l]) + (size_t)row * K;
   const double* bias = reinterpret_cast<const double*>(d.b[l]);
   for (int c = c0; c < Cf; c += 16) {
@@ -415,6 +427,7 @@ __global__ __launch_bounds__(256) void k_fwd_out_f64(DecoderDev d, const Inst<do
 template <typename T>
 __global__ __launch_bounds__(256) void k_filter(const Inst<T>* __restrict__ tab, int add_up) {
   const Inst<T>& I = tab[blockIdx.y];
+  if (!I.active) return;
   const int np = I.n_p, Cf = I.Cf, N = I.N;
   if (np == 0) return;
   __shared__ double Y[NMR_MAX_R][64];  // U^T rec, n_p x Cf (Cf <= 64)
@@ -459,19 +472,33 @@ __device__ inline void load4(const __bf16* p, double (&w)[4]) {
 template <typename T, typename TW>
 __global__ __launch_bounds__(256) void k_bwd_out(DecoderDev d, const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
-  if ((int)blockIdx.x >= I.n_bblk) return;
+  if (!I.active) return;
+  // direct path: all N rows with the seed P a (and the filter transpose);
+  // Gram path: only the cubature DOFs with dt^2 P f_int (the rest of W_L^T P a
+  // is Gam y + gam, added by the Gram kernel as one more partial)
+  if ((int)blockIdx.x >= (I.gram ? I.n_sblk : I.n_bblk)) return;
   const int l = d.L - 1;
   const int K = d.wp[l];
+  const int nrows = I.gram ? I.n_cdofs : I.N;
   const int i0 = blockIdx.x * BWD_ROWS;
-  const int i1 = min(i0 + BWD_ROWS, I.N);
+  const int i1 = min(i0 + BWD_ROWS, nrows);
   __shared__ double s[BWD_ROWS];
+  __shared__ int srow[BWD_ROWS];
   __shared__ double red[4][256];
   const int np = I.n_p;
   const double* uta = I.sum_mass + I.R * I.R + I.R * I.n_q + I.R;
   for (int i = i0 + threadIdx.x; i < i1; i += 256) {
-    double v = (double)I.seed[i];
-    for (int k = 0; k < np; ++k) v -= (double)I.U[(size_t)i * np + k] * uta[k];
+    double v;
+    int row = i;
+    if (I.gram) {
+      row = I.cdofs[i];
+      v = I.dt * I.dt * (double)I.keep[row] * fint_at(I, row);
+    } else {
+      v = (double)I.seed[i];
+      for (int k = 0; k < np; ++k) v -= (double)I.U[(size_t)i * np + k] * uta[k];
+    }
     s[i - i0] = v;
+    srow[i - i0] = row;
   }
   __syncthreads();
   const TW* W = reinterpret_cast<const TW*>(d.W[l]);
@@ -483,7 +510,7 @@ __global__ __launch_bounds__(256) void k_bwd_out(DecoderDev d, const Inst<T>* __
 #pragma unroll 8
       for (int i = i0 + sl; i < i1; i += 4) {
         double w[4];
-        load4(W + (size_t)i * K + col, w);
+        load4(W + (size_t)srow[i - i0] * K + col, w);
         const double si = s[i - i0];
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = fma(w[t], si, acc[t]);
@@ -507,6 +534,7 @@ __global__ __launch_bounds__(256) void k_bwd_out(DecoderDev d, const Inst<T>* __
 template <typename T>
 __global__ __launch_bounds__(256) void k_bwd_reduce(DecoderDev d, const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
+  if (!I.active) return;
   const int l = d.L - 1;  // output layer; its input is hidden layer l-1
   const int K = d.wp[l];
   const int kk = threadIdx.x & 15, sl = threadIdx.x >> 4;
@@ -515,8 +543,9 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(DecoderDev d, const Inst<T>*
   double acc = 0.0;
   if (k < K) {
     const double* src = I.part_bwd + k;
+    const int nb = I.gram ? I.n_sblk + 1 : I.n_bblk;  // Gram: + the Gam y + gam partial
 #pragma unroll 4
-    for (int b = sl; b < I.n_bblk; b += 16) acc += src[(size_t)b * K];
+    for (int b = sl; b < nb; b += 16) acc += src[(size_t)b * K];
   }
   part[sl][kk] = acc;
   __syncthreads();
@@ -544,6 +573,7 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(DecoderDev d, const void* WT
                                                     const Inst<T>* __restrict__ tab) {
   constexpr int NW = splitk_waves<T, NCB>::v;
   const Inst<T>& I = tab[blockIdx.y];
+  if (!I.active) return;
   const int K = d.wp[l + 1];  // reduction over the outputs of layer l
   const int m_in = d.w[l], m_inp = d.wp[l];
   const int row0 = blockIdx.x * 16;

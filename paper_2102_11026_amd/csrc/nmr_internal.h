@@ -57,6 +57,7 @@ struct DecoderDev {
 // the instance with blockIdx.y.
 template <typename T>
 struct Inst {
+  int active;              // 0: an empty slot of a pool; every kernel returns at once
   int N, n, n_p, n_q, R, n_cub;
   int Cp, Cb, Cf;          // padded channel counts: forward, backward, output
   int Np;                  // N padded to NMR_WPAD
@@ -103,6 +104,16 @@ struct Inst {
   double* sum_mass;        // [R*R + R*n_q + R + n_p]
   double* Bq;              // [n_q][n_q] a . H, column j from perturbation j
   double* JTa;             // [n_q]
+  // Gram-folded Newton path (n_p == 0): with the linear output layer W_L and
+  // the constant lumped mass, Jt^T M Jt = F_J^T Gam F_J etc. over the folded
+  // activations F; only the DOFs of cubature tets are decoded per iteration
+  int gram;                // 1: this table entry runs the Gram path
+  int n_gblk;              // Gram partial blocks (K / 16)
+  const int* cdofs;        // [n_cdofs] sorted DOFs touched by cubature tets
+  int n_cdofs;
+  int n_sblk;              // sparse backprop blocks over cdofs (128 rows each)
+  const double* Gam;       // [K][K] W_L^T diag(m keep) W_L
+  const double* gam;       // [K]    W_L^T (keep * c), c_i = -dt^2 m_i g_(i mod 3)
   // weight net (optional)
   int wn_L;
   int wn_w[NMR_MAX_LAYERS + 1];
@@ -112,6 +123,32 @@ struct Inst {
   T* wn_buf;               // [2][max width]
   int wn_maxw;
 };
+
+// Every device buffer lives in global memory, but pointers read out of an
+// Inst table reach the compiler as generic (flat) pointers.  Flat accesses
+// also count against the LDS wait counter, so a kernel mixing them with LDS
+// work waits for both; these casts make the access a global one.
+#define NMR_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ inline const NMR_GLOBAL T* gp(const T* p) {
+  return (const NMR_GLOBAL T*)p;
+}
+template <typename T>
+__device__ inline NMR_GLOBAL T* gpw(T* p) {
+  return (NMR_GLOBAL T*)p;
+}
+
+// f_int[i] = sum of the weighted element forces at DOF i (fixed CSR order)
+template <typename T>
+__device__ inline double fint_at(const Inst<T>& I, int i) {
+  const int v = i / 3, c = i - 3 * v;
+  double f = 0.0;
+  for (int p = I.csr_ptr[v]; p < I.csr_ptr[v + 1]; ++p) {
+    const int ent = I.csr_ent[p];
+    f += (double)I.fe[(size_t)(ent >> 2) * 12 + 3 * (ent & 3) + c];
+  }
+  return f;
+}
 
 // ---- launchers (decoder.hip) -------------------------------------------
 template <typename T>
@@ -149,6 +186,11 @@ void launch_solve(const Inst<T>* tab, int nb, int iter, int mode, double* A_out,
                   hipStream_t s);
 template <typename T>
 void launch_fint(const Inst<T>* tab, T* f_int, int N, hipStream_t s);
+template <typename T>
+void launch_gram(const Inst<T>* tab, int nb, int max_gblk, int K, hipStream_t s);
+template <typename T>
+void launch_gram_setup(const void* W, int prec, int K, const T* mass, const T* keep, int N, double dt,
+                       const double* g, double* Gam, double* gam, hipStream_t s);
 
 // solve modes
 enum { SOLVE_UPDATE = 1, SOLVE_FINISH = 2, SOLVE_WRITE_SYSTEM = 4 };

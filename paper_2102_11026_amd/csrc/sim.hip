@@ -107,6 +107,7 @@ __device__ inline double dot_unrolled(const T* __restrict__ w, const double* __r
 template <typename T>
 __global__ __launch_bounds__(256) void k_step_begin(const Inst<T>* __restrict__ tab, int mode) {
   const Inst<T>& I = tab[blockIdx.y];
+  if (!I.active) return;
   const int R = I.R, np = I.n_p, nq = I.n_q;
   if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < nq; k += 256) {
@@ -164,6 +165,7 @@ template void launch_step_begin<double>(const Inst<double>*, int, int, int, hipS
 template <typename T>
 __global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
+  if (!I.active) return;
   if ((int)blockIdx.x >= I.n_cblk) return;
   const int R = I.R;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -300,17 +302,6 @@ void launch_cubature(const Inst<T>* tab, int nb, int max_cblk, hipStream_t s) {
 template void launch_cubature<float>(const Inst<float>*, int, int, hipStream_t);
 template void launch_cubature<double>(const Inst<double>*, int, int, hipStream_t);
 
-// f_int[i] = sum of the weighted element forces at DOF i (fixed CSR order)
-template <typename T>
-__device__ inline double fint_at(const Inst<T>& I, int i) {
-  const int v = i / 3, c = i - 3 * v;
-  double f = 0.0;
-  for (int p = I.csr_ptr[v]; p < I.csr_ptr[v + 1]; ++p) {
-    const int ent = I.csr_ent[p];
-    f += (double)I.fe[(size_t)(ent >> 2) * 12 + 3 * (ent & 3) + c];
-  }
-  return f;
-}
 
 template <typename T>
 __global__ void k_fint(const Inst<T>* __restrict__ tab, T* f_int) {
@@ -345,6 +336,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 template <typename T>
 __global__ __launch_bounds__(256) void k_mass(const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
+  if (!I.active) return;
   if ((int)blockIdx.x >= I.n_mblk) return;
   const int R = I.R, np = I.n_p, nq = I.n_q, Cf = I.Cf, N = I.N;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -471,6 +463,7 @@ template void launch_mass<double>(const Inst<double>*, int, int, int, int, hipSt
 template <typename T>
 __global__ __launch_bounds__(256) void k_seed_from_a(const Inst<T>* __restrict__ tab, const T* a) {
   const Inst<T>& I = tab[blockIdx.y];
+  if (!I.active) return;
   if ((int)blockIdx.x >= I.n_mblk) return;
   const int R = I.R, np = I.n_p, nq = I.n_q;
   __shared__ double ss[MASS_ROWS];
@@ -505,6 +498,150 @@ void launch_seed_from_a(const Inst<T>* tab, const T* a, int nb, int max_mblk, hi
 template void launch_seed_from_a<float>(const Inst<float>*, const float*, int, int, hipStream_t);
 template void launch_seed_from_a<double>(const Inst<double>*, const double*, int, int, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Gram path of the mass terms (n_p = 0).  The output layer is linear and the
+// lumped mass constant, so with the folded last-hidden activations F (columns
+// F_J = J e_j, F_dJ, F_Hdd before W_L), y = F_J w_r + F_Hdd,
+// Gam = W_L^T diag(m keep) W_L and gam = W_L^T (keep c), c_i = -dt^2 m_i g_c:
+//   Jt^T M Jt = F_J^T Gam F_J,  Jt^T M dJ = F_J^T Gam F_dJ,
+//   phim = F_J^T (Gam y + gam),  and the backprop seed W_L^T P a equals
+//   Gam y + gam + dt^2 W_L^T P f_int  (the last term over cubature DOFs only).
+// Each block takes 16 rows of Gam: T = Gam[rows] X with X = [F_J, F_dJ, y] on
+// the FP64 matrix cores (4 waves split K), then one mass partial
+// F_J[rows]^T T and its 16 entries of Gam y + gam as a backprop partial.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_gram(const Inst<T>* __restrict__ tab, int K) {
+  const Inst<T>& I = tab[blockIdx.y];
+  if (!I.active) return;
+  if (!I.gram || (int)blockIdx.x >= I.n_gblk) return;
+  const int nq = I.n_q, R = I.R;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, kk = lane >> 4;
+  const int row0 = blockIdx.x * 16;
+  const T* F = I.fold;  // [Cf][K]
+  __shared__ double wr[NMR_MAX_R];
+  __shared__ double y[256];
+  __shared__ double tile[16][4 * 16];
+  const double dt = I.dt;
+  if (threadIdx.x < R) wr[threadIdx.x] = I.r[threadIdx.x] - I.rbar[threadIdx.x] - dt * I.rdot[threadIdx.x];
+  __syncthreads();
+  for (int k = threadIdx.x; k < K; k += 256) {
+    double v = (double)F[(size_t)(1 + 2 * nq) * K + k];
+    for (int j = 0; j < nq; ++j) v += (double)F[(size_t)(1 + j) * K + k] * wr[j];
+    y[k] = v;
+  }
+  __syncthreads();
+  const int nx = 2 * nq + 1;  // X columns: F_J, F_dJ, y
+  const int ncb = (nx + 15) / 16;
+  f64x4 acc[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) acc[cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const double* G = I.Gam + (size_t)(row0 + col) * K;
+  const int kper = K / 4;  // each wave a quarter of K (K is a multiple of 32)
+  for (int k0 = wave * kper; k0 < (wave + 1) * kper; k0 += 4) {
+    const int k = k0 + kk;
+    const double a = G[k];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      if (cb < ncb) {
+        const int n = cb * 16 + col;
+        const double b = n < 2 * nq ? (double)F[(size_t)(1 + n) * K + k] : (n == 2 * nq ? y[k] : 0.0);
+        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
+      }
+    }
+  }
+  // wave partial tiles added in wave order (f64 result rows interleaved)
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+        if (cb < ncb)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int rr = 4 * q + kk, cc = cb * 16 + col;
+            tile[rr][cc] = (w == 0 ? 0.0 : tile[rr][cc]) + acc[cb][q];
+          }
+    }
+    __syncthreads();
+  }
+  // T_y + gam for these rows: the backprop partial after the sparse blocks
+  if (threadIdx.x < 16) {
+    const double zb = tile[threadIdx.x][2 * nq] + I.gam[row0 + threadIdx.x];
+    tile[threadIdx.x][2 * nq] = zb;
+    I.part_bwd[(size_t)I.n_sblk * K + row0 + threadIdx.x] = zb;
+  }
+  __syncthreads();
+  // mass partial F_J[rows]^T T in the layout of the direct path
+  const int E = R * R + R * nq + R;
+  double* out = I.part_mass + (size_t)blockIdx.x * E;
+  for (int e = threadIdx.x; e < E; e += 256) {
+    int i, c;
+    if (e < R * R) {
+      i = e / R;
+      c = e % R;
+    } else if (e < R * R + R * nq) {
+      i = (e - R * R) / nq;
+      c = nq + (e - R * R) % nq;
+    } else {
+      i = e - R * R - R * nq;
+      c = 2 * nq;
+    }
+    double v = 0.0;
+    for (int r = 0; r < 16; ++r) v += (double)F[(size_t)(1 + i) * K + row0 + r] * tile[r][c];
+    out[e] = v;
+  }
+}
+
+template <typename T>
+void launch_gram(const Inst<T>* tab, int nb, int max_gblk, int K, hipStream_t s) {
+  k_gram<T><<<dim3(max_gblk, nb), 256, 0, s>>>(tab, K);
+}
+template void launch_gram<float>(const Inst<float>*, int, int, int, hipStream_t);
+template void launch_gram<double>(const Inst<double>*, int, int, int, hipStream_t);
+
+// setup: Gam = W_L^T diag(m keep) W_L over the N rows of this instance and
+// gam = W_L^T (keep c); one thread per entry, rows in order
+template <typename TW>
+__device__ inline double wload(const TW* p) { return (double)(float)*p; }
+template <>
+__device__ inline double wload<double>(const double* p) { return *p; }
+
+template <typename T, typename TW>
+__global__ __launch_bounds__(256) void k_gram_setup(const TW* __restrict__ W, int K, const T* mass, const T* keep,
+                                                    int N, double dt, double g0, double g1, double g2, double* Gam,
+                                                    double* gam) {
+  const int k = blockIdx.x * 16 + (threadIdx.x & 15);
+  const int l = blockIdx.y * 16 + (threadIdx.x >> 4);
+  double acc = 0.0;
+  if (blockIdx.y < (unsigned)(K / 16)) {
+    for (int i = 0; i < N; ++i)
+      acc += wload(W + (size_t)i * K + k) * wload(W + (size_t)i * K + l) * (double)mass[i] * (double)keep[i];
+    Gam[(size_t)k * K + l] = acc;
+  } else if (threadIdx.x < 16) {
+    const double g[3] = {g0, g1, g2};
+    for (int i = 0; i < N; ++i)
+      acc += wload(W + (size_t)i * K + k) * (double)keep[i] * (-dt * dt * (double)mass[i] * g[i % 3]);
+    gam[k] = acc;
+  }
+}
+
+template <typename T>
+void launch_gram_setup(const void* W, int prec, int K, const T* mass, const T* keep, int N, double dt,
+                       const double* g, double* Gam, double* gam, hipStream_t s) {
+  dim3 grid(K / 16, K / 16 + 1);
+  if (prec == PREC_BF16)
+    k_gram_setup<T, __bf16><<<grid, 256, 0, s>>>((const __bf16*)W, K, mass, keep, N, dt, g[0], g[1], g[2], Gam, gam);
+  else if (prec == PREC_FP64)
+    k_gram_setup<T, double><<<grid, 256, 0, s>>>((const double*)W, K, mass, keep, N, dt, g[0], g[1], g[2], Gam, gam);
+  else
+    k_gram_setup<T, float><<<grid, 256, 0, s>>>((const float*)W, K, mass, keep, N, dt, g[0], g[1], g[2], Gam, gam);
+}
+template void launch_gram_setup<float>(const void*, int, int, const float*, const float*, int, double, const double*,
+                                       double*, double*, hipStream_t);
+template void launch_gram_setup<double>(const void*, int, int, const double*, const double*, int, double,
+                                        const double*, double*, double*, hipStream_t);
+
 
 // ---------------------------------------------------------------------------
 // Fixed-order sums of the cubature and mass partials.  Each block takes 16
@@ -514,6 +651,7 @@ template void launch_seed_from_a<double>(const Inst<double>*, const double*, int
 template <typename T>
 __global__ __launch_bounds__(256) void k_sums(const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
+  if (!I.active) return;
   const int R = I.R;
   const int Ec = R * R + R;
   const int Em = R * R + R * I.n_q + R + I.n_p;
@@ -527,8 +665,9 @@ __global__ __launch_bounds__(256) void k_sums(const Inst<T>* __restrict__ tab) {
     for (int b = sl; b < I.n_cblk; b += 16) acc += src[(size_t)b * Ec];
   } else if (e < Ec + Em) {
     const double* src = I.part_mass + (e - Ec);
+    const int nb = I.gram ? I.n_gblk : I.n_mblk;
 #pragma unroll 4
-    for (int b = sl; b < I.n_mblk; b += 16) acc += src[(size_t)b * Em];
+    for (int b = sl; b < nb; b += 16) acc += src[(size_t)b * Em];
   }
   part[sl][kk] = acc;
   __syncthreads();
@@ -550,170 +689,161 @@ template void launch_sums<double>(const Inst<double>*, int, int, hipStream_t);
 // ---------------------------------------------------------------------------
 // Assemble A = Jt^T M [U, J + dJ] + dt^2 Kr + diag(0, a . H) and
 // phi = phim + dt^2 fr (eq. system_mat with the sign differentiation gives),
-// record ||phi||, solve A delta = -phi by LU with partial pivoting and update
-// r += delta.  One wavefront; lane i keeps row i in registers.  Rows are not
-// moved: the pivot of column k is the largest |a_ik| among the rows not yet
-// used as pivots (ties to the lower index), which is partial pivoting with the
-// row exchanges kept as a permutation.  On the last iteration of a step:
-// rdot = (r - rbar)/dt, rbar = r.  A failed instance keeps its last good
-// (rbar, rdot).
+// record ||phi||, solve A delta = -phi and update r += delta.  On the last
+// iteration of a step: rdot = (r - rbar)/dt, rbar = r.  A failed instance
+// keeps its last good (rbar, rdot).
+//
+// The solve is Gauss-Jordan elimination with partial pivoting on the
+// augmented matrix [A | -phi], held in registers across one wavefront: lane
+// (g, c) = (lane / CW, lane % CW) owns column c (c == R is the right-hand
+// side) of rows g, g + G, g + 2G, ...  (G = 64 / CW).  Rows are not moved;
+// the pivot of column k is the row of largest |a_ik| among the rows not yet
+// pivots, compared on the top bits of |a_ik| (sign, exponent and 14 mantissa
+// bits) with ties to the lower row, so a chosen pivot is within a factor
+// 1 + 2^-14 of the largest.  The pivot row is divided by its pivot and
+// eliminated from every other row; after R steps the right-hand column of
+// pivot row p_k holds delta_k.  Every value is broadcast through the LDS
+// crossbar (ds_bpermute) or readlane: no LDS round trip or barrier per step.
 // ---------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
-}
 __device__ inline double readlane_f64(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
   return __hiloint2double(hi, lo);
 }
-__device__ inline double wave_max(double v) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
+__device__ inline double bperm_f64(double v, int src_lane) {
+  const int addr = src_lane << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+  return __hiloint2double(hi, lo);
 }
+__device__ inline unsigned abs_hi(double v) { return (unsigned)__double2hiint(v) & 0x7FFFFFFFu; }
 
-template <typename T>
-__global__ __launch_bounds__(64) void k_solve(const Inst<T>* __restrict__ tab, int iter, int mode, double* A_out,
-                                              double* phi_out) {
-  const Inst<T>& I = tab[blockIdx.y];
+template <typename T, int CW>
+__device__ inline void solve_body(const Inst<T>& I, int iter, int mode, double* A_out, double* phi_out) {
+  constexpr int G = 64 / CW, RPL = CW / G;
   const int R = I.R, np = I.n_p, nq = I.n_q, lane = threadIdx.x;
-  const double dt = I.dt;
-  __shared__ double A[NMR_MAX_R][NMR_MAX_R + 1];
-  __shared__ double b[NMR_MAX_R];
-  __shared__ double xs[NMR_MAX_R];
-  __shared__ int piv[NMR_MAX_R];
-  const double* G = I.sum_mass;
-  const double* E = G + R * R;
-  const double* phim = E + R * nq;
-  const double* Kr = I.sum_cub;
-  const double* fr = Kr + R * R;
+  const int g = lane / CW, c = lane % CW;
+  const double dt = I.dt, dt2 = dt * dt;
+  const auto* Gm = gp(I.sum_mass);
+  const auto* E = Gm + R * R;
+  const auto* phim = E + R * nq;
+  const auto* Kr = gp(I.sum_cub);
+  const auto* fr = Kr + R * R;
+  // Bq is n_q x n_q; with n_q = 0 any valid address stands in (never used)
+  const auto* Bq = nq > 0 ? gp(I.Bq) : Gm;
   const bool row = lane < R;
-  // every global load of the kernel is issued here, in one round trip
-  const int st0 = *I.status;
-  double r_l = 0.0, rbar_l = 0.0, rdot_l = 0.0, phi_l = 0.0;
-  if (row) {
-    r_l = I.r[lane];
-    rbar_l = I.rbar[lane];
-    rdot_l = I.rdot[lane];
-    phi_l = phim[lane] + dt * dt * fr[lane];
-  }
-  constexpr int NE = (NMR_MAX_R * NMR_MAX_R + 63) / 64;
-  double ent[NE];
+  // every global load of the kernel is issued here, unconditionally and from
+  // indices clamped into range, so that they are all in flight together
+  const int st0 = *gp(I.status);
+  const int lr = min(lane, R - 1);
+  const double r_l = row ? gp(I.r)[lr] : 0.0;
+  const double rbar_l = row ? gp(I.rbar)[lr] : 0.0;
+  const double rdot_l = row ? gp(I.rdot)[lr] : 0.0;
+  const int cc = min(c, R - 1), cq = max(cc - np, 0);
+  double a[RPL];
 #pragma unroll
-  for (int t = 0; t < NE; ++t) {
-    const int p = lane + 64 * t;
-    double v = 0.0;
-    if (p < R * R) {
-      const int k = p / R, j = p - k * R;
-      v = G[p] + dt * dt * Kr[p];
-      if (j >= np) v += E[k * nq + (j - np)];
-      if (k >= np && j >= np) v += I.Bq[(k - np) * nq + (j - np)];
-    }
-    ent[t] = v;
+  for (int m = 0; m < RPL; ++m) {
+    const int i = g + G * m;
+    const int ii = min(i, R - 1), iq = max(ii - np, 0);
+    const double gk = Gm[ii * R + cc] + dt2 * Kr[ii * R + cc];
+    const double e = E[ii * nq + cq];
+    const double bq = Bq[nq > 0 ? iq * nq + cq : 0];
+    const double ph = phim[ii] + dt2 * fr[ii];
+    double v = gk;
+    if (c >= np) v += e;
+    if (ii >= np && c >= np) v += bq;
+    a[m] = i >= R ? 0.0 : c < R ? v : c == R ? -ph : 0.0;
   }
+  bool fin = true;
+  unsigned hmax = 0;
+  double ss = 0.0;
 #pragma unroll
-  for (int t = 0; t < NE; ++t) {
-    const int p = lane + 64 * t;
-    if (p < R * R) A[p / R][p % R] = ent[t];
+  for (int m = 0; m < RPL; ++m) {
+    fin = fin && isfinite(a[m]);
+    if (c < R) hmax = max(hmax, abs_hi(a[m]));
+    ss = fma(a[m], a[m], ss);  // nonzero only in the right-hand column
   }
-  if (row) b[lane] = phi_l;
-  __syncthreads();
-  double bb = row ? b[lane] : 0.0;
-  bool finite = isfinite(bb);
-  double amax = 0.0;
-  if (row)
-    for (int j = 0; j < R; ++j) {
-      finite = finite && isfinite(A[lane][j]);
-      amax = fmax(amax, fabs(A[lane][j]));
-    }
-  const double nrm2 = wave_sum(bb * bb);
-  amax = wave_max(amax);
-  const bool all_finite = __all(finite);
+  double nrm2 = 0.0;
+#pragma unroll
+  for (int gg = 0; gg < G; ++gg) nrm2 += readlane_f64(ss, gg * CW + R);
+  for (int off = 32; off > 0; off >>= 1) hmax = max(hmax, (unsigned)__shfl_xor((int)hmax, off));
+  const double amax = __hiloint2double((int)hmax, 0);
+  const bool all_finite = __all(fin);
   int st = st0;
   if (!all_finite && st == 0) st = ST_NONFINITE;
   if (lane == 0) {
-    I.resid[iter] = sqrt(nrm2);
+    gpw(I.resid)[iter] = sqrt(nrm2);
     if (st != st0) atomicOr(I.status, st);
   }
   if (mode & SOLVE_WRITE_SYSTEM) {
-    for (int p = lane; p < R * R; p += 64) A_out[p] = A[p / R][p % R];
-    if (row) phi_out[lane] = bb;
-  }
-  if (!(mode & SOLVE_UPDATE) || st != 0) return;
-  // LU with partial pivoting in registers: lane i holds row i; the pivot row
-  // is broadcast with readlane, the pivot search is one LDS exchange.
-  double a[NMR_MAX_R];
 #pragma unroll
-  for (int j = 0; j < NMR_MAX_R; ++j) a[j] = (row && j < R) ? A[lane][j] : 0.0;
-  double bl = -bb;
-  bool used = !row;
-  bool singular = false;
-  __shared__ double colk[64];
-  for (int k = 0; k < R; ++k) {
-    double ak = 0.0;
-#pragma unroll
-    for (int j = 0; j < NMR_MAX_R; ++j) ak = (j == k) ? a[j] : ak;
-    colk[lane] = used ? -1.0 : fabs(ak);
-    __syncthreads();
-    double best = -1.0;
-    int p = 0;
-    for (int i = 0; i < R; ++i) {
-      const double v = colk[i];
-      if (v > best) {
-        best = v;
-        p = i;
+    for (int m = 0; m < RPL; ++m) {
+      const int i = g + G * m;
+      if (i < R) {
+        if (c < R) gpw(A_out)[i * R + c] = a[m];
+        else if (c == R) gpw(phi_out)[i] = -a[m];
       }
     }
-    p = __builtin_amdgcn_readfirstlane(p);
-    if (!(best > 1e-300 * amax)) singular = true;
-    if (lane == 0) piv[k] = p;
-    if (lane == p) used = true;
-    const double pk = readlane_f64(ak, p);
-    const double f = used ? 0.0 : ak / pk;
+  }
+  if (!(mode & SOLVE_UPDATE) || st != 0) return;
+
+  __shared__ int piv[NMR_MAX_R];
+  __shared__ double xcol[NMR_MAX_R];
+  unsigned used = 0;  // bit i: row i has been a pivot (uniform)
+  bool singular = false;
+  for (int k = 0; k < R; ++k) {
+    // column k of this lane's rows (independent of the pivot: issued first)
+    double f[RPL];
 #pragma unroll
-    for (int j = 0; j < NMR_MAX_R; ++j) {
-      const double pj = readlane_f64(a[j], p);
-      a[j] = (j > k) ? fma(-f, pj, a[j]) : a[j];
+    for (int m = 0; m < RPL; ++m) f[m] = bperm_f64(a[m], g * CW + k);
+    unsigned key = 0;
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) {
+      const int i = g + G * m;
+      const unsigned kv = (abs_hi(a[m]) & ~63u) | (unsigned)(63 - i);
+      key = (i < R && !((used >> i) & 1u)) ? max(key, kv) : key;
     }
-    bl = fma(-f, readlane_f64(bl, p), bl);
-    __syncthreads();
+    unsigned best = 0;
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) best = max(best, (unsigned)__builtin_amdgcn_readlane((int)key, gg * CW + k));
+    const int p = 63 - (int)(best & 63u);  // best >= 32: some row < R is unused
+    const int mp = p / G, src = (p % G) * CW;
+    double sel = a[0];
+#pragma unroll
+    for (int m = 1; m < RPL; ++m) sel = (m == mp) ? a[m] : sel;
+    const double apk = readlane_f64(sel, src + k);
+    if (!(fabs(apk) > 1e-300 * amax)) {
+      singular = true;
+      break;
+    }
+    const double prn = bperm_f64(sel, src + c) / apk;  // pivot row, divided by its pivot
+#pragma unroll
+    for (int m = 0; m < RPL; ++m) a[m] = (g + G * m == p) ? prn : fma(-f[m], prn, a[m]);
+    used |= 1u << p;
+    if (lane == 0) piv[k] = p;
   }
   if (singular) {
     if (lane == 0) atomicOr(I.status, ST_SINGULAR);
     return;
   }
-  // back substitution in pivot order: the pivot row of step k holds U_kj, j >= k
-  double x[NMR_MAX_R];
+  if (c == R) {
 #pragma unroll
-  for (int j = 0; j < NMR_MAX_R; ++j) x[j] = 0.0;
-  for (int k = R - 1; k >= 0; --k) {
-    const int p = __builtin_amdgcn_readfirstlane(piv[k]);
-    double acc = bl, akk = 1.0;
-#pragma unroll
-    for (int j = 0; j < NMR_MAX_R; ++j) {
-      acc = (j > k) ? fma(-a[j], x[j], acc) : acc;
-      akk = (j == k) ? a[j] : akk;
-    }
-    const double xk = readlane_f64(acc / akk, p);
-#pragma unroll
-    for (int j = 0; j < NMR_MAX_R; ++j) x[j] = (j == k) ? xk : x[j];
+    for (int m = 0; m < RPL; ++m)
+      if (g + G * m < R) xcol[g + G * m] = a[m];
   }
-  double xl = 0.0;
-#pragma unroll
-  for (int j = 0; j < NMR_MAX_R; ++j) xl = (j == lane) ? x[j] : xl;
-  if (row) xs[lane] = xl;
+  __syncthreads();
   // new state from registers; the decoder input of the next iteration is
   // taken from the lanes of the q block (exchange through LDS)
-  const double rn = r_l + (row ? xs[lane] : 0.0);
-  const bool fin = mode & SOLVE_FINISH;
-  const double rbar_n = fin ? rn : rbar_l;
-  const double rdot_n = fin ? (rn - rbar_l) / dt : rdot_l;
+  const double rn = r_l + (row ? xcol[piv[lane]] : 0.0);
+  const bool fin_step = mode & SOLVE_FINISH;
+  const double rbar_n = fin_step ? rn : rbar_l;
+  const double rdot_n = fin_step ? (rn - rbar_l) / dt : rdot_l;
   __shared__ double sq[3][NMR_MAX_R];
   if (row) {
-    I.r[lane] = rn;
-    if (fin) {
-      I.rdot[lane] = rdot_n;
-      I.rbar[lane] = rbar_n;
+    gpw(I.r)[lane] = rn;
+    if (fin_step) {
+      gpw(I.rdot)[lane] = rdot_n;
+      gpw(I.rbar)[lane] = rbar_n;
     }
     if (lane >= np) {
       sq[0][lane - np] = rn;
@@ -723,10 +853,20 @@ __global__ __launch_bounds__(64) void k_solve(const Inst<T>* __restrict__ tab, i
   }
   __syncthreads();
   if (lane < nq) {
-    I.dec_in[lane] = sq[0][lane];
-    I.dec_in[nq + lane] = sq[1][lane];
-    I.dec_in[2 * nq + lane] = sq[2][lane];
+    auto* din = gpw(I.dec_in);
+    din[lane] = sq[0][lane];
+    din[nq + lane] = sq[1][lane];
+    din[2 * nq + lane] = sq[2][lane];
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_solve(const Inst<T>* __restrict__ tab, int iter, int mode, double* A_out,
+                                              double* phi_out) {
+  const Inst<T>& I = tab[blockIdx.y];
+  if (!I.active) return;
+  if (I.R < 16) solve_body<T, 16>(I, iter, mode, A_out, phi_out);
+  else solve_body<T, 32>(I, iter, mode, A_out, phi_out);
 }
 
 template <typename T>

@@ -39,7 +39,7 @@ class ProblemDesc(C.Structure):
                 ("gravity", C.c_double * 3), ("dt", C.c_double), ("n_p", C.c_int), ("U", _dp),
                 ("decoder", C.POINTER(MlpDesc)), ("shared_decoder", C.c_void_p), ("n_cub", C.c_int),
                 ("cub_ids", C.POINTER(C.c_int32)), ("cub_w", _dp), ("wnet", C.POINTER(MlpDesc)),
-                ("wnet_scale", C.c_double), ("r0", _dp), ("rdot0", _dp)]
+                ("wnet_scale", C.c_double), ("r0", _dp), ("rdot0", _dp), ("newton_path", C.c_int)]
 
 
 class NmrError(RuntimeError):
@@ -68,6 +68,7 @@ def lib():
             "nmr_instance_create": (i, [vp, C.POINTER(ProblemDesc), i, C.POINTER(vp)]),
             "nmr_instance_destroy": (i, [vp]),
             "nmr_instance_bytes": (i, [vp, C.POINTER(C.c_size_t)]),
+            "nmr_instance_newton_path": (i, [vp, C.POINTER(C.c_int)]),
             "nmr_instance_get_state": (i, [vp, _dp, _dp, vp]),
             "nmr_instance_set_state": (i, [vp, _dp, _dp]),
             "nmr_instance_status": (i, [vp]),
@@ -77,6 +78,11 @@ def lib():
             "reduced_newton_step": (i, [vp, i, _dp]),
             "step_many": (i, [vp, C.POINTER(vp), i, i, i, ip, C.POINTER(C.c_float)]),
             "nmr_time_phase": (i, [vp, i, i, C.POINTER(C.c_float)]),
+            "nmr_pool_create": (i, [vp, i, C.POINTER(vp)]),
+            "nmr_pool_destroy": (i, [vp]),
+            "nmr_pool_attach": (i, [vp, vp, ip]),
+            "nmr_pool_detach": (i, [vp, i]),
+            "nmr_pool_step": (i, [vp, i, ip, C.POINTER(C.c_float)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -141,7 +147,8 @@ class Decoder:
 
 
 class Instance:
-    def __init__(self, ctx: Context, prob, prec: str = "fp32", shared: Optional[Decoder] = None):
+    def __init__(self, ctx: Context, prob, prec: str = "fp32", shared: Optional[Decoder] = None,
+                 path: str = "auto"):
         import torch
         self.ctx, self.prob, self.prec = ctx, prob, prec
         self.N, self.n_p, self.n_q, self.R = prob.N, prob.n_p, prob.n_q, prob.R
@@ -187,6 +194,7 @@ class Instance:
             d.wnet = C.pointer(wm.desc)
         d.wnet_scale = prob.wnet_scale
         d.r0, d.rdot0 = r0.ctypes.data_as(_dp), rd0.ctypes.data_as(_dp)
+        d.newton_path = {"auto": 0, "direct": 1}[path]
         h = C.c_void_p()
         _check(lib().nmr_instance_create(ctx.h, C.byref(d), PREC[prec], C.byref(h)))
         self.h = h
@@ -201,6 +209,13 @@ class Instance:
         b = C.c_size_t()
         _check(lib().nmr_instance_bytes(self.h, C.byref(b)))
         return b.value
+
+    @property
+    def gram(self) -> bool:
+        """True if the instance runs the Gram-folded Newton path."""
+        v = C.c_int()
+        _check(lib().nmr_instance_newton_path(self.h, C.byref(v)))
+        return v.value == 0
 
     # -- state ---------------------------------------------------------------
     def get_state(self, with_u: bool = False):
@@ -280,6 +295,34 @@ class Instance:
         _check(lib().reduced_newton_system(self.h, _ptr(rt), _ptr(A), _ptr(phi)))
         torch.cuda.synchronize(self.dev)
         return A, phi
+
+
+class Pool:
+    """Fixed-capacity slot pool stepped by one captured graph (served form)."""
+
+    def __init__(self, ctx: Context, capacity: int):
+        h = C.c_void_p()
+        _check(lib().nmr_pool_create(ctx.h, capacity, C.byref(h)))
+        self.h, self.ctx, self.capacity = h, ctx, capacity
+
+    def attach(self, inst: Instance) -> int:
+        s = C.c_int()
+        _check(lib().nmr_pool_attach(self.h, inst.h, C.byref(s)))
+        return s.value
+
+    def detach(self, slot: int):
+        _check(lib().nmr_pool_detach(self.h, slot))
+
+    def step(self, n_iters: int, status: bool = False, timing: bool = True):
+        st = (C.c_int * self.capacity)() if status else None
+        ms = C.c_float() if timing else None
+        _check(lib().nmr_pool_step(self.h, n_iters, st, C.byref(ms) if timing else None))
+        return (list(st) if status else None), (ms.value if timing else None)
+
+    def close(self):
+        if self.h:
+            _check(lib().nmr_pool_destroy(self.h))
+            self.h = None
 
 
 def step_many(ctx: Context, insts: Sequence[Instance], n_steps: int, n_iters: int, timings: bool = True):

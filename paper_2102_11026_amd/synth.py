@@ -283,6 +283,93 @@ def config_single_10k(instance: int = 0) -> Problem:
                        steps=100, newton_iters=4, instance=instance)
 
 
+SERVE_A_WIDTHS = [5, 64, 128, 256, 256, 128, 6000]
+SERVE_C_WIDTHS = [30, 64, 128, 256, 512, 1024, 1024, 1024, 1024, 1024, 512, 256, 150000]
+
+
+def config_serve_a(instance: int = 0) -> Problem:
+    """Serving class A: 2,000-vertex bar (10 x 10 x 20), r = 5, depth-6 ELU
+    decoder, full quadrature (7,695 tets), 120 steps x 4 iterations."""
+    return bar_problem("serveA_2k_r5", (10, 10, 20), SERVE_A_WIDTHS, "elu", steps=120, newton_iters=4,
+                       instance=instance, stream_prefix="serveA/")
+
+
+def config_serve_b(instance: int = 0) -> Problem:
+    """Serving class B: the 10,000-vertex, r = 15 problem, 120 steps."""
+    return config_single_10k(instance).replace(steps=120)
+
+
+def config_serve_c(instance: int = 0) -> Problem:
+    """Serving class C: 50,000-vertex bar (20 x 20 x 125, 223,820 tets),
+    r = 30, depth-12 ELU decoder with widths up to 1024, 6,600 cubature tets
+    weighted by a 30 -> 64 -> 64 -> 6600 weight net, 120 steps x 4 iterations."""
+    return bar_problem("serveC_50k_r30", (20, 20, 125), SERVE_C_WIDTHS, "elu", n_cub=6600, steps=120,
+                       newton_iters=4, instance=instance, stream_prefix="serveC/")
+
+
+def fibonacci_sphere(n: int) -> np.ndarray:
+    """n nearly uniform unit vectors (golden-angle spiral)."""
+    k = np.arange(n) + 0.5
+    z = 1.0 - 2.0 * k / n
+    rad = np.sqrt(1.0 - z * z)
+    phi = np.pi * (3.0 - np.sqrt(5.0)) * k
+    return np.stack([rad * np.cos(phi), rad * np.sin(phi), z], axis=1)
+
+
+ROD_LENGTHS = (20, 30, 40, 60)
+ROD_WIDTHS = [5, 32, 64, 128, 720]
+
+
+ROD_OUT_SCALE = 0.25
+
+
+def rod_decoder(seed: int = MASTER_SEED, out_scale: float = ROD_OUT_SCALE):
+    """Shared rod decoder: tanh trunk 5 -> 32 -> 64 -> 128 and one 720 x 128
+    head; a rod of length L uses the first 12 L output rows.  The head is
+    scaled by out_scale: at 1 the random decoder inverts tets of most rods in
+    their initial configuration (one element across the rod), at 1/4 every
+    rod starts with det F > 0.35 and none inverts over its 60 steps."""
+    Ws, bs = xavier_mlp(ROD_WIDTHS, "rods/dec", seed)
+    Ws[-1] = Ws[-1] * out_scale
+    return Ws, bs
+
+
+def rod_problem(i: int, n_rods: int = 320, decoder=None, seed: int = MASTER_SEED) -> Problem:
+    """Rod i of a puffer-ball-like set: a 2 x 2 x L vertex grid (L drawn from
+    {20, 30, 40, 60}) along the i-th direction of a Fibonacci sphere, its root
+    face centred at 0.5 m on that direction and pinned; n_p = 10 linear basis
+    of its own, n_q = 5 shared tanh decoder, full quadrature."""
+    L = int(np.asarray(ROD_LENGTHS)[raw64("rods/len", n_rods, seed)[i] % np.uint64(len(ROD_LENGTHS))])
+    X0, tets = grid_mesh(2, 2, L)
+    d = fibonacci_sphere(n_rods)[i]
+    ref = np.array([0.0, 0.0, 1.0]) if abs(d[2]) < 0.9 else np.array([1.0, 0.0, 0.0])
+    e1 = ref - d * (ref @ d)
+    e1 /= np.linalg.norm(e1)
+    e2 = np.cross(d, e1)
+    # local (x, y, z) = (across 1, across 2, along the rod), right-handed frame
+    X = 0.5 * d + (X0[:, 0:1] - 0.05) * e1 + (X0[:, 1:2] - 0.05) * e2 + X0[:, 2:3] * d
+    n = X.shape[0]
+    N = 3 * n
+    pinned = np.zeros(n, dtype=np.uint8)
+    pinned[:4] = 1
+    Ws, bs = decoder if decoder is not None else rod_decoder(seed)
+    U = random_orthonormal(N, 10, np.repeat(pinned, 3), f"rods/U/{i}", seed)
+    R = 10 + 5
+    r0 = np.zeros(R)
+    r0[10:] = 0.1 * normal(f"rods/q0/{i}", 5, seed)
+    m = tets.shape[0]
+    return Problem(name=f"rod{i}_L{L}", X=X, tets=tets, pinned=pinned, gravity=GRAVITY.copy(), dt=DT, U=U,
+                   weights=Ws, biases=bs, act="tanh", cub_ids=np.arange(m, dtype=np.int32), cub_w=np.ones(m),
+                   r0=r0, rdot0=np.zeros(R), steps=60, newton_iters=3, out_rows=ROD_WIDTHS[-1],
+                   meta=dict(L=L, rod=i), **MATERIAL)
+
+
+def config_rods(n_rods: int = 320):
+    """All rods of the batched workload, sharing one decoder."""
+    dec = rod_decoder()
+    return [rod_problem(i, n_rods, dec) for i in range(n_rods)]
+
+
 def tiny_problem(grid=(2, 2, 3), widths=(2, 4, 4, 36), act="tanh", n_p=0, n_cub=0,
                  q_std=0.1, name="tiny", instance=0, out_scale=1.0) -> Problem:
     return bar_problem(name, grid, list(widths), act, n_p=n_p, n_cub=n_cub, q_std=q_std,

@@ -1,0 +1,293 @@
+"""GPU tests of the headline workload, the precision form, determinism, the
+batched form and failure handling (all through the C ABI)."""
+import numpy as np
+import pytest
+
+from oracle.newton import Instance as OInst
+from paper_2102_11026_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def nmr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2102_11026_amd import nmr as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(nmr):
+    c = nmr.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def big():
+    p = synth.config_single_10k()
+    return p, OInst(p)
+
+
+# ---------------------------------------------------------------------------
+# headline workload at full size
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec,tol", [("fp32", dict(u=1e-5, J=1e-4, dJ=1e-3, Hdd=1e-3, B=1e-3, JTa=1e-4)),
+                                      ("bf16", dict(u=3e-2, J=3e-2, dJ=1e-1, Hdd=1e-1, B=1e-1, JTa=3e-2))])
+def test_headline_decoder_full_size(nmr, ctx, big, prec, tol):
+    p, oi = big
+    rng = np.random.default_rng(0)
+    q = p.r0 + rng.normal(size=p.n_q) * 0.01
+    dq = rng.normal(size=p.n_q) * 0.01
+    qdot = rng.normal(size=p.n_q) * 0.3
+    a = rng.normal(size=p.N)
+    inst = nmr.Instance(ctx, p, prec)
+    try:
+        got = inst.decoder_jacobian_hessian(q, dq, qdot, a)
+    finally:
+        inst.close()
+    ref = oi.decode(q, dq, qdot)
+    JTa, B = oi.left(q, a)
+    errs = dict(u=rel(got["u"].cpu(), ref["m"]), J=rel(got["J"].cpu(), ref["J"]), dJ=rel(got["dJ"].cpu(), ref["dJ"]),
+                Hdd=rel(got["Hdd"].cpu(), ref["Hdd"]), B=rel(got["B"].cpu(), B), JTa=rel(got["JTa"].cpu(), JTa))
+    print(prec, errs)
+    for k, v in errs.items():
+        assert v < tol[k], (k, v)
+
+
+def test_headline_first_step_fp32(nmr, ctx, big):
+    """One implicit-Euler step (4 Newton iterations) of the 10k-vertex bar."""
+    p, oi = big
+    inst = nmr.Instance(ctx, p, "fp32")
+    try:
+        norms = inst.step(p.newton_iters)
+        r, rdot = inst.get_state()
+    finally:
+        inst.close()
+    st, onorms = oi.step(oi.initial_state(), p.newton_iters)
+    print("r rel err", rel(r, st.rbar), "norms", norms, onorms)
+    assert rel(r, st.rbar) < 1e-4
+    np.testing.assert_allclose(norms, onorms, rtol=2e-3, atol=1e-4 * onorms[0])
+
+
+def test_headline_newton_system_precision_report(nmr, ctx, big):
+    """phi and A at the same iterate: FP32 and BF16 errors against the FP64
+    oracle, phi normalised by ||phi|| at the start of the step."""
+    p, oi = big
+    rng = np.random.default_rng(3)
+    r = p.r0 + rng.normal(size=p.R) * 0.005
+    sysd = oi.system(r, p.r0, p.rdot0, oi.cubature_weights(p.r0))
+    phi0 = np.linalg.norm(oi.system(p.r0, p.r0, p.rdot0, oi.cubature_weights(p.r0))["phi"])
+    out = {}
+    for prec in ("fp32", "bf16"):
+        inst = nmr.Instance(ctx, p, prec)
+        try:
+            A, phi = inst.newton_system(r)
+        finally:
+            inst.close()
+        out[prec] = (np.linalg.norm(phi.cpu().numpy() - sysd["phi"]) / phi0, rel(A.cpu(), sysd["A"]))
+    print(out)
+    assert out["fp32"][0] < 1e-4 and out["fp32"][1] < 1e-4
+    assert out["bf16"][0] < 3e-2 and out["bf16"][1] < 3e-2
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 1e-5)])
+def test_gram_path_equals_direct_path(nmr, ctx, prec, tol):
+    """The Gram-folded mass terms (only cubature DOFs decoded) and the direct
+    path (every DOF decoded) give the same Newton system and trajectory."""
+    p = synth.config_plain_fp64() if prec == "fp64" else synth.config_single_10k()
+    rng = np.random.default_rng(4)
+    r = p.r0 + rng.normal(size=p.R) * 0.005
+    out = {}
+    for path in ("auto", "direct"):
+        inst = nmr.Instance(ctx, p, prec, path=path)
+        try:
+            assert inst.gram == (path == "auto")
+            A, phi = inst.newton_system(r)
+            norms = inst.step(p.newton_iters)
+            out[path] = (A.cpu().numpy(), phi.cpu().numpy(), inst.get_state()[0], norms)
+        finally:
+            inst.close()
+    a, d = out["auto"], out["direct"]
+    assert rel(a[0], d[0]) < tol and rel(a[1], d[1]) < tol
+    assert rel(a[2], d[2]) < 10 * tol
+    np.testing.assert_allclose(a[3], d[3], rtol=10 * tol, atol=1e-9 * d[3][0])
+
+
+# ---------------------------------------------------------------------------
+# determinism, checkpoint, batching
+# ---------------------------------------------------------------------------
+def tiny(k=0, **kw):
+    base = dict(grid=(3, 3, 6), widths=(4, 32, 48, 162), act="tanh", name="batch", q_std=0.3, out_scale=0.1)
+    base.update(kw)
+    return synth.tiny_problem(instance=k, **base)
+
+
+def test_bitwise_determinism(nmr, ctx):
+    p = synth.config_plain_fp64()
+    rs = []
+    for _ in range(2):
+        inst = nmr.Instance(ctx, p, "fp32")
+        try:
+            for _ in range(5):
+                inst.step(3, resid=False)
+            rs.append(inst.get_state(with_u=True))
+        finally:
+            inst.close()
+    for a, b in zip(rs[0], rs[1]):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_checkpoint_restore_continuation(nmr, ctx):
+    p = synth.config_plain_fp64()
+    a = nmr.Instance(ctx, p, "fp64")
+    b = nmr.Instance(ctx, p, "fp64")
+    try:
+        for _ in range(10):
+            a.step(3, resid=False)
+        for _ in range(5):
+            b.step(3, resid=False)
+        r, rd = b.get_state()
+        b.close()
+        b = nmr.Instance(ctx, p, "fp64")
+        b.set_state(r, rd)
+        for _ in range(5):
+            b.step(3, resid=False)
+        ra, rda = a.get_state()
+        rb, rdb = b.get_state()
+        np.testing.assert_array_equal(ra, rb)
+        np.testing.assert_array_equal(rda, rdb)
+    finally:
+        a.close()
+        b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batched_equals_alone(nmr, ctx, prec):
+    """Instances sharing a decoder stepped together give the same state as
+    each stepped alone (fixed-order reductions: bitwise)."""
+    base = tiny()
+    dec = nmr.Decoder(ctx, base.weights, base.biases, base.act, prec)
+    probs = []
+    for k in range(5):
+        r0 = np.zeros(base.R)
+        r0[base.n_p:] = 0.3 * synth.normal(f"batch/q0/{k}", base.n_q)
+        probs.append(base.replace(r0=r0))
+    together = [nmr.Instance(ctx, q, prec, shared=dec) for q in probs]
+    alone = [nmr.Instance(ctx, q, prec, shared=dec) for q in probs]
+    try:
+        st, ms = nmr.step_many(ctx, together, 6, 3)
+        assert st == [0] * 5 and len(ms) == 6
+        for x in alone:
+            st1, _ = nmr.step_many(ctx, [x], 6, 3)
+            assert st1 == [0]
+        for x, y in zip(together, alone):
+            rx, rdx = x.get_state()
+            ry, rdy = y.get_state()
+            np.testing.assert_array_equal(rx, ry)
+            np.testing.assert_array_equal(rdx, rdy)
+        # and a single-instance step through reduced_newton_step agrees too
+        z = nmr.Instance(ctx, probs[2], prec, shared=dec)
+        for _ in range(6):
+            z.step(3, resid=False)
+        np.testing.assert_array_equal(z.get_state()[0], together[2].get_state()[0])
+        z.close()
+    finally:
+        for x in together + alone:
+            x.close()
+        dec.close()
+
+
+def test_batched_ragged_instances(nmr, ctx):
+    """Instances of different sizes and decoders in one step_many, each
+    against the oracle."""
+    probs = [tiny(0), tiny(1, grid=(2, 3, 5), widths=(3, 32, 90)),
+             synth.tiny_problem(grid=(3, 4, 4), widths=(5, 40, 144), act="elu", n_p=2, name="rag3", q_std=0.2,
+                                out_scale=0.1)]
+    insts = [nmr.Instance(ctx, q, "fp64") for q in probs]
+    try:
+        st, _ = nmr.step_many(ctx, insts, 3, 3)
+        assert st == [0, 0, 0]
+        for x, q in zip(insts, probs):
+            oi = OInst(q)
+            s = oi.initial_state()
+            for _ in range(3):
+                s, _ = oi.step(s, 3)
+            assert rel(x.get_state()[0], s.rbar) < 1e-9
+    finally:
+        for x in insts:
+            x.close()
+
+
+# ---------------------------------------------------------------------------
+# failures: each forced from the host, every kernel still exits normally
+# ---------------------------------------------------------------------------
+def test_inverted_tet_freezes_instance_only(nmr, ctx):
+    good = tiny(0)
+    bad = tiny(1, out_scale=30.0, q_std=1.0)  # displacements far beyond the element size
+    gi, bi = nmr.Instance(ctx, good, "fp32"), nmr.Instance(ctx, bad, "fp32")
+    try:
+        st, _ = nmr.step_many(ctx, [gi, bi], 2, 3)
+        assert st[0] == 0
+        assert nmr.STATUS[st[1]] == "inverted"
+        r, rd = bi.get_state()
+        np.testing.assert_array_equal(r, bad.r0)  # frozen at its last good state
+        oi = OInst(good)
+        s = oi.initial_state()
+        for _ in range(2):
+            s, _ = oi.step(s, 3)
+        assert rel(gi.get_state()[0], s.rbar) < 1e-4
+        with pytest.raises(nmr.NmrError):
+            bi.step(3)
+    finally:
+        gi.close()
+        bi.close()
+
+
+def test_singular_system_is_reported(nmr, ctx):
+    p = tiny(0, widths=(2, 32, 48, 162))
+    W0 = p.weights[0].copy()
+    W0[:, 1] = W0[:, 0]
+    r0 = p.r0.copy()
+    r0[1] = r0[0]
+    q = p.replace(weights=[W0] + p.weights[1:], r0=r0)
+    inst = nmr.Instance(ctx, q, "fp64")
+    try:
+        with pytest.raises(nmr.NmrError) as e:
+            inst.step(2)
+        assert nmr.STATUS[e.value.code] == "singular"
+        np.testing.assert_array_equal(inst.get_state()[0], r0)
+    finally:
+        inst.close()
+
+
+def test_nonfinite_is_reported(nmr, ctx):
+    p = tiny(0)
+    W = [w.copy() for w in p.weights]
+    W[1][3, 5] = np.nan
+    inst = nmr.Instance(ctx, p.replace(weights=W), "fp32")
+    try:
+        with pytest.raises(nmr.NmrError) as e:
+            inst.step(2)
+        assert nmr.STATUS[e.value.code] in ("nonfinite", "inverted")
+    finally:
+        inst.close()
+
+
+def test_budget_admission(nmr):
+    c = nmr.Context(0, budget_bytes=1 << 16)
+    try:
+        with pytest.raises(nmr.NmrError) as e:
+            nmr.Instance(c, tiny(0), "fp32")
+        assert nmr.STATUS[e.value.code] == "budget"
+    finally:
+        c.close()
