@@ -753,7 +753,7 @@ static void enqueue_iteration(const Group& g, int iter, int mode, double* A_out,
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
   enqueue_decoder_fwd<T>(g, s, 1);
   launch_cubature<T>(tab, g.nb, g.max_cblk, s);
-  if (g.gram) launch_gram<T>(tab, g.nb, g.n_gblk, g.K, s);
+  if (g.gram) launch_gram<T>(tab, g.nb, g.n_gblk, g.K, g.n_q, s);
   else launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
   launch_sums<T>(tab, g.nb, g.max_entries, s);
   enqueue_decoder_bwd<T>(g, s);
@@ -1193,16 +1193,16 @@ static void enqueue_phase(const Group& g, int phase, hipStream_t s) {
       for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, s);
       break;
     case NMR_PHASE_DEC_OUT:
-      launch_fwd_out<T>(d, tab, g.nb, g.maxN, g.Cf, s);
+      launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, s);
       if (g.any_np) launch_filter<T>(tab, g.nb, 1, s);
       break;
     case NMR_PHASE_CUBATURE: launch_cubature<T>(tab, g.nb, g.max_cblk, s); break;
     case NMR_PHASE_MASS:
-      if (g.gram) launch_gram<T>(tab, g.nb, g.n_gblk, g.K, s);
+      if (g.gram) launch_gram<T>(tab, g.nb, g.n_gblk, g.K, g.n_q, s);
       else launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
       break;
     case NMR_PHASE_SUMS: launch_sums<T>(tab, g.nb, g.max_entries, s); break;
-    case NMR_PHASE_BWD_OUT: launch_bwd_out<T>(d, tab, g.nb, g.max_bblk, s); break;
+    case NMR_PHASE_BWD_OUT: launch_bwd_out<T>(d, tab, g.nb, g.gram ? g.max_sblk : g.max_bblk, s); break;
     case NMR_PHASE_BWD_HIDDEN:
       launch_bwd_reduce<T>(d, tab, g.nb, s);
       for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, s);

@@ -104,7 +104,7 @@ __device__ inline void mfma_range(const float* __restrict__ A, int lda, int kb, 
     for (int t = 0; t < PF; ++t) {
       const int k = k0 + 16 * t;
       if (k < ke) {
-        a[t] = *reinterpret_cast<const float4*>(ap + k);
+        a[t] = ldg<float4>(ap + k);
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) b[t][cb] = bload(cb * 16 + rA, k + 4 * g);
       } else {
@@ -146,7 +146,7 @@ __device__ inline void mfma_range(const __bf16* __restrict__ A, int lda, int kb,
     for (int t = 0; t < PF; ++t) {
       const int k = k0 + 32 * t;
       if (k < ke) {
-        a[t] = *reinterpret_cast<const bf16x8*>(ap + k);
+        a[t] = ldg<bf16x8>(ap + k);
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
           b[t][cb] = to_bf16x8(bload(cb * 16 + rA, k + 8 * g), bload(cb * 16 + rA, k + 8 * g + 4));
@@ -182,10 +182,10 @@ __device__ inline void gemm_splitk(const TW* __restrict__ A, int lda, int K, BL 
       const double* ar = A + (size_t)r * lda;
       for (int k = kb; k < ke; k += 4) {
         const double4 b = bload(c, k);
-        acc = fma(ar[k], b.x, acc);
-        acc = fma(ar[k + 1], b.y, acc);
-        acc = fma(ar[k + 2], b.z, acc);
-        acc = fma(ar[k + 3], b.w, acc);
+        acc = fma(ldg<double>(ar + k), b.x, acc);
+        acc = fma(ldg<double>(ar + k + 1), b.y, acc);
+        acc = fma(ldg<double>(ar + k + 2), b.z, acc);
+        acc = fma(ldg<double>(ar + k + 3), b.w, acc);
       }
       red[wave][c][r] = acc;
     }
@@ -234,26 +234,23 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const I
   const T* X = (l & 1) ? I.act0 : I.act1;
   const double* din = I.dec_in;
   // the bias of this tile is loaded before the GEMM (no dependent round trip)
-  const T bias_v = (tid < 16 && row0 + tid < m_out) ? bias[row0 + tid] : T(0);
+  const T bias_v = (tid < 16 && row0 + tid < m_out) ? ldg<T>(bias + row0 + tid) : T(0);
   auto bload = [&](int c, int k) -> V4 {
     if (l == 0) {
-      // input jets: value q, tangents dq (i2) and qdot (i4), unit e_j (i1)
+      // input jets: value q, tangents dq (i2) and qdot (i4), unit e_j (i1);
+      // loads from clamped indices, then selects (no load under a branch)
+      const int ch = min(c, 2);
       T v[4];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int kk = k + t;
-        T x = T(0);
-        if (kk < nq) {
-          if (c == 0) x = (T)din[kk];
-          else if (c == 1) x = (T)din[nq + kk];
-          else if (c == 2) x = (T)din[2 * nq + kk];
-          else if (c >= 4 && c < 4 + nq) x = (c - 4 == kk) ? T(1) : T(0);
-        }
-        v[t] = x;
+        const T x = (T)ldg<double>(din + ch * nq + min(kk, nq - 1));
+        T y = (c < 3) ? x : (c >= 4 && c - 4 == kk) ? T(1) : T(0);
+        v[t] = (kk < nq && c < 4 + nq) ? y : T(0);
       }
       return V4{v[0], v[1], v[2], v[3]};
     }
-    return *reinterpret_cast<const V4*>(X + (size_t)c * m_inp + k);
+    return ldg<V4>(X + (size_t)c * m_inp + k);
   };
   gemm_splitk<T, TW, NCB, NW>(W, m_inp, m_inp, bload, S, red);
 
@@ -267,7 +264,7 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const I
     act_jet(d.act, x0, y, d1, d2, d3);
     sd1[tid] = d1; sd2[tid] = d2; sd3[tid] = d3;
     sx2[tid] = x2; sx4[tid] = x4; sx23[tid] = x23;
-    pre[row] = valid ? x0 : T(0);
+    stg<T>(pre + row, valid ? x0 : T(0));
     S[0][tid] = valid ? y : T(0);
     S[1][tid] = valid ? d1 * x2 : T(0);
     S[2][tid] = valid ? d1 * x4 : T(0);
@@ -280,7 +277,7 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const I
     const T x1 = S[4 + j][r], x12 = S[4 + nq + j][r], x14 = S[4 + 2 * nq + j][r],
             x123 = S[4 + 3 * nq + j][r];
     const T d1 = sd1[r], d2 = sd2[r], d3 = sd3[r], x2 = sx2[r], x4 = sx4[r], x23 = sx23[r];
-    pre[(size_t)(1 + j) * m_outp + row0 + r] = valid ? x1 : T(0);
+    stg<T>(pre + (size_t)(1 + j) * m_outp + row0 + r, valid ? x1 : T(0));
     S[4 + j][r] = valid ? d1 * x1 : T(0);
     S[4 + nq + j][r] = valid ? d1 * x12 + d2 * x1 * x2 : T(0);
     S[4 + 2 * nq + j][r] = valid ? d1 * x14 + d2 * x1 * x4 : T(0);
@@ -292,7 +289,7 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const I
     const int C = 4 + 4 * nq;
     for (int p = tid; p < C * 16; p += nthr) {
       const int c = p >> 4, r = p & 15;
-      out[(size_t)c * m_outp + row0 + r] = S[c][r];
+      stg<T>(out + (size_t)c * m_outp + row0 + r, S[c][r]);
     }
   } else {
     // last hidden layer: fold into the output channels (the output layer is
@@ -308,7 +305,7 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const I
         const int j = c - 1 - nq;
         v = S[4 + 3 * nq + j][r] + T(3) * S[4 + nq + j][r] - dt * S[4 + 2 * nq + j][r];
       } else v = S[3][r];
-      I.fold[(size_t)c * m_outp + row0 + r] = v;
+      stg<T>(I.fold + (size_t)c * m_outp + row0 + r, v);
     }
   }
 }
@@ -345,11 +342,11 @@ __global__ __launch_bounds__(512) void k_fwd_out(DecoderDev d, const Inst<float>
   if (active) {
     const int pos = row0 + rA;
     // past the end: a padded zero row (direct path) or the last listed row
-    const int wrow = I.gram ? I.cdofs[min(pos, nrows - 1)] : pos;
+    const int wrow = I.gram ? ldg<int>(I.cdofs + min(pos, nrows - 1)) : pos;
     const TW* ap = W + (size_t)wrow * K + (KS / 4) * g;
 #pragma unroll
     for (int t = 0; t < NKS; ++t)
-      if (t * KS < K) a[t] = *reinterpret_cast<const AF*>(ap + t * KS);
+      if (t * KS < K) a[t] = ldg<AF>(ap + t * KS);
   }
   // 2) folded activations into LDS
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -357,7 +354,7 @@ __global__ __launch_bounds__(512) void k_fwd_out(DecoderDev d, const Inst<float>
   const int ldf = K + 4;
   for (int p = threadIdx.x; p < NCB * 16 * (K / 4); p += OUT_WAVES * 64) {
     const int c = p / (K / 4), k4 = p - c * (K / 4);
-    *reinterpret_cast<float4*>(F + c * ldf + 4 * k4) = *reinterpret_cast<const float4*>(I.fold + (size_t)c * K + 4 * k4);
+    *reinterpret_cast<float4*>(F + c * ldf + 4 * k4) = ldg<float4>(I.fold + (size_t)c * K + 4 * k4);
   }
   __syncthreads();
   if (!active) return;
@@ -390,9 +387,9 @@ __global__ __launch_bounds__(512) void k_fwd_out(DecoderDev d, const Inst<float>
     for (int i = 0; i < 4; ++i) {
       const int pos = row0 + 4 * g + i, c = cb * 16 + rA;
       if (pos < nrows && c < Cf) {
-        const int row = I.gram ? I.cdofs[pos] : pos;
-        const float v = acc[cb][i] + (c == 0 ? bias[row] : 0.f);
-        I.rec[(size_t)row * Cf + c] = v * I.keep[row];
+        const int row = I.gram ? ldg<int>(I.cdofs + pos) : pos;
+        const float v = acc[cb][i] + (c == 0 ? ldg<float>(bias + row) : 0.f);
+        stg<float>(I.rec + (size_t)row * Cf + c, v * ldg<float>(I.keep + row));
       }
     }
 }
@@ -457,15 +454,16 @@ __global__ __launch_bounds__(256) void k_filter(const Inst<T>* __restrict__ tab,
 // ---------------------------------------------------------------------------
 #define BWD_ROWS 128
 __device__ inline void load4(const float* p, double (&w)[4]) {
-  const float4 v = *reinterpret_cast<const float4*>(p);
+  const float4 v = ldg<float4>(p);
   w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
 }
 __device__ inline void load4(const double* p, double (&w)[4]) {
-  const double4 v = *reinterpret_cast<const double4*>(p);
+  const double2 v01 = ldg<double2>(p), v23 = ldg<double2>(p + 2);
+  const double4 v = make_double4(v01.x, v01.y, v23.x, v23.y);
   w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
 }
 __device__ inline void load4(const __bf16* p, double (&w)[4]) {
-  const bf16x4 v = *reinterpret_cast<const bf16x4*>(p);
+  const bf16x4 v = ldg<bf16x4>(p);
   w[0] = (float)v[0]; w[1] = (float)v[1]; w[2] = (float)v[2]; w[3] = (float)v[3];
 }
 
@@ -491,11 +489,11 @@ __global__ __launch_bounds__(256) void k_bwd_out(DecoderDev d, const Inst<T>* __
     double v;
     int row = i;
     if (I.gram) {
-      row = I.cdofs[i];
-      v = I.dt * I.dt * (double)I.keep[row] * fint_at(I, row);
+      row = ldg<int>(I.cdofs + i);
+      v = I.dt * I.dt * (double)ldg<T>(I.keep + row) * fint_at(I, row);
     } else {
-      v = (double)I.seed[i];
-      for (int k = 0; k < np; ++k) v -= (double)I.U[(size_t)i * np + k] * uta[k];
+      v = (double)ldg<T>(I.seed + i);
+      for (int k = 0; k < np; ++k) v -= (double)ldg<T>(I.U + (size_t)i * np + k) * ldg<double>(uta + k);
     }
     s[i - i0] = v;
     srow[i - i0] = row;
@@ -521,8 +519,8 @@ __global__ __launch_bounds__(256) void k_bwd_out(DecoderDev d, const Inst<T>* __
     __syncthreads();
     const int c = c0 + threadIdx.x;
     if (c < K)
-      I.part_bwd[(size_t)blockIdx.x * K + c] =
-          ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+      stg<double>(I.part_bwd + (size_t)blockIdx.x * K + c,
+                  ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x]);
     __syncthreads();
   }
 }
@@ -545,7 +543,7 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(DecoderDev d, const Inst<T>*
     const double* src = I.part_bwd + k;
     const int nb = I.gram ? I.n_sblk + 1 : I.n_bblk;  // Gram: + the Gam y + gam partial
 #pragma unroll 4
-    for (int b = sl; b < nb; b += 16) acc += src[(size_t)b * K];
+    for (int b = sl; b < nb; b += 16) acc += ldg<double>(src + (size_t)b * K);
   }
   part[sl][kk] = acc;
   __syncthreads();
@@ -553,13 +551,14 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(DecoderDev d, const Inst<T>*
     double zb0 = part[0][kk];
     for (int q = 1; q < 16; ++q) zb0 += part[q][kk];
     const T* pre = I.pre[l - 1];
-    const T x0 = pre[k];
+    const T x0 = ldg<T>(pre + k);
     T d1, d2;
     act_d12(d.act, x0, d1, d2);
     T* xb = I.zb0;
-    xb[k] = (k < d.w[l]) ? (T)(d1 * zb0) : T(0);
+    stg<T>(xb + k, (k < d.w[l]) ? (T)(d1 * zb0) : T(0));
     for (int j = 0; j < I.n_q; ++j)
-      xb[(size_t)(1 + j) * K + k] = (k < d.w[l]) ? (T)(d2 * pre[(size_t)(1 + j) * K + k] * zb0) : T(0);
+      stg<T>(xb + (size_t)(1 + j) * K + k,
+             (k < d.w[l]) ? (T)(d2 * ldg<T>(pre + (size_t)(1 + j) * K + k) * zb0) : T(0));
   }
 }
 
@@ -587,7 +586,7 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(DecoderDev d, const void* WT
   __shared__ T S[NCB * 16][17];
   __shared__ T red[NW][NCB * 16][16];
   typedef typename vec4<T>::type V4;
-  auto bload = [&](int c, int k) -> V4 { return *reinterpret_cast<const V4*>(xb + (size_t)c * K + k); };
+  auto bload = [&](int c, int k) -> V4 { return ldg<V4>(xb + (size_t)c * K + k); };
   // pre-activations of layer l-1 used by the epilogue, loaded before the GEMM
   constexpr int PP = (16 * 32 + 255) / 256;  // items per thread (16 rows x (1 + n_q <= 32) / >= 256 threads)
   T px0[PP], px1[PP];
@@ -598,8 +597,8 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(DecoderDev d, const void* WT
     px0[t] = px1[t] = T(0);
     if (l > 0 && p < 16 * (1 + nq)) {
       const int r = p & 15, c = p >> 4;
-      px0[t] = pre[row0 + r];
-      if (c > 0) px1[t] = pre[(size_t)c * m_inp + row0 + r];
+      px0[t] = ldg<T>(pre + row0 + r);
+      if (c > 0) px1[t] = ldg<T>(pre + (size_t)c * m_inp + row0 + r);
     }
   }
   gemm_splitk<T, TW, NCB, NW>(WT, K, K, bload, S, red);
@@ -615,7 +614,7 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(DecoderDev d, const void* WT
         T v;
         if (c == 0) v = d1 * S[0][r];
         else v = d1 * S[c][r] + d2 * px1[t] * S[0][r];
-        xb_out[(size_t)c * m_inp + row] = (row < m_in) ? v : T(0);
+        stg<T>(xb_out + (size_t)c * m_inp + row, (row < m_in) ? v : T(0));
       }
     }
   } else {
@@ -623,8 +622,8 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(DecoderDev d, const void* WT
       const int r = p & 15, c = p >> 4;
       const int row = row0 + r;
       if (row < nq) {
-        if (c == 0) I.JTa[row] = (double)S[0][r];
-        else I.Bq[(size_t)row * nq + (c - 1)] = (double)S[c][r];
+        if (c == 0) stg<double>(I.JTa + row, (double)S[0][r]);
+        else stg<double>(I.Bq + (size_t)row * nq + (c - 1), (double)S[c][r]);
       }
     }
   }

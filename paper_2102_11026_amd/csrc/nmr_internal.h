@@ -23,6 +23,8 @@
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define NMR_MAX_LAYERS 16
 #define NMR_MAX_R 32
 #define NMR_WPAD 32  // every layer width is padded to a multiple of this
@@ -137,15 +139,50 @@ template <typename T>
 __device__ inline NMR_GLOBAL T* gpw(T* p) {
   return (NMR_GLOBAL T*)p;
 }
+// load / store a V at p through a global pointer.  HIP's vector structs
+// (float4, double4, int4, ...) cannot be copied from an address-space
+// qualified reference, so they move through a raw vector of the same size
+// and alignment.
+template <typename V>
+struct raw_of {
+  typedef unsigned int type __attribute__((ext_vector_type(sizeof(V) / 4), aligned(alignof(V))));
+};
+template <typename V, typename T>
+__device__ inline V ldg(const T* p) {
+  if constexpr (std::is_scalar<V>::value) {
+    static_assert(std::is_same<V, typename std::remove_cv<T>::type>::value, "scalar loads take the pointee type");
+    return *(const NMR_GLOBAL V*)p;
+  } else {
+    static_assert(sizeof(V) % 4 == 0, "vector loads move whole dwords");
+    typedef typename raw_of<V>::type R;
+    const R r = *(const NMR_GLOBAL R*)p;
+    V v;
+    __builtin_memcpy(&v, &r, sizeof(V));
+    return v;
+  }
+}
+template <typename V, typename T>
+__device__ inline void stg(T* p, V v) {
+  if constexpr (std::is_scalar<V>::value) {
+    static_assert(std::is_same<V, T>::value, "scalar stores take the pointee type");
+    *(NMR_GLOBAL V*)p = v;
+  } else {
+    typedef typename raw_of<V>::type R;
+    R r;
+    __builtin_memcpy(&r, &v, sizeof(V));
+    *(NMR_GLOBAL R*)p = r;
+  }
+}
 
 // f_int[i] = sum of the weighted element forces at DOF i (fixed CSR order)
 template <typename T>
 __device__ inline double fint_at(const Inst<T>& I, int i) {
   const int v = i / 3, c = i - 3 * v;
   double f = 0.0;
-  for (int p = I.csr_ptr[v]; p < I.csr_ptr[v + 1]; ++p) {
-    const int ent = I.csr_ent[p];
-    f += (double)I.fe[(size_t)(ent >> 2) * 12 + 3 * (ent & 3) + c];
+  const int p0 = ldg<int>(I.csr_ptr + v), p1 = ldg<int>(I.csr_ptr + v + 1);
+  for (int p = p0; p < p1; ++p) {
+    const int ent = ldg<int>(I.csr_ent + p);
+    f += (double)ldg<T>(I.fe + (size_t)(ent >> 2) * 12 + 3 * (ent & 3) + c);
   }
   return f;
 }
@@ -187,7 +224,7 @@ void launch_solve(const Inst<T>* tab, int nb, int iter, int mode, double* A_out,
 template <typename T>
 void launch_fint(const Inst<T>* tab, T* f_int, int N, hipStream_t s);
 template <typename T>
-void launch_gram(const Inst<T>* tab, int nb, int max_gblk, int K, hipStream_t s);
+void launch_gram(const Inst<T>* tab, int nb, int max_gblk, int K, int nq, hipStream_t s);
 template <typename T>
 void launch_gram_setup(const void* W, int prec, int K, const T* mass, const T* keep, int N, double dt,
                        const double* g, double* Gam, double* gam, hipStream_t s);

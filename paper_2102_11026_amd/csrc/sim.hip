@@ -94,12 +94,12 @@ __device__ inline double dot_unrolled(const T* __restrict__ w, const double* __r
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int k = 0;
   for (; k + 4 <= n; k += 4) {
-    a0 += (double)w[k] * z[k];
-    a1 += (double)w[k + 1] * z[k + 1];
-    a2 += (double)w[k + 2] * z[k + 2];
-    a3 += (double)w[k + 3] * z[k + 3];
+    a0 += (double)ldg<T>(w + k) * z[k];
+    a1 += (double)ldg<T>(w + k + 1) * z[k + 1];
+    a2 += (double)ldg<T>(w + k + 2) * z[k + 2];
+    a3 += (double)ldg<T>(w + k + 3) * z[k + 3];
   }
-  for (; k < n; ++k) a0 += (double)w[k] * z[k];
+  for (; k < n; ++k) a0 += (double)ldg<T>(w + k) * z[k];
   return (a0 + a1) + (a2 + a3);
 }
 
@@ -111,34 +111,37 @@ __global__ __launch_bounds__(256) void k_step_begin(const Inst<T>* __restrict__ 
   const int R = I.R, np = I.n_p, nq = I.n_q;
   if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < nq; k += 256) {
-      const double q = (mode == BEGIN_STEP) ? I.rbar[np + k] : I.r[np + k];
-      I.dec_in[k] = q;
-      I.dec_in[nq + k] = q - I.rbar[np + k];
-      I.dec_in[2 * nq + k] = I.rdot[np + k];
+      const double rb = ldg<double>(I.rbar + np + k), rc = ldg<double>(I.r + np + k);
+      const double rd = ldg<double>(I.rdot + np + k);
+      const double q = (mode == BEGIN_STEP) ? rb : rc;
+      stg<double>(I.dec_in + k, q);
+      stg<double>(I.dec_in + nq + k, q - rb);
+      stg<double>(I.dec_in + 2 * nq + k, rd);
     }
     if (mode == BEGIN_STEP)
-      for (int k = threadIdx.x; k < R; k += 256) I.r[k] = I.rbar[k];
+      for (int k = threadIdx.x; k < R; k += 256) stg<double>(I.r + k, ldg<double>(I.rbar + k));
   }
   if (I.wn_L == 0) return;
   const int last = I.wn_L - 1;
   const int o0 = blockIdx.x * 256;
   if (o0 >= I.wn_w[I.wn_L]) return;
   __shared__ double z[2][WN_MAXW];
-  for (int k = threadIdx.x; k < I.wn_w[0]; k += 256) z[0][k] = I.rbar[k];
+  for (int k = threadIdx.x; k < I.wn_w[0]; k += 256) z[0][k] = ldg<double>(I.rbar + k);
   __syncthreads();
   for (int l = 0; l < last; ++l) {
     const double* in = z[l & 1];
     double* out = z[(l + 1) & 1];
     const int wi = I.wn_w[l], wo = I.wn_w[l + 1];
     for (int o = threadIdx.x; o < wo; o += 256)
-      out[o] = softplus((double)I.wn_b[l][o] + dot_unrolled(I.wn_W[l] + (size_t)o * wi, in, wi));
+      out[o] = softplus((double)ldg<T>(I.wn_b[l] + o) + dot_unrolled(I.wn_W[l] + (size_t)o * wi, in, wi));
     __syncthreads();
   }
   const double* in = z[last & 1];
   const int wi = I.wn_w[last], wo = I.wn_w[last + 1];
   const int o = o0 + threadIdx.x;
   if (o < wo)
-    I.cub_w[o] = (T)(I.wn_scale * softplus((double)I.wn_b[last][o] + dot_unrolled(I.wn_W[last] + (size_t)o * wi, in, wi)));
+    stg<T>(I.cub_w + o, (T)(I.wn_scale * softplus((double)ldg<T>(I.wn_b[last] + o) +
+                                                   dot_unrolled(I.wn_W[last] + (size_t)o * wi, in, wi))));
 }
 
 template <typename T>
@@ -183,26 +186,49 @@ __global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ ta
   double facc = 0.0;
   const int e0 = blockIdx.x * I.cub_per_blk;
   const int e1 = min(e0 + I.cub_per_blk, I.n_cub);
+  constexpr int JT = (12 * NMR_MAX_R + 63) / 64;
   for (int e = e0 + wave; e < e1; e += CUB_WAVES) {
-    const int* tv = I.cub_v + 4 * e;
-    if (lane < 12) {
-      const int dof = 3 * tv[lane / 3] + lane % 3;
-      xs[wave][lane] = I.X[dof] + I.cu_u[(size_t)dof * I.cu_u_ld];
-    }
-    for (int p = lane; p < 12 * R; p += 64) {
+    // first round trip: the tet's vertices, B_m, weight and volume (none
+    // depends on another load)
+    const int4 tv = ldg<int4>(I.cub_v + 4 * e);
+    T Bmv[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) Bmv[q] = ldg<T>(I.cub_Bm + 9 * e + q);
+    const T wV = ldg<T>(I.cu_w + e) * ldg<T>(I.cub_Ve + e);
+    // second round trip: positions and Jacobian rows of the 12 DOFs, every
+    // load from an index clamped into range, then the LDS writes
+    auto dof_of = [&](int ac) {
+      const int a = ac / 3;
+      const int v = a == 0 ? tv.x : a == 1 ? tv.y : a == 2 ? tv.z : tv.w;
+      return 3 * v + (ac - 3 * a);
+    };
+    const int dx = dof_of(min(lane, 11));
+    const T xv = ldg<T>(I.X + dx) + ldg<T>(I.cu_u + (size_t)dx * I.cu_u_ld);
+    T jv[JT];
+#pragma unroll
+    for (int t = 0; t < JT; ++t) {
+      const int p = min(lane + 64 * t, 12 * R - 1);
       const int ac = p / R, r = p - ac * R;
-      const int dof = 3 * tv[ac / 3] + ac % 3;
-      J12[wave][ac][r] =
-          (r < na) ? I.cu_Ja[(size_t)dof * I.cu_Ja_ld + r] : I.cu_Jb[(size_t)dof * I.cu_Jb_ld + (r - na)];
+      const int dof = dof_of(ac);
+      const T* src = (r < na) ? I.cu_Ja + (size_t)dof * I.cu_Ja_ld + r : I.cu_Jb + (size_t)dof * I.cu_Jb_ld + (r - na);
+      jv[t] = ldg<T>(src);
+    }
+    if (lane < 12) xs[wave][lane] = xv;
+#pragma unroll
+    for (int t = 0; t < JT; ++t) {
+      const int p = lane + 64 * t;
+      if (p < 12 * R) {
+        const int ac = p / R, r = p - ac * R;
+        J12[wave][ac][r] = jv[t];
+      }
     }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
-    const T* Bm = I.cub_Bm + 9 * e;
     T G[4][3];
     for (int j = 0; j < 3; ++j) {
-      G[1][j] = Bm[0 * 3 + j];
-      G[2][j] = Bm[1 * 3 + j];
-      G[3][j] = Bm[2 * 3 + j];
+      G[1][j] = Bmv[0 * 3 + j];
+      G[2][j] = Bmv[1 * 3 + j];
+      G[3][j] = Bmv[2 * 3 + j];
       G[0][j] = -(G[1][j] + G[2][j] + G[3][j]);
     }
     T F[3][3];
@@ -230,7 +256,6 @@ __global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ ta
     T P[3][3];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) P[i][j] = mu * (F[i][j] - A[i][j]) + lam * lnJ * A[i][j];
-    const T wV = I.cu_w[e] * I.cub_Ve[e];
     const T c2 = mu - lam * lnJ;
     if (lane < R) {
       const int r = lane;
@@ -261,7 +286,7 @@ __global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ ta
       const int a = lane / 3, i = lane % 3;
       T f = T(0);
       for (int j = 0; j < 3; ++j) f += P[i][j] * G[a][j];
-      I.fe[(size_t)e * 12 + lane] = wV * f;
+      stg<T>(I.fe + (size_t)e * 12 + lane, wV * f);
     }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
@@ -292,7 +317,7 @@ __global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ ta
     __syncthreads();
   }
   double* out = I.part_cub + (size_t)blockIdx.x * E;
-  for (int p = threadIdx.x; p < E; p += 256) out[p] = red[p];
+  for (int p = threadIdx.x; p < E; p += 256) stg<double>(out + p, red[p]);
 }
 
 template <typename T>
@@ -347,34 +372,53 @@ __global__ __launch_bounds__(256) void k_mass(const Inst<T>* __restrict__ tab) {
   T* sJ = reinterpret_cast<T*>(smem_raw);  // [MASS_ROWS][R]
   T* sdJ = sJ + MASS_ROWS * R;               // [MASS_ROWS][nq]
   const double dt = I.dt;
-  if (threadIdx.x < R) wr[threadIdx.x] = I.r[threadIdx.x] - I.rbar[threadIdx.x] - dt * I.rdot[threadIdx.x];
-  __syncthreads();
   const int i0 = blockIdx.x * MASS_ROWS;
+  // one DOF per thread; every load is issued first, from indices clamped
+  // into range, then w_r, then Jt_i and dJ_i are staged and v_i, a_i and the
+  // seed formed
+  const int t = threadIdx.x;
+  const int i = i0 + t;
+  const int ic = min(i, N - 1);
+  const T* rr = I.rec + (size_t)ic * Cf;
+  T jv[NMR_MAX_R], djv[NMR_MAX_R], uv[NMR_MAX_R];
+#pragma unroll
+  for (int j = 0; j < NMR_MAX_R; ++j) {
+    jv[j] = ldg<T>(rr + 1 + min(j, nq - 1));
+    djv[j] = ldg<T>(rr + 1 + nq + min(j, nq - 1));
+  }
+  if (np > 0) {
+#pragma unroll
+    for (int k = 0; k < NMR_MAX_R; ++k) uv[k] = ldg<T>(I.U + (size_t)ic * np + min(k, np - 1));
+  }
+  const T hdd = ldg<T>(rr + 1 + 2 * nq);
+  const double m_i = (double)ldg<T>(I.mass + ic), keep_i = (double)ldg<T>(I.keep + ic);
+  const int lr = min(t, R - 1);
+  const double wrv = ldg<double>(I.r + lr) - ldg<double>(I.rbar + lr) - dt * ldg<double>(I.rdot + lr);
+  const double fi = fint_at(I, ic);
+  if (t < R) wr[t] = wrv;
+  __syncthreads();
   {
-    // one DOF per thread: stage Jt_i and dJ_i, form v_i, a_i and the seed
-    const int t = threadIdx.x;
-    const int i = i0 + t;
     double m = 0.0, v = 0.0, s = 0.0;
     if (i < N) {
-      const T* rr = I.rec + (size_t)i * Cf;
-      m = (double)I.mass[i];
-      const double fi = fint_at(I, i);
+      m = m_i;
       double jw = 0.0;
-      for (int k = 0; k < np; ++k) {
-        const T u = I.U[(size_t)i * np + k];
-        sJ[t * R + k] = u;
-        jw += (double)u * wr[k];
-      }
-      for (int j = 0; j < nq; ++j) {
-        const T Jv = rr[1 + j];
-        sJ[t * R + np + j] = Jv;
-        sdJ[t * nq + j] = rr[1 + nq + j];
-        jw += (double)Jv * wr[np + j];
-      }
-      v = m * (jw + (double)rr[1 + 2 * nq]) - dt * dt * m * I.g[i % 3];
+#pragma unroll
+      for (int k = 0; k < NMR_MAX_R; ++k)
+        if (k < np) {
+          sJ[t * R + k] = uv[k];
+          jw += (double)uv[k] * wr[k];
+        }
+#pragma unroll
+      for (int j = 0; j < NMR_MAX_R; ++j)
+        if (j < nq) {
+          sJ[t * R + np + j] = jv[j];
+          sdJ[t * nq + j] = djv[j];
+          jw += (double)jv[j] * wr[np + j];
+        }
+      v = m * (jw + (double)hdd) - dt * dt * m * I.g[i % 3];
       const double a = v + dt * dt * fi;
-      s = (double)I.keep[i] * a;
-      I.seed[i] = (T)s;
+      s = keep_i * a;
+      stg<T>(I.seed + i, (T)s);
     } else {
       for (int k = 0; k < R; ++k) sJ[t * R + k] = T(0);
       for (int j = 0; j < nq; ++j) sdJ[t * nq + j] = T(0);
@@ -446,7 +490,7 @@ __global__ __launch_bounds__(256) void k_mass(const Inst<T>* __restrict__ tab) {
       v = tile[e2 / nq][R + e2 % nq];
     } else if (e < R * R + R * nq + R) v = tile[e - R * R - R * nq][R + nq];
     else v = tile[e - R * R - R * nq - R][R + nq + 1];
-    out[e] = v;
+    stg<double>(out + e, v);
   }
 }
 
@@ -510,66 +554,106 @@ template void launch_seed_from_a<double>(const Inst<double>*, const double*, int
 // the FP64 matrix cores (4 waves split K), then one mass partial
 // F_J[rows]^T T and its 16 entries of Gam y + gam as a backprop partial.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NCB>
 __global__ __launch_bounds__(256) void k_gram(const Inst<T>* __restrict__ tab, int K) {
   const Inst<T>& I = tab[blockIdx.y];
   if (!I.active) return;
   if (!I.gram || (int)blockIdx.x >= I.n_gblk) return;
-  const int nq = I.n_q, R = I.R;
+  const int nq = I.n_q, R = I.R;  // R = n_q on this path
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kk = lane >> 4;
   const int row0 = blockIdx.x * 16;
-  const T* F = I.fold;  // [Cf][K]
+  const T* F = I.fold;  // [Cf][K], K <= 256
   __shared__ double wr[NMR_MAX_R];
   __shared__ double y[256];
   __shared__ double tile[16][4 * 16];
+  __shared__ double frow[NMR_MAX_R][16];  // F_J[row0 .. row0 + 15], column-major by j
   const double dt = I.dt;
-  if (threadIdx.x < R) wr[threadIdx.x] = I.r[threadIdx.x] - I.rbar[threadIdx.x] - dt * I.rdot[threadIdx.x];
-  __syncthreads();
-  for (int k = threadIdx.x; k < K; k += 256) {
-    double v = (double)F[(size_t)(1 + 2 * nq) * K + k];
-    for (int j = 0; j < nq; ++j) v += (double)F[(size_t)(1 + j) * K + k] * wr[j];
-    y[k] = v;
+  // X columns: F_J, F_dJ, y in NCB = ceil((2 n_q + 1) / 16) column blocks
+  // Every global load is issued before the first wait, from indices clamped
+  // into range: the folded columns of y (thread k), this wave's K-steps of
+  // Gam and of X, the 16 F_J rows of the mass partial and the state.
+  const int kt = min((int)threadIdx.x, K - 1);
+  T fy[NMR_MAX_R];
+#pragma unroll
+  for (int j = 0; j < NMR_MAX_R; ++j) fy[j] = ldg<T>(F + (size_t)(1 + min(j, nq - 1)) * K + kt);
+  const T fh = ldg<T>(F + (size_t)(1 + 2 * nq) * K + kt);
+  constexpr int NST = 256 / 16;  // K-steps of one wave at K = 256 (K/4 entries, 4 per step)
+  const int kper = K / 4, nst = kper / 4;
+  const double* G = I.Gam + (size_t)(row0 + col) * K;
+  double av[NST];
+  T bv[NST][NCB];
+#pragma unroll
+  for (int st = 0; st < NST; ++st) {
+    const int k = min(wave * kper + 4 * st + kk, K - 1);
+    av[st] = ldg<double>(G + k);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) bv[st][cb] = ldg<T>(F + (size_t)(1 + min(cb * 16 + col, 2 * nq - 1)) * K + k);
+  }
+  constexpr int FP = (NMR_MAX_R * 16 + 255) / 256;
+  T fpv[FP];
+#pragma unroll
+  for (int q = 0; q < FP; ++q) {
+    const int p = threadIdx.x + 256 * q;
+    fpv[q] = ldg<T>(F + (size_t)(1 + min(p >> 4, nq - 1)) * K + row0 + (p & 15));
+  }
+  const double gm = ldg<double>(I.gam + row0 + (threadIdx.x & 15));
+  const int lr = min((int)threadIdx.x, R - 1);
+  const double wrv = ldg<double>(I.r + lr) - ldg<double>(I.rbar + lr) - dt * ldg<double>(I.rdot + lr);
+  if ((int)threadIdx.x < R) wr[threadIdx.x] = wrv;
+#pragma unroll
+  for (int q = 0; q < FP; ++q) {
+    const int p = threadIdx.x + 256 * q;
+    if ((p >> 4) < nq) frow[p >> 4][p & 15] = (double)fpv[q];
   }
   __syncthreads();
-  const int nx = 2 * nq + 1;  // X columns: F_J, F_dJ, y
-  const int ncb = (nx + 15) / 16;
-  f64x4 acc[4];
+  if ((int)threadIdx.x < K) {
+    double v = (double)fh;
 #pragma unroll
-  for (int cb = 0; cb < 4; ++cb) acc[cb] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const double* G = I.Gam + (size_t)(row0 + col) * K;
-  const int kper = K / 4;  // each wave a quarter of K (K is a multiple of 32)
-  for (int k0 = wave * kper; k0 < (wave + 1) * kper; k0 += 4) {
-    const int k = k0 + kk;
-    const double a = G[k];
+    for (int j = 0; j < NMR_MAX_R; ++j)
+      if (j < nq) v += (double)fy[j] * wr[j];
+    y[threadIdx.x] = v;
+  }
+  __syncthreads();
+  f64x4 acc[NCB];
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      if (cb < ncb) {
-        const int n = cb * 16 + col;
-        const double b = n < 2 * nq ? (double)F[(size_t)(1 + n) * K + k] : (n == 2 * nq ? y[k] : 0.0);
-        acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
-      }
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // each wave a quarter of K, 4 entries per step, in increasing k.  The y
+  // entries of the wave's steps are read from LDS in one batch and every B
+  // operand is chosen by selects; steps past K/4 (K < 256) multiply a zero
+  // A operand, which adds exact zeros, so the loop is straight-line code
+  double yv[NST];
+#pragma unroll
+  for (int st = 0; st < NST; ++st) yv[st] = y[min(wave * kper + 4 * st + kk, K - 1)];
+#pragma unroll
+  for (int st = 0; st < NST; ++st) {
+    const double a = st < nst ? av[st] : 0.0;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int n = cb * 16 + col;
+      const double fb = n < 2 * nq ? (double)bv[st][cb] : 0.0;
+      const double b = n == 2 * nq ? yv[st] : fb;
+      acc[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[cb], 0, 0, 0);
     }
   }
   // wave partial tiles added in wave order (f64 result rows interleaved)
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
 #pragma unroll
-      for (int cb = 0; cb < 4; ++cb)
-        if (cb < ncb)
+      for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int rr = 4 * q + kk, cc = cb * 16 + col;
-            tile[rr][cc] = (w == 0 ? 0.0 : tile[rr][cc]) + acc[cb][q];
-          }
+        for (int q = 0; q < 4; ++q) {
+          const int rr = 4 * q + kk, cc = cb * 16 + col;
+          tile[rr][cc] = (w == 0 ? 0.0 : tile[rr][cc]) + acc[cb][q];
+        }
     }
     __syncthreads();
   }
   // T_y + gam for these rows: the backprop partial after the sparse blocks
   if (threadIdx.x < 16) {
-    const double zb = tile[threadIdx.x][2 * nq] + I.gam[row0 + threadIdx.x];
+    const double zb = tile[threadIdx.x][2 * nq] + gm;
     tile[threadIdx.x][2 * nq] = zb;
-    I.part_bwd[(size_t)I.n_sblk * K + row0 + threadIdx.x] = zb;
+    stg<double>(I.part_bwd + (size_t)I.n_sblk * K + row0 + threadIdx.x, zb);
   }
   __syncthreads();
   // mass partial F_J[rows]^T T in the layout of the direct path
@@ -588,17 +672,24 @@ __global__ __launch_bounds__(256) void k_gram(const Inst<T>* __restrict__ tab, i
       c = 2 * nq;
     }
     double v = 0.0;
-    for (int r = 0; r < 16; ++r) v += (double)F[(size_t)(1 + i) * K + row0 + r] * tile[r][c];
-    out[e] = v;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v += frow[i][r] * tile[r][c];
+    stg<double>(out + e, v);
   }
 }
 
 template <typename T>
-void launch_gram(const Inst<T>* tab, int nb, int max_gblk, int K, hipStream_t s) {
-  k_gram<T><<<dim3(max_gblk, nb), 256, 0, s>>>(tab, K);
+void launch_gram(const Inst<T>* tab, int nb, int max_gblk, int K, int nq, hipStream_t s) {
+  const dim3 grid(max_gblk, nb);
+  switch ((2 * nq + 1 + 15) / 16) {
+    case 1: k_gram<T, 1><<<grid, 256, 0, s>>>(tab, K); break;
+    case 2: k_gram<T, 2><<<grid, 256, 0, s>>>(tab, K); break;
+    case 3: k_gram<T, 3><<<grid, 256, 0, s>>>(tab, K); break;
+    default: k_gram<T, 4><<<grid, 256, 0, s>>>(tab, K); break;
+  }
 }
-template void launch_gram<float>(const Inst<float>*, int, int, int, hipStream_t);
-template void launch_gram<double>(const Inst<double>*, int, int, int, hipStream_t);
+template void launch_gram<float>(const Inst<float>*, int, int, int, int, hipStream_t);
+template void launch_gram<double>(const Inst<double>*, int, int, int, int, hipStream_t);
 
 // setup: Gam = W_L^T diag(m keep) W_L over the N rows of this instance and
 // gam = W_L^T (keep c); one thread per entry, rows in order
@@ -662,20 +753,20 @@ __global__ __launch_bounds__(256) void k_sums(const Inst<T>* __restrict__ tab) {
   if (e < Ec) {
     const double* src = I.part_cub + e;
 #pragma unroll 4
-    for (int b = sl; b < I.n_cblk; b += 16) acc += src[(size_t)b * Ec];
+    for (int b = sl; b < I.n_cblk; b += 16) acc += ldg<double>(src + (size_t)b * Ec);
   } else if (e < Ec + Em) {
     const double* src = I.part_mass + (e - Ec);
     const int nb = I.gram ? I.n_gblk : I.n_mblk;
 #pragma unroll 4
-    for (int b = sl; b < nb; b += 16) acc += src[(size_t)b * Em];
+    for (int b = sl; b < nb; b += 16) acc += ldg<double>(src + (size_t)b * Em);
   }
   part[sl][kk] = acc;
   __syncthreads();
   if (sl == 0) {
     double v = part[0][kk];
     for (int q = 1; q < 16; ++q) v += part[q][kk];
-    if (e < Ec) I.sum_cub[e] = v;
-    else if (e < Ec + Em) I.sum_mass[e - Ec] = v;
+    if (e < Ec) stg<double>(I.sum_cub + e, v);
+    else if (e < Ec + Em) stg<double>(I.sum_mass + e - Ec, v);
   }
 }
 

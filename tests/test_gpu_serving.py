@@ -55,7 +55,7 @@ def small_class(k):
     p = synth.tiny_problem(grid=(3, 3, 6), widths=(4, 32, 48, 162), act="elu", name="srv", q_std=0.3,
                            out_scale=0.1, n_cub=20)
     r0 = np.zeros(p.R)
-    r0[p.n_p:] = 0.3 * synth.normal(f"srv/q0/{k}", p.n_q)
+    r0[p.n_p:] = 0.1 * synth.normal(f"srv/q0/{k}", p.n_q)  # at 0.3 request 0 inverts in the oracle
     return p.replace(r0=r0)
 
 
