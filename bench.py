@@ -139,23 +139,70 @@ def run_steps(nmr, ctx, insts, steps: int, warmup: int):
 
 def cpu_baseline(p, seconds: float):
     """The FP64 oracle, untuned, on this host's cores: Newton iterations of the
-    same problem from its initial state until about `seconds` have passed."""
+    same problem from its initial state until about `seconds` have passed.
+    Returns the baseline record, the number of steps and the oracle's state."""
     from threadpoolctl import threadpool_info
     from oracle.newton import Instance as OracleInstance
     oi = OracleInstance(p)
     st = oi.initial_state()
     n = 0
+    first = None
     t0 = time.perf_counter()
     while True:
         st, _ = oi.step(st, ITERS)
         n += ITERS
+        first = first or st
         if time.perf_counter() - t0 > seconds:
             break
     dt = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return dict(value=round(n / dt, 4), unit="Newton iters/s", cores=int(threads), kind="oracle",
-                sample=f"first {n // ITERS} implicit-Euler steps x {ITERS} Newton iterations of the same "
-                       f"10k-vertex problem (FP64 numpy/BLAS oracle), {dt:.1f} s")
+    rec = dict(value=round(n / dt, 4), unit="Newton iters/s", cores=int(threads), kind="oracle",
+               sample=f"first {n // ITERS} implicit-Euler steps x {ITERS} Newton iterations of the same "
+                      f"10k-vertex problem (FP64 numpy/BLAS oracle), {dt:.1f} s")
+    return rec, n // ITERS, oi, first, st
+
+
+def rel(a, b) -> float:
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def precision_report(nmr, ctx, p, oi, steps: int, first, last):
+    """FP32 and BF16 forms against the FP64 oracle: the state r after the
+    first step (the bar still moving) and after the oracle's last step (close
+    to rest, where the error is the precision of the equilibrium), the
+    displacement u there, and J (Frobenius) and phi (relative to ||phi|| at
+    the start of the step) and A at a perturbed initial state."""
+    import torch
+    rng = np.random.default_rng(7)
+    r1 = p.r0 + rng.normal(size=p.R) * 0.005
+    w0 = oi.cubature_weights(p.r0)
+    sys_o = oi.system(r1, p.r0, p.rdot0, w0)
+    phi0 = np.linalg.norm(oi.system(p.r0, p.r0, p.rdot0, w0)["phi"])
+    u_o = oi.displacement(last.rbar)
+    zeros = np.zeros(p.n_q)
+    dec_o = oi.decode(p.r0[p.n_p:], zeros, zeros)
+    rep = dict(steps=steps, newton_iters_per_step=ITERS, r_norm_first_step=float(np.linalg.norm(first.rbar)),
+               r_norm_last_step=float(np.linalg.norm(last.rbar)))
+    for prec in ("fp32", "bf16"):
+        x = nmr.Instance(ctx, p, prec)
+        try:
+            A, phi = x.newton_system(r1)
+            J = x.decoder_jacobian_hessian(p.r0[p.n_p:], zeros, zeros)["J"].cpu().numpy()
+            st1, _ = nmr.step_many(ctx, [x], 1, ITERS)
+            ra, _ = x.get_state()
+            st, _ = nmr.step_many(ctx, [x], steps - 1, ITERS)
+            r, _, u = x.get_state(with_u=True)
+            torch.cuda.synchronize()
+        finally:
+            x.close()
+        rep[prec] = dict(status=max(st1[0], st[0], key=abs), r_rel_first_step=rel(ra, first.rbar),
+                         r_rel_last_step=rel(r, last.rbar), r_abs_last_step=float(np.linalg.norm(r - last.rbar)),
+                         u_rel_last_step=rel(u, u_o), J_rel=rel(J, dec_o["J"]),
+                         phi_rel_to_phi0=float(np.linalg.norm(phi.cpu().numpy() - sys_o["phi"]) / phi0),
+                         A_rel=rel(A.cpu().numpy(), sys_o["A"]))
+    return rep
 
 
 def main():
@@ -166,10 +213,23 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--batch", type=int, nargs="*", default=[16, 64])
+    ap.add_argument("--batch", type=int, nargs="*", default=[4, 16, 64])
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the served form (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (the reference kernel that scales "
+                         "hardware byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_calibration_bytes_per_copy=2 * n * 4, read_bytes=n * 4, write_bytes=n * 4)))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the path has no multi-GPU form (instances would shard "
               "across GPUs with no exchange); run with --gpus 1", file=sys.stderr)
@@ -276,10 +336,13 @@ def main():
         out["variants"] = var
         log("variants:", var)
     inst.close()
-    ctx.close()
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        rec, o_steps, oi, o_first, o_last = cpu_baseline(p, args.cpu_seconds)
+        out["cpu_baseline"] = rec
+        log("precision forms against the oracle")
+        out["precision_vs_oracle"] = precision_report(nmr, ctx, p, oi, o_steps, o_first, o_last)
+    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -77,6 +77,32 @@ template <typename T> struct vec4;
 template <> struct vec4<float> { typedef float4 type; };
 template <> struct vec4<double> { typedef double4 type; };
 
+// One layer of the decoder as a launch sees it, passed by value: everything
+// a kernel reads from it arrives with the first kernel-argument load, with
+// no index by a runtime layer number into the decoder's tables.
+struct LayerArgs {
+  const void* W;   // W_l, [m_outp][m_inp] (padded, K contiguous)
+  const void* b;   // b_l, [m_out]
+  const void* WT;  // W_l^T, [m_inp][m_outp] (hidden layers only)
+  int l, L, act;
+  int m_in, m_inp, m_out, m_outp;  // true and padded input / output widths
+};
+
+static LayerArgs layer_args(const DecoderDev& d, int l) {
+  LayerArgs a;
+  a.W = d.W[l];
+  a.b = d.b[l];
+  a.WT = (l < d.L - 1) ? d.WT[l] : nullptr;
+  a.l = l;
+  a.L = d.L;
+  a.act = d.act;
+  a.m_in = d.w[l];
+  a.m_inp = d.wp[l];
+  a.m_out = d.w[l + 1];
+  a.m_outp = d.wp[l + 1];
+  return a;
+}
+
 template <typename TW> struct kstep { static constexpr int v = 16; };
 template <> struct kstep<__bf16> { static constexpr int v = 32; };
 template <> struct kstep<double> { static constexpr int v = 4; };
@@ -215,24 +241,32 @@ __device__ inline void gemm_splitk(const TW* __restrict__ A, int lda, int K, BL 
 // Forward hidden layer l with the jet activation.  One block per 16 rows.
 // ---------------------------------------------------------------------------
 template <typename T, typename TW, int NCB>
-__global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const Inst<T>* __restrict__ tab) {
+__global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab) {
   constexpr int NW = splitk_waves<T, NCB>::v;
   const Inst<T>& I = tab[blockIdx.y];
-  if (!I.active) return;
-  const int m_inp = d.wp[l], m_out = d.w[l + 1], m_outp = d.wp[l + 1];
+  const int l = la.l;
+  // the table entry's fields are read before the activity test so that their
+  // scalar loads leave together
+  const int active = I.active, nq = I.n_q;
+  const T* X = (l & 1) ? I.act0 : I.act1;
+  T* const outp = (l & 1) ? I.act1 : I.act0;
+  T* const pre = I.pre[l];
+  T* const fold = I.fold;
+  const double* din = I.dec_in;
+  const double dt64 = I.dt;
+  const int m_inp = la.m_inp, m_out = la.m_out, m_outp = la.m_outp;
+  load_now(active, nq, X, outp, pre, fold, din, dt64, m_inp, m_out, m_outp, la.W, la.b, la.act, la.L);
+  const T dtT = (T)dt64;
   const int row0 = blockIdx.x * 16;
-  if (row0 >= m_outp) return;
-  const int nq = I.n_q;
+  if (!active || row0 >= m_outp) return;
   const int tid = threadIdx.x, nthr = NW * 64;
-  const TW* W = reinterpret_cast<const TW*>(d.W[l]) + (size_t)row0 * m_inp;
-  const T* bias = reinterpret_cast<const T*>(d.b[l]);
+  const TW* W = reinterpret_cast<const TW*>(la.W) + (size_t)row0 * m_inp;
+  const T* bias = reinterpret_cast<const T*>(la.b);
   __shared__ T S[NCB * 16][17];
   __shared__ T red[NW][NCB * 16][16];
   __shared__ T sd1[16], sd2[16], sd3[16], sx2[16], sx4[16], sx23[16];
   typedef typename vec4<T>::type V4;
 
-  const T* X = (l & 1) ? I.act0 : I.act1;
-  const double* din = I.dec_in;
   // the bias of this tile is loaded before the GEMM (no dependent round trip)
   const T bias_v = (tid < 16 && row0 + tid < m_out) ? ldg<T>(bias + row0 + tid) : T(0);
   auto bload = [&](int c, int k) -> V4 {
@@ -254,14 +288,13 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const I
   };
   gemm_splitk<T, TW, NCB, NW>(W, m_inp, m_inp, bload, S, red);
 
-  T* pre = I.pre[l];
   if (tid < 16) {
     const int row = row0 + tid;
     const bool valid = row < m_out;
     const T x0 = S[0][tid] + bias_v;
     const T x2 = S[1][tid], x4 = S[2][tid], x23 = S[3][tid];
     T y, d1, d2, d3;
-    act_jet(d.act, x0, y, d1, d2, d3);
+    act_jet(la.act, x0, y, d1, d2, d3);
     sd1[tid] = d1; sd2[tid] = d2; sd3[tid] = d3;
     sx2[tid] = x2; sx4[tid] = x4; sx23[tid] = x23;
     stg<T>(pre + row, valid ? x0 : T(0));
@@ -284,8 +317,8 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const I
     S[4 + 3 * nq + j][r] = valid ? d1 * x123 + d2 * (x1 * x23 + T(2) * x2 * x12) + d3 * x1 * x2 * x2 : T(0);
   }
   __syncthreads();
-  if (l + 2 < d.L) {
-    T* out = (l & 1) ? I.act1 : I.act0;
+  if (l + 2 < la.L) {
+    T* out = outp;
     const int C = 4 + 4 * nq;
     for (int p = tid; p < C * 16; p += nthr) {
       const int c = p >> 4, r = p & 15;
@@ -294,7 +327,7 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const I
   } else {
     // last hidden layer: fold into the output channels (the output layer is
     // linear, so eq. delta_j can be combined before it)
-    const T dt = (T)I.dt;
+    const T dt = dtT;
     const int C = 2 + 2 * nq;
     for (int p = tid; p < C * 16; p += nthr) {
       const int c = p >> 4, r = p & 15;
@@ -305,7 +338,7 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const I
         const int j = c - 1 - nq;
         v = S[4 + 3 * nq + j][r] + T(3) * S[4 + nq + j][r] - dt * S[4 + 2 * nq + j][r];
       } else v = S[3][r];
-      stg<T>(I.fold + (size_t)c * m_outp + row0 + r, v);
+      stg<T>(fold + (size_t)c * m_outp + row0 + r, v);
     }
   }
 }
@@ -319,42 +352,77 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(DecoderDev d, int l, const I
 #define OUT_KMAX 256  // weight tile held in registers: K <= 256
 
 template <typename TW, int NCB>
-__global__ __launch_bounds__(512) void k_fwd_out(DecoderDev d, const Inst<float>* __restrict__ tab) {
+__global__ __launch_bounds__(512) void k_fwd_out(LayerArgs la, const Inst<float>* __restrict__ tab) {
   const Inst<float>& I = tab[blockIdx.y];
-  if (!I.active) return;
-  const int l = d.L - 1;
-  const int K = d.wp[l];
+  const int inst_active = I.active, gram = I.gram, n_cd = I.n_cdofs, N = I.N, Cf = I.Cf;
+  const int* cdofs = I.cdofs;
+  const float* fold = I.fold;
+  float* rec = I.rec;
+  const float* keep = I.keep;
+  const int K = la.m_inp;
+  load_now(inst_active, gram, n_cd, N, Cf, cdofs, fold, rec, keep, K, la.W, la.b);
   // rows of the output layer this launch decodes: all N DOFs, or on the Gram
   // path only the DOFs of cubature tets (positions map through cdofs)
-  const int nrows = I.gram ? I.n_cdofs : I.N;
+  const int nrows = gram ? n_cd : N;
   const int blk_row0 = blockIdx.x * (OUT_WAVES * 16);
-  if (blk_row0 >= nrows) return;
+  if (!inst_active || blk_row0 >= nrows) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rA = lane & 15, g = lane >> 4;
   const int row0 = blk_row0 + wave * 16;
   const bool active = row0 < nrows;
-  const TW* W = reinterpret_cast<const TW*>(d.W[l]);
+  const TW* W = reinterpret_cast<const TW*>(la.W);
+  const float* bias = reinterpret_cast<const float*>(la.b);
   constexpr int KS = kstep<TW>::v;
   constexpr int NKS = OUT_KMAX / KS;
-  // 1) weight tile into registers
+  // 1) folded activations: loads issued first (into registers)
+  constexpr int FS = (NCB * 16 * (OUT_KMAX / 4) + OUT_WAVES * 64 - 1) / (OUT_WAVES * 64);
+  const int nf4 = NCB * 16 * (K / 4);
+  float4 fv[FS];
+#pragma unroll
+  for (int t = 0; t < FS; ++t) {
+    const int p = min((int)threadIdx.x + OUT_WAVES * 64 * t, nf4 - 1);
+    const int c = p / (K / 4), k4 = p - c * (K / 4);
+    fv[t] = ldg<float4>(fold + (size_t)c * K + 4 * k4);
+  }
+  // 2) the weight row of this lane and the four output rows of its results
+  // (past the end: a padded zero row on the direct path, the last listed row
+  // on the Gram path), then the weight tile, bias and mask of those rows
+  int wrow = row0 + rA, orow[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) orow[i] = row0 + 4 * g + i;
+  if (gram) {
+    wrow = ldg<int>(cdofs + min(wrow, nrows - 1));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) orow[i] = ldg<int>(cdofs + min(orow[i], nrows - 1));
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) orow[i] = min(orow[i], N - 1);
+  }
   typedef typename std::conditional<std::is_same<TW, float>::value, float4, bf16x8>::type AF;
   AF a[NKS];
+  float bv[4], kv[4];
   if (active) {
-    const int pos = row0 + rA;
-    // past the end: a padded zero row (direct path) or the last listed row
-    const int wrow = I.gram ? ldg<int>(I.cdofs + min(pos, nrows - 1)) : pos;
     const TW* ap = W + (size_t)wrow * K + (KS / 4) * g;
 #pragma unroll
     for (int t = 0; t < NKS; ++t)
       if (t * KS < K) a[t] = ldg<AF>(ap + t * KS);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      bv[i] = ldg<float>(bias + orow[i]);
+      kv[i] = ldg<float>(keep + orow[i]);
+    }
   }
-  // 2) folded activations into LDS
+  // 3) folded activations into LDS
   extern __shared__ __align__(16) unsigned char smem_raw[];
   float* F = reinterpret_cast<float*>(smem_raw);  // [NCB*16][K + 4]
   const int ldf = K + 4;
-  for (int p = threadIdx.x; p < NCB * 16 * (K / 4); p += OUT_WAVES * 64) {
-    const int c = p / (K / 4), k4 = p - c * (K / 4);
-    *reinterpret_cast<float4*>(F + c * ldf + 4 * k4) = ldg<float4>(I.fold + (size_t)c * K + 4 * k4);
+#pragma unroll
+  for (int t = 0; t < FS; ++t) {
+    const int p = (int)threadIdx.x + OUT_WAVES * 64 * t;
+    if (p < nf4) {
+      const int c = p / (K / 4), k4 = p - c * (K / 4);
+      *reinterpret_cast<float4*>(F + c * ldf + 4 * k4) = fv[t];
+    }
   }
   __syncthreads();
   if (!active) return;
@@ -379,35 +447,31 @@ __global__ __launch_bounds__(512) void k_fwd_out(DecoderDev d, const Inst<float>
       }
     }
   }
-  const float* bias = reinterpret_cast<const float*>(d.b[l]);
-  const int Cf = I.Cf;
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int pos = row0 + 4 * g + i, c = cb * 16 + rA;
       if (pos < nrows && c < Cf) {
-        const int row = I.gram ? ldg<int>(I.cdofs + pos) : pos;
-        const float v = acc[cb][i] + (c == 0 ? ldg<float>(bias + row) : 0.f);
-        stg<float>(I.rec + (size_t)row * Cf + c, v * ldg<float>(I.keep + row));
+        const float v = acc[cb][i] + (c == 0 ? bv[i] : 0.f);
+        stg<float>(rec + (size_t)orow[i] * Cf + c, v * kv[i]);
       }
     }
 }
 
 // FP64 form of the output layer (plain FMA; correctness configurations)
-__global__ __launch_bounds__(256) void k_fwd_out_f64(DecoderDev d, const Inst<double>* __restrict__ tab) {
+__global__ __launch_bounds__(256) void k_fwd_out_f64(LayerArgs la, const Inst<double>* __restrict__ tab) {
   const Inst<double>& I = tab[blockIdx.y];
   if (!I.active) return;
-  const int l = d.L - 1;
-  const int K = d.wp[l];
+  const int K = la.m_inp;
   const int Cf = I.Cf;
   const int nrows = I.gram ? I.n_cdofs : I.N;
   const int pos = blockIdx.x * 16 + (threadIdx.x >> 4);
   const int c0 = threadIdx.x & 15;
   if (pos >= nrows) return;
   const int row = I.gram ? I.cdofs[pos] : pos;
-  const double* W = reinterpret_cast<const double*>(d.W[l]) + (size_t)row * K;
-  const double* bias = reinterpret_cast<const double*>(d.b[l]);
+  const double* W = reinterpret_cast<const double*>(la.W) + (size_t)row * K;
+  const double* bias = reinterpret_cast<const double*>(la.b);
   for (int c = c0; c < Cf; c += 16) {
     double acc = 0.0;
     const double* f = I.fold + (size_t)c * K;
@@ -468,15 +532,16 @@ __device__ inline void load4(const __bf16* p, double (&w)[4]) {
 }
 
 template <typename T, typename TW>
-__global__ __launch_bounds__(256) void k_bwd_out(DecoderDev d, const Inst<T>* __restrict__ tab) {
+__global__ __launch_bounds__(256) void k_bwd_out(LayerArgs la, const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
+  load_now(I.active, I.gram, I.n_sblk, I.n_bblk, I.n_cdofs, I.N, I.n_p, I.R, I.n_q, I.sum_mass, I.cdofs, I.keep,
+           I.seed, I.U, I.part_bwd, I.csr_ptr, I.csr_ent, I.fe, la.m_inp, la.W);
   if (!I.active) return;
   // direct path: all N rows with the seed P a (and the filter transpose);
   // Gram path: only the cubature DOFs with dt^2 P f_int (the rest of W_L^T P a
   // is Gam y + gam, added by the Gram kernel as one more partial)
   if ((int)blockIdx.x >= (I.gram ? I.n_sblk : I.n_bblk)) return;
-  const int l = d.L - 1;
-  const int K = d.wp[l];
+  const int K = la.m_inp;
   const int nrows = I.gram ? I.n_cdofs : I.N;
   const int i0 = blockIdx.x * BWD_ROWS;
   const int i1 = min(i0 + BWD_ROWS, nrows);
@@ -499,7 +564,7 @@ __global__ __launch_bounds__(256) void k_bwd_out(DecoderDev d, const Inst<T>* __
     srow[i - i0] = row;
   }
   __syncthreads();
-  const TW* W = reinterpret_cast<const TW*>(d.W[l]);
+  const TW* W = reinterpret_cast<const TW*>(la.W);
   const int cg = threadIdx.x & 63, sl = threadIdx.x >> 6;
   for (int c0 = 0; c0 < K; c0 += 256) {
     const int col = c0 + 4 * cg;
@@ -530,11 +595,13 @@ __global__ __launch_bounds__(256) void k_bwd_out(DecoderDev d, const Inst<T>* __
 // hidden layer: xb0 = s1 zb0, xb1_j = s2 x1_j zb0 (the seed is real).
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_bwd_reduce(DecoderDev d, const Inst<T>* __restrict__ tab) {
+__global__ __launch_bounds__(256) void k_bwd_reduce(LayerArgs la, const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
+  load_now(I.active, I.gram, I.n_sblk, I.n_bblk, I.part_bwd, I.pre[la.l - 1], I.zb0, I.n_q, la.m_inp, la.m_in,
+           la.act);
   if (!I.active) return;
-  const int l = d.L - 1;  // output layer; its input is hidden layer l-1
-  const int K = d.wp[l];
+  const int l = la.l;  // output layer; its input is hidden layer l-1
+  const int K = la.m_inp;
   const int kk = threadIdx.x & 15, sl = threadIdx.x >> 4;
   const int k = blockIdx.x * 16 + kk;
   __shared__ double part[16][17];
@@ -553,12 +620,12 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(DecoderDev d, const Inst<T>*
     const T* pre = I.pre[l - 1];
     const T x0 = ldg<T>(pre + k);
     T d1, d2;
-    act_d12(d.act, x0, d1, d2);
+    act_d12(la.act, x0, d1, d2);
     T* xb = I.zb0;
-    stg<T>(xb + k, (k < d.w[l]) ? (T)(d1 * zb0) : T(0));
+    stg<T>(xb + k, (k < la.m_in) ? (T)(d1 * zb0) : T(0));
     for (int j = 0; j < I.n_q; ++j)
       stg<T>(xb + (size_t)(1 + j) * K + k,
-             (k < d.w[l]) ? (T)(d2 * ldg<T>(pre + (size_t)(1 + j) * K + k) * zb0) : T(0));
+             (k < la.m_in) ? (T)(d2 * ldg<T>(pre + (size_t)(1 + j) * K + k) * zb0) : T(0));
   }
 }
 
@@ -568,21 +635,26 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(DecoderDev d, const Inst<T>*
 // at the input, J^T a and a . H.
 // ---------------------------------------------------------------------------
 template <typename T, typename TW, int NCB>
-__global__ __launch_bounds__(512) void k_bwd_hidden(DecoderDev d, const void* WT_, int l,
-                                                    const Inst<T>* __restrict__ tab) {
+__global__ __launch_bounds__(512) void k_bwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab) {
   constexpr int NW = splitk_waves<T, NCB>::v;
   const Inst<T>& I = tab[blockIdx.y];
-  if (!I.active) return;
-  const int K = d.wp[l + 1];  // reduction over the outputs of layer l
-  const int m_in = d.w[l], m_inp = d.wp[l];
-  const int row0 = blockIdx.x * 16;
-  if (row0 >= m_inp) return;
-  const int nq = I.n_q;
-  const int tid = threadIdx.x, nthr = NW * 64;
-  const int step = d.L - 2 - l;  // 0 for the last hidden layer
+  const int l = la.l;
+  const int step = la.L - 2 - l;  // 0 for the last hidden layer
+  // the table entry's fields are read before the activity test so that their
+  // scalar loads leave together
+  const int active = I.active, nq = I.n_q;
   const T* xb = (step & 1) ? I.zb1 : I.zb0;
-  T* xb_out = (step & 1) ? I.zb0 : I.zb1;
-  const TW* WT = reinterpret_cast<const TW*>(WT_) + (size_t)row0 * K;
+  T* const xb_out = (step & 1) ? I.zb0 : I.zb1;
+  const T* pre = (l > 0) ? I.pre[l - 1] : nullptr;
+  double* const JTa = I.JTa;
+  double* const Bq = I.Bq;
+  const int K = la.m_outp;  // reduction over the outputs of layer l
+  const int m_in = la.m_in, m_inp = la.m_inp;
+  load_now(active, nq, xb, xb_out, pre, JTa, Bq, K, m_in, m_inp, la.WT, la.act);
+  const int row0 = blockIdx.x * 16;
+  if (!active || row0 >= m_inp) return;
+  const int tid = threadIdx.x, nthr = NW * 64;
+  const TW* WT = reinterpret_cast<const TW*>(la.WT) + (size_t)row0 * K;
   __shared__ T S[NCB * 16][17];
   __shared__ T red[NW][NCB * 16][16];
   typedef typename vec4<T>::type V4;
@@ -590,7 +662,6 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(DecoderDev d, const void* WT
   // pre-activations of layer l-1 used by the epilogue, loaded before the GEMM
   constexpr int PP = (16 * 32 + 255) / 256;  // items per thread (16 rows x (1 + n_q <= 32) / >= 256 threads)
   T px0[PP], px1[PP];
-  const T* pre = (l > 0) ? I.pre[l - 1] : nullptr;
 #pragma unroll
   for (int t = 0; t < PP; ++t) {
     const int p = tid + t * nthr;
@@ -610,7 +681,7 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(DecoderDev d, const void* WT
         const int r = p & 15, c = p >> 4;
         const int row = row0 + r;
         T d1, d2;
-        act_d12(d.act, px0[t], d1, d2);
+        act_d12(la.act, px0[t], d1, d2);
         T v;
         if (c == 0) v = d1 * S[0][r];
         else v = d1 * S[c][r] + d2 * px1[t] * S[0][r];
@@ -622,8 +693,8 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(DecoderDev d, const void* WT
       const int r = p & 15, c = p >> 4;
       const int row = row0 + r;
       if (row < nq) {
-        if (c == 0) stg<double>(I.JTa + row, (double)S[0][r]);
-        else stg<double>(I.Bq + (size_t)row * nq + (c - 1), (double)S[c][r]);
+        if (c == 0) stg<double>(JTa + row, (double)S[0][r]);
+        else stg<double>(Bq + (size_t)row * nq + (c - 1), (double)S[c][r]);
       }
     }
   }
@@ -664,7 +735,7 @@ __global__ void k_unpack(const Inst<T>* __restrict__ tab, T* u, T* J, T* dJ, T* 
 template <typename T, typename TW>
 static void fwd_hidden_dispatch(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cp, hipStream_t s) {
   dim3 grid(d.wp[l + 1] / 16, nb);
-#define FWD_H(n) k_fwd_hidden<T, TW, n><<<grid, 64 * splitk_waves<T, n>::v, 0, s>>>(d, l, tab)
+#define FWD_H(n) k_fwd_hidden<T, TW, n><<<grid, 64 * splitk_waves<T, n>::v, 0, s>>>(layer_args(d, l), tab)
   NCB_SWITCH(cp / 16, FWD_H)
 #undef FWD_H
 }
@@ -678,7 +749,7 @@ template <>
 void launch_fwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* tab, int nb, int cp, hipStream_t s) {
   // FP64 decoders take n_q <= 15, i.e. at most 4 column blocks
   dim3 grid(d.wp[l + 1] / 16, nb);
-#define FWD_H64(n) k_fwd_hidden<double, double, n><<<grid, 64 * splitk_waves<double, n>::v, 0, s>>>(d, l, tab)
+#define FWD_H64(n) k_fwd_hidden<double, double, n><<<grid, 64 * splitk_waves<double, n>::v, 0, s>>>(layer_args(d, l), tab)
   switch (cp / 16) {
     case 1: FWD_H64(1); break;
     case 2: FWD_H64(2); break;
@@ -695,7 +766,7 @@ static void fwd_out_dispatch(const DecoderDev& d, const Inst<float>* tab, int nb
   dim3 grid((max_n + rows - 1) / rows, nb);
   const int K = d.wp[d.L - 1];
   const size_t lds = (size_t)cf * (K + 4) * sizeof(float);
-#define FWD_O(n) k_fwd_out<TW, n><<<grid, OUT_WAVES * 64, lds, s>>>(d, tab)
+#define FWD_O(n) k_fwd_out<TW, n><<<grid, OUT_WAVES * 64, lds, s>>>(layer_args(d, d.L - 1), tab)
   switch (cf / 16) {
     case 1: FWD_O(1); break;
     case 2: FWD_O(2); break;
@@ -713,7 +784,7 @@ void launch_fwd_out<float>(const DecoderDev& d, const Inst<float>* tab, int nb, 
 }
 template <>
 void launch_fwd_out<double>(const DecoderDev& d, const Inst<double>* tab, int nb, int max_n, int cf, hipStream_t s) {
-  k_fwd_out_f64<<<dim3((max_n + 15) / 16, nb), 256, 0, s>>>(d, tab);
+  k_fwd_out_f64<<<dim3((max_n + 15) / 16, nb), 256, 0, s>>>(layer_args(d, d.L - 1), tab);
 }
 
 template <typename T>
@@ -726,28 +797,27 @@ template void launch_filter<double>(const Inst<double>*, int, int, hipStream_t);
 template <>
 void launch_bwd_out<float>(const DecoderDev& d, const Inst<float>* tab, int nb, int max_bblk, hipStream_t s) {
   dim3 grid(max_bblk, nb);
-  if (d.prec == PREC_BF16) k_bwd_out<float, __bf16><<<grid, 256, 0, s>>>(d, tab);
-  else k_bwd_out<float, float><<<grid, 256, 0, s>>>(d, tab);
+  if (d.prec == PREC_BF16) k_bwd_out<float, __bf16><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab);
+  else k_bwd_out<float, float><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab);
 }
 template <>
 void launch_bwd_out<double>(const DecoderDev& d, const Inst<double>* tab, int nb, int max_bblk, hipStream_t s) {
   dim3 grid(max_bblk, nb);
-  k_bwd_out<double, double><<<grid, 256, 0, s>>>(d, tab);
+  k_bwd_out<double, double><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab);
 }
 
 template <typename T>
 void launch_bwd_reduce(const DecoderDev& d, const Inst<T>* tab, int nb, hipStream_t s) {
   const int K = d.wp[d.L - 1];
-  k_bwd_reduce<T><<<dim3((K + 15) / 16, nb), 256, 0, s>>>(d, tab);
+  k_bwd_reduce<T><<<dim3((K + 15) / 16, nb), 256, 0, s>>>(layer_args(d, d.L - 1), tab);
 }
 template void launch_bwd_reduce<float>(const DecoderDev&, const Inst<float>*, int, hipStream_t);
 template void launch_bwd_reduce<double>(const DecoderDev&, const Inst<double>*, int, hipStream_t);
 
 template <typename T, typename TW>
-static void bwd_hidden_dispatch(const DecoderDev& d, const void* WT, int l, const Inst<T>* tab, int nb, int cb,
-                                hipStream_t s) {
+static void bwd_hidden_dispatch(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cb, hipStream_t s) {
   dim3 grid(d.wp[l] / 16, nb);
-#define BWD_H(n) k_bwd_hidden<T, TW, n><<<grid, 64 * splitk_waves<T, n>::v, 0, s>>>(d, WT, l, tab)
+#define BWD_H(n) k_bwd_hidden<T, TW, n><<<grid, 64 * splitk_waves<T, n>::v, 0, s>>>(layer_args(d, l), tab)
   switch (cb / 16) {
     case 1: BWD_H(1); break;
     case 2: BWD_H(2); break;
@@ -760,12 +830,12 @@ static void bwd_hidden_dispatch(const DecoderDev& d, const void* WT, int l, cons
 
 template <>
 void launch_bwd_hidden<float>(const DecoderDev& d, int l, const Inst<float>* tab, int nb, int cb, hipStream_t s) {
-  if (d.prec == PREC_BF16) bwd_hidden_dispatch<float, __bf16>(d, d.WT[l], l, tab, nb, cb, s);
-  else bwd_hidden_dispatch<float, float>(d, d.WT[l], l, tab, nb, cb, s);
+  if (d.prec == PREC_BF16) bwd_hidden_dispatch<float, __bf16>(d, l, tab, nb, cb, s);
+  else bwd_hidden_dispatch<float, float>(d, l, tab, nb, cb, s);
 }
 template <>
 void launch_bwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* tab, int nb, int cb, hipStream_t s) {
-  bwd_hidden_dispatch<double, double>(d, d.WT[l], l, tab, nb, cb, s);
+  bwd_hidden_dispatch<double, double>(d, l, tab, nb, cb, s);
 }
 
 template <typename T>

@@ -139,6 +139,19 @@ template <typename T>
 __device__ inline NMR_GLOBAL T* gpw(T* p) {
   return (NMR_GLOBAL T*)p;
 }
+// Uniform values (kernel arguments, fields of an Inst table entry) that a
+// kernel needs are forced into scalar registers at this point: the compiler
+// otherwise sinks each scalar load below the early-exit branches, which
+// turns one round trip into a chain of dependent ones.
+template <typename V>
+__device__ inline void in_sgpr(V v) {
+  asm volatile("" ::"s"(v));
+}
+template <typename... A>
+__device__ inline void load_now(A... a) {  // by value: every load is made at the call
+  (in_sgpr(a), ...);
+}
+
 // load / store a V at p through a global pointer.  HIP's vector structs
 // (float4, double4, int4, ...) cannot be copied from an address-space
 // qualified reference, so they move through a raw vector of the same size

@@ -107,6 +107,7 @@ __device__ inline double dot_unrolled(const T* __restrict__ w, const double* __r
 template <typename T>
 __global__ __launch_bounds__(256) void k_step_begin(const Inst<T>* __restrict__ tab, int mode) {
   const Inst<T>& I = tab[blockIdx.y];
+  load_now(I.active, I.R, I.n_p, I.n_q, I.rbar, I.r, I.rdot, I.dec_in, I.wn_L, I.wn_scale, I.cub_w);
   if (!I.active) return;
   const int R = I.R, np = I.n_p, nq = I.n_q;
   if (blockIdx.x == 0) {
@@ -168,6 +169,8 @@ template void launch_step_begin<double>(const Inst<double>*, int, int, int, hipS
 template <typename T>
 __global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
+  load_now(I.active, I.n_cblk, I.R, I.cu_na, I.mu, I.lam, I.cub_per_blk, I.n_cub, I.cub_v, I.cub_Bm, I.cu_w, I.cub_Ve,
+           I.X, I.cu_u, I.cu_u_ld, I.cu_Ja, I.cu_Ja_ld, I.cu_Jb, I.cu_Jb_ld, I.status, I.fe, I.part_cub);
   if (!I.active) return;
   if ((int)blockIdx.x >= I.n_cblk) return;
   const int R = I.R;
@@ -557,6 +560,8 @@ template void launch_seed_from_a<double>(const Inst<double>*, const double*, int
 template <typename T, int NCB>
 __global__ __launch_bounds__(256) void k_gram(const Inst<T>* __restrict__ tab, int K) {
   const Inst<T>& I = tab[blockIdx.y];
+  load_now(I.active, I.gram, I.n_gblk, I.n_q, I.R, I.fold, I.dt, I.Gam, I.gam, I.r, I.rbar, I.rdot, I.part_bwd,
+           I.n_sblk, I.part_mass);
   if (!I.active) return;
   if (!I.gram || (int)blockIdx.x >= I.n_gblk) return;
   const int nq = I.n_q, R = I.R;  // R = n_q on this path
@@ -742,6 +747,8 @@ template void launch_gram_setup<double>(const void*, int, int, const double*, co
 template <typename T>
 __global__ __launch_bounds__(256) void k_sums(const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
+  load_now(I.active, I.R, I.n_q, I.n_p, I.n_cblk, I.gram, I.n_gblk, I.n_mblk, I.part_cub, I.part_mass, I.sum_cub,
+           I.sum_mass);
   if (!I.active) return;
   const int R = I.R;
   const int Ec = R * R + R;
@@ -955,6 +962,8 @@ template <typename T>
 __global__ __launch_bounds__(64) void k_solve(const Inst<T>* __restrict__ tab, int iter, int mode, double* A_out,
                                               double* phi_out) {
   const Inst<T>& I = tab[blockIdx.y];
+  load_now(I.active, I.R, I.n_p, I.n_q, I.dt, I.sum_mass, I.sum_cub, I.Bq, I.status, I.r, I.rbar, I.rdot, I.resid,
+           I.dec_in);
   if (!I.active) return;
   if (I.R < 16) solve_body<T, 16>(I, iter, mode, A_out, phi_out);
   else solve_body<T, 32>(I, iter, mode, A_out, phi_out);
