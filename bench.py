@@ -35,6 +35,23 @@ FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 FRAME_BUDGET_MS = 1000.0 / 60.0
 PHASE_KERNEL = dict(dec_hidden="k_fwd_hidden", dec_out="k_fwd_out", bwd_out="k_bwd_out", bwd_hidden="k_bwd_hidden")
+# Bytes per launch that reach the memory side of L2 on the FP32 10k-vertex
+# bar, from two rocprofv3 --pmc runs (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the
+# factors a plain 512 MiB device copy gives), averaged over one pass of the
+# phase; see profiles/k_fwd_hidden_bar10k_fp32_pmc.md.  They hold only for the
+# kernel sources they were taken on: with any other sources traffic is null.
+MEASURED_TRAFFIC = dict(k_fwd_hidden=1682545, k_bwd_hidden=987096, k_fwd_out=6657664, k_bwd_out=5776384)
+MEASURED_TRAFFIC_SOURCES = "6b67ce099c2fc28c"
+KERNEL_SOURCES = ("paper_2102_11026_amd/csrc/decoder.hip", "paper_2102_11026_amd/csrc/nmr_internal.h")
+
+
+def kernel_sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -110,7 +127,11 @@ def phase_roofline(p, phase: str, us: float, prec: str, gram: bool):
     us_l = us / launches
     peak_tf = BF16_MFMA_PEAK_TFLOPS if prec == "bf16" else FP32_MFMA_PEAK_TFLOPS
     ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
-    common = dict(traffic=None, kernel=PHASE_KERNEL[phase], phase=phase, launches_per_pass=launches,
+    traffic = None
+    if prec == "fp32" and kernel_sources_digest() == MEASURED_TRAFFIC_SOURCES:
+        traffic = MEASURED_TRAFFIC.get(PHASE_KERNEL[phase])
+    common = dict(traffic=traffic, traffic_unit="bytes per launch", kernel=PHASE_KERNEL[phase], phase=phase,
+                  launches_per_pass=launches,
                   us_per_launch=round(us_l, 3), algorithmic_bytes_per_launch=int(byts),
                   algorithmic_flops_per_launch=int(flops), arithmetic_intensity=round(flops / byts, 2),
                   ridge=round(ridge, 2))
