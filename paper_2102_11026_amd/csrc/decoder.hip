@@ -344,15 +344,25 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
 }
 
 // ---------------------------------------------------------------------------
-// Output layer: rec[i][c] = keep_i (W_L fold + b_L e_0)[i][c].  8 waves per
-// block, one 16-row tile per wave; each wave loads its whole weight tile
-// before staging of the folded activations into LDS completes.
+// Output layer: rec[i][c] = keep_i (W_L fold + b_L e_0)[i][c] for the decoded
+// rows (all N, or the DOFs of cubature tets on the Gram path).  One block per
+// 16-row tile; its OUT_SPLIT waves each take a quarter of K, holding their
+// weight and folded-activation operands in registers, and the partial tiles
+// are added in LDS in wave order.  The row ids are read first, then weights,
+// bias and mask of those rows together with the folded activations.
 // ---------------------------------------------------------------------------
-#define OUT_WAVES 8
-#define OUT_KMAX 256  // weight tile held in registers: K <= 256
+#define OUT_SPLIT 4
+#define OUT_KMAX 256  // last hidden layer: K <= 256
+
+template <typename V>
+__device__ inline V zero_of() {
+  V v;
+  __builtin_memset(&v, 0, sizeof(V));
+  return v;
+}
 
 template <typename TW, int NCB>
-__global__ __launch_bounds__(512) void k_fwd_out(LayerArgs la, const Inst<float>* __restrict__ tab) {
+__global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out(LayerArgs la, const Inst<float>* __restrict__ tab) {
   const Inst<float>& I = tab[blockIdx.y];
   const int inst_active = I.active, gram = I.gram, n_cd = I.n_cdofs, N = I.N, Cf = I.Cf;
   const int* cdofs = I.cdofs;
@@ -361,102 +371,88 @@ __global__ __launch_bounds__(512) void k_fwd_out(LayerArgs la, const Inst<float>
   const float* keep = I.keep;
   const int K = la.m_inp;
   load_now(inst_active, gram, n_cd, N, Cf, cdofs, fold, rec, keep, K, la.W, la.b);
-  // rows of the output layer this launch decodes: all N DOFs, or on the Gram
-  // path only the DOFs of cubature tets (positions map through cdofs)
   const int nrows = gram ? n_cd : N;
-  const int blk_row0 = blockIdx.x * (OUT_WAVES * 16);
-  if (!inst_active || blk_row0 >= nrows) return;
+  const int row0 = blockIdx.x * 16;
+  if (!inst_active || row0 >= nrows) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rA = lane & 15, g = lane >> 4;
-  const int row0 = blk_row0 + wave * 16;
-  const bool active = row0 < nrows;
   const TW* W = reinterpret_cast<const TW*>(la.W);
   const float* bias = reinterpret_cast<const float*>(la.b);
   constexpr int KS = kstep<TW>::v;
-  constexpr int NKS = OUT_KMAX / KS;
-  // 1) folded activations: loads issued first (into registers)
-  constexpr int FS = (NCB * 16 * (OUT_KMAX / 4) + OUT_WAVES * 64 - 1) / (OUT_WAVES * 64);
-  const int nf4 = NCB * 16 * (K / 4);
-  float4 fv[FS];
-#pragma unroll
-  for (int t = 0; t < FS; ++t) {
-    const int p = min((int)threadIdx.x + OUT_WAVES * 64 * t, nf4 - 1);
-    const int c = p / (K / 4), k4 = p - c * (K / 4);
-    fv[t] = ldg<float4>(fold + (size_t)c * K + 4 * k4);
-  }
-  // 2) the weight row of this lane and the four output rows of its results
-  // (past the end: a padded zero row on the direct path, the last listed row
-  // on the Gram path), then the weight tile, bias and mask of those rows
-  int wrow = row0 + rA, orow[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) orow[i] = row0 + 4 * g + i;
-  if (gram) {
-    wrow = ldg<int>(cdofs + min(wrow, nrows - 1));
-#pragma unroll
-    for (int i = 0; i < 4; ++i) orow[i] = ldg<int>(cdofs + min(orow[i], nrows - 1));
-  } else {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) orow[i] = min(orow[i], N - 1);
-  }
+  constexpr int NT = (OUT_KMAX / OUT_SPLIT + KS - 1) / KS;  // K-steps of one wave
+  const int kq = K / OUT_SPLIT, kb = wave * kq, ke = kb + kq;
+  __shared__ float red[OUT_SPLIT][NCB * 16][17];
+  __shared__ int srow[16];
+  __shared__ float sbias[16], skeep[16];
+  // 1) row ids: the weight row of this lane (direct path: rows past N are the
+  //    zero padding of W_L; Gram path: the last listed row) and, for threads
+  //    0..15, the output row of the epilogue; folded activations meanwhile
+  const int wrow = gram ? ldg<int>(cdofs + min(row0 + rA, nrows - 1)) : row0 + rA;
+  const int tr = min(row0 + (int)(threadIdx.x & 15), nrows - 1);
+  const int orow = gram ? ldg<int>(cdofs + tr) : tr;
   typedef typename std::conditional<std::is_same<TW, float>::value, float4, bf16x8>::type AF;
-  AF a[NKS];
-  float bv[4], kv[4];
-  if (active) {
-    const TW* ap = W + (size_t)wrow * K + (KS / 4) * g;
+  float4 bf[NT][NCB][KS / 16];
 #pragma unroll
-    for (int t = 0; t < NKS; ++t)
-      if (t * KS < K) a[t] = ldg<AF>(ap + t * KS);
+  for (int t = 0; t < NT; ++t)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      bv[i] = ldg<float>(bias + orow[i]);
-      kv[i] = ldg<float>(keep + orow[i]);
-    }
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int h = 0; h < KS / 16; ++h) {
+        const int k = min(kb + t * KS + (KS / 4) * g + 4 * h, K - 4);
+        bf[t][cb][h] = ldg<float4>(fold + (size_t)(cb * 16 + rA) * K + k);
+      }
+  // 2) weights of this lane's row, bias and mask of the output rows
+  // a lane group whose K entries start past this wave's quarter (K < 256)
+  // contributes a zero A operand; its load is from a clamped address
+  AF a[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int kk = kb + t * KS + (KS / 4) * g;
+    const AF v = ldg<AF>(W + (size_t)wrow * K + min(kk, K - KS / 4));
+    a[t] = kk < ke ? v : zero_of<AF>();
   }
-  // 3) folded activations into LDS
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  float* F = reinterpret_cast<float*>(smem_raw);  // [NCB*16][K + 4]
-  const int ldf = K + 4;
-#pragma unroll
-  for (int t = 0; t < FS; ++t) {
-    const int p = (int)threadIdx.x + OUT_WAVES * 64 * t;
-    if (p < nf4) {
-      const int c = p / (K / 4), k4 = p - c * (K / 4);
-      *reinterpret_cast<float4*>(F + c * ldf + 4 * k4) = fv[t];
-    }
+  if (threadIdx.x < 16) {
+    srow[threadIdx.x] = orow;
+    sbias[threadIdx.x] = ldg<float>(bias + orow);
+    skeep[threadIdx.x] = ldg<float>(keep + orow);
   }
-  __syncthreads();
-  if (!active) return;
   f32x4 acc[NCB];
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int t = 0; t < NKS; ++t) {
-    if (t * KS >= K) break;
+  for (int t = 0; t < NT; ++t) {
+    if (kb + t * KS < ke) {
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      const float* fp = F + (cb * 16 + rA) * ldf + t * KS + (KS / 4) * g;
-      if constexpr (std::is_same<TW, float>::value) {
-        const float4 b = *reinterpret_cast<const float4*>(fp);
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].x, b.x, acc[cb], 0, 0, 0);
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].y, b.y, acc[cb], 0, 0, 0);
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].z, b.z, acc[cb], 0, 0, 0);
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].w, b.w, acc[cb], 0, 0, 0);
-      } else {
-        const bf16x8 b = to_bf16x8(*reinterpret_cast<const float4*>(fp), *reinterpret_cast<const float4*>(fp + 4));
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b, acc[cb], 0, 0, 0);
+      for (int cb = 0; cb < NCB; ++cb) {
+        if constexpr (std::is_same<TW, float>::value) {
+          const float4 b = bf[t][cb][0];
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].x, b.x, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].y, b.y, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].z, b.z, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t].w, b.w, acc[cb], 0, 0, 0);
+        } else {
+          const bf16x8 b = to_bf16x8(bf[t][cb][0], bf[t][cb][KS / 16 - 1]);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[t], b, acc[cb], 0, 0, 0);
+        }
       }
     }
   }
+  // partial tiles: item i of lane l is D[4 (l/16) + i][l % 16]
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int pos = row0 + 4 * g + i, c = cb * 16 + rA;
-      if (pos < nrows && c < Cf) {
-        const float v = acc[cb][i] + (c == 0 ? bv[i] : 0.f);
-        stg<float>(rec + (size_t)orow[i] * Cf + c, v * kv[i]);
-      }
+    for (int i = 0; i < 4; ++i) red[wave][cb * 16 + rA][4 * g + i] = acc[cb][i];
+  __syncthreads();
+  for (int p = threadIdx.x; p < 16 * Cf; p += 64 * OUT_SPLIT) {
+    const int c = p >> 4, r = p & 15;
+    if (row0 + r < nrows) {
+      float v = red[0][c][r];
+#pragma unroll
+      for (int w = 1; w < OUT_SPLIT; ++w) v += red[w][c][r];
+      if (c == 0) v += sbias[r];
+      stg<float>(rec + (size_t)srow[r] * Cf + c, v * skeep[r]);
     }
+  }
 }
 
 // FP64 form of the output layer (plain FMA; correctness configurations)
@@ -762,11 +758,8 @@ void launch_fwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* t
 
 template <typename TW>
 static void fwd_out_dispatch(const DecoderDev& d, const Inst<float>* tab, int nb, int max_n, int cf, hipStream_t s) {
-  const int rows = OUT_WAVES * 16;
-  dim3 grid((max_n + rows - 1) / rows, nb);
-  const int K = d.wp[d.L - 1];
-  const size_t lds = (size_t)cf * (K + 4) * sizeof(float);
-#define FWD_O(n) k_fwd_out<TW, n><<<grid, OUT_WAVES * 64, lds, s>>>(layer_args(d, d.L - 1), tab)
+  dim3 grid((max_n + 15) / 16, nb);
+#define FWD_O(n) k_fwd_out<TW, n><<<grid, OUT_SPLIT * 64, 0, s>>>(layer_args(d, d.L - 1), tab)
   switch (cf / 16) {
     case 1: FWD_O(1); break;
     case 2: FWD_O(2); break;
