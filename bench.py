@@ -240,7 +240,29 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (the reference kernel that scales "
                          "hardware byte counters) and exit")
+    ap.add_argument("--profile-batch", type=int, default=0, metavar="B",
+                    help="only step B instances of the 10k-vertex problem sharing one FP32 decoder (for a "
+                         "profiler) and exit")
     args = ap.parse_args()
+    if args.profile_batch:
+        import torch
+        from paper_2102_11026_amd import nmr, synth
+        p = synth.config_single_10k()
+        ctx = nmr.Context(0)
+        dec = nmr.Decoder(ctx, p.weights, p.biases, p.act, "fp32")
+        insts = []
+        for k in range(args.profile_batch):
+            r0 = np.zeros(p.R)
+            r0[p.n_p:] = 0.1 * synth.normal(f"q0/{k}", p.n_q)
+            insts.append(nmr.Instance(ctx, p.replace(r0=r0), "fp32", shared=dec))
+        secs, ms = run_steps(nmr, ctx, insts, args.steps, args.warmup)
+        print(json.dumps(dict(instances=args.profile_batch, steps=args.steps,
+                              newton_iters_per_s=round(ITERS * args.steps * args.profile_batch / secs, 1))))
+        for x in insts:
+            x.close()
+        dec.close()
+        ctx.close()
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 4

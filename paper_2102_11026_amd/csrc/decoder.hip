@@ -191,16 +191,22 @@ __device__ inline void mfma_range(const __bf16* __restrict__ A, int lda, int kb,
   }
 }
 
-// Split-K tile: NW waves each take a slice of K; the partial tiles are added
-// in wave order into S[c][r] (c = column < NCB*16, r = row < 16).
-template <typename T, typename TW, int NCB, int NW, typename BL>
-__device__ inline void gemm_splitk(const TW* __restrict__ A, int lda, int K, BL bload, T (*S)[17],
-                                   T (*red)[NCB * 16][16]) {
+// Split-K tile over IB instance slots: the NW waves of a block are IB slots x
+// KSPL = NW / IB K-slices.  Wave w computes the partial 16 x (NCB*16) tile of
+// slot w / KSPL over its slice of K (A is [16][lda], K contiguous; B through
+// bload(c, k)), and the slices of each slot are added in slice order into
+// S[slot][c][r] (c = column < NCB*16, r = row < 16).  A slot that is not in
+// use (use == false) contributes zeros; every wave reaches every barrier.
+template <typename T, typename TW, int NCB, int NW, int IB, typename BL>
+__device__ inline void gemm_splitk(const TW* __restrict__ A, int lda, int K, bool use, BL bload,
+                                   T (*S)[NCB * 16][17], T (*red)[NCB * 16][16]) {
+  constexpr int KSPL = NW / IB;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ks = wave % KSPL;
   constexpr int KS = kstep<TW>::v;
   const int nks = K / KS;
-  const int per = (nks + NW - 1) / NW;
-  const int kb = min(K, wave * per * KS), ke = min(K, kb + per * KS);
+  const int per = (nks + KSPL - 1) / KSPL;
+  const int kb = min(K, ks * per * KS), ke = use ? min(K, kb + per * KS) : kb;
   if constexpr (std::is_same<TW, double>::value) {
     for (int o = lane; o < NCB * 16 * 16; o += 64) {
       const int c = o >> 4, r = o & 15;
@@ -227,26 +233,42 @@ __device__ inline void gemm_splitk(const TW* __restrict__ A, int lda, int K, BL 
       for (int i = 0; i < 4; ++i) red[wave][cb * 16 + rA][4 * g + i] = acc[cb][i];
   }
   __syncthreads();
-  for (int p = threadIdx.x; p < NCB * 16 * 16; p += NW * 64) {
-    const int c = p >> 4, r = p & 15;
-    T v = red[0][c][r];
+  for (int p = threadIdx.x; p < IB * NCB * 16 * 16; p += NW * 64) {
+    const int slot = p / (NCB * 16 * 16), q = p - slot * (NCB * 16 * 16);
+    const int c = q >> 4, r = q & 15;
+    T v = red[slot * KSPL][c][r];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) v += red[w][c][r];
-    S[c][r] = v;
+    for (int w = 1; w < KSPL; ++w) v += red[slot * KSPL + w][c][r];
+    S[slot][c][r] = v;
   }
   __syncthreads();
+}
+
+// instances per block of a hidden-layer launch: stack instances (sharing the
+// weight tile, a longer MFMA run per block) once there are enough blocks to
+// fill the chip without it
+__host__ inline int stack_instances(int row_tiles, int nb, bool f64) {
+  if (f64) return 1;
+  if (row_tiles * ((nb + 3) / 4) >= 512) return 4;
+  if (row_tiles * ((nb + 1) / 2) >= 512) return 2;
+  return 1;
 }
 
 // ---------------------------------------------------------------------------
 // Forward hidden layer l with the jet activation.  One block per 16 rows.
 // ---------------------------------------------------------------------------
-template <typename T, typename TW, int NCB>
-__global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab) {
+template <typename T, typename TW, int NCB, int IB>
+__global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab, int nb) {
   constexpr int NW = splitk_waves<T, NCB>::v;
-  const Inst<T>& I = tab[blockIdx.y];
+  constexpr int KSPL = NW / IB;
+  constexpr int NG = KSPL * 64;  // threads of one instance slot
   const int l = la.l;
-  // the table entry's fields are read before the activity test so that their
-  // scalar loads leave together
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int slot = wave / KSPL, tg = tid - slot * NG;
+  const int inst = blockIdx.y * IB + slot;
+  const Inst<T>& I = tab[min(inst, nb - 1)];
+  // the table entry's fields are read before any test so that their scalar
+  // loads leave together
   const int active = I.active, nq = I.n_q;
   const T* X = (l & 1) ? I.act0 : I.act1;
   T* const outp = (l & 1) ? I.act1 : I.act0;
@@ -256,19 +278,19 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
   const double dt64 = I.dt;
   const int m_inp = la.m_inp, m_out = la.m_out, m_outp = la.m_outp;
   load_now(active, nq, X, outp, pre, fold, din, dt64, m_inp, m_out, m_outp, la.W, la.b, la.act, la.L);
+  const bool use = inst < nb && active;
   const T dtT = (T)dt64;
   const int row0 = blockIdx.x * 16;
-  if (!active || row0 >= m_outp) return;
-  const int tid = threadIdx.x, nthr = NW * 64;
+  if (row0 >= m_outp || (IB == 1 && !use)) return;  // uniform over the block
   const TW* W = reinterpret_cast<const TW*>(la.W) + (size_t)row0 * m_inp;
   const T* bias = reinterpret_cast<const T*>(la.b);
-  __shared__ T S[NCB * 16][17];
+  __shared__ T S[IB][NCB * 16][17];
   __shared__ T red[NW][NCB * 16][16];
-  __shared__ T sd1[16], sd2[16], sd3[16], sx2[16], sx4[16], sx23[16];
+  __shared__ T sd1[IB][16], sd2[IB][16], sd3[IB][16], sx2[IB][16], sx4[IB][16], sx23[IB][16];
   typedef typename vec4<T>::type V4;
 
   // the bias of this tile is loaded before the GEMM (no dependent round trip)
-  const T bias_v = (tid < 16 && row0 + tid < m_out) ? ldg<T>(bias + row0 + tid) : T(0);
+  const T bias_v = (tg < 16 && row0 + tg < m_out) ? ldg<T>(bias + row0 + tg) : T(0);
   auto bload = [&](int c, int k) -> V4 {
     if (l == 0) {
       // input jets: value q, tangents dq (i2) and qdot (i4), unit e_j (i1);
@@ -286,58 +308,61 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
     }
     return ldg<V4>(X + (size_t)c * m_inp + k);
   };
-  gemm_splitk<T, TW, NCB, NW>(W, m_inp, m_inp, bload, S, red);
+  gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload, S, red);
 
-  if (tid < 16) {
-    const int row = row0 + tid;
+  T(*Ss)[17] = S[slot];
+  if (use && tg < 16) {
+    const int row = row0 + tg;
     const bool valid = row < m_out;
-    const T x0 = S[0][tid] + bias_v;
-    const T x2 = S[1][tid], x4 = S[2][tid], x23 = S[3][tid];
+    const T x0 = Ss[0][tg] + bias_v;
+    const T x2 = Ss[1][tg], x4 = Ss[2][tg], x23 = Ss[3][tg];
     T y, d1, d2, d3;
     act_jet(la.act, x0, y, d1, d2, d3);
-    sd1[tid] = d1; sd2[tid] = d2; sd3[tid] = d3;
-    sx2[tid] = x2; sx4[tid] = x4; sx23[tid] = x23;
+    sd1[slot][tg] = d1; sd2[slot][tg] = d2; sd3[slot][tg] = d3;
+    sx2[slot][tg] = x2; sx4[slot][tg] = x4; sx23[slot][tg] = x23;
     stg<T>(pre + row, valid ? x0 : T(0));
-    S[0][tid] = valid ? y : T(0);
-    S[1][tid] = valid ? d1 * x2 : T(0);
-    S[2][tid] = valid ? d1 * x4 : T(0);
-    S[3][tid] = valid ? d1 * x23 + d2 * x2 * x2 : T(0);
+    Ss[0][tg] = valid ? y : T(0);
+    Ss[1][tg] = valid ? d1 * x2 : T(0);
+    Ss[2][tg] = valid ? d1 * x4 : T(0);
+    Ss[3][tg] = valid ? d1 * x23 + d2 * x2 * x2 : T(0);
   }
   __syncthreads();
-  for (int p = tid; p < 16 * nq; p += nthr) {
-    const int r = p & 15, j = p >> 4;
-    const bool valid = row0 + r < m_out;
-    const T x1 = S[4 + j][r], x12 = S[4 + nq + j][r], x14 = S[4 + 2 * nq + j][r],
-            x123 = S[4 + 3 * nq + j][r];
-    const T d1 = sd1[r], d2 = sd2[r], d3 = sd3[r], x2 = sx2[r], x4 = sx4[r], x23 = sx23[r];
-    stg<T>(pre + (size_t)(1 + j) * m_outp + row0 + r, valid ? x1 : T(0));
-    S[4 + j][r] = valid ? d1 * x1 : T(0);
-    S[4 + nq + j][r] = valid ? d1 * x12 + d2 * x1 * x2 : T(0);
-    S[4 + 2 * nq + j][r] = valid ? d1 * x14 + d2 * x1 * x4 : T(0);
-    S[4 + 3 * nq + j][r] = valid ? d1 * x123 + d2 * (x1 * x23 + T(2) * x2 * x12) + d3 * x1 * x2 * x2 : T(0);
+  if (use) {
+    for (int p = tg; p < 16 * nq; p += NG) {
+      const int r = p & 15, j = p >> 4;
+      const bool valid = row0 + r < m_out;
+      const T x1 = Ss[4 + j][r], x12 = Ss[4 + nq + j][r], x14 = Ss[4 + 2 * nq + j][r], x123 = Ss[4 + 3 * nq + j][r];
+      const T d1 = sd1[slot][r], d2 = sd2[slot][r], d3 = sd3[slot][r];
+      const T x2 = sx2[slot][r], x4 = sx4[slot][r], x23 = sx23[slot][r];
+      stg<T>(pre + (size_t)(1 + j) * m_outp + row0 + r, valid ? x1 : T(0));
+      Ss[4 + j][r] = valid ? d1 * x1 : T(0);
+      Ss[4 + nq + j][r] = valid ? d1 * x12 + d2 * x1 * x2 : T(0);
+      Ss[4 + 2 * nq + j][r] = valid ? d1 * x14 + d2 * x1 * x4 : T(0);
+      Ss[4 + 3 * nq + j][r] = valid ? d1 * x123 + d2 * (x1 * x23 + T(2) * x2 * x12) + d3 * x1 * x2 * x2 : T(0);
+    }
   }
   __syncthreads();
+  if (!use) return;
   if (l + 2 < la.L) {
-    T* out = outp;
     const int C = 4 + 4 * nq;
-    for (int p = tid; p < C * 16; p += nthr) {
+    for (int p = tg; p < C * 16; p += NG) {
       const int c = p >> 4, r = p & 15;
-      stg<T>(out + (size_t)c * m_outp + row0 + r, S[c][r]);
+      stg<T>(outp + (size_t)c * m_outp + row0 + r, Ss[c][r]);
     }
   } else {
     // last hidden layer: fold into the output channels (the output layer is
     // linear, so eq. delta_j can be combined before it)
     const T dt = dtT;
     const int C = 2 + 2 * nq;
-    for (int p = tid; p < C * 16; p += nthr) {
+    for (int p = tg; p < C * 16; p += NG) {
       const int c = p >> 4, r = p & 15;
       T v;
-      if (c == 0) v = S[0][r];
-      else if (c <= nq) v = S[4 + c - 1][r];
+      if (c == 0) v = Ss[0][r];
+      else if (c <= nq) v = Ss[4 + c - 1][r];
       else if (c <= 2 * nq) {
         const int j = c - 1 - nq;
-        v = S[4 + 3 * nq + j][r] + T(3) * S[4 + nq + j][r] - dt * S[4 + 2 * nq + j][r];
-      } else v = S[3][r];
+        v = Ss[4 + 3 * nq + j][r] + T(3) * Ss[4 + nq + j][r] - dt * Ss[4 + 2 * nq + j][r];
+      } else v = Ss[3][r];
       stg<T>(fold + (size_t)c * m_outp + row0 + r, v);
     }
   }
@@ -630,14 +655,19 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(LayerArgs la, const Inst<T>*
 // transposed weights stored row-major), then either sigma' of layer l-1 or,
 // at the input, J^T a and a . H.
 // ---------------------------------------------------------------------------
-template <typename T, typename TW, int NCB>
-__global__ __launch_bounds__(512) void k_bwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab) {
+template <typename T, typename TW, int NCB, int IB>
+__global__ __launch_bounds__(512) void k_bwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab, int nb) {
   constexpr int NW = splitk_waves<T, NCB>::v;
-  const Inst<T>& I = tab[blockIdx.y];
+  constexpr int KSPL = NW / IB;
+  constexpr int NG = KSPL * 64;  // threads of one instance slot
   const int l = la.l;
   const int step = la.L - 2 - l;  // 0 for the last hidden layer
-  // the table entry's fields are read before the activity test so that their
-  // scalar loads leave together
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int slot = wave / KSPL, tg = tid - slot * NG;
+  const int inst = blockIdx.y * IB + slot;
+  const Inst<T>& I = tab[min(inst, nb - 1)];
+  // the table entry's fields are read before any test so that their scalar
+  // loads leave together
   const int active = I.active, nq = I.n_q;
   const T* xb = (step & 1) ? I.zb1 : I.zb0;
   T* const xb_out = (step & 1) ? I.zb0 : I.zb1;
@@ -647,50 +677,52 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(LayerArgs la, const Inst<T>*
   const int K = la.m_outp;  // reduction over the outputs of layer l
   const int m_in = la.m_in, m_inp = la.m_inp;
   load_now(active, nq, xb, xb_out, pre, JTa, Bq, K, m_in, m_inp, la.WT, la.act);
+  const bool use = inst < nb && active;
   const int row0 = blockIdx.x * 16;
-  if (!active || row0 >= m_inp) return;
-  const int tid = threadIdx.x, nthr = NW * 64;
+  if (row0 >= m_inp || (IB == 1 && !use)) return;  // uniform over the block
   const TW* WT = reinterpret_cast<const TW*>(la.WT) + (size_t)row0 * K;
-  __shared__ T S[NCB * 16][17];
+  __shared__ T S[IB][NCB * 16][17];
   __shared__ T red[NW][NCB * 16][16];
   typedef typename vec4<T>::type V4;
   auto bload = [&](int c, int k) -> V4 { return ldg<V4>(xb + (size_t)c * K + k); };
   // pre-activations of layer l-1 used by the epilogue, loaded before the GEMM
-  constexpr int PP = (16 * 32 + 255) / 256;  // items per thread (16 rows x (1 + n_q <= 32) / >= 256 threads)
+  constexpr int PP = (16 * 32 + NG - 1) / NG;  // items per thread: 16 rows x (1 + n_q <= 32) channels
   T px0[PP], px1[PP];
 #pragma unroll
   for (int t = 0; t < PP; ++t) {
-    const int p = tid + t * nthr;
+    const int p = tg + t * NG;
     px0[t] = px1[t] = T(0);
-    if (l > 0 && p < 16 * (1 + nq)) {
+    if (use && l > 0 && p < 16 * (1 + nq)) {
       const int r = p & 15, c = p >> 4;
       px0[t] = ldg<T>(pre + row0 + r);
       if (c > 0) px1[t] = ldg<T>(pre + (size_t)c * m_inp + row0 + r);
     }
   }
-  gemm_splitk<T, TW, NCB, NW>(WT, K, K, bload, S, red);
+  gemm_splitk<T, TW, NCB, NW, IB>(WT, K, K, use, bload, S, red);
+  if (!use) return;
+  T(*Ss)[17] = S[slot];
   if (l > 0) {
 #pragma unroll
     for (int t = 0; t < PP; ++t) {
-      const int p = tid + t * nthr;
+      const int p = tg + t * NG;
       if (p < 16 * (1 + nq)) {
         const int r = p & 15, c = p >> 4;
         const int row = row0 + r;
         T d1, d2;
         act_d12(la.act, px0[t], d1, d2);
         T v;
-        if (c == 0) v = d1 * S[0][r];
-        else v = d1 * S[c][r] + d2 * px1[t] * S[0][r];
+        if (c == 0) v = d1 * Ss[0][r];
+        else v = d1 * Ss[c][r] + d2 * px1[t] * Ss[0][r];
         stg<T>(xb_out + (size_t)c * m_inp + row, (row < m_in) ? v : T(0));
       }
     }
   } else {
-    for (int p = tid; p < 16 * (1 + nq); p += nthr) {
+    for (int p = tg; p < 16 * (1 + nq); p += NG) {
       const int r = p & 15, c = p >> 4;
       const int row = row0 + r;
       if (row < nq) {
-        if (c == 0) stg<double>(JTa + row, (double)S[0][r]);
-        else stg<double>(Bq + (size_t)row * nq + (c - 1), (double)S[c][r]);
+        if (c == 0) stg<double>(JTa + row, (double)Ss[0][r]);
+        else stg<double>(Bq + (size_t)row * nq + (c - 1), (double)Ss[c][r]);
       }
     }
   }
@@ -728,10 +760,20 @@ __global__ void k_unpack(const Inst<T>* __restrict__ tab, T* u, T* J, T* dJ, T* 
     default: break;           \
   }
 
+template <typename T, typename TW, int NCB>
+static void fwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb, hipStream_t s) {
+  const int tiles = d.wp[l + 1] / 16;
+  const int ib = stack_instances(tiles, nb, std::is_same<T, double>::value);
+  const int threads = 64 * splitk_waves<T, NCB>::v;
+  const LayerArgs la = layer_args(d, l);
+  if (ib == 4) k_fwd_hidden<T, TW, NCB, 4><<<dim3(tiles, (nb + 3) / 4), threads, 0, s>>>(la, tab, nb);
+  else if (ib == 2) k_fwd_hidden<T, TW, NCB, 2><<<dim3(tiles, (nb + 1) / 2), threads, 0, s>>>(la, tab, nb);
+  else k_fwd_hidden<T, TW, NCB, 1><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
+}
+
 template <typename T, typename TW>
 static void fwd_hidden_dispatch(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cp, hipStream_t s) {
-  dim3 grid(d.wp[l + 1] / 16, nb);
-#define FWD_H(n) k_fwd_hidden<T, TW, n><<<grid, 64 * splitk_waves<T, n>::v, 0, s>>>(layer_args(d, l), tab)
+#define FWD_H(n) fwd_hidden_ib<T, TW, n>(d, l, tab, nb, s)
   NCB_SWITCH(cp / 16, FWD_H)
 #undef FWD_H
 }
@@ -743,9 +785,10 @@ void launch_fwd_hidden<float>(const DecoderDev& d, int l, const Inst<float>* tab
 }
 template <>
 void launch_fwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* tab, int nb, int cp, hipStream_t s) {
-  // FP64 decoders take n_q <= 15, i.e. at most 4 column blocks
+  // FP64 decoders take n_q <= 15, i.e. at most 4 column blocks; one instance per block
   dim3 grid(d.wp[l + 1] / 16, nb);
-#define FWD_H64(n) k_fwd_hidden<double, double, n><<<grid, 64 * splitk_waves<double, n>::v, 0, s>>>(layer_args(d, l), tab)
+#define FWD_H64(n) \
+  k_fwd_hidden<double, double, n, 1><<<grid, 64 * splitk_waves<double, n>::v, 0, s>>>(layer_args(d, l), tab, nb)
   switch (cp / 16) {
     case 1: FWD_H64(1); break;
     case 2: FWD_H64(2); break;
@@ -807,18 +850,26 @@ void launch_bwd_reduce(const DecoderDev& d, const Inst<T>* tab, int nb, hipStrea
 template void launch_bwd_reduce<float>(const DecoderDev&, const Inst<float>*, int, hipStream_t);
 template void launch_bwd_reduce<double>(const DecoderDev&, const Inst<double>*, int, hipStream_t);
 
+template <typename T, typename TW, int NCB>
+static void bwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb, hipStream_t s) {
+  const int tiles = d.wp[l] / 16;
+  const int ib = stack_instances(tiles, nb, std::is_same<T, double>::value);
+  const int threads = 64 * splitk_waves<T, NCB>::v;
+  const LayerArgs la = layer_args(d, l);
+  if (ib == 4) k_bwd_hidden<T, TW, NCB, 4><<<dim3(tiles, (nb + 3) / 4), threads, 0, s>>>(la, tab, nb);
+  else if (ib == 2) k_bwd_hidden<T, TW, NCB, 2><<<dim3(tiles, (nb + 1) / 2), threads, 0, s>>>(la, tab, nb);
+  else k_bwd_hidden<T, TW, NCB, 1><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
+}
+
 template <typename T, typename TW>
 static void bwd_hidden_dispatch(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cb, hipStream_t s) {
-  dim3 grid(d.wp[l] / 16, nb);
-#define BWD_H(n) k_bwd_hidden<T, TW, n><<<grid, 64 * splitk_waves<T, n>::v, 0, s>>>(layer_args(d, l), tab)
   switch (cb / 16) {
-    case 1: BWD_H(1); break;
-    case 2: BWD_H(2); break;
-    case 3: BWD_H(3); break;
-    case 4: BWD_H(4); break;
+    case 1: bwd_hidden_ib<T, TW, 1>(d, l, tab, nb, s); break;
+    case 2: bwd_hidden_ib<T, TW, 2>(d, l, tab, nb, s); break;
+    case 3: bwd_hidden_ib<T, TW, 3>(d, l, tab, nb, s); break;
+    case 4: bwd_hidden_ib<T, TW, 4>(d, l, tab, nb, s); break;
     default: break;
   }
-#undef BWD_H
 }
 
 template <>
