@@ -376,6 +376,9 @@ def main():
                              budget_gb=200, slots_per_class=args.serve_slots)
                 var[f"served_{prec}"] = stats
                 log(f"served {prec}:", stats)
+        # NEXT row: the fictitious force and consistency in dt (FP64, through the C ABI)
+        from paper_2102_11026_amd import experiments
+        var["experiment_fictitious_force"] = experiments.consistency_in_dt(nmr, ctx, "fp64")
         out["variants"] = var
         log("variants:", var)
     inst.close()

@@ -98,6 +98,12 @@ typedef struct {
                             /*    constant, so Jt^T M Jt = F^T (W^T M W) F and  */
                             /*    only cubature DOFs are decoded per iteration); */
                             /* 1: direct (every DOF decoded each iteration)     */
+  int trimmed;              /* 0: the paper's formulation (eq. our_equation_   */
+                            /*    of_motion with f_fict); 1: f_fict dropped, as */
+                            /*    in latent space dynamics (Sec. 3.3, Sec. 6):  */
+                            /*    phi has no Jt^T M H(dq,dq) term and the Newton */
+                            /*    matrix is its exact derivative, i.e. dJ =     */
+                            /*    H.(dq - dt qdot) and Hdd = 0 in every output  */
 } nmr_problem;
 
 /* ---- lifecycle ---------------------------------------------------------- */

@@ -172,8 +172,14 @@ def right_contractions(weights, biases, act, q, dq, qdot_bar, n_rows=None, h=H_C
     )
 
 
-def delta_J(rc: dict, dt: float) -> np.ndarray:
-    """eq. delta_j: (S . dq) . dq + H . (3 dq - dt qdot_bar), per column j."""
+def delta_J(rc: dict, dt: float, trimmed: bool = False) -> np.ndarray:
+    """eq. delta_j: (S . dq) . dq + H . (3 dq - dt qdot_bar), per column j.
+
+    trimmed: the derivative of M J w_r alone, H . (dq - dt qdot_bar), which is
+    what remains of the Newton matrix once the fictitious force is dropped
+    (its derivative M (S . dq . dq + 2 H . dq) is the rest of eq. delta_j)."""
+    if trimmed:
+        return rc["Hdq"] - dt * rc["Hv"]
     return rc["Sdd"] + 3.0 * rc["Hdq"] - dt * rc["Hv"]
 
 

@@ -20,6 +20,11 @@ weight net at rbar once per step (Sec. 5.2).  The matrix is not symmetric
 each step from r = rbar and takes a fixed number of full steps; after them
 rdot = (r - rbar) / dt and rbar = r (Sec. 3.2).
 
+Trimmed formulation (the comparison with latent space dynamics, Sec. 3.3
+and Sec. 6): f_fict is dropped from phi, and the Newton matrix is the exact
+derivative of that phi, i.e. dJ becomes H . (dq - dt qdot_bar) and a has no
+M H(dq, dq) term.
+
 Parity: phi pinned by textbook reductions (full-space implicit Euler when
 the basis spans every free DOF; linear reduction for identity activations);
 the Newton matrix pinned by central differences of phi and by quadratic
@@ -76,9 +81,11 @@ class Instance:
             return dict(m=z, J=np.zeros((self.N, 0)), dJ=np.zeros((self.N, 0)), Hdd=z.copy())
         rc = dec.right_contractions(p.weights, p.biases, p.act, q, dq, qdot_bar,
                                     n_rows=self.N, h=self.h)
-        dJ = dec.delta_J(rc, self.dt)
+        trimmed = p.formulation == "trimmed"
+        dJ = dec.delta_J(rc, self.dt, trimmed)
         f = lambda x: dec.filter_pin(x, p.U, self.pin_dof)
-        return dict(m=f(rc["m"]), J=f(rc["J"]), dJ=f(dJ), Hdd=f(rc["Hdd"]))
+        Hdd = np.zeros(self.N) if trimmed else f(rc["Hdd"])
+        return dict(m=f(rc["m"]), J=f(rc["J"]), dJ=f(dJ), Hdd=Hdd)
 
     def left(self, q, a):
         """(J^T a, a . H) of D = P (I - U U^T) m through complex-step BP."""

@@ -497,6 +497,7 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   CHK(dalloc_t(M, (size_t)s.mblk_alloc * (s.R * s.R + s.R * s.n_q + s.R + s.n_p), &I.part_mass));
   CHK(dalloc_t(M, (size_t)s.bblk_alloc * d.wp[s.L - 1], &I.part_bwd));
   I.gram = s.gram;
+  I.trimmed = p->trimmed;
   I.n_gblk = s.n_gblk;
   I.n_cdofs = s.n_cdofs;
   I.n_sblk = s.n_sblk;
@@ -630,7 +631,8 @@ extern "C" int nmr_instance_create(nmr_ctx* ctx, const nmr_problem* p, int prec,
   CHK(set_device(ctx));
   if (prec < PREC_FP64 || prec > PREC_BF16) return fail(NMR_ERR_ARG, "bad precision");
   if (p->n_vertices <= 0 || !p->X || p->n_tets <= 0 || !p->tets || !p->pinned || p->n_cub <= 0 || !p->cub_ids ||
-      !p->r0 || !p->rdot0 || p->n_p < 0 || (p->n_p > 0 && !p->U) || !(p->dt > 0))
+      !p->r0 || !p->rdot0 || p->n_p < 0 || (p->n_p > 0 && !p->U) || !(p->dt > 0) ||
+      (p->trimmed != 0 && p->trimmed != 1))
     return fail(NMR_ERR_ARG, "incomplete problem");
   nmr_decoder* dec = p->shared_decoder;
   bool own = false;

@@ -269,7 +269,7 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
   const Inst<T>& I = tab[min(inst, nb - 1)];
   // the table entry's fields are read before any test so that their scalar
   // loads leave together
-  const int active = I.active, nq = I.n_q;
+  const int active = I.active, nq = I.n_q, trimmed = I.trimmed;
   const T* X = (l & 1) ? I.act0 : I.act1;
   T* const outp = (l & 1) ? I.act1 : I.act0;
   T* const pre = I.pre[l];
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
   const double* din = I.dec_in;
   const double dt64 = I.dt;
   const int m_inp = la.m_inp, m_out = la.m_out, m_outp = la.m_outp;
-  load_now(active, nq, X, outp, pre, fold, din, dt64, m_inp, m_out, m_outp, la.W, la.b, la.act, la.L);
+  load_now(active, nq, trimmed, X, outp, pre, fold, din, dt64, m_inp, m_out, m_outp, la.W, la.b, la.act, la.L);
   const bool use = inst < nb && active;
   const T dtT = (T)dt64;
   const int row0 = blockIdx.x * 16;
@@ -351,7 +351,8 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
     }
   } else {
     // last hidden layer: fold into the output channels (the output layer is
-    // linear, so eq. delta_j can be combined before it)
+    // linear, so eq. delta_j can be combined before it); the trimmed
+    // formulation keeps H.(dq - dt qdot) and no H(dq, dq)
     const T dt = dtT;
     const int C = 2 + 2 * nq;
     for (int p = tg; p < C * 16; p += NG) {
@@ -361,8 +362,9 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
       else if (c <= nq) v = Ss[4 + c - 1][r];
       else if (c <= 2 * nq) {
         const int j = c - 1 - nq;
-        v = Ss[4 + 3 * nq + j][r] + T(3) * Ss[4 + nq + j][r] - dt * Ss[4 + 2 * nq + j][r];
-      } else v = Ss[3][r];
+        v = trimmed ? Ss[4 + nq + j][r] - dt * Ss[4 + 2 * nq + j][r]
+                    : Ss[4 + 3 * nq + j][r] + T(3) * Ss[4 + nq + j][r] - dt * Ss[4 + 2 * nq + j][r];
+      } else v = trimmed ? T(0) : Ss[3][r];
       stg<T>(fold + (size_t)c * m_outp + row0 + r, v);
     }
   }

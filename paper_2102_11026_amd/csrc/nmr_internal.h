@@ -60,6 +60,7 @@ struct DecoderDev {
 template <typename T>
 struct Inst {
   int active;              // 0: an empty slot of a pool; every kernel returns at once
+  int trimmed;             // 1: fictitious force dropped (dJ = H.(dq - dt qdot), Hdd = 0)
   int N, n, n_p, n_q, R, n_cub;
   int Cp, Cb, Cf;          // padded channel counts: forward, backward, output
   int Np;                  // N padded to NMR_WPAD

@@ -159,6 +159,7 @@ class Problem:
     newton_iters: int = 1
     out_rows: int = 0          # rows of the output layer (>= N; prefix used)
     meta: dict = field(default_factory=dict)
+    formulation: str = "full"  # "full" | "trimmed" (fictitious force dropped)
 
     @property
     def n(self) -> int:
@@ -368,6 +369,19 @@ def config_rods(n_rods: int = 320):
     """All rods of the batched workload, sharing one decoder."""
     dec = rod_decoder()
     return [rod_problem(i, n_rods, dec) for i in range(n_rods)]
+
+
+def lsd_problem() -> Problem:
+    """Fast-motion problem of the fictitious-force comparison: a soft 3 x 3 x 10
+    vertex bar (E = 1e3), n_p = 0, full quadrature, a sine decoder
+    [3, 32, 32, 32, 270] whose first layer has 10x the Xavier gain (the
+    latent map is curved over one step's displacement), output scaled by
+    0.05, started at rest shape with an abrupt latent velocity of 2 N(0, 1)."""
+    p = tiny_problem(grid=(3, 3, 10), widths=(3, 32, 32, 32, 270), act="sin", n_p=0, name="lsd", q_std=0.0,
+                     out_scale=0.05)
+    W = [w.copy() for w in p.weights]
+    W[0] = W[0] * 10.0
+    return p.replace(E=1e3, weights=W, rdot0=2.0 * normal("lsd/rdot0", p.R), steps=15, newton_iters=6)
 
 
 def tiny_problem(grid=(2, 2, 3), widths=(2, 4, 4, 36), act="tanh", n_p=0, n_cub=0,

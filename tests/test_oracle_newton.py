@@ -163,3 +163,51 @@ def test_wnet_closed_form():
     # one layer, generic: scale * log(1 + exp(W r + b))
     W, b, r = rng.normal(size=(6, 3)), rng.normal(size=6), rng.normal(size=3)
     np.testing.assert_allclose(wnet_weights([W], [b], 1.7, r), 1.7 * np.log1p(np.exp(W @ r + b)), rtol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# trimmed formulation: the fictitious force dropped (Sec. 3.3, Sec. 6)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("act,n_p", [("tanh", 0), ("sin", 2)])
+def test_trimmed_newton_matrix_is_the_derivative_of_trimmed_phi(act, n_p):
+    """With f_fict dropped, dJ = H . (dq - dt qdot_bar) and a without M Hdd
+    still give the exact Newton matrix of the trimmed phi (central differences)."""
+    p = synth.tiny_problem(widths=(2, 6, 6, 36), act=act, n_p=n_p, name=f"tr{act}{n_p}", q_std=0.3, out_scale=0.05)
+    inst = Instance(p.replace(formulation="trimmed"))
+    r, rbar, rdot = moving_state(inst)
+    w = np.ones(p.tets.shape[0]) * 1.3
+    A = inst.system(r, rbar, rdot, w)["A"]
+    eps = 1e-6
+    fd = np.stack([(inst.system(r + eps * e, rbar, rdot, w)["phi"] - inst.system(r - eps * e, rbar, rdot, w)["phi"])
+                   / (2 * eps) for e in np.eye(inst.R)], axis=1)
+    np.testing.assert_allclose(A, fd, rtol=1e-6, atol=1e-6 * np.abs(A).max())
+    # the full-formulation matrix is not the derivative of the trimmed phi
+    A_full = Instance(p).system(r, rbar, rdot, w)["A"]
+    assert np.abs(A_full - fd).max() > 1e3 * np.abs(A - fd).max()
+
+
+def test_trimmed_equals_full_for_a_linear_decoder():
+    """Identity activations: H = S = 0, so dropping f_fict changes nothing."""
+    p = synth.tiny_problem(widths=(2, 6, 6, 36), act="identity", n_p=1, name="trlin", q_std=0.3, out_scale=0.05)
+    a, b = Instance(p), Instance(p.replace(formulation="trimmed"))
+    r, rbar, rdot = moving_state(a)
+    w = np.ones(p.tets.shape[0])
+    sa, sb = a.system(r, rbar, rdot, w), b.system(r, rbar, rdot, w)
+    np.testing.assert_array_equal(sa["phi"], sb["phi"])
+    np.testing.assert_array_equal(sa["A"], sb["A"])
+
+
+def test_full_minus_trimmed_phi_is_the_fictitious_force():
+    """phi_full - phi_trimmed = Jt^T M H(dq, dq), H from the exhaustive
+    one-pass-per-pair Hessian (eq. mcfd_hessian), not from the collective seed."""
+    p = synth.tiny_problem(widths=(3, 8, 8, 36), act="sin", n_p=2, name="trff", q_std=0.3, out_scale=0.05)
+    full, trim = Instance(p), Instance(p.replace(formulation="trimmed"))
+    r, rbar, rdot = moving_state(full, scale=0.02)
+    w = np.ones(p.tets.shape[0])
+    sf, st = full.system(r, rbar, rdot, w), trim.system(r, rbar, rdot, w)
+    q, dq = r[p.n_p:], (r - rbar)[p.n_p:]
+    H = dec.full_hessian(p.weights, p.biases, p.act, q)[: p.N]
+    Hdd = dec.filter_pin(np.einsum("ikl,k,l->i", H, dq, dq), p.U, full.pin_dof)
+    Jt = np.concatenate([p.U, sf["J"]], axis=1)
+    np.testing.assert_allclose(sf["phi"] - st["phi"], Jt.T @ (full.mass * Hdd), rtol=1e-9,
+                               atol=1e-12 * np.abs(sf["phi"]).max())
