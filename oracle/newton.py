@@ -38,6 +38,7 @@ import numpy as np
 import scipy.linalg
 
 from . import decoder as dec
+from . import fd
 from . import fem
 from .wnet import wnet_weights
 
@@ -51,9 +52,12 @@ class State:
 class Instance:
     """Precomputed rest-shape data of one problem (a synth.Problem)."""
 
-    def __init__(self, prob, h_cs: float = dec.H_CS):
+    def __init__(self, prob, h_cs: float = dec.H_CS, fd_h: float = None, fd_dtype=np.float64):
+        """fd_h: derivatives by recursive central differences of step fd_h
+        (oracle/fd.py, evaluated in fd_dtype) instead of complex steps."""
         self.p = prob
         self.h = h_cs
+        self.fd_h, self.fd_dtype = fd_h, fd_dtype
         self.N = prob.N
         self.n_p = prob.n_p
         self.n_q = prob.n_q if prob.weights else 0
@@ -79,8 +83,11 @@ class Instance:
         if self.n_q == 0:
             z = np.zeros(self.N)
             return dict(m=z, J=np.zeros((self.N, 0)), dJ=np.zeros((self.N, 0)), Hdd=z.copy())
-        rc = dec.right_contractions(p.weights, p.biases, p.act, q, dq, qdot_bar,
-                                    n_rows=self.N, h=self.h)
+        if self.fd_h is None:
+            rc = dec.right_contractions(p.weights, p.biases, p.act, q, dq, qdot_bar, n_rows=self.N, h=self.h)
+        else:
+            rc = fd.right_contractions_fd(p.weights, p.biases, p.act, q, dq, qdot_bar, n_rows=self.N, h=self.fd_h,
+                                          dtype=self.fd_dtype)
         trimmed = p.formulation == "trimmed"
         dJ = dec.delta_J(rc, self.dt, trimmed)
         f = lambda x: dec.filter_pin(x, p.U, self.pin_dof)
@@ -91,6 +98,8 @@ class Instance:
         """(J^T a, a . H) of D = P (I - U U^T) m through complex-step BP."""
         p = self.p
         s = dec.filter_pin_T(a, p.U, self.pin_dof)
+        if self.fd_h is not None:
+            return fd.left_contraction_fd(p.weights, p.biases, p.act, q, s, h=self.fd_h, dtype=self.fd_dtype)
         return dec.left_contraction(p.weights, p.biases, p.act, q, s, h=self.h)
 
     # -- one Newton linearisation ------------------------------------------
