@@ -379,6 +379,7 @@ def main():
         # NEXT row: the fictitious force and consistency in dt (FP64, through the C ABI)
         from paper_2102_11026_amd import experiments
         var["experiment_fictitious_force"] = experiments.consistency_in_dt(nmr, ctx, "fp64")
+        var["experiment_fd_vs_csfd"] = experiments.fd_vs_csfd(nmr, ctx)
         out["variants"] = var
         log("variants:", var)
     inst.close()

@@ -104,6 +104,12 @@ typedef struct {
                             /*    phi has no Jt^T M H(dq,dq) term and the Newton */
                             /*    matrix is its exact derivative, i.e. dJ =     */
                             /*    H.(dq - dt qdot) and Hdd = 0 in every output  */
+  double fd_h;              /* 0: derivatives by collective complex steps (the  */
+                            /*    paper); > 0: by recursive central differences */
+                            /*    of step fd_h instead (the comparison of Sec. */
+                            /*    6): 14 n_q + 3 plain forward passes and real */
+                            /*    backpropagation at q, q +- fd_h e_j.  Needs   */
+                            /*    n_q <= 8 (n_q <= 4 in FP64)                   */
 } nmr_problem;
 
 /* ---- lifecycle ---------------------------------------------------------- */

@@ -57,7 +57,8 @@ class Instance:
         (oracle/fd.py, evaluated in fd_dtype) instead of complex steps."""
         self.p = prob
         self.h = h_cs
-        self.fd_h, self.fd_dtype = fd_h, fd_dtype
+        self.fd_h = fd_h if fd_h is not None else (prob.fd_h if getattr(prob, "fd_h", 0.0) > 0 else None)
+        self.fd_dtype = fd_dtype
         self.N = prob.N
         self.n_p = prob.n_p
         self.n_q = prob.n_q if prob.weights else 0

@@ -116,6 +116,7 @@ struct nmr_inst {
   int N = 0, n = 0, n_p = 0, n_q = 0, R = 0, n_cub = 0;
   int Cp = 0, Cb = 0, Cf = 0, n_mblk = 0, n_cblk = 0, n_bblk = 0;
   int gram = 0, n_cdofs = 0, n_sblk = 0;
+  int fd = 0;  // central-difference derivatives
   size_t bytes = 0;
   DevMem mem;
   void* tab = nullptr;      // Inst<T> on the device
@@ -391,8 +392,12 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   s.R = s.n_p + s.n_q;
   s.n_cub = p->n_cub;
   s.L = d.L;
-  s.Cp = pad_to(4 + 4 * s.n_q, 16);
-  s.Cb = pad_to(1 + s.n_q, 16);
+  // jet channels (complex steps) or stencil columns (central differences)
+  const bool fd = p->fd_h > 0;
+  s.Cp = fd ? pad_to(14 * s.n_q + 3, 16) : pad_to(4 + 4 * s.n_q, 16);
+  s.Cb = fd ? pad_to(1 + 2 * s.n_q, 16) : pad_to(1 + s.n_q, 16);
+  if (fd && s.Cp > (d.prec == PREC_FP64 ? 64 : 128))
+    return fail(NMR_ERR_ARG, "central-difference derivatives need n_q <= 8 (n_q <= 4 in FP64)");
   s.Cf = pad_to(2 + 2 * s.n_q, 16);
   s.Wmax = 0;
   for (int l = 1; l < d.L; ++l) s.Wmax = std::max(s.Wmax, d.wp[l]);
@@ -452,6 +457,7 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   in->Cp = s.Cp; in->Cb = s.Cb; in->Cf = s.Cf;
   in->n_mblk = s.n_mblk; in->n_cblk = s.n_cblk; in->n_bblk = s.n_bblk;
   in->gram = s.gram; in->n_cdofs = s.n_cdofs; in->n_sblk = s.n_sblk;
+  in->fd = p->fd_h > 0 ? 1 : 0;
   in->host.assign(sizeof(Inst<T>), 0);
   Inst<T>& I = host_inst<T>(in);
   I.active = 1;
@@ -498,6 +504,8 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   CHK(dalloc_t(M, (size_t)s.bblk_alloc * d.wp[s.L - 1], &I.part_bwd));
   I.gram = s.gram;
   I.trimmed = p->trimmed;
+  I.fd = p->fd_h > 0 ? 1 : 0;
+  I.fd_h = p->fd_h;
   I.n_gblk = s.n_gblk;
   I.n_cdofs = s.n_cdofs;
   I.n_sblk = s.n_sblk;
@@ -632,7 +640,7 @@ extern "C" int nmr_instance_create(nmr_ctx* ctx, const nmr_problem* p, int prec,
   if (prec < PREC_FP64 || prec > PREC_BF16) return fail(NMR_ERR_ARG, "bad precision");
   if (p->n_vertices <= 0 || !p->X || p->n_tets <= 0 || !p->tets || !p->pinned || p->n_cub <= 0 || !p->cub_ids ||
       !p->r0 || !p->rdot0 || p->n_p < 0 || (p->n_p > 0 && !p->U) || !(p->dt > 0) ||
-      (p->trimmed != 0 && p->trimmed != 1))
+      (p->trimmed != 0 && p->trimmed != 1) || !(p->fd_h >= 0) || !std::isfinite(p->fd_h))
     return fail(NMR_ERR_ARG, "incomplete problem");
   nmr_decoder* dec = p->shared_decoder;
   bool own = false;
@@ -702,6 +710,7 @@ struct Group {
   void* tab;  // device array of Inst<T>
   int nb, Cp, Cb, Cf, maxN, maxR, n_q, max_mblk, max_cblk, max_bblk, max_entries, max_cub;
   bool any_np;
+  bool fd;  // central-difference derivatives (every member: the column count says so)
   bool gram;  // every table entry runs the Gram-folded path
   int max_cdofs, max_sblk, n_gblk, K;
 };
@@ -713,6 +722,7 @@ static Group group_of(const std::vector<nmr_inst*>& v, void* tab) {
   g.tab = tab;
   g.nb = (int)v.size();
   g.Cp = v[0]->Cp; g.Cb = v[0]->Cb; g.Cf = v[0]->Cf; g.n_q = v[0]->n_q;
+  g.fd = v[0]->fd != 0;
   g.K = g.dec->d.wp[g.dec->d.L - 1];
   g.n_gblk = g.K / 16;
   g.gram = true;
@@ -736,7 +746,7 @@ template <typename T>
 static void enqueue_decoder_fwd(const Group& g, hipStream_t s, int add_up) {
   const DecoderDev& d = g.dec->d;
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
-  for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, s);
+  for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, s);
   launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, s);
   if (g.any_np) launch_filter<T>(tab, g.nb, add_up, s);
 }
@@ -747,7 +757,7 @@ static void enqueue_decoder_bwd(const Group& g, hipStream_t s) {
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
   launch_bwd_out<T>(d, tab, g.nb, g.gram ? g.max_sblk : g.max_bblk, s);
   launch_bwd_reduce<T>(d, tab, g.nb, s);
-  for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, s);
+  for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, g.fd, s);
 }
 
 template <typename T>
@@ -838,9 +848,11 @@ extern "C" int step_many(nmr_ctx* c, nmr_inst* const* insts, int n_inst, int n_s
   auto git = per_k.find(n_iters);
   if (git == per_k.end()) {
     // group by decoder (instances sharing weights run as one batched launch)
+    // and derivative scheme (the column count of the decoder passes)
     std::vector<std::pair<nmr_decoder*, std::vector<nmr_inst*>>> byd;
     for (nmr_inst* in : key) {
-      auto f = std::find_if(byd.begin(), byd.end(), [&](auto& pr) { return pr.first == in->dec; });
+      auto f = std::find_if(byd.begin(), byd.end(),
+                            [&](auto& pr) { return pr.first == in->dec && pr.second[0]->Cp == in->Cp; });
       if (f == byd.end()) byd.push_back({in->dec, {in}});
       else f->second.push_back(in);
     }
@@ -1098,7 +1110,8 @@ extern "C" int nmr_pool_destroy(nmr_pool* p) {
 }
 
 static bool same_class(const nmr_inst* a, const nmr_inst* b) {
-  return a->dec == b->dec && a->prec == b->prec && a->N == b->N && a->n_p == b->n_p && a->n_q == b->n_q &&
+  return a->dec == b->dec && a->prec == b->prec && a->Cp == b->Cp && a->N == b->N && a->n_p == b->n_p &&
+         a->n_q == b->n_q &&
          a->n_cub == b->n_cub && a->n_mblk == b->n_mblk && a->n_cblk == b->n_cblk && a->n_bblk == b->n_bblk;
 }
 
@@ -1192,7 +1205,7 @@ static void enqueue_phase(const Group& g, int phase, hipStream_t s) {
   const DecoderDev& d = g.dec->d;
   switch (phase) {
     case NMR_PHASE_DEC_HIDDEN:
-      for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, s);
+      for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, s);
       break;
     case NMR_PHASE_DEC_OUT:
       launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, s);
@@ -1207,7 +1220,7 @@ static void enqueue_phase(const Group& g, int phase, hipStream_t s) {
     case NMR_PHASE_BWD_OUT: launch_bwd_out<T>(d, tab, g.nb, g.gram ? g.max_sblk : g.max_bblk, s); break;
     case NMR_PHASE_BWD_HIDDEN:
       launch_bwd_reduce<T>(d, tab, g.nb, s);
-      for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, s);
+      for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, g.fd, s);
       break;
     case NMR_PHASE_SOLVE: launch_solve<T>(tab, g.nb, 0, SOLVE_UPDATE, nullptr, nullptr, s); break;
     default: break;

@@ -257,7 +257,30 @@ __host__ inline int stack_instances(int row_tiles, int nb, bool f64) {
 // ---------------------------------------------------------------------------
 // Forward hidden layer l with the jet activation.  One block per 16 rows.
 // ---------------------------------------------------------------------------
-template <typename T, typename TW, int NCB, int IB>
+// Input k of stencil column c of the central differences (the column order
+// of the last hidden layer's stencils; zero past the 14 n_q + 3 columns).
+template <typename T>
+__device__ inline T fd_input(int c, int k, int nq, T q, T dq, T qd, T h) {
+  if (c == 0) return q;
+  if (c < 1 + 2 * nq) {
+    const int idx = c - 1, j = idx >> 1;
+    return q + ((k == j) ? ((idx & 1) ? -h : h) : T(0));
+  }
+  if (c < 1 + 14 * nq) {
+    const int idx = c - 1 - 2 * nq, blk = idx / (4 * nq), rem = idx - blk * 4 * nq;
+    const int j = rem >> 2, sub = rem & 3;
+    const T e = (k == j) ? ((sub & 1) ? -h : h) : T(0);
+    const T v = (blk == 1 ? h * qd : blk == 2 ? T(2) * h * dq : h * dq);
+    return (q + e) + ((sub & 2) ? -v : v);
+  }
+  if (c < 3 + 14 * nq) {
+    const T v = T(2) * h * dq;
+    return (c == 1 + 14 * nq) ? q + v : q - v;
+  }
+  return T(0);
+}
+
+template <typename T, typename TW, int NCB, int IB, bool FD>
 __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab, int nb) {
   constexpr int NW = splitk_waves<T, NCB>::v;
   constexpr int KSPL = NW / IB;
@@ -269,15 +292,16 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
   const Inst<T>& I = tab[min(inst, nb - 1)];
   // the table entry's fields are read before any test so that their scalar
   // loads leave together
+  constexpr bool fd = FD;  // central differences instead of complex-step jets
   const int active = I.active, nq = I.n_q, trimmed = I.trimmed;
   const T* X = (l & 1) ? I.act0 : I.act1;
   T* const outp = (l & 1) ? I.act1 : I.act0;
   T* const pre = I.pre[l];
   T* const fold = I.fold;
   const double* din = I.dec_in;
-  const double dt64 = I.dt;
+  const double dt64 = I.dt, fdh64 = I.fd_h;
   const int m_inp = la.m_inp, m_out = la.m_out, m_outp = la.m_outp;
-  load_now(active, nq, trimmed, X, outp, pre, fold, din, dt64, m_inp, m_out, m_outp, la.W, la.b, la.act, la.L);
+  load_now(active, nq, trimmed, X, outp, pre, fold, din, dt64, fdh64, m_inp, m_out, m_outp, la.W, la.b, la.act, la.L);
   const bool use = inst < nb && active;
   const T dtT = (T)dt64;
   const int row0 = blockIdx.x * 16;
@@ -292,6 +316,21 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
   // the bias of this tile is loaded before the GEMM (no dependent round trip)
   const T bias_v = (tg < 16 && row0 + tg < m_out) ? ldg<T>(bias + row0 + tg) : T(0);
   auto bload = [&](int c, int k) -> V4 {
+    if (FD && l == 0) {
+      // stencil columns of the central differences: q, q +- h e_j, then per j
+      // q +- h e_j +- v for v = h dq, h qdot, 2h dq, then q +- 2h dq; every
+      // input formed in T (loads from clamped indices, then selects)
+      T v[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int kk = min(k + t, nq - 1);
+        const T q = (T)ldg<double>(din + kk), dq = (T)ldg<double>(din + nq + kk);
+        const T qd = (T)ldg<double>(din + 2 * nq + kk);
+        v[t] = fd_input<T>(c, kk, nq, q, dq, qd, (T)fdh64);
+        v[t] = (k + t < nq) ? v[t] : T(0);
+      }
+      return V4{v[0], v[1], v[2], v[3]};
+    }
     if (l == 0) {
       // input jets: value q, tangents dq (i2) and qdot (i4), unit e_j (i1);
       // loads from clamped indices, then selects (no load under a branch)
@@ -311,6 +350,27 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
   gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload, S, red);
 
   T(*Ss)[17] = S[slot];
+  if constexpr (FD) {
+    // central differences: every column is a forward pass of its own (bias
+    // and activation on each); the base and q +- h e_j keep their
+    // pre-activations for backpropagation.  fd is the same for every slot.
+    __shared__ T sbias[IB][16];
+    if (use && tg < 16) sbias[slot][tg] = bias_v;
+    __syncthreads();
+    if (use) {
+      const int C = 14 * nq + 3;
+      for (int p = tg; p < 16 * C; p += NG) {
+        const int r = p & 15, c = p >> 4;
+        const bool valid = row0 + r < m_out;
+        const T x = Ss[c][r] + sbias[slot][r];
+        T y, d1, d2, d3;
+        act_jet(la.act, x, y, d1, d2, d3);
+        if (c < 1 + 2 * nq) stg<T>(pre + (size_t)c * m_outp + row0 + r, valid ? x : T(0));
+        Ss[c][r] = valid ? y : T(0);
+      }
+    }
+    __syncthreads();
+  } else {
   if (use && tg < 16) {
     const int row = row0 + tg;
     const bool valid = row < m_out;
@@ -342,9 +402,10 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
     }
   }
   __syncthreads();
+  }
   if (!use) return;
   if (l + 2 < la.L) {
-    const int C = 4 + 4 * nq;
+    const int C = fd ? 14 * nq + 3 : 4 + 4 * nq;
     for (int p = tg; p < C * 16; p += NG) {
       const int c = p >> 4, r = p & 15;
       stg<T>(outp + (size_t)c * m_outp + row0 + r, Ss[c][r]);
@@ -355,6 +416,34 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
     // formulation keeps H.(dq - dt qdot) and no H(dq, dq)
     const T dt = dtT;
     const int C = 2 + 2 * nq;
+    if constexpr (FD) {
+      // the stencils of the central differences (as in the FP64 oracle's
+      // order of operations); the trimmed formulation as above
+      const T h = (T)fdh64, h2 = T(2) * h, h4 = T(4) * h * h;
+      const int base = 1 + 2 * nq;
+      for (int p = tg; p < C * 16; p += NG) {
+        const int c = p >> 4, r = p & 15;
+        T v;
+        if (c == 0) v = Ss[0][r];
+        else if (c <= nq) {
+          const int j = c - 1;
+          v = (Ss[1 + 2 * j][r] - Ss[2 + 2 * j][r]) / h2;
+        } else if (c <= 2 * nq) {
+          const int j = c - 1 - nq;
+          const int b0 = base + 4 * j, b1 = base + 4 * (nq + j), b2 = base + 4 * (2 * nq + j);
+          const T Hdq = (Ss[b0][r] - Ss[b0 + 1][r] - Ss[b0 + 2][r] + Ss[b0 + 3][r]) / h4;
+          const T Hv = (Ss[b1][r] - Ss[b1 + 1][r] - Ss[b1 + 2][r] + Ss[b1 + 3][r]) / h4;
+          const T gp = (Ss[b2][r] - T(2) * Ss[1 + 2 * j][r] + Ss[b2 + 2][r]) / h4;
+          const T gm = (Ss[b2 + 1][r] - T(2) * Ss[2 + 2 * j][r] + Ss[b2 + 3][r]) / h4;
+          const T Sdd = (gp - gm) / h2;
+          v = trimmed ? Hdq - dt * Hv : Sdd + T(3) * Hdq - dt * Hv;
+        } else {
+          v = trimmed ? T(0) : (Ss[base + 12 * nq][r] - T(2) * Ss[0][r] + Ss[base + 12 * nq + 1][r]) / h4;
+        }
+        stg<T>(fold + (size_t)c * m_outp + row0 + r, v);
+      }
+      return;
+    }
     for (int p = tg; p < C * 16; p += NG) {
       const int c = p >> 4, r = p & 15;
       T v;
@@ -620,8 +709,8 @@ __global__ __launch_bounds__(256) void k_bwd_out(LayerArgs la, const Inst<T>* __
 template <typename T>
 __global__ __launch_bounds__(256) void k_bwd_reduce(LayerArgs la, const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
-  load_now(I.active, I.gram, I.n_sblk, I.n_bblk, I.part_bwd, I.pre[la.l - 1], I.zb0, I.n_q, la.m_inp, la.m_in,
-           la.act);
+  load_now(I.active, I.gram, I.fd, I.n_sblk, I.n_bblk, I.part_bwd, I.pre[la.l - 1], I.zb0, I.n_q, la.m_inp,
+           la.m_in, la.act);
   if (!I.active) return;
   const int l = la.l;  // output layer; its input is hidden layer l-1
   const int K = la.m_inp;
@@ -641,14 +730,23 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(LayerArgs la, const Inst<T>*
     double zb0 = part[0][kk];
     for (int q = 1; q < 16; ++q) zb0 += part[q][kk];
     const T* pre = I.pre[l - 1];
-    const T x0 = ldg<T>(pre + k);
-    T d1, d2;
-    act_d12(la.act, x0, d1, d2);
     T* xb = I.zb0;
-    stg<T>(xb + k, (k < la.m_in) ? (T)(d1 * zb0) : T(0));
-    for (int j = 0; j < I.n_q; ++j)
-      stg<T>(xb + (size_t)(1 + j) * K + k,
-             (k < la.m_in) ? (T)(d2 * ldg<T>(pre + (size_t)(1 + j) * K + k) * zb0) : T(0));
+    if (I.fd) {
+      // real backpropagation of every kept stencil column (base, q +- h e_j)
+      for (int c = 0; c < 1 + 2 * I.n_q; ++c) {
+        T d1, d2;
+        act_d12(la.act, ldg<T>(pre + (size_t)c * K + k), d1, d2);
+        stg<T>(xb + (size_t)c * K + k, (k < la.m_in) ? (T)(d1 * zb0) : T(0));
+      }
+    } else {
+      const T x0 = ldg<T>(pre + k);
+      T d1, d2;
+      act_d12(la.act, x0, d1, d2);
+      stg<T>(xb + k, (k < la.m_in) ? (T)(d1 * zb0) : T(0));
+      for (int j = 0; j < I.n_q; ++j)
+        stg<T>(xb + (size_t)(1 + j) * K + k,
+               (k < la.m_in) ? (T)(d2 * ldg<T>(pre + (size_t)(1 + j) * K + k) * zb0) : T(0));
+    }
   }
 }
 
@@ -657,7 +755,7 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(LayerArgs la, const Inst<T>*
 // transposed weights stored row-major), then either sigma' of layer l-1 or,
 // at the input, J^T a and a . H.
 // ---------------------------------------------------------------------------
-template <typename T, typename TW, int NCB, int IB>
+template <typename T, typename TW, int NCB, int IB, bool FD>
 __global__ __launch_bounds__(512) void k_bwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab, int nb) {
   constexpr int NW = splitk_waves<T, NCB>::v;
   constexpr int KSPL = NW / IB;
@@ -670,15 +768,20 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(LayerArgs la, const Inst<T>*
   const Inst<T>& I = tab[min(inst, nb - 1)];
   // the table entry's fields are read before any test so that their scalar
   // loads leave together
+  constexpr bool fd = FD;  // central differences instead of complex-step jets
   const int active = I.active, nq = I.n_q;
   const T* xb = (step & 1) ? I.zb1 : I.zb0;
   T* const xb_out = (step & 1) ? I.zb0 : I.zb1;
   const T* pre = (l > 0) ? I.pre[l - 1] : nullptr;
   double* const JTa = I.JTa;
   double* const Bq = I.Bq;
+  const double fdh64 = I.fd_h;
   const int K = la.m_outp;  // reduction over the outputs of layer l
   const int m_in = la.m_in, m_inp = la.m_inp;
-  load_now(active, nq, xb, xb_out, pre, JTa, Bq, K, m_in, m_inp, la.WT, la.act);
+  load_now(active, nq, xb, xb_out, pre, JTa, Bq, fdh64, K, m_in, m_inp, la.WT, la.act);
+  // channels: value and the e_j tangents (complex steps), or the base and
+  // q +- h e_j stencil columns (central differences)
+  const int nch = fd ? 1 + 2 * nq : 1 + nq;
   const bool use = inst < nb && active;
   const int row0 = blockIdx.x * 16;
   if (row0 >= m_inp || (IB == 1 && !use)) return;  // uniform over the block
@@ -694,7 +797,7 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(LayerArgs la, const Inst<T>*
   for (int t = 0; t < PP; ++t) {
     const int p = tg + t * NG;
     px0[t] = px1[t] = T(0);
-    if (use && l > 0 && p < 16 * (1 + nq)) {
+    if (use && l > 0 && p < 16 * nch) {
       const int r = p & 15, c = p >> 4;
       px0[t] = ldg<T>(pre + row0 + r);
       if (c > 0) px1[t] = ldg<T>(pre + (size_t)c * m_inp + row0 + r);
@@ -707,14 +810,20 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(LayerArgs la, const Inst<T>*
 #pragma unroll
     for (int t = 0; t < PP; ++t) {
       const int p = tg + t * NG;
-      if (p < 16 * (1 + nq)) {
+      if (p < 16 * nch) {
         const int r = p & 15, c = p >> 4;
         const int row = row0 + r;
-        T d1, d2;
-        act_d12(la.act, px0[t], d1, d2);
         T v;
-        if (c == 0) v = d1 * Ss[0][r];
-        else v = d1 * Ss[c][r] + d2 * px1[t] * Ss[0][r];
+        if constexpr (FD) {  // each column through sigma' of its own pre-activation
+          T d1, d2;
+          act_d12(la.act, c == 0 ? px0[t] : px1[t], d1, d2);
+          v = d1 * Ss[c][r];
+        } else {
+          T d1, d2;
+          act_d12(la.act, px0[t], d1, d2);
+          if (c == 0) v = d1 * Ss[0][r];
+          else v = d1 * Ss[c][r] + d2 * px1[t] * Ss[0][r];
+        }
         stg<T>(xb_out + (size_t)c * m_inp + row, (row < m_in) ? v : T(0));
       }
     }
@@ -724,6 +833,9 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(LayerArgs la, const Inst<T>*
       const int row = row0 + r;
       if (row < nq) {
         if (c == 0) stg<double>(JTa + row, (double)Ss[0][r]);
+        else if constexpr (FD)  // (grad at q + h e_j - grad at q - h e_j) / 2h
+          stg<double>(Bq + (size_t)row * nq + (c - 1),
+                      (double)((Ss[2 * c - 1][r] - Ss[2 * c][r]) / (T(2) * (T)fdh64)));
         else stg<double>(Bq + (size_t)row * nq + (c - 1), (double)Ss[c][r]);
       }
     }
@@ -763,34 +875,48 @@ __global__ void k_unpack(const Inst<T>* __restrict__ tab, T* u, T* J, T* dJ, T* 
   }
 
 template <typename T, typename TW, int NCB>
-static void fwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb, hipStream_t s) {
+static void fwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb, bool fd, hipStream_t s) {
   const int tiles = d.wp[l + 1] / 16;
-  const int ib = stack_instances(tiles, nb, std::is_same<T, double>::value);
   const int threads = 64 * splitk_waves<T, NCB>::v;
   const LayerArgs la = layer_args(d, l);
-  if (ib == 4) k_fwd_hidden<T, TW, NCB, 4><<<dim3(tiles, (nb + 3) / 4), threads, 0, s>>>(la, tab, nb);
-  else if (ib == 2) k_fwd_hidden<T, TW, NCB, 2><<<dim3(tiles, (nb + 1) / 2), threads, 0, s>>>(la, tab, nb);
-  else k_fwd_hidden<T, TW, NCB, 1><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
+  if (fd) {  // the central-difference form: one instance per block
+    k_fwd_hidden<T, TW, NCB, 1, true><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
+    return;
+  }
+  const int ib = stack_instances(tiles, nb, std::is_same<T, double>::value);
+  if (ib == 4) k_fwd_hidden<T, TW, NCB, 4, false><<<dim3(tiles, (nb + 3) / 4), threads, 0, s>>>(la, tab, nb);
+  else if (ib == 2) k_fwd_hidden<T, TW, NCB, 2, false><<<dim3(tiles, (nb + 1) / 2), threads, 0, s>>>(la, tab, nb);
+  else k_fwd_hidden<T, TW, NCB, 1, false><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
 }
 
 template <typename T, typename TW>
-static void fwd_hidden_dispatch(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cp, hipStream_t s) {
-#define FWD_H(n) fwd_hidden_ib<T, TW, n>(d, l, tab, nb, s)
+static void fwd_hidden_dispatch(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cp, bool fd,
+                                hipStream_t s) {
+#define FWD_H(n) fwd_hidden_ib<T, TW, n>(d, l, tab, nb, fd, s)
   NCB_SWITCH(cp / 16, FWD_H)
 #undef FWD_H
 }
 
 template <>
-void launch_fwd_hidden<float>(const DecoderDev& d, int l, const Inst<float>* tab, int nb, int cp, hipStream_t s) {
-  if (d.prec == PREC_BF16) fwd_hidden_dispatch<float, __bf16>(d, l, tab, nb, cp, s);
-  else fwd_hidden_dispatch<float, float>(d, l, tab, nb, cp, s);
+void launch_fwd_hidden<float>(const DecoderDev& d, int l, const Inst<float>* tab, int nb, int cp, bool fd,
+                              hipStream_t s) {
+  if (d.prec == PREC_BF16) fwd_hidden_dispatch<float, __bf16>(d, l, tab, nb, cp, fd, s);
+  else fwd_hidden_dispatch<float, float>(d, l, tab, nb, cp, fd, s);
 }
 template <>
-void launch_fwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* tab, int nb, int cp, hipStream_t s) {
+void launch_fwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* tab, int nb, int cp, bool fd,
+                               hipStream_t s) {
   // FP64 decoders take n_q <= 15, i.e. at most 4 column blocks; one instance per block
   dim3 grid(d.wp[l + 1] / 16, nb);
-#define FWD_H64(n) \
-  k_fwd_hidden<double, double, n, 1><<<grid, 64 * splitk_waves<double, n>::v, 0, s>>>(layer_args(d, l), tab, nb)
+#define FWD_H64(n)                                                                                               \
+  do {                                                                                                          \
+    if (fd)                                                                                                     \
+      k_fwd_hidden<double, double, n, 1, true><<<grid, 64 * splitk_waves<double, n>::v, 0, s>>>(layer_args(d, l), \
+                                                                                               tab, nb);       \
+    else                                                                                                        \
+      k_fwd_hidden<double, double, n, 1, false><<<grid, 64 * splitk_waves<double, n>::v, 0, s>>>(              \
+          layer_args(d, l), tab, nb);                                                                           \
+  } while (0)
   switch (cp / 16) {
     case 1: FWD_H64(1); break;
     case 2: FWD_H64(2); break;
@@ -853,35 +979,42 @@ template void launch_bwd_reduce<float>(const DecoderDev&, const Inst<float>*, in
 template void launch_bwd_reduce<double>(const DecoderDev&, const Inst<double>*, int, hipStream_t);
 
 template <typename T, typename TW, int NCB>
-static void bwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb, hipStream_t s) {
+static void bwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb, bool fd, hipStream_t s) {
   const int tiles = d.wp[l] / 16;
-  const int ib = stack_instances(tiles, nb, std::is_same<T, double>::value);
   const int threads = 64 * splitk_waves<T, NCB>::v;
   const LayerArgs la = layer_args(d, l);
-  if (ib == 4) k_bwd_hidden<T, TW, NCB, 4><<<dim3(tiles, (nb + 3) / 4), threads, 0, s>>>(la, tab, nb);
-  else if (ib == 2) k_bwd_hidden<T, TW, NCB, 2><<<dim3(tiles, (nb + 1) / 2), threads, 0, s>>>(la, tab, nb);
-  else k_bwd_hidden<T, TW, NCB, 1><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
+  if (fd) {  // the central-difference form: one instance per block
+    k_bwd_hidden<T, TW, NCB, 1, true><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
+    return;
+  }
+  const int ib = stack_instances(tiles, nb, std::is_same<T, double>::value);
+  if (ib == 4) k_bwd_hidden<T, TW, NCB, 4, false><<<dim3(tiles, (nb + 3) / 4), threads, 0, s>>>(la, tab, nb);
+  else if (ib == 2) k_bwd_hidden<T, TW, NCB, 2, false><<<dim3(tiles, (nb + 1) / 2), threads, 0, s>>>(la, tab, nb);
+  else k_bwd_hidden<T, TW, NCB, 1, false><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
 }
 
 template <typename T, typename TW>
-static void bwd_hidden_dispatch(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cb, hipStream_t s) {
+static void bwd_hidden_dispatch(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cb, bool fd,
+                                hipStream_t s) {
   switch (cb / 16) {
-    case 1: bwd_hidden_ib<T, TW, 1>(d, l, tab, nb, s); break;
-    case 2: bwd_hidden_ib<T, TW, 2>(d, l, tab, nb, s); break;
-    case 3: bwd_hidden_ib<T, TW, 3>(d, l, tab, nb, s); break;
-    case 4: bwd_hidden_ib<T, TW, 4>(d, l, tab, nb, s); break;
+    case 1: bwd_hidden_ib<T, TW, 1>(d, l, tab, nb, fd, s); break;
+    case 2: bwd_hidden_ib<T, TW, 2>(d, l, tab, nb, fd, s); break;
+    case 3: bwd_hidden_ib<T, TW, 3>(d, l, tab, nb, fd, s); break;
+    case 4: bwd_hidden_ib<T, TW, 4>(d, l, tab, nb, fd, s); break;
     default: break;
   }
 }
 
 template <>
-void launch_bwd_hidden<float>(const DecoderDev& d, int l, const Inst<float>* tab, int nb, int cb, hipStream_t s) {
-  if (d.prec == PREC_BF16) bwd_hidden_dispatch<float, __bf16>(d, l, tab, nb, cb, s);
-  else bwd_hidden_dispatch<float, float>(d, l, tab, nb, cb, s);
+void launch_bwd_hidden<float>(const DecoderDev& d, int l, const Inst<float>* tab, int nb, int cb, bool fd,
+                              hipStream_t s) {
+  if (d.prec == PREC_BF16) bwd_hidden_dispatch<float, __bf16>(d, l, tab, nb, cb, fd, s);
+  else bwd_hidden_dispatch<float, float>(d, l, tab, nb, cb, fd, s);
 }
 template <>
-void launch_bwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* tab, int nb, int cb, hipStream_t s) {
-  bwd_hidden_dispatch<double, double>(d, l, tab, nb, cb, s);
+void launch_bwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* tab, int nb, int cb, bool fd,
+                               hipStream_t s) {
+  bwd_hidden_dispatch<double, double>(d, l, tab, nb, cb, fd, s);
 }
 
 template <typename T>

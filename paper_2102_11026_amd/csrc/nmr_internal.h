@@ -61,6 +61,8 @@ template <typename T>
 struct Inst {
   int active;              // 0: an empty slot of a pool; every kernel returns at once
   int trimmed;             // 1: fictitious force dropped (dJ = H.(dq - dt qdot), Hdd = 0)
+  int fd;                  // 1: derivatives by recursive central differences of step fd_h
+  double fd_h;
   int N, n, n_p, n_q, R, n_cub;
   int Cp, Cb, Cf;          // padded channel counts: forward, backward, output
   int Np;                  // N padded to NMR_WPAD
@@ -203,7 +205,8 @@ __device__ inline double fint_at(const Inst<T>& I, int i) {
 
 // ---- launchers (decoder.hip) -------------------------------------------
 template <typename T>
-void launch_fwd_hidden(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int max_cp, hipStream_t s);
+void launch_fwd_hidden(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int max_cp, bool fd,
+                       hipStream_t s);
 template <typename T>
 void launch_fwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_np, int max_cf, hipStream_t s);
 template <typename T>
@@ -213,7 +216,8 @@ void launch_bwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_bbl
 template <typename T>
 void launch_bwd_reduce(const DecoderDev& d, const Inst<T>* tab, int nb, hipStream_t s);
 template <typename T>
-void launch_bwd_hidden(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cb, hipStream_t s);
+void launch_bwd_hidden(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cb, bool fd,
+                       hipStream_t s);
 template <typename T>
 void launch_unpack(const Inst<T>* tab, T* u, T* J, T* dJ, T* Hdd, int N, hipStream_t s);
 

@@ -40,7 +40,7 @@ class ProblemDesc(C.Structure):
                 ("decoder", C.POINTER(MlpDesc)), ("shared_decoder", C.c_void_p), ("n_cub", C.c_int),
                 ("cub_ids", C.POINTER(C.c_int32)), ("cub_w", _dp), ("wnet", C.POINTER(MlpDesc)),
                 ("wnet_scale", C.c_double), ("r0", _dp), ("rdot0", _dp), ("newton_path", C.c_int),
-                ("trimmed", C.c_int)]
+                ("trimmed", C.c_int), ("fd_h", C.c_double)]
 
 
 class NmrError(RuntimeError):
@@ -197,6 +197,7 @@ class Instance:
         d.r0, d.rdot0 = r0.ctypes.data_as(_dp), rd0.ctypes.data_as(_dp)
         d.newton_path = {"auto": 0, "direct": 1}[path]
         d.trimmed = {"full": 0, "trimmed": 1}[getattr(prob, "formulation", "full")]
+        d.fd_h = float(getattr(prob, "fd_h", 0.0) or 0.0)
         h = C.c_void_p()
         _check(lib().nmr_instance_create(ctx.h, C.byref(d), PREC[prec], C.byref(h)))
         self.h = h

@@ -160,6 +160,7 @@ class Problem:
     out_rows: int = 0          # rows of the output layer (>= N; prefix used)
     meta: dict = field(default_factory=dict)
     formulation: str = "full"  # "full" | "trimmed" (fictitious force dropped)
+    fd_h: float = 0.0          # > 0: derivatives by central differences of this step
 
     @property
     def n(self) -> int:
