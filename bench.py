@@ -144,6 +144,30 @@ def phase_roofline(p, phase: str, us: float, prec: str, gram: bool):
                 **common)
 
 
+def tile_report(nmr, ctx, p):
+    """The autotuned tiles of the batched forward jet layers, each with its
+    algorithmic MFMA rate (2 w_out w_in (4 + 4 n_q) flops per instance, true
+    widths) against the peak of its precision."""
+    w = [p.weights[0].shape[1]] + [W.shape[0] for W in p.weights]
+    pad = lambda x: -(-x // 32) * 32
+    cols = 4 + 4 * p.n_q
+    out = []
+    for e in ctx.tiling_table():
+        if not e["forward"]:
+            continue
+        layers = [l for l in range(len(w) - 2) if pad(w[l]) == e["m_in"] and pad(w[l + 1]) == e["m_out"]]
+        if not layers:
+            continue
+        l = layers[0]
+        flops = 2.0 * w[l] * w[l + 1] * cols * e["n_inst"]
+        peak = BF16_MFMA_PEAK_TFLOPS if e["prec"] == nmr.PREC["bf16"] else FP32_MFMA_PEAK_TFLOPS
+        tf = flops / (e["us"] * 1e-6) / 1e12
+        out.append(dict(prec={v: k for k, v in nmr.PREC.items()}[e["prec"]], instances=e["n_inst"],
+                        layer=f"{w[l]}->{w[l + 1]}", ib=e["ib"], mr=e["mr"], us_per_launch=round(e["us"], 2),
+                        tflops=round(tf, 2), frac_of_mfma_peak=round(tf / peak, 4)))
+    return out
+
+
 def run_steps(nmr, ctx, insts, steps: int, warmup: int):
     import torch
     if warmup:
@@ -234,7 +258,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--batch", type=int, nargs="*", default=[4, 16, 64])
+    ap.add_argument("--batch", type=int, nargs="*", default=[4, 16, 64, 128])
+    ap.add_argument("--tiling", choices=["rule", "autotune"], default="rule",
+                    help="tile choice of the batched hidden layers in --profile-batch mode")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the served form (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -249,6 +275,7 @@ def main():
         from paper_2102_11026_amd import nmr, synth
         p = synth.config_single_10k()
         ctx = nmr.Context(0)
+        ctx.set_tiling(args.tiling)
         dec = nmr.Decoder(ctx, p.weights, p.biases, p.act, "fp32")
         insts = []
         for k in range(args.profile_batch):
@@ -335,14 +362,20 @@ def main():
                     r0[p.n_p:] = 0.1 * synth.normal(f"q0/{k}", p.n_q)
                     insts.append(nmr.Instance(ctx, p.replace(r0=r0), prec, shared=dec))
                 nsteps = max(args.steps // 5, 5)
-                s_m, ms_m = run_steps(nmr, ctx, insts, nsteps, 2)
-                var[f"batched_{prec}_B{B}"] = dict(
-                    newton_iters_per_s=round(ITERS * nsteps * B / s_m, 2),
-                    p50_step_ms=round(float(np.percentile(ms_m, 50)), 4),
-                    p99_step_ms=round(float(np.percentile(ms_m, 99)), 4))
+                rec = {}
+                for tiling in ("rule", "autotune"):
+                    ctx.set_tiling(tiling)
+                    s_m, ms_m = run_steps(nmr, ctx, insts, nsteps, 2)
+                    rec[tiling] = dict(newton_iters_per_s=round(ITERS * nsteps * B / s_m, 2),
+                                       p50_step_ms=round(float(np.percentile(ms_m, 50)), 4),
+                                       p99_step_ms=round(float(np.percentile(ms_m, 99)), 4))
+                ctx.set_tiling("rule")
+                var[f"batched_{prec}_B{B}"] = dict(rec["rule"], tiling="rule", autotuned=rec["autotune"])
+                log(f"batched {prec} B={B}:", var[f"batched_{prec}_B{B}"])
                 for x in insts:
                     x.close()
             dec.close()
+        var["decoder_gemm_tiles"] = tile_report(nmr, ctx, p)
         # batched ragged rods: 320 rods sharing one decoder, one launch sequence
         rods = synth.config_rods(320)
         for prec in ("fp32", "bf16"):

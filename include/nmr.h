@@ -217,6 +217,48 @@ int nmr_pool_detach(nmr_pool* pool, int slot);
  * time of the step (synchronizes). */
 int nmr_pool_step(nmr_pool* pool, int n_iters, int* status_or_null, float* ms_or_null);
 
+/* ---- tile configurations of batched launches ---------------------------- */
+
+/* How the hidden-layer GEMM launches of step_many and of slot pools choose
+ * their tiles.  A configuration is (ib, mr): ib instances per block (1, 2 or
+ * 4; stacked instances share the weight tile) and mr 16-row output tiles per
+ * wavefront (1; or 2 and 4, "tall" tiles in which one wavefront covers one
+ * instance's 16 mr rows over the whole reduction, so each operand fragment
+ * feeds several MFMAs).  Eligible: ib <= the number of instances in the
+ * launch; ib > 1 or mr > 1 only for FP32/BF16 complex-step jets; mr > 1 only
+ * with ib = 4, in a forward layer of at most 64 jet columns whose padded
+ * output width 16 mr divides.  Launches of one instance always run (1, 1).
+ *   NMR_TILES_RULE (the default): a fixed rule from the layer's row count,
+ *     its columns and the number of instances (tall tiles for forward layers
+ *     once there are 1024 waves of 16 mr rows, instances stacked once the
+ *     chip is full without it); results are bitwise reproducible.
+ *   NMR_TILES_AUTOTUNE: the first time a (direction, layer widths, columns,
+ *     instances, precision, derivative scheme) occurs in a step_many call (or
+ *     a pool step with at least half its slots attached), every eligible
+ *     configuration is timed on the context stream on the group's own decoder
+ *     buffers and the fastest is kept for the context's lifetime.
+ *   NMR_TILES_FORCE: (ib, mr) wherever it is eligible, the rule elsewhere.
+ * Configurations split the reduction over K differently, so results under
+ * different tiles agree to rounding, not bitwise.  Changing the mode drops
+ * the graphs captured under the previous one (synchronizes).  NMR_ERR_ARG for
+ * an unknown mode or, when forcing, ib or mr outside {1, 2, 4}. */
+typedef enum { NMR_TILES_RULE = 0, NMR_TILES_AUTOTUNE = 1, NMR_TILES_FORCE = 2 } nmr_tiling;
+int nmr_set_tiling(nmr_ctx* ctx, int mode, int ib, int mr);
+
+typedef struct {
+  int forward;     /* 1: forward jet layer, 0: backpropagation layer */
+  int m_in, m_out; /* padded input and output widths of the layer */
+  int cols;        /* jet (forward) or adjoint (backward) columns */
+  int n_inst;      /* instances in the launch */
+  int prec;        /* nmr_prec */
+  int ib, mr;      /* the configuration chosen */
+  float us;        /* its measured device time per launch, microseconds */
+} nmr_tile_choice;
+
+/* The autotuned choices so far: copies min(count, cap) entries to out (host)
+ * and that number to *n. */
+int nmr_tiling_table(nmr_ctx* ctx, nmr_tile_choice* out, int cap, int* n);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Phases of one Newton iteration, in launch order. */

@@ -8,6 +8,7 @@
 #include "nmr.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -99,6 +100,10 @@ struct nmr_ctx {
   size_t used = 0;
   std::map<std::vector<nmr_inst*>, std::map<int, GraphEntry>> many_graphs;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  int tile_mode = NMR_TILES_RULE, tile_ib = 1, tile_mr = 1;
+  int tile_epoch = 0;  // bumped when the mode changes (pools recapture)
+  // autotuned choices by (forward, m_in, m_out, cols, n_inst, prec, fd)
+  std::map<std::array<int, 7>, nmr_tile_choice> tuned;
 };
 
 struct nmr_decoder {
@@ -713,6 +718,7 @@ struct Group {
   bool fd;  // central-difference derivatives (every member: the column count says so)
   bool gram;  // every table entry runs the Gram-folded path
   int max_cdofs, max_sblk, n_gblk, K;
+  TileCfg tf[NMR_MAX_LAYERS], tb[NMR_MAX_LAYERS];  // hidden-layer tiles (ib == 0: the rule)
 };
 
 static Group group_of(const std::vector<nmr_inst*>& v, void* tab) {
@@ -746,7 +752,7 @@ template <typename T>
 static void enqueue_decoder_fwd(const Group& g, hipStream_t s, int add_up) {
   const DecoderDev& d = g.dec->d;
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
-  for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, s);
+  for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, g.tf[l], s);
   launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, s);
   if (g.any_np) launch_filter<T>(tab, g.nb, add_up, s);
 }
@@ -757,7 +763,7 @@ static void enqueue_decoder_bwd(const Group& g, hipStream_t s) {
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
   launch_bwd_out<T>(d, tab, g.nb, g.gram ? g.max_sblk : g.max_bblk, s);
   launch_bwd_reduce<T>(d, tab, g.nb, s);
-  for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, g.fd, s);
+  for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, g.fd, g.tb[l], s);
 }
 
 template <typename T>
@@ -782,6 +788,99 @@ static void enqueue_step(const Group& g, int K, hipStream_t s) {
       else enqueue_iteration<float>(g, it, SOLVE_UPDATE | (it == K - 1 ? SOLVE_FINISH : 0), nullptr, nullptr, s);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// tile choice of a group's hidden-layer launches
+// ---------------------------------------------------------------------------
+static const int kTuneReps = 10;
+
+// Times every eligible configuration of one hidden layer on the group's own
+// buffers (the layer only writes decoder scratch that the next real pass
+// overwrites) and keeps the fastest for the context's lifetime.
+template <typename T>
+static int tune_layer(nmr_ctx* c, const Group& g, int l, bool fwd, TileCfg* out) {
+  const DecoderDev& d = g.dec->d;
+  const int cols = fwd ? g.Cp : g.Cb;
+  const std::array<int, 7> key{fwd ? 1 : 0, d.wp[l], d.wp[l + 1], cols, g.nb, d.prec, g.fd ? 1 : 0};
+  auto it = c->tuned.find(key);
+  if (it != c->tuned.end()) {
+    *out = TileCfg{it->second.ib, it->second.mr};
+    return NMR_OK;
+  }
+  TileCfg cand[8];
+  const int n = tile_candidates(d, l, g.nb, cols, g.fd, g.f64, fwd, cand);
+  *out = tile_rule(d, l, g.nb, cols, g.fd, g.f64, fwd);
+  if (n <= 1) return NMR_OK;
+  const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
+  float best = 0.f;
+  for (int k = 0; k < n; ++k) {
+    auto run = [&]() {
+      if (fwd) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, cand[k], c->stream);
+      else launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, g.fd, cand[k], c->stream);
+    };
+    run();
+    run();
+    HIPCHK(hipEventRecord(c->ev[0], c->stream));
+    for (int r = 0; r < kTuneReps; ++r) run();
+    HIPCHK(hipEventRecord(c->ev[1], c->stream));
+    HIPCHK(hipEventSynchronize(c->ev[1]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+    const float us = 1e3f * ms / kTuneReps;
+    if (k == 0 || us < best) {
+      best = us;
+      *out = cand[k];
+    }
+  }
+  HIPCHK(hipGetLastError());
+  nmr_tile_choice e{key[0], key[1], key[2], key[3], key[4], key[5], out->ib, out->mr, best};
+  c->tuned.emplace(key, e);
+  return NMR_OK;
+}
+
+// may_tune: the group's table holds live instances (timings mean something)
+static int choose_tiles(nmr_ctx* c, Group& g, bool may_tune) {
+  const DecoderDev& d = g.dec->d;
+  for (int l = 0; l < d.L - 1; ++l)
+    for (int fwd = 0; fwd < 2; ++fwd) {
+      TileCfg& t = fwd ? g.tf[l] : g.tb[l];
+      const int cols = fwd ? g.Cp : g.Cb;
+      t = tile_rule(d, l, g.nb, cols, g.fd, g.f64, fwd);
+      if (c->tile_mode == NMR_TILES_FORCE) {
+        const TileCfg f{c->tile_ib, c->tile_mr};
+        if (tile_eligible(d, l, g.nb, cols, g.fd, g.f64, fwd, f)) t = f;
+      } else if (c->tile_mode == NMR_TILES_AUTOTUNE && may_tune) {
+        CHK(g.f64 ? tune_layer<double>(c, g, l, fwd, &t) : tune_layer<float>(c, g, l, fwd, &t));
+      }
+    }
+  return NMR_OK;
+}
+
+extern "C" int nmr_set_tiling(nmr_ctx* c, int mode, int ib, int mr) {
+  if (!c) return fail(NMR_ERR_ARG, "null context");
+  if (mode < NMR_TILES_RULE || mode > NMR_TILES_FORCE) return fail(NMR_ERR_ARG, "unknown tiling mode");
+  if (mode == NMR_TILES_FORCE && !((ib == 1 || ib == 2 || ib == 4) && (mr == 1 || mr == 2 || mr == 4)))
+    return fail(NMR_ERR_ARG, "forced tiles: ib and mr must be 1, 2 or 4");
+  CHK(set_device(c));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  drop_many_graphs(c, nullptr);
+  c->tile_mode = mode;
+  c->tile_ib = mode == NMR_TILES_FORCE ? ib : 1;
+  c->tile_mr = mode == NMR_TILES_FORCE ? mr : 1;
+  c->tile_epoch++;
+  return NMR_OK;
+}
+
+extern "C" int nmr_tiling_table(nmr_ctx* c, nmr_tile_choice* out, int cap, int* n) {
+  if (!c || !n || cap < 0 || (cap > 0 && !out)) return fail(NMR_ERR_ARG, "bad argument");
+  int k = 0;
+  for (auto& kv : c->tuned) {
+    if (k < cap) out[k] = kv.second;
+    ++k;
+  }
+  *n = std::min(k, cap);
+  return NMR_OK;
 }
 
 static int capture(nmr_ctx* c, const std::vector<Group>& groups, int K, hipGraphExec_t* exec) {
@@ -873,6 +972,11 @@ extern "C" int step_many(nmr_ctx* c, nmr_inst* const* insts, int n_inst, int n_s
       ge.tabs.push_back(tab);
       HIPCHK(hipMemcpy(tab, host.data(), host.size(), hipMemcpyHostToDevice));
       groups.push_back(group_of(pr.second, tab));
+      int rc = choose_tiles(c, groups.back(), true);
+      if (rc != NMR_OK) {
+        for (void* p : ge.tabs) (void)hipFree(p);
+        return rc;
+      }
     }
     int rc = capture(c, groups, n_iters, &ge.exec);
     if (rc != NMR_OK) {
@@ -1080,6 +1184,7 @@ struct nmr_pool {
   void* tab = nullptr;        // device table of capacity Inst<T>
   size_t isz = 0;
   std::map<int, hipGraphExec_t> graphs;
+  int tile_epoch = 0;  // the context's tiling epoch the graphs were captured in
 };
 
 extern "C" int nmr_pool_create(nmr_ctx* c, int capacity, nmr_pool** out) {
@@ -1160,10 +1265,17 @@ extern "C" int nmr_pool_step(nmr_pool* p, int n_iters, int* status, float* ms) {
   if (!p->proto) return NMR_OK;  // nothing ever attached
   nmr_ctx* c = p->ctx;
   CHK(set_device(c));
+  if (p->tile_epoch != c->tile_epoch) {
+    pool_drop_graphs(p);
+    p->tile_epoch = c->tile_epoch;
+  }
   auto it = p->graphs.find(n_iters);
   if (it == p->graphs.end()) {
     Group g = group_of({p->proto}, p->tab);
     g.nb = p->capacity;
+    int live = 0;
+    for (nmr_inst* x : p->slots) live += x != nullptr;
+    CHK(choose_tiles(c, g, 2 * live >= p->capacity));
     hipGraphExec_t ex;
     CHK(capture(c, {g}, n_iters, &ex));
     it = p->graphs.emplace(n_iters, ex).first;
@@ -1205,7 +1317,7 @@ static void enqueue_phase(const Group& g, int phase, hipStream_t s) {
   const DecoderDev& d = g.dec->d;
   switch (phase) {
     case NMR_PHASE_DEC_HIDDEN:
-      for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, s);
+      for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, g.tf[l], s);
       break;
     case NMR_PHASE_DEC_OUT:
       launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, s);
@@ -1220,7 +1332,7 @@ static void enqueue_phase(const Group& g, int phase, hipStream_t s) {
     case NMR_PHASE_BWD_OUT: launch_bwd_out<T>(d, tab, g.nb, g.gram ? g.max_sblk : g.max_bblk, s); break;
     case NMR_PHASE_BWD_HIDDEN:
       launch_bwd_reduce<T>(d, tab, g.nb, s);
-      for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, g.fd, s);
+      for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, g.fd, g.tb[l], s);
       break;
     case NMR_PHASE_SOLVE: launch_solve<T>(tab, g.nb, 0, SOLVE_UPDATE, nullptr, nullptr, s); break;
     default: break;

@@ -255,7 +255,127 @@ __host__ inline int stack_instances(int row_tiles, int nb, bool f64) {
 }
 
 // ---------------------------------------------------------------------------
-// Forward hidden layer l with the jet activation.  One block per 16 rows.
+// Tall tiles for launches with many instances: one wave per instance slot
+// computes MR stacked 16-row tiles x NCB column blocks over the whole K, so
+// every B fragment (the instance's activations) serves MR MFMAs and every A
+// fragment (the shared weights) NCB.  The operands of the next K-batch are
+// loaded before the MFMAs of the current one.  A is [16 MR][lda], K
+// contiguous; rows past the layer are never read (16 MR divides m_outp).
+// ---------------------------------------------------------------------------
+template <int MR, int NCB, typename BL>
+__device__ inline void mfma_tall(const float* __restrict__ A, int lda, int K, BL bload, f32x4 (&acc)[MR][NCB]) {
+  constexpr int PF = 2;  // K-steps of 16 per batch
+  const int lane = threadIdx.x & 63;
+  const int rA = lane & 15, g = lane >> 4;
+  const float* ap = A + (size_t)rA * lda + 4 * g;
+  float4 a0[PF][MR], b0[PF][NCB], a1[PF][MR], b1[PF][NCB];
+  auto load = [&](int k0, float4(&a)[PF][MR], float4(&b)[PF][NCB]) {
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+      const int k = k0 + 16 * t;
+      if (k < K) {
+#pragma unroll
+        for (int m = 0; m < MR; ++m) a[t][m] = ldg<float4>(ap + (size_t)16 * m * lda + k);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) b[t][cb] = bload(cb * 16 + rA, k + 4 * g);
+      } else {
+#pragma unroll
+        for (int m = 0; m < MR; ++m) a[t][m] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) b[t][cb] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+  };
+  auto mma = [&](const float4(&a)[PF][MR], const float4(&b)[PF][NCB]) {
+#pragma unroll
+    for (int t = 0; t < PF; ++t)
+#pragma unroll
+      for (int m = 0; m < MR; ++m)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][m].x, b[t][cb].x, acc[m][cb], 0, 0, 0);
+          acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][m].y, b[t][cb].y, acc[m][cb], 0, 0, 0);
+          acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][m].z, b[t][cb].z, acc[m][cb], 0, 0, 0);
+          acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][m].w, b[t][cb].w, acc[m][cb], 0, 0, 0);
+        }
+  };
+  constexpr int KB = 16 * PF;
+  load(0, a0, b0);
+  for (int k0 = 0; k0 < K; k0 += 2 * KB) {
+    load(k0 + KB, a1, b1);
+    mma(a0, b0);
+    if (k0 + KB >= K) break;
+    load(k0 + 2 * KB, a0, b0);
+    mma(a1, b1);
+  }
+}
+
+template <int MR, int NCB, typename BL>
+__device__ inline void mfma_tall(const __bf16* __restrict__ A, int lda, int K, BL bload, f32x4 (&acc)[MR][NCB]) {
+  const int lane = threadIdx.x & 63;
+  const int rA = lane & 15, g = lane >> 4;
+  const __bf16* ap = A + (size_t)rA * lda + 8 * g;
+  bf16x8 a0[MR], a1[MR];
+  float4 b0[NCB][2], b1[NCB][2];
+  auto load = [&](int k, bf16x8(&a)[MR], float4(&b)[NCB][2]) {
+    if (k < K) {
+#pragma unroll
+      for (int m = 0; m < MR; ++m) a[m] = ldg<bf16x8>(ap + (size_t)16 * m * lda + k);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        b[cb][0] = bload(cb * 16 + rA, k + 8 * g);
+        b[cb][1] = bload(cb * 16 + rA, k + 8 * g + 4);
+      }
+    } else {
+      const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int m = 0; m < MR; ++m) a[m] = to_bf16x8(z, z);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) b[cb][0] = b[cb][1] = z;
+    }
+  };
+  auto mma = [&](const bf16x8(&a)[MR], const float4(&b)[NCB][2]) {
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const bf16x8 bb = to_bf16x8(b[cb][0], b[cb][1]);
+#pragma unroll
+      for (int m = 0; m < MR; ++m) acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb, acc[m][cb], 0, 0, 0);
+    }
+  };
+  load(0, a0, b0);
+  for (int k0 = 0; k0 < K; k0 += 64) {
+    load(k0 + 32, a1, b1);
+    mma(a0, b0);
+    if (k0 + 32 >= K) break;
+    load(k0 + 64, a0, b0);
+    mma(a1, b1);
+  }
+}
+
+// Tall tile of every instance slot (wave w = slot w) into S[slot][c][r],
+// r < 16 MR; a slot not in use writes zeros.  Ends with a barrier.
+template <typename TW, int NCB, int MR, typename BL>
+__device__ inline void gemm_tall(const TW* __restrict__ A, int lda, int K, bool use, BL bload,
+                                 float (*S)[NCB * 16][16 * MR + 1]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  f32x4 acc[MR][NCB];
+#pragma unroll
+  for (int m = 0; m < MR; ++m)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[m][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (use) mfma_tall<MR, NCB>(A, lda, K, bload, acc);
+  const int rA = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int m = 0; m < MR; ++m)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) S[wave][cb * 16 + rA][16 * m + 4 * g + i] = acc[m][cb][i];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Forward hidden layer l with the jet activation.  One block per 16 MR rows.
 // ---------------------------------------------------------------------------
 // Input k of stencil column c of the central differences (the column order
 // of the last hidden layer's stencils; zero past the 14 n_q + 3 columns).
@@ -280,9 +400,11 @@ __device__ inline T fd_input(int c, int k, int nq, T q, T dq, T qd, T h) {
   return T(0);
 }
 
-template <typename T, typename TW, int NCB, int IB, bool FD>
-__global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab, int nb) {
-  constexpr int NW = splitk_waves<T, NCB>::v;
+template <typename T, typename TW, int NCB, int IB, bool FD, int MR>
+__global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab, int nb) {
+  static_assert(MR == 1 || (!FD && std::is_same<T, float>::value), "tall tiles: complex-step FP32 jets only");
+  constexpr int ROWS = 16 * MR;  // output rows of a block
+  constexpr int NW = MR > 1 ? IB : splitk_waves<T, NCB>::v;
   constexpr int KSPL = NW / IB;
   constexpr int NG = KSPL * 64;  // threads of one instance slot
   const int l = la.l;
@@ -304,17 +426,17 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
   load_now(active, nq, trimmed, X, outp, pre, fold, din, dt64, fdh64, m_inp, m_out, m_outp, la.W, la.b, la.act, la.L);
   const bool use = inst < nb && active;
   const T dtT = (T)dt64;
-  const int row0 = blockIdx.x * 16;
+  const int row0 = blockIdx.x * ROWS;
   if (row0 >= m_outp || (IB == 1 && !use)) return;  // uniform over the block
   const TW* W = reinterpret_cast<const TW*>(la.W) + (size_t)row0 * m_inp;
   const T* bias = reinterpret_cast<const T*>(la.b);
-  __shared__ T S[IB][NCB * 16][17];
-  __shared__ T red[NW][NCB * 16][16];
-  __shared__ T sd1[IB][16], sd2[IB][16], sd3[IB][16], sx2[IB][16], sx4[IB][16], sx23[IB][16];
+  __shared__ T S[IB][NCB * 16][ROWS + 1];
+  __shared__ T red[MR == 1 ? NW : 1][NCB * 16][16];
+  __shared__ T sd1[IB][ROWS], sd2[IB][ROWS], sd3[IB][ROWS], sx2[IB][ROWS], sx4[IB][ROWS], sx23[IB][ROWS];
   typedef typename vec4<T>::type V4;
 
   // the bias of this tile is loaded before the GEMM (no dependent round trip)
-  const T bias_v = (tg < 16 && row0 + tg < m_out) ? ldg<T>(bias + row0 + tg) : T(0);
+  const T bias_v = (tg < ROWS && row0 + tg < m_out) ? ldg<T>(bias + row0 + tg) : T(0);
   auto bload = [&](int c, int k) -> V4 {
     if (FD && l == 0) {
       // stencil columns of the central differences: q, q +- h e_j, then per j
@@ -347,9 +469,10 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
     }
     return ldg<V4>(X + (size_t)c * m_inp + k);
   };
-  gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload, S, red);
+  if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload, S, red);
+  else gemm_tall<TW, NCB, MR>(W, m_inp, m_inp, use, bload, S);
 
-  T(*Ss)[17] = S[slot];
+  T(*Ss)[ROWS + 1] = S[slot];
   if constexpr (FD) {
     // central differences: every column is a forward pass of its own (bias
     // and activation on each); the base and q +- h e_j keep their
@@ -371,7 +494,7 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
     }
     __syncthreads();
   } else {
-  if (use && tg < 16) {
+  if (use && tg < ROWS) {
     const int row = row0 + tg;
     const bool valid = row < m_out;
     const T x0 = Ss[0][tg] + bias_v;
@@ -388,8 +511,8 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
   }
   __syncthreads();
   if (use) {
-    for (int p = tg; p < 16 * nq; p += NG) {
-      const int r = p & 15, j = p >> 4;
+    for (int p = tg; p < ROWS * nq; p += NG) {
+      const int r = p & (ROWS - 1), j = p / ROWS;
       const bool valid = row0 + r < m_out;
       const T x1 = Ss[4 + j][r], x12 = Ss[4 + nq + j][r], x14 = Ss[4 + 2 * nq + j][r], x123 = Ss[4 + 3 * nq + j][r];
       const T d1 = sd1[slot][r], d2 = sd2[slot][r], d3 = sd3[slot][r];
@@ -406,8 +529,8 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
   if (!use) return;
   if (l + 2 < la.L) {
     const int C = fd ? 14 * nq + 3 : 4 + 4 * nq;
-    for (int p = tg; p < C * 16; p += NG) {
-      const int c = p >> 4, r = p & 15;
+    for (int p = tg; p < C * ROWS; p += NG) {
+      const int c = p / ROWS, r = p & (ROWS - 1);
       stg<T>(outp + (size_t)c * m_outp + row0 + r, Ss[c][r]);
     }
   } else {
@@ -444,8 +567,8 @@ __global__ __launch_bounds__(512) void k_fwd_hidden(LayerArgs la, const Inst<T>*
       }
       return;
     }
-    for (int p = tg; p < C * 16; p += NG) {
-      const int c = p >> 4, r = p & 15;
+    for (int p = tg; p < C * ROWS; p += NG) {
+      const int c = p / ROWS, r = p & (ROWS - 1);
       T v;
       if (c == 0) v = Ss[0][r];
       else if (c <= nq) v = Ss[4 + c - 1][r];
@@ -874,48 +997,99 @@ __global__ void k_unpack(const Inst<T>* __restrict__ tab, T* u, T* J, T* dJ, T* 
     default: break;           \
   }
 
+// ---------------------------------------------------------------------------
+// tile configurations of the hidden-layer launches
+// ---------------------------------------------------------------------------
+static int hidden_rows(const DecoderDev& d, int l, bool fwd) { return fwd ? d.wp[l + 1] : d.wp[l]; }
+
+// Forward layers of at most 64 jet columns take tall tiles once there are
+// 1024 (row tile, instance) waves of 16 mr rows, the largest mr first (the
+// crossover measured on the 10k-vertex decoder at 64 and 128 instances);
+// otherwise instances are stacked once the chip is full without it.
+TileCfg tile_rule(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd) {
+  if (fd || f64) return TileCfg{1, 1};
+  const int rows = hidden_rows(d, l, fwd);
+  if (fwd && cols <= 64 && nb >= 4)
+    for (int mr = 4; mr >= 2; mr /= 2)
+      if (rows % (16 * mr) == 0 && (rows / (16 * mr)) * nb >= 1024) return TileCfg{4, mr};
+  return TileCfg{stack_instances(rows / 16, nb, false), 1};
+}
+
+bool tile_eligible(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd, TileCfg c) {
+  if (c.ib == 1 && c.mr == 1) return true;
+  if (fd || f64 || nb < c.ib) return false;
+  if (c.mr == 1) return c.ib == 2 || c.ib == 4;
+  return fwd && c.ib == 4 && (c.mr == 2 || c.mr == 4) && cols <= 64 && hidden_rows(d, l, fwd) % (16 * c.mr) == 0;
+}
+
+int tile_candidates(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd, TileCfg* out) {
+  static const TileCfg all[] = {{1, 1}, {2, 1}, {4, 1}, {4, 2}, {4, 4}};
+  int n = 0;
+  for (const TileCfg& c : all)
+    if (tile_eligible(d, l, nb, cols, fd, f64, fwd, c)) out[n++] = c;
+  return n;
+}
+
 template <typename T, typename TW, int NCB>
-static void fwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb, bool fd, hipStream_t s) {
-  const int tiles = d.wp[l + 1] / 16;
+static void fwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb, bool fd, TileCfg cfg,
+                          hipStream_t s) {
+  const int rows = d.wp[l + 1], tiles = rows / 16;
   const int threads = 64 * splitk_waves<T, NCB>::v;
   const LayerArgs la = layer_args(d, l);
   if (fd) {  // the central-difference form: one instance per block
-    k_fwd_hidden<T, TW, NCB, 1, true><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
+    k_fwd_hidden<T, TW, NCB, 1, true, 1><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
     return;
   }
-  const int ib = stack_instances(tiles, nb, std::is_same<T, double>::value);
-  if (ib == 4) k_fwd_hidden<T, TW, NCB, 4, false><<<dim3(tiles, (nb + 3) / 4), threads, 0, s>>>(la, tab, nb);
-  else if (ib == 2) k_fwd_hidden<T, TW, NCB, 2, false><<<dim3(tiles, (nb + 1) / 2), threads, 0, s>>>(la, tab, nb);
-  else k_fwd_hidden<T, TW, NCB, 1, false><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
+  if constexpr (std::is_same<T, float>::value && NCB <= 4) {
+    if (cfg.mr == 4) {
+      k_fwd_hidden<T, TW, NCB, 4, false, 4><<<dim3(rows / 64, (nb + 3) / 4), 256, 0, s>>>(la, tab, nb);
+      return;
+    }
+    if (cfg.mr == 2) {
+      k_fwd_hidden<T, TW, NCB, 4, false, 2><<<dim3(rows / 32, (nb + 3) / 4), 256, 0, s>>>(la, tab, nb);
+      return;
+    }
+  }
+  if (cfg.ib == 4) k_fwd_hidden<T, TW, NCB, 4, false, 1><<<dim3(tiles, (nb + 3) / 4), threads, 0, s>>>(la, tab, nb);
+  else if (cfg.ib == 2)
+    k_fwd_hidden<T, TW, NCB, 2, false, 1><<<dim3(tiles, (nb + 1) / 2), threads, 0, s>>>(la, tab, nb);
+  else k_fwd_hidden<T, TW, NCB, 1, false, 1><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
 }
 
 template <typename T, typename TW>
 static void fwd_hidden_dispatch(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cp, bool fd,
-                                hipStream_t s) {
-#define FWD_H(n) fwd_hidden_ib<T, TW, n>(d, l, tab, nb, fd, s)
+                                TileCfg cfg, hipStream_t s) {
+#define FWD_H(n) fwd_hidden_ib<T, TW, n>(d, l, tab, nb, fd, cfg, s)
   NCB_SWITCH(cp / 16, FWD_H)
 #undef FWD_H
 }
 
+// cfg.ib == 0, or a configuration the layer cannot run: the rule
+static TileCfg resolve(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd, TileCfg cfg) {
+  if (cfg.ib == 0 || !tile_eligible(d, l, nb, cols, fd, f64, fwd, cfg)) return tile_rule(d, l, nb, cols, fd, f64, fwd);
+  return cfg;
+}
+
 template <>
 void launch_fwd_hidden<float>(const DecoderDev& d, int l, const Inst<float>* tab, int nb, int cp, bool fd,
-                              hipStream_t s) {
-  if (d.prec == PREC_BF16) fwd_hidden_dispatch<float, __bf16>(d, l, tab, nb, cp, fd, s);
-  else fwd_hidden_dispatch<float, float>(d, l, tab, nb, cp, fd, s);
+                              TileCfg cfg, hipStream_t s) {
+  cfg = resolve(d, l, nb, cp, fd, false, true, cfg);
+  if (d.prec == PREC_BF16) fwd_hidden_dispatch<float, __bf16>(d, l, tab, nb, cp, fd, cfg, s);
+  else fwd_hidden_dispatch<float, float>(d, l, tab, nb, cp, fd, cfg, s);
 }
 template <>
 void launch_fwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* tab, int nb, int cp, bool fd,
-                               hipStream_t s) {
+                               TileCfg, hipStream_t s) {
   // FP64 decoders take n_q <= 15, i.e. at most 4 column blocks; one instance per block
   dim3 grid(d.wp[l + 1] / 16, nb);
-#define FWD_H64(n)                                                                                               \
-  do {                                                                                                          \
-    if (fd)                                                                                                     \
-      k_fwd_hidden<double, double, n, 1, true><<<grid, 64 * splitk_waves<double, n>::v, 0, s>>>(layer_args(d, l), \
-                                                                                               tab, nb);       \
-    else                                                                                                        \
-      k_fwd_hidden<double, double, n, 1, false><<<grid, 64 * splitk_waves<double, n>::v, 0, s>>>(              \
-          layer_args(d, l), tab, nb);                                                                           \
+#define FWD_H64(n)                                                                                                \
+  do {                                                                                                           \
+    if (fd)                                                                                                      \
+      k_fwd_hidden<double, double, n, 1, true, 1><<<grid, 64 * splitk_waves<double, n>::v, 0, s>>>(              \
+          layer_args(d, l), tab, nb);                                                                            \
+    else                                                                                                         \
+      k_fwd_hidden<double, double, n, 1, false, 1><<<grid, 64 * splitk_waves<double, n>::v, 0, s>>>(             \
+          layer_args(d, l), tab, nb);                                                                            \
   } while (0)
   switch (cp / 16) {
     case 1: FWD_H64(1); break;
@@ -979,7 +1153,8 @@ template void launch_bwd_reduce<float>(const DecoderDev&, const Inst<float>*, in
 template void launch_bwd_reduce<double>(const DecoderDev&, const Inst<double>*, int, hipStream_t);
 
 template <typename T, typename TW, int NCB>
-static void bwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb, bool fd, hipStream_t s) {
+static void bwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb, bool fd, TileCfg cfg,
+                          hipStream_t s) {
   const int tiles = d.wp[l] / 16;
   const int threads = 64 * splitk_waves<T, NCB>::v;
   const LayerArgs la = layer_args(d, l);
@@ -987,34 +1162,35 @@ static void bwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb
     k_bwd_hidden<T, TW, NCB, 1, true><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
     return;
   }
-  const int ib = stack_instances(tiles, nb, std::is_same<T, double>::value);
-  if (ib == 4) k_bwd_hidden<T, TW, NCB, 4, false><<<dim3(tiles, (nb + 3) / 4), threads, 0, s>>>(la, tab, nb);
-  else if (ib == 2) k_bwd_hidden<T, TW, NCB, 2, false><<<dim3(tiles, (nb + 1) / 2), threads, 0, s>>>(la, tab, nb);
+  if (cfg.ib == 4) k_bwd_hidden<T, TW, NCB, 4, false><<<dim3(tiles, (nb + 3) / 4), threads, 0, s>>>(la, tab, nb);
+  else if (cfg.ib == 2)
+    k_bwd_hidden<T, TW, NCB, 2, false><<<dim3(tiles, (nb + 1) / 2), threads, 0, s>>>(la, tab, nb);
   else k_bwd_hidden<T, TW, NCB, 1, false><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
 }
 
 template <typename T, typename TW>
 static void bwd_hidden_dispatch(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cb, bool fd,
-                                hipStream_t s) {
+                                TileCfg cfg, hipStream_t s) {
   switch (cb / 16) {
-    case 1: bwd_hidden_ib<T, TW, 1>(d, l, tab, nb, fd, s); break;
-    case 2: bwd_hidden_ib<T, TW, 2>(d, l, tab, nb, fd, s); break;
-    case 3: bwd_hidden_ib<T, TW, 3>(d, l, tab, nb, fd, s); break;
-    case 4: bwd_hidden_ib<T, TW, 4>(d, l, tab, nb, fd, s); break;
+    case 1: bwd_hidden_ib<T, TW, 1>(d, l, tab, nb, fd, cfg, s); break;
+    case 2: bwd_hidden_ib<T, TW, 2>(d, l, tab, nb, fd, cfg, s); break;
+    case 3: bwd_hidden_ib<T, TW, 3>(d, l, tab, nb, fd, cfg, s); break;
+    case 4: bwd_hidden_ib<T, TW, 4>(d, l, tab, nb, fd, cfg, s); break;
     default: break;
   }
 }
 
 template <>
 void launch_bwd_hidden<float>(const DecoderDev& d, int l, const Inst<float>* tab, int nb, int cb, bool fd,
-                              hipStream_t s) {
-  if (d.prec == PREC_BF16) bwd_hidden_dispatch<float, __bf16>(d, l, tab, nb, cb, fd, s);
-  else bwd_hidden_dispatch<float, float>(d, l, tab, nb, cb, fd, s);
+                              TileCfg cfg, hipStream_t s) {
+  cfg = resolve(d, l, nb, cb, fd, false, false, cfg);
+  if (d.prec == PREC_BF16) bwd_hidden_dispatch<float, __bf16>(d, l, tab, nb, cb, fd, cfg, s);
+  else bwd_hidden_dispatch<float, float>(d, l, tab, nb, cb, fd, cfg, s);
 }
 template <>
 void launch_bwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* tab, int nb, int cb, bool fd,
-                               hipStream_t s) {
-  bwd_hidden_dispatch<double, double>(d, l, tab, nb, cb, fd, s);
+                               TileCfg, hipStream_t s) {
+  bwd_hidden_dispatch<double, double>(d, l, tab, nb, cb, fd, TileCfg{1, 1}, s);
 }
 
 template <typename T>

@@ -203,9 +203,21 @@ __device__ inline double fint_at(const Inst<T>& I, int i) {
   return f;
 }
 
+// ---- tile configurations of the hidden-layer launches (decoder.hip) ----
+// ib instances per block (stacked instances share the weight tile); mr
+// 16-row tiles per wave (mr > 1: tall tiles, one wave per instance over the
+// whole K).  ib == 0: the rule.
+struct TileCfg {
+  int ib, mr;
+};
+TileCfg tile_rule(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd);
+bool tile_eligible(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd, TileCfg c);
+// eligible configurations of hidden layer l (at most 5), the rule's among them
+int tile_candidates(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd, TileCfg* out);
+
 // ---- launchers (decoder.hip) -------------------------------------------
 template <typename T>
-void launch_fwd_hidden(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int max_cp, bool fd,
+void launch_fwd_hidden(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int max_cp, bool fd, TileCfg cfg,
                        hipStream_t s);
 template <typename T>
 void launch_fwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_np, int max_cf, hipStream_t s);
@@ -216,7 +228,7 @@ void launch_bwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_bbl
 template <typename T>
 void launch_bwd_reduce(const DecoderDev& d, const Inst<T>* tab, int nb, hipStream_t s);
 template <typename T>
-void launch_bwd_hidden(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cb, bool fd,
+void launch_bwd_hidden(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int cb, bool fd, TileCfg cfg,
                        hipStream_t s);
 template <typename T>
 void launch_unpack(const Inst<T>* tab, T* u, T* J, T* dJ, T* Hdd, int N, hipStream_t s);

@@ -43,6 +43,14 @@ class ProblemDesc(C.Structure):
                 ("trimmed", C.c_int), ("fd_h", C.c_double)]
 
 
+class TileChoice(C.Structure):
+    _fields_ = [("forward", C.c_int), ("m_in", C.c_int), ("m_out", C.c_int), ("cols", C.c_int),
+                ("n_inst", C.c_int), ("prec", C.c_int), ("ib", C.c_int), ("mr", C.c_int), ("us", C.c_float)]
+
+
+TILING = {"rule": 0, "autotune": 1, "force": 2}
+
+
 class NmrError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -79,6 +87,8 @@ def lib():
             "reduced_newton_step": (i, [vp, i, _dp]),
             "step_many": (i, [vp, C.POINTER(vp), i, i, i, ip, C.POINTER(C.c_float)]),
             "nmr_time_phase": (i, [vp, i, i, C.POINTER(C.c_float)]),
+            "nmr_set_tiling": (i, [vp, i, i, i]),
+            "nmr_tiling_table": (i, [vp, C.POINTER(TileChoice), i, ip]),
             "nmr_pool_create": (i, [vp, i, C.POINTER(vp)]),
             "nmr_pool_destroy": (i, [vp]),
             "nmr_pool_attach": (i, [vp, vp, ip]),
@@ -125,6 +135,20 @@ class Context:
         h = C.c_void_p()
         _check(lib().nmr_create(device, C.c_void_p(stream.cuda_stream), budget_bytes, C.byref(h)))
         self.h = h
+
+    def set_tiling(self, mode: str = "rule", ib: int = 1, mr: int = 1):
+        """Tile choice of batched hidden-layer launches: "rule", "autotune" or
+        "force" (ib instances per block, mr 16-row tiles per wave)."""
+        _check(lib().nmr_set_tiling(self.h, TILING[mode], ib, mr))
+
+    def tiling_table(self) -> list:
+        """The autotuned choices so far, as dicts."""
+        cap = 256
+        buf = (TileChoice * cap)()
+        n = C.c_int()
+        _check(lib().nmr_tiling_table(self.h, buf, cap, C.byref(n)))
+        names = [f[0] for f in TileChoice._fields_]
+        return [{k: getattr(buf[j], k) for k in names} for j in range(n.value)]
 
     def close(self):
         if self.h:
