@@ -226,12 +226,14 @@ int nmr_pool_step(nmr_pool* pool, int n_iters, int* status_or_null, float* ms_or
  * instance's 16 mr rows over the whole reduction, so each operand fragment
  * feeds several MFMAs).  Eligible: ib <= the number of instances in the
  * launch; ib > 1 or mr > 1 only for FP32/BF16 complex-step jets; mr > 1 only
- * with ib = 4, in a forward layer of at most 64 jet columns whose padded
- * output width 16 mr divides.  Launches of one instance always run (1, 1).
+ * with ib = 4, in a forward layer of at most 64 jet columns or a backward
+ * layer of at most 32 adjoint columns, whose padded row count (the output
+ * width forward, the input width backward) 16 mr divides.  Launches of one
+ * instance always run (1, 1).
  *   NMR_TILES_RULE (the default): a fixed rule from the layer's row count,
- *     its columns and the number of instances (tall tiles for forward layers
- *     once there are 1024 waves of 16 mr rows, instances stacked once the
- *     chip is full without it); results are bitwise reproducible.
+ *     its columns and the number of instances (tall tiles once there are
+ *     1024 waves of 16 mr rows, instances stacked once the chip is full
+ *     without it); results are bitwise reproducible.
  *   NMR_TILES_AUTOTUNE: the first time a (direction, layer widths, columns,
  *     instances, precision, derivative scheme) occurs in a step_many call (or
  *     a pool step with at least half its slots attached), every eligible

@@ -694,6 +694,123 @@ __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out(LayerArgs la, const 
   }
 }
 
+// Output layer for many instances: a block of OUT_SPLIT waves stages the
+// instance's folded activations [Cf][K] in LDS once and each wave takes
+// OUT_TILES 16-row tiles over the whole K, the weights of its next tile loaded
+// while the MFMAs of the current one run.  The K quarters of the split kernel
+// above are kept as four accumulators and added in the same order, so both
+// give the same bits.
+#define OUT_TILES 2
+template <typename TW, int NCB>
+__global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out_wide(LayerArgs la, const Inst<float>* __restrict__ tab) {
+  const Inst<float>& I = tab[blockIdx.y];
+  const int inst_active = I.active, gram = I.gram, n_cd = I.n_cdofs, N = I.N, Cf = I.Cf;
+  const int* cdofs = I.cdofs;
+  const float* fold = I.fold;
+  float* rec = I.rec;
+  const float* keep = I.keep;
+  const int K = la.m_inp;
+  load_now(inst_active, gram, n_cd, N, Cf, cdofs, fold, rec, keep, K, la.W, la.b);
+  const int nrows = gram ? n_cd : N;
+  constexpr int BROWS = 16 * OUT_SPLIT * OUT_TILES;
+  const int blk0 = blockIdx.x * BROWS;
+  if (!inst_active || blk0 >= nrows) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rA = lane & 15, g = lane >> 4;
+  const TW* W = reinterpret_cast<const TW*>(la.W);
+  const float* bias = reinterpret_cast<const float*>(la.b);
+  constexpr int KS = kstep<TW>::v;
+  constexpr int NT = (OUT_KMAX / OUT_SPLIT + KS - 1) / KS;  // K-steps of one quarter
+  const int kq = K / OUT_SPLIT;
+  typedef typename std::conditional<std::is_same<TW, float>::value, float4, bf16x8>::type AF;
+  __shared__ __align__(16) float Fs[NCB * 16][OUT_KMAX + 4];
+  // the folded activations, coalesced, once per block
+  for (int p = threadIdx.x; p < NCB * 16 * (K / 4); p += 64 * OUT_SPLIT) {
+    const int c = p / (K / 4), k4 = p - c * (K / 4);
+    *reinterpret_cast<float4*>(&Fs[c][4 * k4]) = ldg<float4>(fold + (size_t)c * K + 4 * k4);
+  }
+  // weights of one tile (clamped row ids, zero A past each quarter's end)
+  // and the output rows, bias and mask of this lane's four result rows
+  struct Tile {
+    AF a[OUT_SPLIT][NT];
+    int orow[4];
+    float b[4], m[4];
+  };
+  auto load_tile = [&](int row0, Tile& t) {
+    const int wrow = gram ? ldg<int>(cdofs + min(row0 + rA, nrows - 1)) : min(row0 + rA, nrows - 1);
+#pragma unroll
+    for (int q = 0; q < OUT_SPLIT; ++q)
+#pragma unroll
+      for (int s2 = 0; s2 < NT; ++s2) {
+        const int kk = q * kq + s2 * KS + (KS / 4) * g;
+        const AF v = ldg<AF>(W + (size_t)wrow * K + min(kk, K - KS / 4));
+        t.a[q][s2] = kk < (q + 1) * kq ? v : zero_of<AF>();
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int tr = min(row0 + 4 * g + i, nrows - 1);
+      const int orow = gram ? ldg<int>(cdofs + tr) : tr;
+      t.orow[i] = orow;
+      t.b[i] = ldg<float>(bias + orow);
+      t.m[i] = ldg<float>(keep + orow);
+    }
+  };
+  auto run_tile = [&](int row0, const Tile& t) {
+    f32x4 acc[OUT_SPLIT][NCB];
+#pragma unroll
+    for (int q = 0; q < OUT_SPLIT; ++q)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        acc[q][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s2 = 0; s2 < NT; ++s2) {
+          if (s2 * KS < kq) {
+            const int k = q * kq + s2 * KS + (KS / 4) * g;
+            if constexpr (std::is_same<TW, float>::value) {
+              const float4 b = *reinterpret_cast<const float4*>(&Fs[cb * 16 + rA][min(k, K - 4)]);
+              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].x, b.x, acc[q][cb], 0, 0, 0);
+              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].y, b.y, acc[q][cb], 0, 0, 0);
+              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].z, b.z, acc[q][cb], 0, 0, 0);
+              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].w, b.w, acc[q][cb], 0, 0, 0);
+            } else {
+              const float4 b0 = *reinterpret_cast<const float4*>(&Fs[cb * 16 + rA][min(k, K - 4)]);
+              const float4 b1 = *reinterpret_cast<const float4*>(&Fs[cb * 16 + rA][min(k + 4, K - 4)]);
+              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(t.a[q][s2], to_bf16x8(b0, b1), acc[q][cb], 0, 0, 0);
+            }
+          }
+        }
+      }
+    // item i of lane l is D[4 (l/16) + i][l % 16]; quarters added in order
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (row0 + 4 * g + i < nrows) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const int c = cb * 16 + rA;
+          if (c < Cf) {
+            float v = acc[0][cb][i];
+#pragma unroll
+            for (int q = 1; q < OUT_SPLIT; ++q) v += acc[q][cb][i];
+            if (c == 0) v += t.b[i];
+            stg<float>(rec + (size_t)t.orow[i] * Cf + c, v * t.m[i]);
+          }
+        }
+      }
+    }
+  };
+  const int r0 = blk0 + wave * 16 * OUT_TILES;
+  Tile t0, t1;
+  load_tile(r0, t0);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < OUT_TILES; j += 2) {
+    if (j + 1 < OUT_TILES) load_tile(r0 + 16 * (j + 1), t1);
+    if (r0 + 16 * j < nrows) run_tile(r0 + 16 * j, t0);
+    if (j + 2 < OUT_TILES) load_tile(r0 + 16 * (j + 2), t0);
+    if (j + 1 < OUT_TILES && r0 + 16 * (j + 1) < nrows) run_tile(r0 + 16 * (j + 1), t1);
+  }
+}
+
 // FP64 form of the output layer (plain FMA; correctness configurations)
 __global__ __launch_bounds__(256) void k_fwd_out_f64(LayerArgs la, const Inst<double>* __restrict__ tab) {
   const Inst<double>& I = tab[blockIdx.y];
@@ -878,9 +995,12 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(LayerArgs la, const Inst<T>*
 // transposed weights stored row-major), then either sigma' of layer l-1 or,
 // at the input, J^T a and a . H.
 // ---------------------------------------------------------------------------
-template <typename T, typename TW, int NCB, int IB, bool FD>
-__global__ __launch_bounds__(512) void k_bwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab, int nb) {
-  constexpr int NW = splitk_waves<T, NCB>::v;
+template <typename T, typename TW, int NCB, int IB, bool FD, int MR>
+__global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_bwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab,
+                                                                     int nb) {
+  static_assert(MR == 1 || (!FD && std::is_same<T, float>::value), "tall tiles: complex-step FP32 jets only");
+  constexpr int ROWS = 16 * MR;  // rows (layer inputs) of a block
+  constexpr int NW = MR > 1 ? IB : splitk_waves<T, NCB>::v;
   constexpr int KSPL = NW / IB;
   constexpr int NG = KSPL * 64;  // threads of one instance slot
   const int l = la.l;
@@ -906,35 +1026,36 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(LayerArgs la, const Inst<T>*
   // q +- h e_j stencil columns (central differences)
   const int nch = fd ? 1 + 2 * nq : 1 + nq;
   const bool use = inst < nb && active;
-  const int row0 = blockIdx.x * 16;
+  const int row0 = blockIdx.x * ROWS;
   if (row0 >= m_inp || (IB == 1 && !use)) return;  // uniform over the block
   const TW* WT = reinterpret_cast<const TW*>(la.WT) + (size_t)row0 * K;
-  __shared__ T S[IB][NCB * 16][17];
-  __shared__ T red[NW][NCB * 16][16];
+  __shared__ T S[IB][NCB * 16][ROWS + 1];
+  __shared__ T red[MR == 1 ? NW : 1][NCB * 16][16];
   typedef typename vec4<T>::type V4;
   auto bload = [&](int c, int k) -> V4 { return ldg<V4>(xb + (size_t)c * K + k); };
   // pre-activations of layer l-1 used by the epilogue, loaded before the GEMM
-  constexpr int PP = (16 * 32 + NG - 1) / NG;  // items per thread: 16 rows x (1 + n_q <= 32) channels
+  constexpr int PP = (ROWS * 32 + NG - 1) / NG;  // items per thread: ROWS rows x (1 + n_q <= 32) channels
   T px0[PP], px1[PP];
 #pragma unroll
   for (int t = 0; t < PP; ++t) {
     const int p = tg + t * NG;
     px0[t] = px1[t] = T(0);
-    if (use && l > 0 && p < 16 * nch) {
-      const int r = p & 15, c = p >> 4;
+    if (use && l > 0 && p < ROWS * nch) {
+      const int r = p & (ROWS - 1), c = p / ROWS;
       px0[t] = ldg<T>(pre + row0 + r);
       if (c > 0) px1[t] = ldg<T>(pre + (size_t)c * m_inp + row0 + r);
     }
   }
-  gemm_splitk<T, TW, NCB, NW, IB>(WT, K, K, use, bload, S, red);
+  if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(WT, K, K, use, bload, S, red);
+  else gemm_tall<TW, NCB, MR>(WT, K, K, use, bload, S);
   if (!use) return;
-  T(*Ss)[17] = S[slot];
+  T(*Ss)[ROWS + 1] = S[slot];
   if (l > 0) {
 #pragma unroll
     for (int t = 0; t < PP; ++t) {
       const int p = tg + t * NG;
-      if (p < 16 * nch) {
-        const int r = p & 15, c = p >> 4;
+      if (p < ROWS * nch) {
+        const int r = p & (ROWS - 1), c = p / ROWS;
         const int row = row0 + r;
         T v;
         if constexpr (FD) {  // each column through sigma' of its own pre-activation
@@ -951,8 +1072,8 @@ __global__ __launch_bounds__(512) void k_bwd_hidden(LayerArgs la, const Inst<T>*
       }
     }
   } else {
-    for (int p = tg; p < 16 * (1 + nq); p += NG) {
-      const int r = p & 15, c = p >> 4;
+    for (int p = tg; p < ROWS * (1 + nq); p += NG) {
+      const int r = p & (ROWS - 1), c = p / ROWS;
       const int row = row0 + r;
       if (row < nq) {
         if (c == 0) stg<double>(JTa + row, (double)Ss[0][r]);
@@ -1002,14 +1123,15 @@ __global__ void k_unpack(const Inst<T>* __restrict__ tab, T* u, T* J, T* dJ, T* 
 // ---------------------------------------------------------------------------
 static int hidden_rows(const DecoderDev& d, int l, bool fwd) { return fwd ? d.wp[l + 1] : d.wp[l]; }
 
-// Forward layers of at most 64 jet columns take tall tiles once there are
-// 1024 (row tile, instance) waves of 16 mr rows, the largest mr first (the
-// crossover measured on the 10k-vertex decoder at 64 and 128 instances);
-// otherwise instances are stacked once the chip is full without it.
+// Layers with tall tiles (at most 64 jet columns forward, 32 adjoint columns
+// backward) take them once there are 1024 (row tile, instance) waves of 16 mr
+// rows, the largest mr first (the crossover measured on the 10k-vertex
+// decoder at 64 and 128 instances); otherwise instances are stacked once the
+// chip is full without it.
 TileCfg tile_rule(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd) {
   if (fd || f64) return TileCfg{1, 1};
   const int rows = hidden_rows(d, l, fwd);
-  if (fwd && cols <= 64 && nb >= 4)
+  if (cols <= (fwd ? 64 : 32) && nb >= 4)
     for (int mr = 4; mr >= 2; mr /= 2)
       if (rows % (16 * mr) == 0 && (rows / (16 * mr)) * nb >= 1024) return TileCfg{4, mr};
   return TileCfg{stack_instances(rows / 16, nb, false), 1};
@@ -1019,7 +1141,7 @@ bool tile_eligible(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f
   if (c.ib == 1 && c.mr == 1) return true;
   if (fd || f64 || nb < c.ib) return false;
   if (c.mr == 1) return c.ib == 2 || c.ib == 4;
-  return fwd && c.ib == 4 && (c.mr == 2 || c.mr == 4) && cols <= 64 && hidden_rows(d, l, fwd) % (16 * c.mr) == 0;
+  return c.ib == 4 && (c.mr == 2 || c.mr == 4) && cols <= (fwd ? 64 : 32) && hidden_rows(d, l, fwd) % (16 * c.mr) == 0;
 }
 
 int tile_candidates(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd, TileCfg* out) {
@@ -1101,10 +1223,19 @@ void launch_fwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* t
 #undef FWD_H64
 }
 
+// the wide form once the instances fill the chip with OUT_TILES-fold fewer blocks
+static bool fwd_out_wide(int max_n, int nb) { return nb >= 8 && ((max_n + 127) / 128) * nb >= 1024; }
+
 template <typename TW>
 static void fwd_out_dispatch(const DecoderDev& d, const Inst<float>* tab, int nb, int max_n, int cf, hipStream_t s) {
+  const bool wide = fwd_out_wide(max_n, nb);
   dim3 grid((max_n + 15) / 16, nb);
-#define FWD_O(n) k_fwd_out<TW, n><<<grid, OUT_SPLIT * 64, 0, s>>>(layer_args(d, d.L - 1), tab)
+  dim3 gridw((max_n + 16 * OUT_SPLIT * OUT_TILES - 1) / (16 * OUT_SPLIT * OUT_TILES), nb);
+#define FWD_O(n)                                                                          \
+  do {                                                                                    \
+    if (wide) k_fwd_out_wide<TW, n><<<gridw, OUT_SPLIT * 64, 0, s>>>(layer_args(d, d.L - 1), tab); \
+    else k_fwd_out<TW, n><<<grid, OUT_SPLIT * 64, 0, s>>>(layer_args(d, d.L - 1), tab);   \
+  } while (0)
   switch (cf / 16) {
     case 1: FWD_O(1); break;
     case 2: FWD_O(2); break;
@@ -1159,13 +1290,23 @@ static void bwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb
   const int threads = 64 * splitk_waves<T, NCB>::v;
   const LayerArgs la = layer_args(d, l);
   if (fd) {  // the central-difference form: one instance per block
-    k_bwd_hidden<T, TW, NCB, 1, true><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
+    k_bwd_hidden<T, TW, NCB, 1, true, 1><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
     return;
   }
-  if (cfg.ib == 4) k_bwd_hidden<T, TW, NCB, 4, false><<<dim3(tiles, (nb + 3) / 4), threads, 0, s>>>(la, tab, nb);
+  if constexpr (std::is_same<T, float>::value && NCB <= 2) {
+    if (cfg.mr == 4) {
+      k_bwd_hidden<T, TW, NCB, 4, false, 4><<<dim3(d.wp[l] / 64, (nb + 3) / 4), 256, 0, s>>>(la, tab, nb);
+      return;
+    }
+    if (cfg.mr == 2) {
+      k_bwd_hidden<T, TW, NCB, 4, false, 2><<<dim3(d.wp[l] / 32, (nb + 3) / 4), 256, 0, s>>>(la, tab, nb);
+      return;
+    }
+  }
+  if (cfg.ib == 4) k_bwd_hidden<T, TW, NCB, 4, false, 1><<<dim3(tiles, (nb + 3) / 4), threads, 0, s>>>(la, tab, nb);
   else if (cfg.ib == 2)
-    k_bwd_hidden<T, TW, NCB, 2, false><<<dim3(tiles, (nb + 1) / 2), threads, 0, s>>>(la, tab, nb);
-  else k_bwd_hidden<T, TW, NCB, 1, false><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
+    k_bwd_hidden<T, TW, NCB, 2, false, 1><<<dim3(tiles, (nb + 1) / 2), threads, 0, s>>>(la, tab, nb);
+  else k_bwd_hidden<T, TW, NCB, 1, false, 1><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
 }
 
 template <typename T, typename TW>

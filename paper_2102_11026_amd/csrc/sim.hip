@@ -163,16 +163,20 @@ template void launch_step_begin<double>(const Inst<double>*, int, int, int, hipS
 // K_e.  Neo-Hookean: P = mu (F - F^-T) + lam ln J F^-T,
 //   dP[dF] = mu dF + (mu - lam ln J) F^-T dF^T F^-T + lam tr(F^-1 dF) F^-T.
 // Element math in T, accumulation in FP64; the four wave sums are added in
-// wave order.
+// wave order.  Launches of many instances merge m consecutive blocks of tets
+// into one (fewer, longer blocks; partial b then covers blocks b m .. b m +
+// m - 1 and the sums read ceil(n_cblk / m) partials).
 // ---------------------------------------------------------------------------
 #define CUB_WAVES 4
+static int cubature_merge(int nb) { return nb >= 64 ? 8 : nb >= 16 ? 4 : 1; }
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ tab) {
+__global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ tab, int m) {
   const Inst<T>& I = tab[blockIdx.y];
   load_now(I.active, I.n_cblk, I.R, I.cu_na, I.mu, I.lam, I.cub_per_blk, I.n_cub, I.cub_v, I.cub_Bm, I.cu_w, I.cub_Ve,
            I.X, I.cu_u, I.cu_u_ld, I.cu_Ja, I.cu_Ja_ld, I.cu_Jb, I.cu_Jb_ld, I.status, I.fe, I.part_cub);
   if (!I.active) return;
-  if ((int)blockIdx.x >= I.n_cblk) return;
+  if ((int)blockIdx.x * m >= I.n_cblk) return;
   const int R = I.R;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int na = I.cu_na;
@@ -187,8 +191,8 @@ __global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ ta
 #pragma unroll
   for (int i = 0; i < KT; ++i) kacc[i] = 0.0;
   double facc = 0.0;
-  const int e0 = blockIdx.x * I.cub_per_blk;
-  const int e1 = min(e0 + I.cub_per_blk, I.n_cub);
+  const int e0 = blockIdx.x * m * I.cub_per_blk;
+  const int e1 = min(e0 + m * I.cub_per_blk, I.n_cub);
   constexpr int JT = (12 * NMR_MAX_R + 63) / 64;
   for (int e = e0 + wave; e < e1; e += CUB_WAVES) {
     // first round trip: the tet's vertices, B_m, weight and volume (none
@@ -325,7 +329,8 @@ __global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ ta
 
 template <typename T>
 void launch_cubature(const Inst<T>* tab, int nb, int max_cblk, hipStream_t s) {
-  k_cubature<T><<<dim3(max_cblk, nb), 64 * CUB_WAVES, 0, s>>>(tab);
+  const int m = cubature_merge(nb);
+  k_cubature<T><<<dim3((max_cblk + m - 1) / m, nb), 64 * CUB_WAVES, 0, s>>>(tab, m);
 }
 template void launch_cubature<float>(const Inst<float>*, int, int, hipStream_t);
 template void launch_cubature<double>(const Inst<double>*, int, int, hipStream_t);
@@ -745,7 +750,7 @@ template void launch_gram_setup<double>(const void*, int, int, const double*, co
 // slice sums are added in slice order.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_sums(const Inst<T>* __restrict__ tab) {
+__global__ __launch_bounds__(256) void k_sums(const Inst<T>* __restrict__ tab, int cub_m) {
   const Inst<T>& I = tab[blockIdx.y];
   load_now(I.active, I.R, I.n_q, I.n_p, I.n_cblk, I.gram, I.n_gblk, I.n_mblk, I.part_cub, I.part_mass, I.sum_cub,
            I.sum_mass);
@@ -759,8 +764,9 @@ __global__ __launch_bounds__(256) void k_sums(const Inst<T>* __restrict__ tab) {
   double acc = 0.0;
   if (e < Ec) {
     const double* src = I.part_cub + e;
+    const int nc = (I.n_cblk + cub_m - 1) / cub_m;
 #pragma unroll 4
-    for (int b = sl; b < I.n_cblk; b += 16) acc += ldg<double>(src + (size_t)b * Ec);
+    for (int b = sl; b < nc; b += 16) acc += ldg<double>(src + (size_t)b * Ec);
   } else if (e < Ec + Em) {
     const double* src = I.part_mass + (e - Ec);
     const int nb = I.gram ? I.n_gblk : I.n_mblk;
@@ -779,7 +785,7 @@ __global__ __launch_bounds__(256) void k_sums(const Inst<T>* __restrict__ tab) {
 
 template <typename T>
 void launch_sums(const Inst<T>* tab, int nb, int max_entries, hipStream_t s) {
-  k_sums<T><<<dim3((max_entries + 15) / 16, nb), 256, 0, s>>>(tab);
+  k_sums<T><<<dim3((max_entries + 15) / 16, nb), 256, 0, s>>>(tab, cubature_merge(nb));
 }
 template void launch_sums<float>(const Inst<float>*, int, int, hipStream_t);
 template void launch_sums<double>(const Inst<double>*, int, int, hipStream_t);

@@ -1,0 +1,115 @@
+"""GPU tests of the launch shapes that only large batches take: the wide
+output-layer kernel (folded activations staged once per block; the same bits
+as the split kernel) and merged cubature blocks (a different FP64 summation
+order: equal to rounding).  All through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_2102_11026_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def nmr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2102_11026_amd import nmr as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(nmr):
+    c = nmr.Context(0)
+    yield c
+    c.close()
+
+
+def batch_vs_alone(nmr, ctx, probs, prec, steps, iters, path="auto"):
+    dec = nmr.Decoder(ctx, probs[0].weights, probs[0].biases, probs[0].act, prec)
+    together = [nmr.Instance(ctx, q, prec, shared=dec, path=path) for q in probs]
+    try:
+        st, _ = nmr.step_many(ctx, together, steps, iters)
+        assert st == [0] * len(probs)
+        got = [x.get_state(with_u=True) for x in together]
+    finally:
+        for x in together:
+            x.close()
+    alone = []
+    for q in probs:
+        x = nmr.Instance(ctx, q, prec, shared=dec, path=path)
+        try:
+            st, _ = nmr.step_many(ctx, [x], steps, iters)
+            assert st == [0]
+            alone.append(x.get_state(with_u=True))
+        finally:
+            x.close()
+    dec.close()
+    return got, alone
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_wide_output_layer_is_bitwise_the_split_one(nmr, ctx, prec):
+    """Eight 10k-vertex instances on the direct path (30,000 decoded rows
+    each): the output layer runs the wide kernel, everything else as alone."""
+    p = synth.config_single_10k()
+    probs = [p.replace(r0=p.r0 + 0.02 * synth.normal(f"wide/q0/{k}", p.R)) for k in range(8)]
+    got, alone = batch_vs_alone(nmr, ctx, probs, prec, 1, p.newton_iters, path="direct")
+    for (r, rd, u), (ra, rda, ua) in zip(got, alone):
+        np.testing.assert_array_equal(r, ra)
+        np.testing.assert_array_equal(rd, rda)
+        np.testing.assert_array_equal(u, ua)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_merged_cubature_blocks_match_alone(nmr, ctx, prec, tol):
+    """Twenty instances: the cubature pass merges four blocks of tets into
+    one and the sums read a quarter of the partials."""
+    base = synth.tiny_problem(grid=(3, 3, 6), widths=(4, 32, 48, 162), act="tanh", name="merge", q_std=0.3,
+                              out_scale=0.1)
+    probs = []
+    for k in range(20):
+        r0 = np.zeros(base.R)
+        r0[base.n_p:] = 0.2 * synth.normal(f"merge/q0/{k}", base.n_q)
+        probs.append(base.replace(r0=r0))
+    got, alone = batch_vs_alone(nmr, ctx, probs, prec, 4, 3)
+    for k, ((r, rd, u), (ra, rda, ua)) in enumerate(zip(got, alone)):
+        assert rel(r, ra) < tol and rel(rd, rda) < tol and rel(u, ua) < tol, k
+
+
+def test_large_pool_matches_alone(nmr, ctx):
+    """A request in a 32-slot pool (merged cubature blocks) against the same
+    request alone, to FP32 rounding."""
+    base = synth.tiny_problem(grid=(3, 3, 6), widths=(4, 32, 48, 162), act="elu", name="bigpool", q_std=0.3,
+                              out_scale=0.1, n_cub=20)
+    probs = []
+    for k in range(20):
+        r0 = np.zeros(base.R)
+        r0[base.n_p:] = 0.1 * synth.normal(f"bigpool/q0/{k}", base.n_q)
+        probs.append(base.replace(r0=r0))
+    dec = nmr.Decoder(ctx, base.weights, base.biases, base.act, "fp32")
+    pool = nmr.Pool(ctx, 32)
+    insts = [nmr.Instance(ctx, q, "fp32", shared=dec) for q in probs]
+    ref = nmr.Instance(ctx, probs[0], "fp32", shared=dec)
+    try:
+        for x in insts:
+            pool.attach(x)
+        for _ in range(5):
+            st, _ = pool.step(3, status=True)
+            assert all(v == 0 for v in st)
+        st, _ = nmr.step_many(ctx, [ref], 5, 3)
+        assert st == [0]
+        assert rel(insts[0].get_state()[0], ref.get_state()[0]) < 1e-5
+    finally:
+        pool.close()
+        for x in insts + [ref]:
+            x.close()
+        dec.close()

@@ -141,12 +141,15 @@ def test_autotune_records_eligible_choices(nmr):
             dec.close()
         table = ctx.tiling_table()
         # forward: 3 hidden layers; backward: 3 (each with more than one candidate)
+        print(table)
         assert sum(e["forward"] for e in table) == 3 and len(table) == 6, table
         for e in table:
             assert e["n_inst"] == 8 and e["us"] > 0
             assert (e["ib"], e["mr"]) in CONFIGS
             if e["mr"] > 1:
-                assert e["forward"] == 1 and e["ib"] == 4 and e["m_out"] % (16 * e["mr"]) == 0
+                rows = e["m_out"] if e["forward"] else e["m_in"]
+                assert e["ib"] == 4 and rows % (16 * e["mr"]) == 0
+                assert e["cols"] <= (64 if e["forward"] else 32)
     finally:
         ctx.close()
 
