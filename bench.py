@@ -40,8 +40,8 @@ PHASE_KERNEL = dict(dec_hidden="k_fwd_hidden", dec_out="k_fwd_out", bwd_out="k_b
 # factors a plain 512 MiB device copy gives), averaged over one pass of the
 # phase; see profiles/k_fwd_hidden_bar10k_fp32_pmc.md.  They hold only for the
 # kernel sources they were taken on: with any other sources traffic is null.
-MEASURED_TRAFFIC = dict(k_fwd_hidden=1682545, k_bwd_hidden=987096, k_fwd_out=6657664, k_bwd_out=5776384)
-MEASURED_TRAFFIC_SOURCES = "6b67ce099c2fc28c"
+MEASURED_TRAFFIC = dict(k_fwd_hidden=1684411, k_bwd_hidden=978806, k_fwd_out=6702327, k_bwd_out=5767942)
+MEASURED_TRAFFIC_SOURCES = "2bd9d14e895fd180"
 KERNEL_SOURCES = ("paper_2102_11026_amd/csrc/decoder.hip", "paper_2102_11026_amd/csrc/nmr_internal.h")
 
 
@@ -261,13 +261,15 @@ def main():
     ap.add_argument("--batch", type=int, nargs="*", default=[4, 16, 64, 128])
     ap.add_argument("--tiling", choices=["rule", "autotune"], default="rule",
                     help="tile choice of the batched hidden layers in --profile-batch mode")
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32",
+                    help="decoder precision in --profile-batch mode")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="arrival window of the served form (0: skip)")
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (the reference kernel that scales "
                          "hardware byte counters) and exit")
     ap.add_argument("--profile-batch", type=int, default=0, metavar="B",
-                    help="only step B instances of the 10k-vertex problem sharing one FP32 decoder (for a "
+                    help="only step B instances of the 10k-vertex problem sharing one decoder (for a "
                          "profiler) and exit")
     args = ap.parse_args()
     if args.profile_batch:
@@ -276,14 +278,14 @@ def main():
         p = synth.config_single_10k()
         ctx = nmr.Context(0)
         ctx.set_tiling(args.tiling)
-        dec = nmr.Decoder(ctx, p.weights, p.biases, p.act, "fp32")
+        dec = nmr.Decoder(ctx, p.weights, p.biases, p.act, args.precision)
         insts = []
         for k in range(args.profile_batch):
             r0 = np.zeros(p.R)
             r0[p.n_p:] = 0.1 * synth.normal(f"q0/{k}", p.n_q)
-            insts.append(nmr.Instance(ctx, p.replace(r0=r0), "fp32", shared=dec))
+            insts.append(nmr.Instance(ctx, p.replace(r0=r0), args.precision, shared=dec))
         secs, ms = run_steps(nmr, ctx, insts, args.steps, args.warmup)
-        print(json.dumps(dict(instances=args.profile_batch, steps=args.steps,
+        print(json.dumps(dict(instances=args.profile_batch, precision=args.precision, steps=args.steps,
                               newton_iters_per_s=round(ITERS * args.steps * args.profile_batch / secs, 1))))
         for x in insts:
             x.close()
