@@ -757,11 +757,13 @@ static void enqueue_decoder_fwd(const Group& g, hipStream_t s, int add_up) {
   if (g.any_np) launch_filter<T>(tab, g.nb, add_up, s);
 }
 
+// with_out: launch the output-layer backpropagation too (else the caller
+// has, fused with the sums)
 template <typename T>
-static void enqueue_decoder_bwd(const Group& g, hipStream_t s) {
+static void enqueue_decoder_bwd(const Group& g, hipStream_t s, bool with_out = true) {
   const DecoderDev& d = g.dec->d;
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
-  launch_bwd_out<T>(d, tab, g.nb, g.gram ? g.max_sblk : g.max_bblk, s);
+  if (with_out) launch_bwd_out<T>(d, tab, g.nb, g.gram ? g.max_sblk : g.max_bblk, s);
   launch_bwd_reduce<T>(d, tab, g.nb, s);
   for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, g.fd, g.tb[l], s);
 }
@@ -770,11 +772,18 @@ template <typename T>
 static void enqueue_iteration(const Group& g, int iter, int mode, double* A_out, double* phi_out, hipStream_t s) {
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
   enqueue_decoder_fwd<T>(g, s, 1);
-  launch_cubature<T>(tab, g.nb, g.max_cblk, s);
-  if (g.gram) launch_gram<T>(tab, g.nb, g.n_gblk, g.K, g.n_q, s);
-  else launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
-  launch_sums<T>(tab, g.nb, g.max_entries, s);
-  enqueue_decoder_bwd<T>(g, s);
+  if (g.gram) {
+    // the Gram terms need only the folded activations and the state, and the
+    // output-layer seed only the element forces: each pair is one launch
+    launch_cub_gram<T>(tab, g.nb, g.max_cblk, g.n_gblk, g.K, g.n_q, s);
+    launch_sums_bwd_out<T>(g.dec->d, tab, g.nb, g.max_entries, g.max_sblk, s);
+    enqueue_decoder_bwd<T>(g, s, false);
+  } else {
+    launch_cubature<T>(tab, g.nb, g.max_cblk, s);
+    launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
+    launch_sums<T>(tab, g.nb, g.max_entries, s);
+    enqueue_decoder_bwd<T>(g, s);
+  }
   launch_solve<T>(tab, g.nb, iter, mode, A_out, phi_out, s);
 }
 

@@ -884,18 +884,18 @@ __device__ inline void load4(const __bf16* p, double (&w)[4]) {
 }
 
 template <typename T, typename TW>
-__global__ __launch_bounds__(256) void k_bwd_out(LayerArgs la, const Inst<T>* __restrict__ tab) {
-  const Inst<T>& I = tab[blockIdx.y];
+__device__ inline void bwd_out_block(const LayerArgs& la, const Inst<T>* __restrict__ tab, int bx, int by) {
+  const Inst<T>& I = tab[by];
   load_now(I.active, I.gram, I.n_sblk, I.n_bblk, I.n_cdofs, I.N, I.n_p, I.R, I.n_q, I.sum_mass, I.cdofs, I.keep,
            I.seed, I.U, I.part_bwd, I.csr_ptr, I.csr_ent, I.fe, la.m_inp, la.W);
   if (!I.active) return;
   // direct path: all N rows with the seed P a (and the filter transpose);
   // Gram path: only the cubature DOFs with dt^2 P f_int (the rest of W_L^T P a
   // is Gam y + gam, added by the Gram kernel as one more partial)
-  if ((int)blockIdx.x >= (I.gram ? I.n_sblk : I.n_bblk)) return;
+  if (bx >= (I.gram ? I.n_sblk : I.n_bblk)) return;
   const int K = la.m_inp;
   const int nrows = I.gram ? I.n_cdofs : I.N;
-  const int i0 = blockIdx.x * BWD_ROWS;
+  const int i0 = bx * BWD_ROWS;
   const int i1 = min(i0 + BWD_ROWS, nrows);
   __shared__ double s[BWD_ROWS];
   __shared__ int srow[BWD_ROWS];
@@ -936,10 +936,25 @@ __global__ __launch_bounds__(256) void k_bwd_out(LayerArgs la, const Inst<T>* __
     __syncthreads();
     const int c = c0 + threadIdx.x;
     if (c < K)
-      stg<double>(I.part_bwd + (size_t)blockIdx.x * K + c,
+      stg<double>(I.part_bwd + (size_t)bx * K + c,
                   ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x]);
     __syncthreads();
   }
+}
+
+template <typename T, typename TW>
+__global__ __launch_bounds__(256) void k_bwd_out(LayerArgs la, const Inst<T>* __restrict__ tab) {
+  bwd_out_block<T, TW>(la, tab, blockIdx.x, blockIdx.y);
+}
+
+// The partial sums and the output-layer backpropagation in one launch (Gram
+// path: the seed dt^2 P f_int needs the element forces, not the sums):
+// blocks below n_sum run the sums, the rest the output-layer rows.
+template <typename T, typename TW>
+__global__ __launch_bounds__(256) void k_sums_bwd_out(LayerArgs la, const Inst<T>* __restrict__ tab, int cub_m,
+                                                      int n_sum) {
+  if ((int)blockIdx.x < n_sum) sums_block<T>(tab, blockIdx.x, blockIdx.y, cub_m);
+  else bwd_out_block<T, TW>(la, tab, blockIdx.x - n_sum, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1273,6 +1288,23 @@ template <>
 void launch_bwd_out<double>(const DecoderDev& d, const Inst<double>* tab, int nb, int max_bblk, hipStream_t s) {
   dim3 grid(max_bblk, nb);
   k_bwd_out<double, double><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab);
+}
+
+template <>
+void launch_sums_bwd_out<float>(const DecoderDev& d, const Inst<float>* tab, int nb, int max_entries, int max_sblk,
+                                hipStream_t s) {
+  const int n_sum = (max_entries + 15) / 16;
+  dim3 grid(n_sum + max_sblk, nb);
+  if (d.prec == PREC_BF16)
+    k_sums_bwd_out<float, __bf16><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab, cubature_merge(nb), n_sum);
+  else k_sums_bwd_out<float, float><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab, cubature_merge(nb), n_sum);
+}
+template <>
+void launch_sums_bwd_out<double>(const DecoderDev& d, const Inst<double>* tab, int nb, int max_entries, int max_sblk,
+                                 hipStream_t s) {
+  const int n_sum = (max_entries + 15) / 16;
+  dim3 grid(n_sum + max_sblk, nb);
+  k_sums_bwd_out<double, double><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab, cubature_merge(nb), n_sum);
 }
 
 template <typename T>

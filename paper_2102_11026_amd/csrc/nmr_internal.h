@@ -203,6 +203,48 @@ __device__ inline double fint_at(const Inst<T>& I, int i) {
   return f;
 }
 
+// ---- fixed-order sums of the cubature and mass partials ------------------
+// Launches of many instances merge m consecutive blocks of tets into one
+// cubature block (fewer, longer blocks); the sums read ceil(n_cblk / m)
+// cubature partials.
+inline int cubature_merge(int nb) { return nb >= 64 ? 8 : nb >= 16 ? 4 : 1; }
+
+// Block bx of instance by takes 16 entries; 16 slices of 16 threads add every
+// sixteenth partial, then the 16 slice sums are added in slice order.
+template <typename T>
+__device__ inline void sums_block(const Inst<T>* __restrict__ tab, int bx, int by, int cub_m) {
+  const Inst<T>& I = tab[by];
+  load_now(I.active, I.R, I.n_q, I.n_p, I.n_cblk, I.gram, I.n_gblk, I.n_mblk, I.part_cub, I.part_mass, I.sum_cub,
+           I.sum_mass);
+  if (!I.active) return;
+  const int R = I.R;
+  const int Ec = R * R + R;
+  const int Em = R * R + R * I.n_q + R + I.n_p;
+  const int kk = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int e = bx * 16 + kk;
+  __shared__ double part[16][17];
+  double acc = 0.0;
+  if (e < Ec) {
+    const double* src = I.part_cub + e;
+    const int nc = (I.n_cblk + cub_m - 1) / cub_m;
+#pragma unroll 4
+    for (int b = sl; b < nc; b += 16) acc += ldg<double>(src + (size_t)b * Ec);
+  } else if (e < Ec + Em) {
+    const double* src = I.part_mass + (e - Ec);
+    const int nb = I.gram ? I.n_gblk : I.n_mblk;
+#pragma unroll 4
+    for (int b = sl; b < nb; b += 16) acc += ldg<double>(src + (size_t)b * Em);
+  }
+  part[sl][kk] = acc;
+  __syncthreads();
+  if (sl == 0) {
+    double v = part[0][kk];
+    for (int q = 1; q < 16; ++q) v += part[q][kk];
+    if (e < Ec) stg<double>(I.sum_cub + e, v);
+    else if (e < Ec + Em) stg<double>(I.sum_mass + e - Ec, v);
+  }
+}
+
 // ---- tile configurations of the hidden-layer launches (decoder.hip) ----
 // ib instances per block (stacked instances share the weight tile); mr
 // 16-row tiles per wave (mr > 1: tall tiles, one wave per instance over the
@@ -225,6 +267,11 @@ template <typename T>
 void launch_filter(const Inst<T>* tab, int nb, int add_up, hipStream_t s);
 template <typename T>
 void launch_bwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_bblk, hipStream_t s);
+// the partial sums and the output-layer backpropagation in one launch (Gram
+// path, where the seed needs only the element forces)
+template <typename T>
+void launch_sums_bwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_entries, int max_sblk,
+                         hipStream_t s);
 template <typename T>
 void launch_bwd_reduce(const DecoderDev& d, const Inst<T>* tab, int nb, hipStream_t s);
 template <typename T>
@@ -242,6 +289,9 @@ template <typename T>
 void launch_step_begin(const Inst<T>* tab, int nb, int mode, int max_cub, hipStream_t s);
 template <typename T>
 void launch_cubature(const Inst<T>* tab, int nb, int max_cblk, hipStream_t s);
+// the cubature pass and the Gram kernel in one launch (Gram path)
+template <typename T>
+void launch_cub_gram(const Inst<T>* tab, int nb, int max_cblk, int max_gblk, int K, int nq, hipStream_t s);
 template <typename T>
 void launch_mass(const Inst<T>* tab, int nb, int max_mblk, int R, int nq, hipStream_t s);
 template <typename T>

@@ -163,20 +163,19 @@ template void launch_step_begin<double>(const Inst<double>*, int, int, int, hipS
 // K_e.  Neo-Hookean: P = mu (F - F^-T) + lam ln J F^-T,
 //   dP[dF] = mu dF + (mu - lam ln J) F^-T dF^T F^-T + lam tr(F^-1 dF) F^-T.
 // Element math in T, accumulation in FP64; the four wave sums are added in
-// wave order.  Launches of many instances merge m consecutive blocks of tets
-// into one (fewer, longer blocks; partial b then covers blocks b m .. b m +
-// m - 1 and the sums read ceil(n_cblk / m) partials).
+// wave order.  Launches of many instances merge m = cubature_merge(nb)
+// consecutive blocks of tets into one (partial b then covers blocks b m ..
+// b m + m - 1).
 // ---------------------------------------------------------------------------
 #define CUB_WAVES 4
-static int cubature_merge(int nb) { return nb >= 64 ? 8 : nb >= 16 ? 4 : 1; }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ tab, int m) {
-  const Inst<T>& I = tab[blockIdx.y];
+__device__ inline void cubature_block(const Inst<T>* __restrict__ tab, int bx, int by, int m) {
+  const Inst<T>& I = tab[by];
   load_now(I.active, I.n_cblk, I.R, I.cu_na, I.mu, I.lam, I.cub_per_blk, I.n_cub, I.cub_v, I.cub_Bm, I.cu_w, I.cub_Ve,
            I.X, I.cu_u, I.cu_u_ld, I.cu_Ja, I.cu_Ja_ld, I.cu_Jb, I.cu_Jb_ld, I.status, I.fe, I.part_cub);
   if (!I.active) return;
-  if ((int)blockIdx.x * m >= I.n_cblk) return;
+  if (bx * m >= I.n_cblk) return;
   const int R = I.R;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int na = I.cu_na;
@@ -191,7 +190,7 @@ __global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ ta
 #pragma unroll
   for (int i = 0; i < KT; ++i) kacc[i] = 0.0;
   double facc = 0.0;
-  const int e0 = blockIdx.x * m * I.cub_per_blk;
+  const int e0 = bx * m * I.cub_per_blk;
   const int e1 = min(e0 + m * I.cub_per_blk, I.n_cub);
   constexpr int JT = (12 * NMR_MAX_R + 63) / 64;
   for (int e = e0 + wave; e < e1; e += CUB_WAVES) {
@@ -323,8 +322,13 @@ __global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ ta
     }
     __syncthreads();
   }
-  double* out = I.part_cub + (size_t)blockIdx.x * E;
+  double* out = I.part_cub + (size_t)bx * E;
   for (int p = threadIdx.x; p < E; p += 256) stg<double>(out + p, red[p]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ tab, int m) {
+  cubature_block<T>(tab, blockIdx.x, blockIdx.y, m);
 }
 
 template <typename T>
@@ -563,16 +567,16 @@ template void launch_seed_from_a<double>(const Inst<double>*, const double*, int
 // F_J[rows]^T T and its 16 entries of Gam y + gam as a backprop partial.
 // ---------------------------------------------------------------------------
 template <typename T, int NCB>
-__global__ __launch_bounds__(256) void k_gram(const Inst<T>* __restrict__ tab, int K) {
-  const Inst<T>& I = tab[blockIdx.y];
+__device__ inline void gram_block(const Inst<T>* __restrict__ tab, int bx, int by, int K) {
+  const Inst<T>& I = tab[by];
   load_now(I.active, I.gram, I.n_gblk, I.n_q, I.R, I.fold, I.dt, I.Gam, I.gam, I.r, I.rbar, I.rdot, I.part_bwd,
            I.n_sblk, I.part_mass);
   if (!I.active) return;
-  if (!I.gram || (int)blockIdx.x >= I.n_gblk) return;
+  if (!I.gram || bx >= I.n_gblk) return;
   const int nq = I.n_q, R = I.R;  // R = n_q on this path
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kk = lane >> 4;
-  const int row0 = blockIdx.x * 16;
+  const int row0 = bx * 16;
   const T* F = I.fold;  // [Cf][K], K <= 256
   __shared__ double wr[NMR_MAX_R];
   __shared__ double y[256];
@@ -668,7 +672,7 @@ __global__ __launch_bounds__(256) void k_gram(const Inst<T>* __restrict__ tab, i
   __syncthreads();
   // mass partial F_J[rows]^T T in the layout of the direct path
   const int E = R * R + R * nq + R;
-  double* out = I.part_mass + (size_t)blockIdx.x * E;
+  double* out = I.part_mass + (size_t)bx * E;
   for (int e = threadIdx.x; e < E; e += 256) {
     int i, c;
     if (e < R * R) {
@@ -688,6 +692,20 @@ __global__ __launch_bounds__(256) void k_gram(const Inst<T>* __restrict__ tab, i
   }
 }
 
+template <typename T, int NCB>
+__global__ __launch_bounds__(256) void k_gram(const Inst<T>* __restrict__ tab, int K) {
+  gram_block<T, NCB>(tab, blockIdx.x, blockIdx.y, K);
+}
+
+// The cubature pass and the Gram kernel in one launch (the Gram terms need
+// only the folded activations and the state, not the decoded rows): blocks
+// below n_cub_blocks run the cubature, the rest the Gram rows.
+template <typename T, int NCB>
+__global__ __launch_bounds__(256) void k_cub_gram(const Inst<T>* __restrict__ tab, int m, int K, int n_cub_blocks) {
+  if ((int)blockIdx.x < n_cub_blocks) cubature_block<T>(tab, blockIdx.x, blockIdx.y, m);
+  else gram_block<T, NCB>(tab, blockIdx.x - n_cub_blocks, blockIdx.y, K);
+}
+
 template <typename T>
 void launch_gram(const Inst<T>* tab, int nb, int max_gblk, int K, int nq, hipStream_t s) {
   const dim3 grid(max_gblk, nb);
@@ -700,6 +718,20 @@ void launch_gram(const Inst<T>* tab, int nb, int max_gblk, int K, int nq, hipStr
 }
 template void launch_gram<float>(const Inst<float>*, int, int, int, int, hipStream_t);
 template void launch_gram<double>(const Inst<double>*, int, int, int, int, hipStream_t);
+
+template <typename T>
+void launch_cub_gram(const Inst<T>* tab, int nb, int max_cblk, int max_gblk, int K, int nq, hipStream_t s) {
+  const int m = cubature_merge(nb), ncb = (max_cblk + m - 1) / m;
+  const dim3 grid(ncb + max_gblk, nb);
+  switch ((2 * nq + 1 + 15) / 16) {
+    case 1: k_cub_gram<T, 1><<<grid, 256, 0, s>>>(tab, m, K, ncb); break;
+    case 2: k_cub_gram<T, 2><<<grid, 256, 0, s>>>(tab, m, K, ncb); break;
+    case 3: k_cub_gram<T, 3><<<grid, 256, 0, s>>>(tab, m, K, ncb); break;
+    default: k_cub_gram<T, 4><<<grid, 256, 0, s>>>(tab, m, K, ncb); break;
+  }
+}
+template void launch_cub_gram<float>(const Inst<float>*, int, int, int, int, int, hipStream_t);
+template void launch_cub_gram<double>(const Inst<double>*, int, int, int, int, int, hipStream_t);
 
 // setup: Gam = W_L^T diag(m keep) W_L over the N rows of this instance and
 // gam = W_L^T (keep c); one thread per entry, rows in order
@@ -745,42 +777,11 @@ template void launch_gram_setup<double>(const void*, int, int, const double*, co
 
 
 // ---------------------------------------------------------------------------
-// Fixed-order sums of the cubature and mass partials.  Each block takes 16
-// entries; 16 slices of 16 threads add every sixteenth partial, then the 16
-// slice sums are added in slice order.
+// Fixed-order sums of the cubature and mass partials (sums_block).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(256) void k_sums(const Inst<T>* __restrict__ tab, int cub_m) {
-  const Inst<T>& I = tab[blockIdx.y];
-  load_now(I.active, I.R, I.n_q, I.n_p, I.n_cblk, I.gram, I.n_gblk, I.n_mblk, I.part_cub, I.part_mass, I.sum_cub,
-           I.sum_mass);
-  if (!I.active) return;
-  const int R = I.R;
-  const int Ec = R * R + R;
-  const int Em = R * R + R * I.n_q + R + I.n_p;
-  const int kk = threadIdx.x & 15, sl = threadIdx.x >> 4;
-  const int e = blockIdx.x * 16 + kk;
-  __shared__ double part[16][17];
-  double acc = 0.0;
-  if (e < Ec) {
-    const double* src = I.part_cub + e;
-    const int nc = (I.n_cblk + cub_m - 1) / cub_m;
-#pragma unroll 4
-    for (int b = sl; b < nc; b += 16) acc += ldg<double>(src + (size_t)b * Ec);
-  } else if (e < Ec + Em) {
-    const double* src = I.part_mass + (e - Ec);
-    const int nb = I.gram ? I.n_gblk : I.n_mblk;
-#pragma unroll 4
-    for (int b = sl; b < nb; b += 16) acc += ldg<double>(src + (size_t)b * Em);
-  }
-  part[sl][kk] = acc;
-  __syncthreads();
-  if (sl == 0) {
-    double v = part[0][kk];
-    for (int q = 1; q < 16; ++q) v += part[q][kk];
-    if (e < Ec) stg<double>(I.sum_cub + e, v);
-    else if (e < Ec + Em) stg<double>(I.sum_mass + e - Ec, v);
-  }
+  sums_block<T>(tab, blockIdx.x, blockIdx.y, cub_m);
 }
 
 template <typename T>
