@@ -884,7 +884,7 @@ __device__ inline void load4(const __bf16* p, double (&w)[4]) {
 }
 
 template <typename T, typename TW>
-__device__ inline void bwd_out_block(const LayerArgs& la, const Inst<T>* __restrict__ tab, int bx, int by) {
+__device__ __forceinline__ void bwd_out_block(const LayerArgs& la, const Inst<T>* __restrict__ tab, int bx, int by) {
   const Inst<T>& I = tab[by];
   load_now(I.active, I.gram, I.n_sblk, I.n_bblk, I.n_cdofs, I.N, I.n_p, I.R, I.n_q, I.sum_mass, I.cdofs, I.keep,
            I.seed, I.U, I.part_bwd, I.csr_ptr, I.csr_ent, I.fe, la.m_inp, la.W);

@@ -212,7 +212,7 @@ inline int cubature_merge(int nb) { return nb >= 64 ? 8 : nb >= 16 ? 4 : 1; }
 // Block bx of instance by takes 16 entries; 16 slices of 16 threads add every
 // sixteenth partial, then the 16 slice sums are added in slice order.
 template <typename T>
-__device__ inline void sums_block(const Inst<T>* __restrict__ tab, int bx, int by, int cub_m) {
+__device__ __forceinline__ void sums_block(const Inst<T>* __restrict__ tab, int bx, int by, int cub_m) {
   const Inst<T>& I = tab[by];
   load_now(I.active, I.R, I.n_q, I.n_p, I.n_cblk, I.gram, I.n_gblk, I.n_mblk, I.part_cub, I.part_mass, I.sum_cub,
            I.sum_mass);

@@ -170,7 +170,7 @@ template void launch_step_begin<double>(const Inst<double>*, int, int, int, hipS
 #define CUB_WAVES 4
 
 template <typename T>
-__device__ inline void cubature_block(const Inst<T>* __restrict__ tab, int bx, int by, int m) {
+__device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, int bx, int by, int m) {
   const Inst<T>& I = tab[by];
   load_now(I.active, I.n_cblk, I.R, I.cu_na, I.mu, I.lam, I.cub_per_blk, I.n_cub, I.cub_v, I.cub_Bm, I.cu_w, I.cub_Ve,
            I.X, I.cu_u, I.cu_u_ld, I.cu_Ja, I.cu_Ja_ld, I.cu_Jb, I.cu_Jb_ld, I.status, I.fe, I.part_cub);
@@ -567,7 +567,7 @@ template void launch_seed_from_a<double>(const Inst<double>*, const double*, int
 // F_J[rows]^T T and its 16 entries of Gam y + gam as a backprop partial.
 // ---------------------------------------------------------------------------
 template <typename T, int NCB>
-__device__ inline void gram_block(const Inst<T>* __restrict__ tab, int bx, int by, int K) {
+__device__ __forceinline__ void gram_block(const Inst<T>* __restrict__ tab, int bx, int by, int K) {
   const Inst<T>& I = tab[by];
   load_now(I.active, I.gram, I.n_gblk, I.n_q, I.R, I.fold, I.dt, I.Gam, I.gam, I.r, I.rbar, I.rdot, I.part_bwd,
            I.n_sblk, I.part_mass);
