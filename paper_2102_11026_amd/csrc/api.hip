@@ -768,11 +768,16 @@ static void enqueue_decoder_bwd(const Group& g, hipStream_t s, bool with_out = t
   for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, g.fd, g.tb[l], s);
 }
 
+// Independent kernels share a launch while the instances leave the chip
+// idle; from this many instances on, each runs at its own occupancy (the
+// shared grid takes the larger register and LDS footprint of the two).
+static const int kShareLaunchMax = 16;
+
 template <typename T>
 static void enqueue_iteration(const Group& g, int iter, int mode, double* A_out, double* phi_out, hipStream_t s) {
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
   enqueue_decoder_fwd<T>(g, s, 1);
-  if (g.gram) {
+  if (g.gram && g.nb < kShareLaunchMax) {
     // the Gram terms need only the folded activations and the state, and the
     // output-layer seed only the element forces: each pair is one launch
     launch_cub_gram<T>(tab, g.nb, g.max_cblk, g.n_gblk, g.K, g.n_q, s);
@@ -780,7 +785,8 @@ static void enqueue_iteration(const Group& g, int iter, int mode, double* A_out,
     enqueue_decoder_bwd<T>(g, s, false);
   } else {
     launch_cubature<T>(tab, g.nb, g.max_cblk, s);
-    launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
+    if (g.gram) launch_gram<T>(tab, g.nb, g.n_gblk, g.K, g.n_q, s);
+    else launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
     launch_sums<T>(tab, g.nb, g.max_entries, s);
     enqueue_decoder_bwd<T>(g, s);
   }
