@@ -121,6 +121,7 @@ struct nmr_inst {
   int N = 0, n = 0, n_p = 0, n_q = 0, R = 0, n_cub = 0;
   int Cp = 0, Cb = 0, Cf = 0, n_mblk = 0, n_cblk = 0, n_bblk = 0;
   int gram = 0, n_cdofs = 0, n_sblk = 0;
+  std::vector<int> cdofs;  // host copy of the decoded rows of the Gram path
   int fd = 0;  // central-difference derivatives
   size_t bytes = 0;
   DevMem mem;
@@ -462,6 +463,7 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   in->Cp = s.Cp; in->Cb = s.Cb; in->Cf = s.Cf;
   in->n_mblk = s.n_mblk; in->n_cblk = s.n_cblk; in->n_bblk = s.n_bblk;
   in->gram = s.gram; in->n_cdofs = s.n_cdofs; in->n_sblk = s.n_sblk;
+  in->cdofs = s.cdofs;
   in->fd = p->fd_h > 0 ? 1 : 0;
   in->host.assign(sizeof(Inst<T>), 0);
   Inst<T>& I = host_inst<T>(in);
@@ -719,6 +721,7 @@ struct Group {
   bool gram;  // every table entry runs the Gram-folded path
   int max_cdofs, max_sblk, n_gblk, K;
   TileCfg tf[NMR_MAX_LAYERS], tb[NMR_MAX_LAYERS];  // hidden-layer tiles (ib == 0: the rule)
+  bool same_rows;  // every member decodes the same output rows (checked exactly)
 };
 
 static Group group_of(const std::vector<nmr_inst*>& v, void* tab) {
@@ -745,6 +748,9 @@ static Group group_of(const std::vector<nmr_inst*>& v, void* tab) {
     g.max_entries = std::max(g.max_entries, 2 * in->R * in->R + in->R * in->n_q + 2 * in->R + in->n_p);
     g.any_np = g.any_np || in->n_p > 0;
   }
+  g.same_rows = true;
+  for (nmr_inst* in : v)
+    g.same_rows = g.same_rows && (g.gram ? in->cdofs == v[0]->cdofs : in->N == v[0]->N);
   return g;
 }
 
@@ -753,7 +759,7 @@ static void enqueue_decoder_fwd(const Group& g, hipStream_t s, int add_up) {
   const DecoderDev& d = g.dec->d;
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
   for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, g.tf[l], s);
-  launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, s);
+  launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, g.same_rows, s);
   if (g.any_np) launch_filter<T>(tab, g.nb, add_up, s);
 }
 
@@ -1288,6 +1294,7 @@ extern "C" int nmr_pool_step(nmr_pool* p, int n_iters, int* status, float* ms) {
   if (it == p->graphs.end()) {
     Group g = group_of({p->proto}, p->tab);
     g.nb = p->capacity;
+    g.same_rows = false;  // later members need not share the first one's rows
     int live = 0;
     for (nmr_inst* x : p->slots) live += x != nullptr;
     CHK(choose_tiles(c, g, 2 * live >= p->capacity));
@@ -1335,7 +1342,7 @@ static void enqueue_phase(const Group& g, int phase, hipStream_t s) {
       for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, g.tf[l], s);
       break;
     case NMR_PHASE_DEC_OUT:
-      launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, s);
+      launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, g.same_rows, s);
       if (g.any_np) launch_filter<T>(tab, g.nb, 1, s);
       break;
     case NMR_PHASE_CUBATURE: launch_cubature<T>(tab, g.nb, g.max_cblk, s); break;

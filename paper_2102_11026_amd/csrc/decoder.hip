@@ -695,26 +695,39 @@ __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out(LayerArgs la, const 
 }
 
 // Output layer for many instances: a block of OUT_SPLIT waves stages the
-// instance's folded activations [Cf][K] in LDS once and each wave takes
+// folded activations [Cf][K] of NI instances in LDS once and each wave takes
 // OUT_TILES 16-row tiles over the whole K, the weights of its next tile loaded
-// while the MFMAs of the current one run.  The K quarters of the split kernel
-// above are kept as four accumulators and added in the same order, so both
-// give the same bits.
+// while the MFMAs of the current one run.  NI = 2 when every instance of the
+// launch decodes the same rows (the same cubature DOFs, or all N rows of equal
+// N): the two instances of a block then share each weight fragment.  The K
+// quarters of the split kernel above are kept as four accumulators and added
+// in the same order, so both kernels give the same bits.
 #define OUT_TILES 2
-template <typename TW, int NCB>
-__global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out_wide(LayerArgs la, const Inst<float>* __restrict__ tab) {
-  const Inst<float>& I = tab[blockIdx.y];
-  const int inst_active = I.active, gram = I.gram, n_cd = I.n_cdofs, N = I.N, Cf = I.Cf;
+template <typename TW, int NCB, int NI>
+__global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out_wide(LayerArgs la, const Inst<float>* __restrict__ tab,
+                                                                 int nb) {
+  const int i0 = blockIdx.y * NI;
+  const Inst<float>& I = tab[i0];                       // the row set of the block
+  const Inst<float>& I1 = tab[min(i0 + NI - 1, nb - 1)];  // the second instance (NI = 2)
+  const int act0 = I.active, act1 = I1.active, gram = I.gram, n_cd = I.n_cdofs, N = I.N, Cf = I.Cf;
   const int* cdofs = I.cdofs;
-  const float* fold = I.fold;
-  float* rec = I.rec;
-  const float* keep = I.keep;
+  const float* fold0 = I.fold;
+  const float* fold1 = I1.fold;
+  float* rec0 = I.rec;
+  float* rec1 = I1.rec;
+  const float* keep0 = I.keep;
+  const float* keep1 = I1.keep;
   const int K = la.m_inp;
-  load_now(inst_active, gram, n_cd, N, Cf, cdofs, fold, rec, keep, K, la.W, la.b);
+  load_now(act0, act1, gram, n_cd, N, Cf, cdofs, fold0, fold1, rec0, rec1, keep0, keep1, K, la.W, la.b);
+  bool use[NI];
+  use[0] = act0 != 0;
+  if constexpr (NI > 1) use[1] = act1 != 0 && i0 + 1 < nb;
   const int nrows = gram ? n_cd : N;
   constexpr int BROWS = 16 * OUT_SPLIT * OUT_TILES;
   const int blk0 = blockIdx.x * BROWS;
-  if (!inst_active || blk0 >= nrows) return;
+  bool any = use[0];
+  if constexpr (NI > 1) any = any || use[1];
+  if (!any || blk0 >= nrows) return;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int rA = lane & 15, g = lane >> 4;
   const TW* W = reinterpret_cast<const TW*>(la.W);
@@ -723,18 +736,24 @@ __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out_wide(LayerArgs la, c
   constexpr int NT = (OUT_KMAX / OUT_SPLIT + KS - 1) / KS;  // K-steps of one quarter
   const int kq = K / OUT_SPLIT;
   typedef typename std::conditional<std::is_same<TW, float>::value, float4, bf16x8>::type AF;
-  __shared__ __align__(16) float Fs[NCB * 16][OUT_KMAX + 4];
-  // the folded activations, coalesced, once per block
-  for (int p = threadIdx.x; p < NCB * 16 * (K / 4); p += 64 * OUT_SPLIT) {
-    const int c = p / (K / 4), k4 = p - c * (K / 4);
-    *reinterpret_cast<float4*>(&Fs[c][4 * k4]) = ldg<float4>(fold + (size_t)c * K + 4 * k4);
+  __shared__ __align__(16) float Fs[NI][NCB * 16][OUT_KMAX + 4];
+  // the folded activations, coalesced, once per block (an instance not in
+  // use leaves its copy unwritten; its results are never stored)
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    const float* fold = j == 0 ? fold0 : fold1;
+    if (use[j])
+      for (int p = threadIdx.x; p < NCB * 16 * (K / 4); p += 64 * OUT_SPLIT) {
+        const int c = p / (K / 4), k4 = p - c * (K / 4);
+        *reinterpret_cast<float4*>(&Fs[j][c][4 * k4]) = ldg<float4>(fold + (size_t)c * K + 4 * k4);
+      }
   }
   // weights of one tile (clamped row ids, zero A past each quarter's end)
-  // and the output rows, bias and mask of this lane's four result rows
+  // and the output rows, bias and masks of this lane's four result rows
   struct Tile {
     AF a[OUT_SPLIT][NT];
     int orow[4];
-    float b[4], m[4];
+    float b[4], m[NI][4];
   };
   auto load_tile = [&](int row0, Tile& t) {
     const int wrow = gram ? ldg<int>(cdofs + min(row0 + rA, nrows - 1)) : min(row0 + rA, nrows - 1);
@@ -752,47 +771,54 @@ __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out_wide(LayerArgs la, c
       const int orow = gram ? ldg<int>(cdofs + tr) : tr;
       t.orow[i] = orow;
       t.b[i] = ldg<float>(bias + orow);
-      t.m[i] = ldg<float>(keep + orow);
+      t.m[0][i] = ldg<float>(keep0 + orow);
+      if constexpr (NI > 1) t.m[1][i] = ldg<float>(keep1 + orow);
     }
   };
   auto run_tile = [&](int row0, const Tile& t) {
-    f32x4 acc[OUT_SPLIT][NCB];
 #pragma unroll
-    for (int q = 0; q < OUT_SPLIT; ++q)
+    for (int j = 0; j < NI; ++j) {
+      if (!use[j]) continue;
+      f32x4 acc[OUT_SPLIT][NCB];
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        acc[q][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int q = 0; q < OUT_SPLIT; ++q)
 #pragma unroll
-        for (int s2 = 0; s2 < NT; ++s2) {
-          if (s2 * KS < kq) {
-            const int k = q * kq + s2 * KS + (KS / 4) * g;
-            if constexpr (std::is_same<TW, float>::value) {
-              const float4 b = *reinterpret_cast<const float4*>(&Fs[cb * 16 + rA][min(k, K - 4)]);
-              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].x, b.x, acc[q][cb], 0, 0, 0);
-              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].y, b.y, acc[q][cb], 0, 0, 0);
-              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].z, b.z, acc[q][cb], 0, 0, 0);
-              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].w, b.w, acc[q][cb], 0, 0, 0);
-            } else {
-              const float4 b0 = *reinterpret_cast<const float4*>(&Fs[cb * 16 + rA][min(k, K - 4)]);
-              const float4 b1 = *reinterpret_cast<const float4*>(&Fs[cb * 16 + rA][min(k + 4, K - 4)]);
-              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(t.a[q][s2], to_bf16x8(b0, b1), acc[q][cb], 0, 0, 0);
+        for (int cb = 0; cb < NCB; ++cb) {
+          acc[q][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int s2 = 0; s2 < NT; ++s2) {
+            if (s2 * KS < kq) {
+              const int k = q * kq + s2 * KS + (KS / 4) * g;
+              if constexpr (std::is_same<TW, float>::value) {
+                const float4 b = *reinterpret_cast<const float4*>(&Fs[j][cb * 16 + rA][min(k, K - 4)]);
+                acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].x, b.x, acc[q][cb], 0, 0, 0);
+                acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].y, b.y, acc[q][cb], 0, 0, 0);
+                acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].z, b.z, acc[q][cb], 0, 0, 0);
+                acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].w, b.w, acc[q][cb], 0, 0, 0);
+              } else {
+                const float4 b0 = *reinterpret_cast<const float4*>(&Fs[j][cb * 16 + rA][min(k, K - 4)]);
+                const float4 b1 = *reinterpret_cast<const float4*>(&Fs[j][cb * 16 + rA][min(k + 4, K - 4)]);
+                acc[q][cb] =
+                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(t.a[q][s2], to_bf16x8(b0, b1), acc[q][cb], 0, 0, 0);
+              }
             }
           }
         }
-      }
-    // item i of lane l is D[4 (l/16) + i][l % 16]; quarters added in order
+      // item i of lane l is D[4 (l/16) + i][l % 16]; quarters added in order
+      float* rec = j == 0 ? rec0 : rec1;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (row0 + 4 * g + i < nrows) {
+      for (int i = 0; i < 4; ++i) {
+        if (row0 + 4 * g + i < nrows) {
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          const int c = cb * 16 + rA;
-          if (c < Cf) {
-            float v = acc[0][cb][i];
+          for (int cb = 0; cb < NCB; ++cb) {
+            const int c = cb * 16 + rA;
+            if (c < Cf) {
+              float v = acc[0][cb][i];
 #pragma unroll
-            for (int q = 1; q < OUT_SPLIT; ++q) v += acc[q][cb][i];
-            if (c == 0) v += t.b[i];
-            stg<float>(rec + (size_t)t.orow[i] * Cf + c, v * t.m[i]);
+              for (int q = 1; q < OUT_SPLIT; ++q) v += acc[q][cb][i];
+              if (c == 0) v += t.b[i];
+              stg<float>(rec + (size_t)t.orow[i] * Cf + c, v * t.m[j][i]);
+            }
           }
         }
       }
@@ -1238,18 +1264,24 @@ void launch_fwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* t
 #undef FWD_H64
 }
 
-// the wide form once the instances fill the chip with OUT_TILES-fold fewer blocks
+// the wide form once the instances fill the chip with OUT_TILES-fold fewer
+// blocks; two instances per block when they decode the same rows and there
+// are enough of them
 static bool fwd_out_wide(int max_n, int nb) { return nb >= 8 && ((max_n + 127) / 128) * nb >= 1024; }
 
 template <typename TW>
-static void fwd_out_dispatch(const DecoderDev& d, const Inst<float>* tab, int nb, int max_n, int cf, hipStream_t s) {
+static void fwd_out_dispatch(const DecoderDev& d, const Inst<float>* tab, int nb, int max_n, int cf, bool same_rows,
+                             hipStream_t s) {
   const bool wide = fwd_out_wide(max_n, nb);
-  dim3 grid((max_n + 15) / 16, nb);
-  dim3 gridw((max_n + 16 * OUT_SPLIT * OUT_TILES - 1) / (16 * OUT_SPLIT * OUT_TILES), nb);
-#define FWD_O(n)                                                                          \
-  do {                                                                                    \
-    if (wide) k_fwd_out_wide<TW, n><<<gridw, OUT_SPLIT * 64, 0, s>>>(layer_args(d, d.L - 1), tab); \
-    else k_fwd_out<TW, n><<<grid, OUT_SPLIT * 64, 0, s>>>(layer_args(d, d.L - 1), tab);   \
+  const bool pair = wide && same_rows && ((max_n + 127) / 128) * ((nb + 1) / 2) >= 1024;
+  const int n_rg = (max_n + 16 * OUT_SPLIT * OUT_TILES - 1) / (16 * OUT_SPLIT * OUT_TILES);
+  const dim3 grid((max_n + 15) / 16, nb), gridw(n_rg, nb), gridp(n_rg, (nb + 1) / 2);
+  const LayerArgs la = layer_args(d, d.L - 1);
+#define FWD_O(n)                                                                       \
+  do {                                                                                 \
+    if (pair) k_fwd_out_wide<TW, n, 2><<<gridp, OUT_SPLIT * 64, 0, s>>>(la, tab, nb);  \
+    else if (wide) k_fwd_out_wide<TW, n, 1><<<gridw, OUT_SPLIT * 64, 0, s>>>(la, tab, nb); \
+    else k_fwd_out<TW, n><<<grid, OUT_SPLIT * 64, 0, s>>>(la, tab);                     \
   } while (0)
   switch (cf / 16) {
     case 1: FWD_O(1); break;
@@ -1262,12 +1294,14 @@ static void fwd_out_dispatch(const DecoderDev& d, const Inst<float>* tab, int nb
 }
 
 template <>
-void launch_fwd_out<float>(const DecoderDev& d, const Inst<float>* tab, int nb, int max_n, int cf, hipStream_t s) {
-  if (d.prec == PREC_BF16) fwd_out_dispatch<__bf16>(d, tab, nb, max_n, cf, s);
-  else fwd_out_dispatch<float>(d, tab, nb, max_n, cf, s);
+void launch_fwd_out<float>(const DecoderDev& d, const Inst<float>* tab, int nb, int max_n, int cf, bool same_rows,
+                           hipStream_t s) {
+  if (d.prec == PREC_BF16) fwd_out_dispatch<__bf16>(d, tab, nb, max_n, cf, same_rows, s);
+  else fwd_out_dispatch<float>(d, tab, nb, max_n, cf, same_rows, s);
 }
 template <>
-void launch_fwd_out<double>(const DecoderDev& d, const Inst<double>* tab, int nb, int max_n, int cf, hipStream_t s) {
+void launch_fwd_out<double>(const DecoderDev& d, const Inst<double>* tab, int nb, int max_n, int cf, bool,
+                            hipStream_t s) {
   k_fwd_out_f64<<<dim3((max_n + 15) / 16, nb), 256, 0, s>>>(layer_args(d, d.L - 1), tab);
 }
 

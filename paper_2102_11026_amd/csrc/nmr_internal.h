@@ -261,8 +261,11 @@ int tile_candidates(const DecoderDev& d, int l, int nb, int cols, bool fd, bool 
 template <typename T>
 void launch_fwd_hidden(const DecoderDev& d, int l, const Inst<T>* tab, int nb, int max_cp, bool fd, TileCfg cfg,
                        hipStream_t s);
+// same_rows: every instance of the table decodes the same rows (the same
+// cubature DOFs on the Gram path, or all N rows of one N)
 template <typename T>
-void launch_fwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_np, int max_cf, hipStream_t s);
+void launch_fwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_np, int max_cf, bool same_rows,
+                    hipStream_t s);
 template <typename T>
 void launch_filter(const Inst<T>* tab, int nb, int add_up, hipStream_t s);
 template <typename T>

@@ -58,15 +58,54 @@ def batch_vs_alone(nmr, ctx, probs, prec, steps, iters, path="auto"):
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_wide_output_layer_is_bitwise_the_split_one(nmr, ctx, prec):
-    """Eight 10k-vertex instances on the direct path (30,000 decoded rows
-    each): the output layer runs the wide kernel, everything else as alone."""
+    """Eleven 10k-vertex instances on the direct path (30,000 decoded rows
+    each, the same for all): the output layer runs the wide kernel with two
+    instances per block (the last block holds one), everything else as
+    alone."""
     p = synth.config_single_10k()
-    probs = [p.replace(r0=p.r0 + 0.02 * synth.normal(f"wide/q0/{k}", p.R)) for k in range(8)]
+    probs = [p.replace(r0=p.r0 + 0.02 * synth.normal(f"wide/q0/{k}", p.R)) for k in range(11)]
     got, alone = batch_vs_alone(nmr, ctx, probs, prec, 1, p.newton_iters, path="direct")
     for (r, rd, u), (ra, rda, ua) in zip(got, alone):
         np.testing.assert_array_equal(r, ra)
         np.testing.assert_array_equal(rd, rda)
         np.testing.assert_array_equal(u, ua)
+
+
+def test_wide_output_layer_rows_per_instance(nmr, ctx):
+    """48 10k-vertex instances on the Gram path.  With one cubature set the
+    output layer pairs instances (shared weight rows); with two alternating
+    sets it must not, and every instance still decodes its own rows.  All
+    three batches take the same launch shapes otherwise, and the paired and
+    single kernels give the same bits, so each instance of the mixed batch
+    equals the same instance of the one-set batch bitwise."""
+    p = synth.config_single_10k()
+    other = np.sort(synth.permutation("wide/cub2", len(p.tets))[:p.cub_ids.size]).astype(np.int32)
+    assert not np.array_equal(other, p.cub_ids)
+
+    def batch(sets):
+        probs = []
+        for k, use_other in enumerate(sets):
+            q = p.replace(r0=p.r0 + 0.02 * synth.normal(f"wide48/q0/{k}", p.R))
+            probs.append(q.replace(cub_ids=other) if use_other else q)
+        dec = nmr.Decoder(ctx, p.weights, p.biases, p.act, "fp32")
+        insts = [nmr.Instance(ctx, q, "fp32", shared=dec) for q in probs]
+        try:
+            st, _ = nmr.step_many(ctx, insts, 1, p.newton_iters)
+            assert st == [0] * len(insts)
+            return [x.get_state(with_u=True) for x in insts]
+        finally:
+            for x in insts:
+                x.close()
+            dec.close()
+
+    first, second = batch([False] * 48), batch([True] * 48)
+    mixed = batch([k % 2 == 1 for k in range(48)])
+    for k in range(48):
+        ref = second[k] if k % 2 else first[k]
+        for a, b in zip(mixed[k], ref):
+            np.testing.assert_array_equal(a, b)
+    # the two sets decode different rows: the states differ
+    assert rel(first[1][2], second[1][2]) > 1e-3
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
