@@ -997,7 +997,15 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(LayerArgs la, const Inst<T>*
   const int K = la.m_inp;
   const int kk = threadIdx.x & 15, sl = threadIdx.x >> 4;
   const int k = blockIdx.x * 16 + kk;
+  const int nch = I.fd ? 1 + 2 * I.n_q : 1 + I.n_q;  // real backpropagation columns / value + e_j tangents
+  const T* pre = I.pre[l - 1];
   __shared__ double part[16][17];
+  // every load leaves before the first wait: the partials of slice sl and
+  // the pre-activations of this thread's channels (sl, sl + 16) at column k
+  const int kc = min(k, K - 1);
+  const T x0 = ldg<T>(pre + kc);
+  const T xa = ldg<T>(pre + (size_t)min(sl, nch - 1) * K + kc);
+  const T xb2 = ldg<T>(pre + (size_t)min(sl + 16, nch - 1) * K + kc);
   double acc = 0.0;
   if (k < K) {
     const double* src = I.part_bwd + k;
@@ -1007,27 +1015,28 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(LayerArgs la, const Inst<T>*
   }
   part[sl][kk] = acc;
   __syncthreads();
-  if (sl == 0 && k < K) {
-    double zb0 = part[0][kk];
-    for (int q = 1; q < 16; ++q) zb0 += part[q][kk];
-    const T* pre = I.pre[l - 1];
-    T* xb = I.zb0;
+  if (k >= K) return;
+  double zb0 = part[0][kk];
+  for (int q = 1; q < 16; ++q) zb0 += part[q][kk];
+  T* xb = I.zb0;
+  const bool in = k < la.m_in;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = sl + 16 * h;
+    if (c >= nch) break;
+    const T xc = h == 0 ? xa : xb2;
+    T v;
     if (I.fd) {
       // real backpropagation of every kept stencil column (base, q +- h e_j)
-      for (int c = 0; c < 1 + 2 * I.n_q; ++c) {
-        T d1, d2;
-        act_d12(la.act, ldg<T>(pre + (size_t)c * K + k), d1, d2);
-        stg<T>(xb + (size_t)c * K + k, (k < la.m_in) ? (T)(d1 * zb0) : T(0));
-      }
+      T d1, d2;
+      act_d12(la.act, xc, d1, d2);
+      v = (T)(d1 * zb0);
     } else {
-      const T x0 = ldg<T>(pre + k);
       T d1, d2;
       act_d12(la.act, x0, d1, d2);
-      stg<T>(xb + k, (k < la.m_in) ? (T)(d1 * zb0) : T(0));
-      for (int j = 0; j < I.n_q; ++j)
-        stg<T>(xb + (size_t)(1 + j) * K + k,
-               (k < la.m_in) ? (T)(d2 * ldg<T>(pre + (size_t)(1 + j) * K + k) * zb0) : T(0));
+      v = c == 0 ? (T)(d1 * zb0) : (T)(d2 * xc * zb0);
     }
+    stg<T>(xb + (size_t)c * K + k, in ? v : T(0));
   }
 }
 
