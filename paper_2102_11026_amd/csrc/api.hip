@@ -58,7 +58,10 @@ int dalloc(DevMem& m, size_t bytes, void** out) {
     (void)hipGetLastError();
     return fail(NMR_ERR_OOM, "hipMalloc failed");
   }
-  if (hipMemset(p, 0, round256(bytes)) != hipSuccess) {
+  // the zero fill runs on the null stream; a context stream the library
+  // created is non-blocking, so wait for it here, before any kernel on that
+  // stream may write the buffer
+  if (hipMemset(p, 0, round256(bytes)) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
     (void)hipFree(p);
     return fail(NMR_ERR_DEVICE, "hipMemset failed");
   }
