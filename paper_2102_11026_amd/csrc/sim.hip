@@ -193,24 +193,24 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
   const int e0 = bx * m * I.cub_per_blk;
   const int e1 = min(e0 + m * I.cub_per_blk, I.n_cub);
   constexpr int JT = (12 * NMR_MAX_R + 63) / 64;
-  for (int e = e0 + wave; e < e1; e += CUB_WAVES) {
-    // first round trip: the tet's vertices, B_m, weight and volume (none
-    // depends on another load)
-    const int4 tv = ldg<int4>(I.cub_v + 4 * e);
-    T Bmv[9];
+  // first round trip of tet e: its vertices, B_m, weight and volume (none
+  // depends on another load)
+  auto load_r1 = [&](int e, int4& tv, T (&Bmv)[9], T& wV) {
+    tv = ldg<int4>(I.cub_v + 4 * e);
 #pragma unroll
     for (int q = 0; q < 9; ++q) Bmv[q] = ldg<T>(I.cub_Bm + 9 * e + q);
-    const T wV = ldg<T>(I.cu_w + e) * ldg<T>(I.cub_Ve + e);
-    // second round trip: positions and Jacobian rows of the 12 DOFs, every
-    // load from an index clamped into range, then the LDS writes
+    wV = ldg<T>(I.cu_w + e) * ldg<T>(I.cub_Ve + e);
+  };
+  // second round trip: positions and Jacobian rows of the 12 DOFs, every
+  // load from an index clamped into range
+  auto load_r2 = [&](const int4& tv, T& xv, T (&jv)[JT]) {
     auto dof_of = [&](int ac) {
       const int a = ac / 3;
       const int v = a == 0 ? tv.x : a == 1 ? tv.y : a == 2 ? tv.z : tv.w;
       return 3 * v + (ac - 3 * a);
     };
     const int dx = dof_of(min(lane, 11));
-    const T xv = ldg<T>(I.X + dx) + ldg<T>(I.cu_u + (size_t)dx * I.cu_u_ld);
-    T jv[JT];
+    xv = ldg<T>(I.X + dx) + ldg<T>(I.cu_u + (size_t)dx * I.cu_u_ld);
 #pragma unroll
     for (int t = 0; t < JT; ++t) {
       const int p = min(lane + 64 * t, 12 * R - 1);
@@ -219,6 +219,15 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
       const T* src = (r < na) ? I.cu_Ja + (size_t)dof * I.cu_Ja_ld + r : I.cu_Jb + (size_t)dof * I.cu_Jb_ld + (r - na);
       jv[t] = ldg<T>(src);
     }
+  };
+  // this wave's LDS writes are visible to its own reads (outstanding global
+  // loads, the prefetches of the next tets, stay in flight)
+  auto lds_fence = []() {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+  };
+  // tet e from its loaded operands
+  auto tet = [&](int e, const T (&Bmv)[9], const T wV, const T xv, const T (&jv)[JT]) {
     if (lane < 12) xs[wave][lane] = xv;
 #pragma unroll
     for (int t = 0; t < JT; ++t) {
@@ -228,8 +237,7 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
         J12[wave][ac][r] = jv[t];
       }
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
+    lds_fence();
     T G[4][3];
     for (int j = 0; j < 3; ++j) {
       G[1][j] = Bmv[0 * 3 + j];
@@ -294,8 +302,7 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
       for (int j = 0; j < 3; ++j) f += P[i][j] * G[a][j];
       stg<T>(I.fe + (size_t)e * 12 + lane, wV * f);
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
+    lds_fence();
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
       const int p = lane + 64 * t;
@@ -306,8 +313,43 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
         kacc[t] += (double)wV * (double)acc;
       }
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
+    lds_fence();
+  };
+  int e = e0 + wave;
+  if (e1 - e0 <= CUB_WAVES) {
+    // at most one tet per wave: nothing to overlap
+    if (e < e1) {
+      int4 tv;
+      T Bmv[9], wV, xv, jv[JT];
+      load_r1(e, tv, Bmv, wV);
+      load_r2(tv, xv, jv);
+      tet(e, Bmv, wV, xv, jv);
+    }
+  } else if (e < e1) {
+    // three-stage pipeline: while tet e is computed, the second round trip
+    // of the next tet and the first of the one after are in flight (indices
+    // clamped to the last tet of the range; past it the loads go unused)
+    int4 tv1, tv2;
+    T Bm0[9], Bm1[9], Bm2[9], wV0, wV1, wV2, xv0, xv1, jv0[JT], jv1[JT];
+    load_r1(e, tv2, Bm0, wV0);
+    load_r1(min(e + CUB_WAVES, e1 - 1), tv1, Bm1, wV1);
+    load_r2(tv2, xv0, jv0);
+    for (; e < e1; e += CUB_WAVES) {
+      load_r1(min(e + 2 * CUB_WAVES, e1 - 1), tv2, Bm2, wV2);
+      load_r2(tv1, xv1, jv1);
+      tet(e, Bm0, wV0, xv0, jv0);
+      tv1 = tv2;
+      wV0 = wV1;
+      wV1 = wV2;
+      xv0 = xv1;
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        Bm0[q] = Bm1[q];
+        Bm1[q] = Bm2[q];
+      }
+#pragma unroll
+      for (int t = 0; t < JT; ++t) jv0[t] = jv1[t];
+    }
   }
   // wave sums added in wave order
   const int E = R * R + R;
