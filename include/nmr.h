@@ -226,9 +226,9 @@ int nmr_pool_step(nmr_pool* pool, int n_iters, int* status_or_null, float* ms_or
  * instance's 16 mr rows over the whole reduction, so each operand fragment
  * feeds several MFMAs).  Eligible: ib <= the number of instances in the
  * launch; ib > 1 or mr > 1 only for FP32/BF16 complex-step jets; mr > 1 only
- * with ib = 4, in a forward layer of at most 64 jet columns or a backward
- * layer of at most 32 adjoint columns, whose padded row count (the output
- * width forward, the input width backward) 16 mr divides.  Launches of one
+ * with ib = 4, in a forward layer of at most 64 jet columns (128 for mr = 2)
+ * or a backward layer of at most 32 adjoint columns, whose padded row count
+ * (the output width forward, the input width backward) 16 mr divides.  Launches of one
  * instance always run (1, 1).
  *   NMR_TILES_RULE (the default): a fixed rule from the layer's row count,
  *     its columns and the number of instances (tall tiles once there are

@@ -1173,6 +1173,10 @@ __global__ void k_unpack(const Inst<T>* __restrict__ tab, T* u, T* J, T* dJ, T* 
 // ---------------------------------------------------------------------------
 static int hidden_rows(const DecoderDev& d, int l, bool fwd) { return fwd ? d.wp[l + 1] : d.wp[l]; }
 
+// columns a tall tile holds in registers: MR x NCB accumulators and two
+// K-batches of MR + NCB operand fragments per wave
+static int tall_max_cols(int mr, bool fwd) { return fwd ? (mr == 2 ? 128 : 64) : 32; }
+
 // Layers with tall tiles (at most 64 jet columns forward, 32 adjoint columns
 // backward) take them once there are 1024 (row tile, instance) waves of 16 mr
 // rows, the largest mr first (the crossover measured on the 10k-vertex
@@ -1181,9 +1185,10 @@ static int hidden_rows(const DecoderDev& d, int l, bool fwd) { return fwd ? d.wp
 TileCfg tile_rule(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd) {
   if (fd || f64) return TileCfg{1, 1};
   const int rows = hidden_rows(d, l, fwd);
-  if (cols <= (fwd ? 64 : 32) && nb >= 4)
+  if (nb >= 4)
     for (int mr = 4; mr >= 2; mr /= 2)
-      if (rows % (16 * mr) == 0 && (rows / (16 * mr)) * nb >= 1024) return TileCfg{4, mr};
+      if (cols <= tall_max_cols(mr, fwd) && rows % (16 * mr) == 0 && (rows / (16 * mr)) * nb >= 1024)
+        return TileCfg{4, mr};
   return TileCfg{stack_instances(rows / 16, nb, false), 1};
 }
 
@@ -1191,7 +1196,8 @@ bool tile_eligible(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f
   if (c.ib == 1 && c.mr == 1) return true;
   if (fd || f64 || nb < c.ib) return false;
   if (c.mr == 1) return c.ib == 2 || c.ib == 4;
-  return c.ib == 4 && (c.mr == 2 || c.mr == 4) && cols <= (fwd ? 64 : 32) && hidden_rows(d, l, fwd) % (16 * c.mr) == 0;
+  return c.ib == 4 && (c.mr == 2 || c.mr == 4) && cols <= tall_max_cols(c.mr, fwd) &&
+         hidden_rows(d, l, fwd) % (16 * c.mr) == 0;
 }
 
 int tile_candidates(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd, TileCfg* out) {
@@ -1217,6 +1223,8 @@ static void fwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb
       k_fwd_hidden<T, TW, NCB, 4, false, 4><<<dim3(rows / 64, (nb + 3) / 4), 256, 0, s>>>(la, tab, nb);
       return;
     }
+  }
+  if constexpr (std::is_same<T, float>::value && NCB <= 8) {
     if (cfg.mr == 2) {
       k_fwd_hidden<T, TW, NCB, 4, false, 2><<<dim3(rows / 32, (nb + 3) / 4), 256, 0, s>>>(la, tab, nb);
       return;

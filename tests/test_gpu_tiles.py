@@ -29,7 +29,7 @@ def nmr():
     return m
 
 
-def family(n_q, n_inst, name):
+def family(n_q, n_inst, name, q_scale=0.6):
     """n_inst instances sharing one decoder whose hidden widths (64, 128, 64)
     admit every tall tile; each starts from its own latent state."""
     base = synth.tiny_problem(grid=(3, 3, 6), widths=(n_q, 64, 128, 64, 162), act="tanh", name=name,
@@ -37,7 +37,7 @@ def family(n_q, n_inst, name):
     probs = []
     for k in range(n_inst):
         r0 = np.zeros(base.R)
-        r0[base.n_p:] = (0.6 / np.sqrt(n_q)) * synth.normal(f"{name}/q0/{k}", base.n_q)
+        r0[base.n_p:] = (q_scale / np.sqrt(n_q)) * synth.normal(f"{name}/q0/{k}", base.n_q)
         probs.append(base.replace(r0=r0))
     return base, probs
 
@@ -68,12 +68,13 @@ def oracle_states(probs, steps, iters):
     return out
 
 
-@pytest.mark.parametrize("n_q", [15, 4])
-def test_forced_tiles_fp32_match_oracle(nmr, n_q):
+@pytest.mark.parametrize("n_q,q_scale", [(15, 0.6), (4, 0.6), (30, 0.3)])
+def test_forced_tiles_fp32_match_oracle(nmr, n_q, q_scale):
     """Six instances (a ragged last block of four slots), every configuration
     forced: each instance against the FP64 oracle, and every configuration
-    against the one-instance-per-block tiles."""
-    base, probs = family(n_q, 6, f"tiles{n_q}")
+    against the one-instance-per-block tiles.  n_q = 30 gives 128 jet
+    columns, where only the two-row tall tile is eligible forward."""
+    base, probs = family(n_q, 6, f"tiles{n_q}", q_scale)
     ref = oracle_states(probs, 3, 3)
     ctx = nmr.Context(0)
     try:
@@ -149,7 +150,7 @@ def test_autotune_records_eligible_choices(nmr):
             if e["mr"] > 1:
                 rows = e["m_out"] if e["forward"] else e["m_in"]
                 assert e["ib"] == 4 and rows % (16 * e["mr"]) == 0
-                assert e["cols"] <= (64 if e["forward"] else 32)
+                assert e["cols"] <= ((128 if e["mr"] == 2 else 64) if e["forward"] else 32)
     finally:
         ctx.close()
 
