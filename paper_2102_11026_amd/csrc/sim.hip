@@ -185,10 +185,16 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
   __shared__ T dFs[CUB_WAVES][NMR_MAX_R][9];
   __shared__ T dPs[CUB_WAVES][NMR_MAX_R][9];
   __shared__ double red[NMR_MAX_R * NMR_MAX_R + NMR_MAX_R];
-  constexpr int KT = (NMR_MAX_R * NMR_MAX_R + 63) / 64;
-  double kacc[KT];
+  // the R x R stiffness sums in 2 x 2 blocks: lane l owns blocks l + 64 t,
+  // block b covering rows 2 (b / nb2) + {0, 1} and columns 2 (b % nb2) + {0, 1}
+  // (each entry the same 9-term dot product in the same order as unblocked)
+  constexpr int BT = ((NMR_MAX_R + 1) / 2 * ((NMR_MAX_R + 1) / 2) + 63) / 64;
+  const int nb2 = (R + 1) / 2;
+  double kacc[BT][4];
 #pragma unroll
-  for (int i = 0; i < KT; ++i) kacc[i] = 0.0;
+  for (int t = 0; t < BT; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) kacc[t][q] = 0.0;
   double facc = 0.0;
   const int e0 = bx * m * I.cub_per_blk;
   const int e1 = min(e0 + m * I.cub_per_blk, I.n_cub);
@@ -304,13 +310,25 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
     }
     lds_fence();
 #pragma unroll
-    for (int t = 0; t < KT; ++t) {
-      const int p = lane + 64 * t;
-      if (p < R * R) {
-        const int r = p / R, s = p - r * R;
-        T acc = T(0);
-        for (int k = 0; k < 9; ++k) acc += dPs[wave][r][k] * dFs[wave][s][k];
-        kacc[t] += (double)wV * (double)acc;
+    for (int t = 0; t < BT; ++t) {
+      const int b = lane + 64 * t;
+      if (b < nb2 * nb2) {
+        const int r0 = 2 * (b / nb2), s0 = 2 * (b % nb2);
+        const int r1 = min(r0 + 1, R - 1), s1 = min(s0 + 1, R - 1);
+        T a00 = T(0), a01 = T(0), a10 = T(0), a11 = T(0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          const T p0 = dPs[wave][r0][k], p1 = dPs[wave][r1][k];
+          const T f0 = dFs[wave][s0][k], f1 = dFs[wave][s1][k];
+          a00 += p0 * f0;
+          a01 += p0 * f1;
+          a10 += p1 * f0;
+          a11 += p1 * f1;
+        }
+        kacc[t][0] += (double)wV * (double)a00;
+        kacc[t][1] += (double)wV * (double)a01;
+        kacc[t][2] += (double)wV * (double)a10;
+        kacc[t][3] += (double)wV * (double)a11;
       }
     }
     lds_fence();
@@ -356,9 +374,16 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
   for (int w = 0; w < CUB_WAVES; ++w) {
     if (wave == w) {
 #pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        const int p = lane + 64 * t;
-        if (p < R * R) red[p] = (w == 0 ? 0.0 : red[p]) + kacc[t];
+      for (int t = 0; t < BT; ++t) {
+        const int b = lane + 64 * t;
+        if (b < nb2 * nb2) {
+          const int r0 = 2 * (b / nb2), s0 = 2 * (b % nb2);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int r = r0 + (q >> 1), c = s0 + (q & 1);
+            if (r < R && c < R) red[r * R + c] = (w == 0 ? 0.0 : red[r * R + c]) + kacc[t][q];
+          }
+        }
       }
       if (lane < R) red[R * R + lane] = (w == 0 ? 0.0 : red[R * R + lane]) + facc;
     }
