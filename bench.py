@@ -163,7 +163,7 @@ def tile_report(nmr, ctx, p):
         peak = BF16_MFMA_PEAK_TFLOPS if e["prec"] == nmr.PREC["bf16"] else FP32_MFMA_PEAK_TFLOPS
         tf = flops / (e["us"] * 1e-6) / 1e12
         out.append(dict(prec={v: k for k, v in nmr.PREC.items()}[e["prec"]], instances=e["n_inst"],
-                        layer=f"{w[l]}->{w[l + 1]}", ib=e["ib"], mr=e["mr"], us_per_launch=round(e["us"], 2),
+                        layer=f"{w[l]}->{w[l + 1]}", ib=e["ib"], mr=e["mr"], jet_groups=e["jet_groups"], us_per_launch=round(e["us"], 2),
                         tflops=round(tf, 2), frac_of_mfma_peak=round(tf / peak, 4)))
     return out
 

@@ -228,18 +228,26 @@ int nmr_pool_step(nmr_pool* pool, int n_iters, int* status_or_null, float* ms_or
  * launch; ib > 1 or mr > 1 only for FP32/BF16 complex-step jets; mr > 1 only
  * with ib = 4, in a forward layer of at most 64 jet columns (128 for mr = 2)
  * or a backward layer of at most 32 adjoint columns, whose padded row count
- * (the output width forward, the input width backward) 16 mr divides.  Launches of one
- * instance always run (1, 1).
+ * (the output width forward, the input width backward) 16 mr divides.
+ * Forward layers at (1, 1) with more than 16 jet columns may also take jet
+ * groups (jet_groups = 1): the columns of a 16-row tile split over
+ * ceil(n_q / 3) blocks, each computing the four base channels and the four
+ * channels of three perturbations.  With at most 64 jet columns (n_q <= 15)
+ * every column is the same sum as without groups, so the results are the
+ * same bits; wider whole tiles split K over fewer waves and agree to
+ * rounding.  Launches of one instance run (1, 1).
  *   NMR_TILES_RULE (the default): a fixed rule from the layer's row count,
  *     its columns and the number of instances (tall tiles once there are
  *     1024 waves of 16 mr rows, instances stacked once the chip is full
- *     without it); results are bitwise reproducible.
+ *     without it, jet groups in forward layers of fewer than 256 row-tile x
+ *     instance blocks); results are bitwise reproducible.
  *   NMR_TILES_AUTOTUNE: the first time a (direction, layer widths, columns,
  *     instances, precision, derivative scheme) occurs in a step_many call (or
  *     a pool step with at least half its slots attached), every eligible
  *     configuration is timed on the context stream on the group's own decoder
  *     buffers and the fastest is kept for the context's lifetime.
- *   NMR_TILES_FORCE: (ib, mr) wherever it is eligible, the rule elsewhere.
+ *   NMR_TILES_FORCE: (ib, mr) without jet groups wherever it is eligible,
+ *     the rule elsewhere.
  * Configurations split the reduction over K differently, so results under
  * different tiles agree to rounding, not bitwise.  Changing the mode drops
  * the graphs captured under the previous one (synchronizes).  NMR_ERR_ARG for
@@ -254,6 +262,7 @@ typedef struct {
   int n_inst;      /* instances in the launch */
   int prec;        /* nmr_prec */
   int ib, mr;      /* the configuration chosen */
+  int jet_groups;  /* 1: with jet groups */
   float us;        /* its measured device time per launch, microseconds */
 } nmr_tile_choice;
 

@@ -829,7 +829,7 @@ static int tune_layer(nmr_ctx* c, const Group& g, int l, bool fwd, TileCfg* out)
   const std::array<int, 7> key{fwd ? 1 : 0, d.wp[l], d.wp[l + 1], cols, g.nb, d.prec, g.fd ? 1 : 0};
   auto it = c->tuned.find(key);
   if (it != c->tuned.end()) {
-    *out = TileCfg{it->second.ib, it->second.mr};
+    *out = TileCfg{it->second.ib, it->second.mr, it->second.jet_groups};
     return NMR_OK;
   }
   TileCfg cand[8];
@@ -858,7 +858,7 @@ static int tune_layer(nmr_ctx* c, const Group& g, int l, bool fwd, TileCfg* out)
     }
   }
   HIPCHK(hipGetLastError());
-  nmr_tile_choice e{key[0], key[1], key[2], key[3], key[4], key[5], out->ib, out->mr, best};
+  nmr_tile_choice e{key[0], key[1], key[2], key[3], key[4], key[5], out->ib, out->mr, out->jg, best};
   c->tuned.emplace(key, e);
   return NMR_OK;
 }

@@ -400,9 +400,17 @@ __device__ inline T fd_input(int c, int k, int nq, T q, T dq, T qd, T h) {
   return T(0);
 }
 
-template <typename T, typename TW, int NCB, int IB, bool FD, int MR>
+// JG > 0: jet groups.  A block computes the four base channels and the four
+// channels of JG perturbations e_j (16 columns for JG = 3), so the columns
+// of one row tile spread over ceil(n_q / JG) blocks (blockIdx.y = instance x
+// groups + group), each splitting K over eight waves.  Where the whole-tile
+// form does the same (at most four column blocks) every column is the same
+// K sum, so the results are the same bits.  The base channels, which every
+// group needs for its activation derivatives, are stored by group 0 only.
+template <typename T, typename TW, int NCB, int IB, bool FD, int MR, int JG = 0>
 __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab, int nb) {
   static_assert(MR == 1 || (!FD && std::is_same<T, float>::value), "tall tiles: complex-step FP32 jets only");
+  static_assert(JG == 0 || (NCB == 1 && IB == 1 && MR == 1 && !FD && 4 + 4 * JG == 16), "jet groups: one column block");
   constexpr int ROWS = 16 * MR;  // output rows of a block
   constexpr int NW = MR > 1 ? IB : splitk_waves<T, NCB>::v;
   constexpr int KSPL = NW / IB;
@@ -410,7 +418,9 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
   const int l = la.l;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int slot = wave / KSPL, tg = tid - slot * NG;
-  const int inst = blockIdx.y * IB + slot;
+  const int ngrp = JG ? gridDim.y / nb : 1;
+  const int inst = JG ? blockIdx.y / ngrp : blockIdx.y * IB + slot;
+  const int grp = JG ? blockIdx.y - inst * ngrp : 0;
   const Inst<T>& I = tab[min(inst, nb - 1)];
   // the table entry's fields are read before any test so that their scalar
   // loads leave together
@@ -469,7 +479,21 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
     }
     return ldg<V4>(X + (size_t)c * m_inp + k);
   };
-  if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload, S, red);
+  // jet channel of local column c of a jet group (-1: past n_q)
+  auto gcol = [&](int c) -> int {
+    if (c < 4) return c;
+    constexpr int jg = JG > 0 ? JG : 1;
+    const int role = (c - 4) / jg, j = grp * jg + (c - 4 - role * jg);
+    return j < nq ? 4 + role * nq + j : -1;
+  };
+  if constexpr (JG > 0) {
+    auto bload_g = [&](int c, int k) -> V4 {
+      const int gc = gcol(c);
+      const V4 v = bload(max(gc, 0), k);
+      return gc >= 0 ? v : V4{T(0), T(0), T(0), T(0)};
+    };
+    gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload_g, S, red);
+  } else if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload, S, red);
   else gemm_tall<TW, NCB, MR>(W, m_inp, m_inp, use, bload, S);
 
   T(*Ss)[ROWS + 1] = S[slot];
@@ -503,7 +527,7 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
     act_jet(la.act, x0, y, d1, d2, d3);
     sd1[slot][tg] = d1; sd2[slot][tg] = d2; sd3[slot][tg] = d3;
     sx2[slot][tg] = x2; sx4[slot][tg] = x4; sx23[slot][tg] = x23;
-    stg<T>(pre + row, valid ? x0 : T(0));
+    if (grp == 0) stg<T>(pre + row, valid ? x0 : T(0));
     Ss[0][tg] = valid ? y : T(0);
     Ss[1][tg] = valid ? d1 * x2 : T(0);
     Ss[2][tg] = valid ? d1 * x4 : T(0);
@@ -511,23 +535,33 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
   }
   __syncthreads();
   if (use) {
-    for (int p = tg; p < ROWS * nq; p += NG) {
-      const int r = p & (ROWS - 1), j = p / ROWS;
+    // the jets of perturbation j sit in local columns 4 + jl + {0,1,2,3} nl
+    const int nl = JG ? JG : nq;
+    for (int p = tg; p < ROWS * nl; p += NG) {
+      const int r = p & (ROWS - 1), jl = p / ROWS, j = grp * JG + jl;
+      if (JG && j >= nq) continue;
       const bool valid = row0 + r < m_out;
-      const T x1 = Ss[4 + j][r], x12 = Ss[4 + nq + j][r], x14 = Ss[4 + 2 * nq + j][r], x123 = Ss[4 + 3 * nq + j][r];
+      const T x1 = Ss[4 + jl][r], x12 = Ss[4 + nl + jl][r], x14 = Ss[4 + 2 * nl + jl][r], x123 = Ss[4 + 3 * nl + jl][r];
       const T d1 = sd1[slot][r], d2 = sd2[slot][r], d3 = sd3[slot][r];
       const T x2 = sx2[slot][r], x4 = sx4[slot][r], x23 = sx23[slot][r];
       stg<T>(pre + (size_t)(1 + j) * m_outp + row0 + r, valid ? x1 : T(0));
-      Ss[4 + j][r] = valid ? d1 * x1 : T(0);
-      Ss[4 + nq + j][r] = valid ? d1 * x12 + d2 * x1 * x2 : T(0);
-      Ss[4 + 2 * nq + j][r] = valid ? d1 * x14 + d2 * x1 * x4 : T(0);
-      Ss[4 + 3 * nq + j][r] = valid ? d1 * x123 + d2 * (x1 * x23 + T(2) * x2 * x12) + d3 * x1 * x2 * x2 : T(0);
+      Ss[4 + jl][r] = valid ? d1 * x1 : T(0);
+      Ss[4 + nl + jl][r] = valid ? d1 * x12 + d2 * x1 * x2 : T(0);
+      Ss[4 + 2 * nl + jl][r] = valid ? d1 * x14 + d2 * x1 * x4 : T(0);
+      Ss[4 + 3 * nl + jl][r] = valid ? d1 * x123 + d2 * (x1 * x23 + T(2) * x2 * x12) + d3 * x1 * x2 * x2 : T(0);
     }
   }
   __syncthreads();
   }
   if (!use) return;
   if (l + 2 < la.L) {
+    if constexpr (JG > 0) {
+      for (int p = tg; p < 16 * 16; p += NG) {
+        const int c = p >> 4, r = p & 15, gc = gcol(c);
+        if (gc >= 0 && (c >= 4 || grp == 0)) stg<T>(outp + (size_t)gc * m_outp + row0 + r, Ss[c][r]);
+      }
+      return;
+    }
     const int C = fd ? 14 * nq + 3 : 4 + 4 * nq;
     for (int p = tg; p < C * ROWS; p += NG) {
       const int c = p / ROWS, r = p & (ROWS - 1);
@@ -562,6 +596,33 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
           v = trimmed ? Hdq - dt * Hv : Sdd + T(3) * Hdq - dt * Hv;
         } else {
           v = trimmed ? T(0) : (Ss[base + 12 * nq][r] - T(2) * Ss[0][r] + Ss[base + 12 * nq + 1][r]) / h4;
+        }
+        stg<T>(fold + (size_t)c * m_outp + row0 + r, v);
+      }
+      return;
+    }
+    if constexpr (JG > 0) {
+      // fold entry f of a group: 0 the value and 1 the (dq, dq) channel
+      // (group 0), then J and dJ of the group's perturbations
+      for (int p = tg; p < (2 + 2 * JG) * 16; p += NG) {
+        const int f = p >> 4, r = p & 15;
+        const int jl = (f - 2) % JG, j = grp * JG + jl;
+        if (f < 2 ? grp != 0 : j >= nq) continue;
+        T v;
+        int c;
+        if (f == 0) {
+          c = 0;
+          v = Ss[0][r];
+        } else if (f == 1) {
+          c = 1 + 2 * nq;
+          v = trimmed ? T(0) : Ss[3][r];
+        } else if (f < 2 + JG) {
+          c = 1 + j;
+          v = Ss[4 + jl][r];
+        } else {
+          c = 1 + nq + j;
+          v = trimmed ? Ss[4 + JG + jl][r] - dt * Ss[4 + 2 * JG + jl][r]
+                      : Ss[4 + 3 * JG + jl][r] + T(3) * Ss[4 + JG + jl][r] - dt * Ss[4 + 2 * JG + jl][r];
         }
         stg<T>(fold + (size_t)c * m_outp + row0 + r, v);
       }
@@ -1177,11 +1238,16 @@ static int hidden_rows(const DecoderDev& d, int l, bool fwd) { return fwd ? d.wp
 // K-batches of MR + NCB operand fragments per wave
 static int tall_max_cols(int mr, bool fwd) { return fwd ? (mr == 2 ? 128 : 64) : 32; }
 
+// perturbations per jet group, and the groups of a decoder's input width
+static constexpr int kJetGroup = 3;
+static int jet_groups(const DecoderDev& d) { return (d.w[0] + kJetGroup - 1) / kJetGroup; }
+
 // Layers with tall tiles (at most 64 jet columns forward, 32 adjoint columns
 // backward) take them once there are 1024 (row tile, instance) waves of 16 mr
 // rows, the largest mr first (the crossover measured on the 10k-vertex
 // decoder at 64 and 128 instances); otherwise instances are stacked once the
-// chip is full without it.
+// chip is full without it.  Forward layers whose (row tile, instance) blocks
+// leave most CUs idle split the jet columns into groups instead.
 TileCfg tile_rule(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd) {
   if (fd || f64) return TileCfg{1, 1};
   const int rows = hidden_rows(d, l, fwd);
@@ -1189,10 +1255,13 @@ TileCfg tile_rule(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f6
     for (int mr = 4; mr >= 2; mr /= 2)
       if (cols <= tall_max_cols(mr, fwd) && rows % (16 * mr) == 0 && (rows / (16 * mr)) * nb >= 1024)
         return TileCfg{4, mr};
-  return TileCfg{stack_instances(rows / 16, nb, false), 1};
+  const int ib = stack_instances(rows / 16, nb, false);
+  if (ib == 1 && fwd && cols > 16 && (rows / 16) * nb < kJetGroupBlocks) return TileCfg{1, 1, 1};
+  return TileCfg{ib, 1};
 }
 
 bool tile_eligible(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd, TileCfg c) {
+  if (c.jg) return c.ib == 1 && c.mr == 1 && fwd && !fd && !f64 && cols > 16 && nb * jet_groups(d) <= 65535;
   if (c.ib == 1 && c.mr == 1) return true;
   if (fd || f64 || nb < c.ib) return false;
   if (c.mr == 1) return c.ib == 2 || c.ib == 4;
@@ -1201,7 +1270,7 @@ bool tile_eligible(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f
 }
 
 int tile_candidates(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd, TileCfg* out) {
-  static const TileCfg all[] = {{1, 1}, {2, 1}, {4, 1}, {4, 2}, {4, 4}};
+  static const TileCfg all[] = {{1, 1}, {1, 1, 1}, {2, 1}, {4, 1}, {4, 2}, {4, 4}};
   int n = 0;
   for (const TileCfg& c : all)
     if (tile_eligible(d, l, nb, cols, fd, f64, fwd, c)) out[n++] = c;
@@ -1217,6 +1286,12 @@ static void fwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb
   if (fd) {  // the central-difference form: one instance per block
     k_fwd_hidden<T, TW, NCB, 1, true, 1><<<dim3(tiles, nb), threads, 0, s>>>(la, tab, nb);
     return;
+  }
+  if constexpr (std::is_same<T, float>::value) {
+    if (cfg.jg) {
+      k_fwd_hidden<T, TW, 1, 1, false, 1, kJetGroup><<<dim3(tiles, nb * jet_groups(d)), 512, 0, s>>>(la, tab, nb);
+      return;
+    }
   }
   if constexpr (std::is_same<T, float>::value && NCB <= 4) {
     if (cfg.mr == 4) {

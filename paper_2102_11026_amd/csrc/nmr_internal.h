@@ -248,13 +248,16 @@ __device__ __forceinline__ void sums_block(const Inst<T>* __restrict__ tab, int 
 // ---- tile configurations of the hidden-layer launches (decoder.hip) ----
 // ib instances per block (stacked instances share the weight tile); mr
 // 16-row tiles per wave (mr > 1: tall tiles, one wave per instance over the
-// whole K).  ib == 0: the rule.
+// whole K); jg (forward, ib = mr = 1): the jet columns of a row tile split
+// into groups of three perturbations, one block each.  ib == 0: the rule.
 struct TileCfg {
-  int ib, mr;
+  int ib, mr, jg = 0;
 };
+// jet-group blocks: below this many (row tile, instance) blocks
+static constexpr int kJetGroupBlocks = 256;
 TileCfg tile_rule(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd);
 bool tile_eligible(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd, TileCfg c);
-// eligible configurations of hidden layer l (at most 5), the rule's among them
+// eligible configurations of hidden layer l (at most 6), the rule's among them
 int tile_candidates(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd, TileCfg* out);
 
 // ---- launchers (decoder.hip) -------------------------------------------

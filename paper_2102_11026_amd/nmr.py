@@ -45,7 +45,8 @@ class ProblemDesc(C.Structure):
 
 class TileChoice(C.Structure):
     _fields_ = [("forward", C.c_int), ("m_in", C.c_int), ("m_out", C.c_int), ("cols", C.c_int),
-                ("n_inst", C.c_int), ("prec", C.c_int), ("ib", C.c_int), ("mr", C.c_int), ("us", C.c_float)]
+                ("n_inst", C.c_int), ("prec", C.c_int), ("ib", C.c_int), ("mr", C.c_int), ("jet_groups", C.c_int),
+                ("us", C.c_float)]
 
 
 TILING = {"rule": 0, "autotune": 1, "force": 2}

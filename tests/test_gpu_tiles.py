@@ -42,13 +42,15 @@ def family(n_q, n_inst, name, q_scale=0.6):
     return base, probs
 
 
-def run(nmr, ctx, base, probs, prec, steps, iters, tiling):
+def run(nmr, ctx, base, probs, prec, steps, iters, tiling, full=False):
     ctx.set_tiling(*tiling)
     dec = nmr.Decoder(ctx, base.weights, base.biases, base.act, prec)
     insts = [nmr.Instance(ctx, q, prec, shared=dec) for q in probs]
     try:
         st, _ = nmr.step_many(ctx, insts, steps, iters)
         assert st == [0] * len(insts)
+        if full:
+            return [x.get_state(with_u=True) for x in insts]
         return [x.get_state()[0] for x in insts]
     finally:
         for x in insts:
@@ -104,6 +106,38 @@ def test_forced_tiles_bf16_match_oracle(nmr):
         ctx.close()
 
 
+@pytest.mark.parametrize("n_q,prec,form", [(4, "fp32", "full"), (15, "fp32", "trimmed"), (15, "bf16", "full"),
+                                           (30, "fp32", "full")])
+def test_jet_groups_are_bitwise_the_whole_tile(nmr, n_q, prec, form):
+    """One and three instances: under the rule the forward jet layers split
+    their columns into groups of three perturbations (a ragged last group for
+    n_q = 4), forced (1, 1) keeps whole tiles.  Up to 64 jet columns (n_q <=
+    15) both split K over eight waves, so every column is the same sum and
+    the states (r, rdot, u) agree bitwise.  Whole tiles of 128 columns (n_q =
+    30) split K over four waves: there the bar between the two is the one
+    between tile configurations.  The FP32 rule run is also held to the
+    oracle."""
+    base, probs = family(n_q, 3, f"jg{n_q}", 0.3 if n_q == 30 else 0.6)
+    base = base.replace(formulation=form)
+    probs = [q.replace(formulation=form) for q in probs]
+    ctx = nmr.Context(0)
+    try:
+        for n in (1, 3):
+            grouped = run(nmr, ctx, base, probs[:n], prec, 2, 3, ("rule",), full=True)
+            whole = run(nmr, ctx, base, probs[:n], prec, 2, 3, ("force", 1, 1), full=True)
+            for k in range(n):
+                for a, b in zip(grouped[k], whole[k]):
+                    if n_q <= 15:
+                        np.testing.assert_array_equal(a, b)
+                    else:
+                        assert rel(a, b) < 1e-4
+        if prec == "fp32":
+            for (r, _, _), o in zip(grouped, oracle_states(probs, 2, 3)):
+                assert rel(r, o) < 1e-4
+    finally:
+        ctx.close()
+
+
 def test_tall_tiles_at_headline_shape(nmr):
     """Eight 10k-vertex instances (K = 512 layers, 64 jet columns): the tall
     tiles against the rule after one step."""
@@ -147,6 +181,8 @@ def test_autotune_records_eligible_choices(nmr):
         for e in table:
             assert e["n_inst"] == 8 and e["us"] > 0
             assert (e["ib"], e["mr"]) in CONFIGS
+            if e["jet_groups"]:
+                assert e["forward"] and e["ib"] == 1 and e["mr"] == 1
             if e["mr"] > 1:
                 rows = e["m_out"] if e["forward"] else e["m_in"]
                 assert e["ib"] == 4 and rows % (16 * e["mr"]) == 0
