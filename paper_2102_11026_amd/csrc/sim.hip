@@ -654,10 +654,13 @@ __device__ __forceinline__ void gram_block(const Inst<T>* __restrict__ tab, int 
   // Every global load is issued before the first wait, from indices clamped
   // into range: the folded columns of y (thread k), this wave's K-steps of
   // Gam and of X, the 16 F_J rows of the mass partial and the state.
+  // NCB column blocks hold 2 n_q + 1 < 16 NCB columns, so n_q < QM
+  constexpr int QM = 8 * NCB;
+  static_assert(QM <= NMR_MAX_R, "column blocks");
   const int kt = min((int)threadIdx.x, K - 1);
-  T fy[NMR_MAX_R];
+  T fy[QM];
 #pragma unroll
-  for (int j = 0; j < NMR_MAX_R; ++j) fy[j] = ldg<T>(F + (size_t)(1 + min(j, nq - 1)) * K + kt);
+  for (int j = 0; j < QM; ++j) fy[j] = ldg<T>(F + (size_t)(1 + min(j, nq - 1)) * K + kt);
   const T fh = ldg<T>(F + (size_t)(1 + 2 * nq) * K + kt);
   constexpr int NST = 256 / 16;  // K-steps of one wave at K = 256 (K/4 entries, 4 per step)
   const int kper = K / 4, nst = kper / 4;
@@ -671,7 +674,7 @@ __device__ __forceinline__ void gram_block(const Inst<T>* __restrict__ tab, int 
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) bv[st][cb] = ldg<T>(F + (size_t)(1 + min(cb * 16 + col, 2 * nq - 1)) * K + k);
   }
-  constexpr int FP = (NMR_MAX_R * 16 + 255) / 256;
+  constexpr int FP = (QM * 16 + 255) / 256;
   T fpv[FP];
 #pragma unroll
   for (int q = 0; q < FP; ++q) {
@@ -691,7 +694,7 @@ __device__ __forceinline__ void gram_block(const Inst<T>* __restrict__ tab, int 
   if ((int)threadIdx.x < K) {
     double v = (double)fh;
 #pragma unroll
-    for (int j = 0; j < NMR_MAX_R; ++j)
+    for (int j = 0; j < QM; ++j)
       if (j < nq) v += (double)fy[j] * wr[j];
     y[threadIdx.x] = v;
   }
