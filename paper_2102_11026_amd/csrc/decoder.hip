@@ -269,21 +269,20 @@ __device__ inline void mfma_tall(const float* __restrict__ A, int lda, int K, BL
   const int rA = lane & 15, g = lane >> 4;
   const float* ap = A + (size_t)rA * lda + 4 * g;
   float4 a0[PF][MR], b0[PF][NCB], a1[PF][MR], b1[PF][NCB];
+  // K (a padded width) is a multiple of the batch, so a batch lies wholly
+  // inside or past K.  Every batch's loads are issued unconditionally (a
+  // batch past K re-reads the last one and is never multiplied): with the
+  // same loads on every path the wait before a batch's MFMAs counts only
+  // that batch's loads, and the next batch's stay in flight.
   auto load = [&](int k0, float4(&a)[PF][MR], float4(&b)[PF][NCB]) {
+    const int kc = min(k0, K - 16 * PF);
 #pragma unroll
     for (int t = 0; t < PF; ++t) {
-      const int k = k0 + 16 * t;
-      if (k < K) {
+      const int k = kc + 16 * t;
 #pragma unroll
-        for (int m = 0; m < MR; ++m) a[t][m] = ldg<float4>(ap + (size_t)16 * m * lda + k);
+      for (int m = 0; m < MR; ++m) a[t][m] = ldg<float4>(ap + (size_t)16 * m * lda + k);
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) b[t][cb] = bload(cb * 16 + rA, k + 4 * g);
-      } else {
-#pragma unroll
-        for (int m = 0; m < MR; ++m) a[t][m] = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) b[t][cb] = make_float4(0.f, 0.f, 0.f, 0.f);
-      }
+      for (int cb = 0; cb < NCB; ++cb) b[t][cb] = bload(cb * 16 + rA, k + 4 * g);
     }
   };
   auto mma = [&](const float4(&a)[PF][MR], const float4(&b)[PF][NCB]) {
@@ -299,15 +298,23 @@ __device__ inline void mfma_tall(const float* __restrict__ A, int lda, int K, BL
           acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][m].w, b[t][cb].w, acc[m][cb], 0, 0, 0);
         }
   };
+  // two batches per trip with no branch inside (a load under a branch would
+  // be sunk to its use); an odd last batch is already in a0 after the loop.
+  // The scheduling barriers keep each batch's loads ahead of the MFMAs of
+  // the batch before it.
   constexpr int KB = 16 * PF;
+  const int nbat = K / KB;
   load(0, a0, b0);
-  for (int k0 = 0; k0 < K; k0 += 2 * KB) {
-    load(k0 + KB, a1, b1);
+  int i = 0;
+  for (; i + 1 < nbat; i += 2) {
+    load((i + 1) * KB, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
     mma(a0, b0);
-    if (k0 + KB >= K) break;
-    load(k0 + 2 * KB, a0, b0);
+    load((i + 2) * KB, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
     mma(a1, b1);
   }
+  if (i < nbat) mma(a0, b0);
 }
 
 template <int MR, int NCB, typename BL>
@@ -317,21 +324,15 @@ __device__ inline void mfma_tall(const __bf16* __restrict__ A, int lda, int K, B
   const __bf16* ap = A + (size_t)rA * lda + 8 * g;
   bf16x8 a0[MR], a1[MR];
   float4 b0[NCB][2], b1[NCB][2];
+  // unconditional loads of whole K-steps, as in the FP32 form
   auto load = [&](int k, bf16x8(&a)[MR], float4(&b)[NCB][2]) {
-    if (k < K) {
+    const int kc = min(k, K - 32);
 #pragma unroll
-      for (int m = 0; m < MR; ++m) a[m] = ldg<bf16x8>(ap + (size_t)16 * m * lda + k);
+    for (int m = 0; m < MR; ++m) a[m] = ldg<bf16x8>(ap + (size_t)16 * m * lda + kc);
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        b[cb][0] = bload(cb * 16 + rA, k + 8 * g);
-        b[cb][1] = bload(cb * 16 + rA, k + 8 * g + 4);
-      }
-    } else {
-      const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-      for (int m = 0; m < MR; ++m) a[m] = to_bf16x8(z, z);
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) b[cb][0] = b[cb][1] = z;
+    for (int cb = 0; cb < NCB; ++cb) {
+      b[cb][0] = bload(cb * 16 + rA, kc + 8 * g);
+      b[cb][1] = bload(cb * 16 + rA, kc + 8 * g + 4);
     }
   };
   auto mma = [&](const bf16x8(&a)[MR], const float4(&b)[NCB][2]) {
@@ -342,14 +343,18 @@ __device__ inline void mfma_tall(const __bf16* __restrict__ A, int lda, int K, B
       for (int m = 0; m < MR; ++m) acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb, acc[m][cb], 0, 0, 0);
     }
   };
+  const int nbat = K / 32;
   load(0, a0, b0);
-  for (int k0 = 0; k0 < K; k0 += 64) {
-    load(k0 + 32, a1, b1);
+  int i = 0;
+  for (; i + 1 < nbat; i += 2) {
+    load((i + 1) * 32, a1, b1);
+    __builtin_amdgcn_sched_barrier(0);
     mma(a0, b0);
-    if (k0 + 32 >= K) break;
-    load(k0 + 64, a0, b0);
+    load((i + 2) * 32, a0, b0);
+    __builtin_amdgcn_sched_barrier(0);
     mma(a1, b1);
   }
+  if (i < nbat) mma(a0, b0);
 }
 
 // Tall tile of every instance slot (wave w = slot w) into S[slot][c][r],
@@ -447,8 +452,11 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
 
   // the bias of this tile is loaded before the GEMM (no dependent round trip)
   const T bias_v = (tg < ROWS && row0 + tg < m_out) ? ldg<T>(bias + row0 + tg) : T(0);
-  auto bload = [&](int c, int k) -> V4 {
-    if (FD && l == 0) {
+  // B operands: the input jets (layer 0, formed from the decoder input) or
+  // the previous layer's jets.  The GEMM is instantiated once for each, so
+  // that its K loop has the same loads on every path.
+  auto bload_in = [&](int c, int k) -> V4 {
+    if constexpr (FD) {
       // stencil columns of the central differences: q, q +- h e_j, then per j
       // q +- h e_j +- v for v = h dq, h qdot, 2h dq, then q +- 2h dq; every
       // input formed in T (loads from clamped indices, then selects)
@@ -463,22 +471,20 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
       }
       return V4{v[0], v[1], v[2], v[3]};
     }
-    if (l == 0) {
-      // input jets: value q, tangents dq (i2) and qdot (i4), unit e_j (i1);
-      // loads from clamped indices, then selects (no load under a branch)
-      const int ch = min(c, 2);
-      T v[4];
+    // input jets: value q, tangents dq (i2) and qdot (i4), unit e_j (i1);
+    // loads from clamped indices, then selects (no load under a branch)
+    const int ch = min(c, 2);
+    T v[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int kk = k + t;
-        const T x = (T)ldg<double>(din + ch * nq + min(kk, nq - 1));
-        T y = (c < 3) ? x : (c >= 4 && c - 4 == kk) ? T(1) : T(0);
-        v[t] = (kk < nq && c < 4 + nq) ? y : T(0);
-      }
-      return V4{v[0], v[1], v[2], v[3]};
+    for (int t = 0; t < 4; ++t) {
+      const int kk = k + t;
+      const T x = (T)ldg<double>(din + ch * nq + min(kk, nq - 1));
+      T y = (c < 3) ? x : (c >= 4 && c - 4 == kk) ? T(1) : T(0);
+      v[t] = (kk < nq && c < 4 + nq) ? y : T(0);
     }
-    return ldg<V4>(X + (size_t)c * m_inp + k);
+    return V4{v[0], v[1], v[2], v[3]};
   };
+  auto bload_x = [&](int c, int k) -> V4 { return ldg<V4>(X + (size_t)c * m_inp + k); };
   // jet channel of local column c of a jet group (-1: past n_q)
   auto gcol = [&](int c) -> int {
     if (c < 4) return c;
@@ -486,15 +492,19 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
     const int role = (c - 4) / jg, j = grp * jg + (c - 4 - role * jg);
     return j < nq ? 4 + role * nq + j : -1;
   };
-  if constexpr (JG > 0) {
-    auto bload_g = [&](int c, int k) -> V4 {
-      const int gc = gcol(c);
-      const V4 v = bload(max(gc, 0), k);
-      return gc >= 0 ? v : V4{T(0), T(0), T(0), T(0)};
-    };
-    gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload_g, S, red);
-  } else if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload, S, red);
-  else gemm_tall<TW, NCB, MR>(W, m_inp, m_inp, use, bload, S);
+  auto gemm = [&](auto bload) {
+    if constexpr (JG > 0) {
+      auto bload_g = [&](int c, int k) -> V4 {
+        const int gc = gcol(c);
+        const V4 v = bload(max(gc, 0), k);
+        return gc >= 0 ? v : V4{T(0), T(0), T(0), T(0)};
+      };
+      gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload_g, S, red);
+    } else if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload, S, red);
+    else gemm_tall<TW, NCB, MR>(W, m_inp, m_inp, use, bload, S);
+  };
+  if (l == 0) gemm(bload_in);  // uniform over the block
+  else gemm(bload_x);
 
   T(*Ss)[ROWS + 1] = S[slot];
   if constexpr (FD) {
