@@ -808,17 +808,30 @@ __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out_wide(LayerArgs la, c
   const int kq = K / OUT_SPLIT;
   typedef typename std::conditional<std::is_same<TW, float>::value, float4, bf16x8>::type AF;
   __shared__ __align__(16) float Fs[NI][NCB * 16][OUT_KMAX + 4];
-  // the folded activations, coalesced, once per block (an instance not in
-  // use leaves its copy unwritten; its results are never stored)
+  // the folded activations, coalesced, once per block: every load of an
+  // instance is issued (from clamped indices) before its LDS writes.  An
+  // instance not in use leaves its copy unwritten; its results are never
+  // stored.
+  auto stage_fold = [&]() {
+    constexpr int FI = NCB * 16 * (OUT_KMAX / 4) / (64 * OUT_SPLIT);  // float4 items per thread at K = OUT_KMAX
+    const int nk4 = K / 4, nit = NCB * 16 * nk4;
 #pragma unroll
-  for (int j = 0; j < NI; ++j) {
-    const float* fold = j == 0 ? fold0 : fold1;
-    if (use[j])
-      for (int p = threadIdx.x; p < NCB * 16 * (K / 4); p += 64 * OUT_SPLIT) {
-        const int c = p / (K / 4), k4 = p - c * (K / 4);
-        *reinterpret_cast<float4*>(&Fs[j][c][4 * k4]) = ldg<float4>(fold + (size_t)c * K + 4 * k4);
+    for (int j = 0; j < NI; ++j) {
+      if (!use[j]) continue;
+      const float* fold = j == 0 ? fold0 : fold1;
+      float4 v[FI];
+#pragma unroll
+      for (int it = 0; it < FI; ++it) {
+        const int p = min((int)threadIdx.x + it * 64 * OUT_SPLIT, nit - 1), c = p / nk4;
+        v[it] = ldg<float4>(fold + (size_t)c * K + 4 * (p - c * nk4));
       }
-  }
+#pragma unroll
+      for (int it = 0; it < FI; ++it) {
+        const int p = (int)threadIdx.x + it * 64 * OUT_SPLIT, c = p / nk4;
+        if (p < nit) *reinterpret_cast<float4*>(&Fs[j][c][4 * (p - c * nk4)]) = v[it];
+      }
+    }
+  };
   // weights of one tile (clamped row ids, zero A past each quarter's end)
   // and the output rows, bias and masks of this lane's four result rows
   struct Tile {
@@ -827,7 +840,15 @@ __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out_wide(LayerArgs la, c
     float b[4], m[NI][4];
   };
   auto load_tile = [&](int row0, Tile& t) {
-    const int wrow = gram ? ldg<int>(cdofs + min(row0 + rA, nrows - 1)) : min(row0 + rA, nrows - 1);
+    // every row id first (one wait), then all the loads that depend on them
+    int wrow = min(row0 + rA, nrows - 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t.orow[i] = min(row0 + 4 * g + i, nrows - 1);
+    if (gram) {
+      wrow = ldg<int>(cdofs + wrow);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) t.orow[i] = ldg<int>(cdofs + t.orow[i]);
+    }
 #pragma unroll
     for (int q = 0; q < OUT_SPLIT; ++q)
 #pragma unroll
@@ -838,12 +859,9 @@ __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out_wide(LayerArgs la, c
       }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int tr = min(row0 + 4 * g + i, nrows - 1);
-      const int orow = gram ? ldg<int>(cdofs + tr) : tr;
-      t.orow[i] = orow;
-      t.b[i] = ldg<float>(bias + orow);
-      t.m[0][i] = ldg<float>(keep0 + orow);
-      if constexpr (NI > 1) t.m[1][i] = ldg<float>(keep1 + orow);
+      t.b[i] = ldg<float>(bias + t.orow[i]);
+      t.m[0][i] = ldg<float>(keep0 + t.orow[i]);
+      if constexpr (NI > 1) t.m[1][i] = ldg<float>(keep1 + t.orow[i]);
     }
   };
   auto run_tile = [&](int row0, const Tile& t) {
@@ -856,22 +874,23 @@ __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out_wide(LayerArgs la, c
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
           acc[q][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+          // K-steps past the quarter's end multiply the zeroed A operand
+          // (exact: they add +0), so the unrolled steps carry no branch and
+          // their LDS reads can be issued ahead of the MFMAs
 #pragma unroll
           for (int s2 = 0; s2 < NT; ++s2) {
-            if (s2 * KS < kq) {
-              const int k = q * kq + s2 * KS + (KS / 4) * g;
-              if constexpr (std::is_same<TW, float>::value) {
-                const float4 b = *reinterpret_cast<const float4*>(&Fs[j][cb * 16 + rA][min(k, K - 4)]);
-                acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].x, b.x, acc[q][cb], 0, 0, 0);
-                acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].y, b.y, acc[q][cb], 0, 0, 0);
-                acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].z, b.z, acc[q][cb], 0, 0, 0);
-                acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].w, b.w, acc[q][cb], 0, 0, 0);
-              } else {
-                const float4 b0 = *reinterpret_cast<const float4*>(&Fs[j][cb * 16 + rA][min(k, K - 4)]);
-                const float4 b1 = *reinterpret_cast<const float4*>(&Fs[j][cb * 16 + rA][min(k + 4, K - 4)]);
-                acc[q][cb] =
-                    __builtin_amdgcn_mfma_f32_16x16x32_bf16(t.a[q][s2], to_bf16x8(b0, b1), acc[q][cb], 0, 0, 0);
-              }
+            const int k = q * kq + s2 * KS + (KS / 4) * g;
+            if constexpr (std::is_same<TW, float>::value) {
+              const float4 b = *reinterpret_cast<const float4*>(&Fs[j][cb * 16 + rA][min(k, K - 4)]);
+              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].x, b.x, acc[q][cb], 0, 0, 0);
+              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].y, b.y, acc[q][cb], 0, 0, 0);
+              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].z, b.z, acc[q][cb], 0, 0, 0);
+              acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].w, b.w, acc[q][cb], 0, 0, 0);
+            } else {
+              const float4 b0 = *reinterpret_cast<const float4*>(&Fs[j][cb * 16 + rA][min(k, K - 4)]);
+              const float4 b1 = *reinterpret_cast<const float4*>(&Fs[j][cb * 16 + rA][min(k + 4, K - 4)]);
+              acc[q][cb] =
+                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(t.a[q][s2], to_bf16x8(b0, b1), acc[q][cb], 0, 0, 0);
             }
           }
         }
@@ -898,6 +917,7 @@ __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out_wide(LayerArgs la, c
   const int r0 = blk0 + wave * 16 * OUT_TILES;
   Tile t0, t1;
   load_tile(r0, t0);
+  stage_fold();
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < OUT_TILES; j += 2) {
