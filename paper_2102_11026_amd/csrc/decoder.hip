@@ -874,12 +874,15 @@ __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out_wide(LayerArgs la, c
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
           acc[q][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-          // K-steps past the quarter's end multiply the zeroed A operand
-          // (exact: they add +0), so the unrolled steps carry no branch and
-          // their LDS reads can be issued ahead of the MFMAs
+          // BF16: K-steps past the quarter's end multiply the zeroed A
+          // operand (exact: they add +0), so the unrolled steps carry no
+          // branch and their LDS reads are issued ahead of the MFMAs.  FP32
+          // skips them (measured: 4% faster at 128 instances than without
+          // the branch; BF16 is 1.5% faster without)
 #pragma unroll
           for (int s2 = 0; s2 < NT; ++s2) {
             const int k = q * kq + s2 * KS + (KS / 4) * g;
+            if (std::is_same<TW, float>::value && s2 * KS >= kq) continue;
             if constexpr (std::is_same<TW, float>::value) {
               const float4 b = *reinterpret_cast<const float4*>(&Fs[j][cb * 16 + rA][min(k, K - 4)]);
               acc[q][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(t.a[q][s2].x, b.x, acc[q][cb], 0, 0, 0);
