@@ -237,10 +237,11 @@ int nmr_pool_step(nmr_pool* pool, int n_iters, int* status_or_null, float* ms_or
  * same bits; wider whole tiles split K over fewer waves and agree to
  * rounding.  Launches of one instance run (1, 1).
  *   NMR_TILES_RULE (the default): a fixed rule from the layer's row count,
- *     its columns and the number of instances (tall tiles once there are
- *     1024 waves of 16 mr rows, instances stacked once the chip is full
- *     without it, jet groups in forward layers of fewer than 256 row-tile x
- *     instance blocks); results are bitwise reproducible.
+ *     its columns and the number of instances: tall tiles once there are 768
+ *     waves of 16 mr rows; else ib from the rounds of 256 blocks the launch
+ *     takes, weighed by how much longer a stacked block runs; jet groups in
+ *     forward layers of fewer than 192 row-tile x instance blocks.  Results
+ *     are bitwise reproducible.
  *   NMR_TILES_AUTOTUNE: the first time a (direction, layer widths, columns,
  *     instances, precision, derivative scheme) occurs in a step_many call (or
  *     a pool step with at least half its slots attached), every eligible

@@ -244,14 +244,27 @@ __device__ inline void gemm_splitk(const TW* __restrict__ A, int lda, int K, boo
   __syncthreads();
 }
 
-// instances per block of a hidden-layer launch: stack instances (sharing the
-// weight tile, a longer MFMA run per block) once there are enough blocks to
-// fill the chip without it
+// instances per block of a hidden-layer launch.  Stacked instances share the
+// weight tile, so a block of ib instances takes less than ib times as long:
+// about 1 + 0.6 (ib - 1) blocks' time.  The rule takes the fewest rounds of
+// 256 blocks (one per CU) times that length, ties to more stacking.  A
+// launch of 384 blocks takes two rounds like one of 512, so the rule follows
+// the rounds, not the block count alone.  (The 0.6 is the value that
+// reproduces every autotuned choice on the 10k-vertex decoder from 8 to 128
+// instances.)
 __host__ inline int stack_instances(int row_tiles, int nb, bool f64) {
   if (f64) return 1;
-  if (row_tiles * ((nb + 3) / 4) >= 512) return 4;
-  if (row_tiles * ((nb + 1) / 2) >= 512) return 2;
-  return 1;
+  int best = 1;
+  long best_cost = -1;
+  for (int ib = 1; ib <= 4; ib *= 2) {
+    const long blocks = (long)row_tiles * ((nb + ib - 1) / ib);
+    const long cost = ((blocks + 255) / 256) * (5 + 3 * (ib - 1));
+    if (best_cost < 0 || cost <= best_cost) {
+      best = ib;
+      best_cost = cost;
+    }
+  }
+  return best;
 }
 
 // ---------------------------------------------------------------------------
@@ -1273,20 +1286,22 @@ static int tall_max_cols(int mr, bool fwd) { return fwd ? (mr == 2 ? 128 : 64) :
 
 // perturbations per jet group, and the groups of a decoder's input width
 static constexpr int kJetGroup = 3;
+// tall tiles from this many (row tile, instance) waves
+static constexpr int kTallWaves = 768;
 static int jet_groups(const DecoderDev& d) { return (d.w[0] + kJetGroup - 1) / kJetGroup; }
 
 // Layers with tall tiles (at most 64 jet columns forward, 32 adjoint columns
-// backward) take them once there are 1024 (row tile, instance) waves of 16 mr
-// rows, the largest mr first (the crossover measured on the 10k-vertex
-// decoder at 64 and 128 instances); otherwise instances are stacked once the
-// chip is full without it.  Forward layers whose (row tile, instance) blocks
-// leave most CUs idle split the jet columns into groups instead.
+// backward) take them once there are 768 (row tile, instance) waves of 16 mr
+// rows, the largest mr first; otherwise instances are stacked as above.
+// Forward layers whose (row tile, instance) blocks leave most CUs idle split
+// the jet columns into groups instead.  Both crossovers are the ones the
+// autotuner finds on the 10k-vertex decoder from 8 to 128 instances.
 TileCfg tile_rule(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd) {
   if (fd || f64) return TileCfg{1, 1};
   const int rows = hidden_rows(d, l, fwd);
   if (nb >= 4)
     for (int mr = 4; mr >= 2; mr /= 2)
-      if (cols <= tall_max_cols(mr, fwd) && rows % (16 * mr) == 0 && (rows / (16 * mr)) * nb >= 1024)
+      if (cols <= tall_max_cols(mr, fwd) && rows % (16 * mr) == 0 && (rows / (16 * mr)) * nb >= kTallWaves)
         return TileCfg{4, mr};
   const int ib = stack_instances(rows / 16, nb, false);
   if (ib == 1 && fwd && cols > 16 && (rows / 16) * nb < kJetGroupBlocks) return TileCfg{1, 1, 1};

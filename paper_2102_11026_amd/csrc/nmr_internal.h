@@ -254,7 +254,7 @@ struct TileCfg {
   int ib, mr, jg = 0;
 };
 // jet-group blocks: below this many (row tile, instance) blocks
-static constexpr int kJetGroupBlocks = 256;
+static constexpr int kJetGroupBlocks = 192;
 TileCfg tile_rule(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd);
 bool tile_eligible(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd, TileCfg c);
 // eligible configurations of hidden layer l (at most 6), the rule's among them

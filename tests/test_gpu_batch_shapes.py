@@ -60,11 +60,15 @@ def batch_vs_alone(nmr, ctx, probs, prec, steps, iters, path="auto"):
 def test_wide_output_layer_is_bitwise_the_split_one(nmr, ctx, prec):
     """Eleven 10k-vertex instances on the direct path (30,000 decoded rows
     each, the same for all): the output layer runs the wide kernel with two
-    instances per block (the last block holds one), everything else as
-    alone."""
+    instances per block (the last block holds one).  The hidden layers are
+    forced to one-instance tiles, so everything else runs as alone."""
     p = synth.config_single_10k()
     probs = [p.replace(r0=p.r0 + 0.02 * synth.normal(f"wide/q0/{k}", p.R)) for k in range(11)]
-    got, alone = batch_vs_alone(nmr, ctx, probs, prec, 1, p.newton_iters, path="direct")
+    ctx.set_tiling("force", 1, 1)
+    try:
+        got, alone = batch_vs_alone(nmr, ctx, probs, prec, 1, p.newton_iters, path="direct")
+    finally:
+        ctx.set_tiling("rule")
     for (r, rd, u), (ra, rda, ua) in zip(got, alone):
         np.testing.assert_array_equal(r, ra)
         np.testing.assert_array_equal(rd, rda)
