@@ -260,6 +260,9 @@ static int decoder_build(nmr_ctx* ctx, const nmr_mlp_desc* desc, int prec, nmr_d
   d->d.L = L;
   d->d.act = desc->act;
   d->d.prec = prec;
+  // the GEMM kernels take whole 32-wide K batches (the tall tiles' double
+  // buffer, the BF16 K-steps), so every padded width is a multiple of 32
+  static_assert(NMR_WPAD % 32 == 0, "layer widths must be padded to a multiple of 32");
   for (int l = 0; l <= L; ++l) {
     d->d.w[l] = desc->widths[l];
     d->d.wp[l] = pad_to(desc->widths[l], NMR_WPAD);
