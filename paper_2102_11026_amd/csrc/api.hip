@@ -421,7 +421,7 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   s.K = d.wp[d.L - 1];
   s.gram = (p->newton_path == 0 && s.n_p == 0 && s.K <= 256) ? 1 : 0;
   s.n_cdofs = 0;
-  s.n_gblk = s.K / 16;
+  s.n_gblk = kGramKParts * (s.K / 16);
   s.n_sblk = 0;
   if (s.gram) {
     std::vector<char> hit(s.N, 0);
@@ -440,7 +440,7 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
     s.n_sblk = (s.n_cdofs + 127) / 128;
   }
   s.mblk_alloc = std::max(s.n_mblk, s.n_gblk);
-  s.bblk_alloc = std::max(s.n_bblk, s.n_sblk + 1);
+  s.bblk_alloc = std::max(s.n_bblk, s.n_sblk + kGramKParts);
   if (s.R > NMR_MAX_R - 1) return fail(NMR_ERR_ARG, "n_p + n_q must be <= 31");
   if (d.w[d.L] < s.N) return fail(NMR_ERR_ARG, "decoder output smaller than 3 * n_vertices");
   if (s.Cf > 64) return fail(NMR_ERR_ARG, "n_q too large for the output layer");
@@ -739,7 +739,7 @@ static Group group_of(const std::vector<nmr_inst*>& v, void* tab) {
   g.Cp = v[0]->Cp; g.Cb = v[0]->Cb; g.Cf = v[0]->Cf; g.n_q = v[0]->n_q;
   g.fd = v[0]->fd != 0;
   g.K = g.dec->d.wp[g.dec->d.L - 1];
-  g.n_gblk = g.K / 16;
+  g.n_gblk = kGramKParts * (g.K / 16);
   g.gram = true;
   for (nmr_inst* in : v) {
     g.gram = g.gram && in->gram;

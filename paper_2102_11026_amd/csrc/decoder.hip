@@ -1116,7 +1116,7 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(LayerArgs la, const Inst<T>*
   double acc = 0.0;
   if (k < K) {
     const double* src = I.part_bwd + k;
-    const int nb = I.gram ? I.n_sblk + 1 : I.n_bblk;  // Gram: + the Gam y + gam partial
+    const int nb = I.gram ? I.n_sblk + kGramKParts : I.n_bblk;  // Gram: + the Gam y (+ gam) partials
 #pragma unroll 4
     for (int b = sl; b < nb; b += 16) acc += ldg<double>(src + (size_t)b * K);
   }

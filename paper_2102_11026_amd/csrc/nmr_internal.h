@@ -113,7 +113,7 @@ struct Inst {
   // the constant lumped mass, Jt^T M Jt = F_J^T Gam F_J etc. over the folded
   // activations F; only the DOFs of cubature tets are decoded per iteration
   int gram;                // 1: this table entry runs the Gram path
-  int n_gblk;              // Gram partial blocks (K / 16)
+  int n_gblk;              // Gram partial blocks (kGramKParts x K / 16)
   const int* cdofs;        // [n_cdofs] sorted DOFs touched by cubature tets
   int n_cdofs;
   int n_sblk;              // sparse backprop blocks over cdofs (128 rows each)
@@ -255,6 +255,9 @@ struct TileCfg {
 };
 // jet-group blocks: below this many (row tile, instance) blocks
 static constexpr int kJetGroupBlocks = 192;
+// K parts of a 16-row block of the Gram terms: each part is a block of its
+// own with its own mass and backpropagation partials
+static constexpr int kGramKParts = 2;
 TileCfg tile_rule(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd);
 bool tile_eligible(const DecoderDev& d, int l, int nb, int cols, bool fd, bool f64, bool fwd, TileCfg c);
 // eligible configurations of hidden layer l (at most 6), the rule's among them

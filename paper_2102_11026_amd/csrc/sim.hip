@@ -643,7 +643,11 @@ __device__ __forceinline__ void gram_block(const Inst<T>* __restrict__ tab, int 
   const int nq = I.n_q, R = I.R;  // R = n_q on this path
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int col = lane & 15, kk = lane >> 4;
-  const int row0 = bx * 16;
+  // rows [row0, row0 + 16) over the K part [kb0, kb0 + kh): each part has
+  // its own partials (the mass terms and T y are linear in the K sum), gam
+  // is added by part 0
+  const int rb = bx / kGramKParts, kpart = bx - rb * kGramKParts;
+  const int row0 = rb * 16, kh = K / kGramKParts, kb0 = kpart * kh;
   const T* F = I.fold;  // [Cf][K], K <= 256
   __shared__ double wr[NMR_MAX_R];
   __shared__ double y[256];
@@ -657,19 +661,19 @@ __device__ __forceinline__ void gram_block(const Inst<T>* __restrict__ tab, int 
   // NCB column blocks hold 2 n_q + 1 < 16 NCB columns, so n_q < QM
   constexpr int QM = 8 * NCB;
   static_assert(QM <= NMR_MAX_R, "column blocks");
-  const int kt = min((int)threadIdx.x, K - 1);
+  const int kt = kb0 + min((int)threadIdx.x, kh - 1);
   T fy[QM];
 #pragma unroll
   for (int j = 0; j < QM; ++j) fy[j] = ldg<T>(F + (size_t)(1 + min(j, nq - 1)) * K + kt);
   const T fh = ldg<T>(F + (size_t)(1 + 2 * nq) * K + kt);
-  constexpr int NST = 256 / 16;  // K-steps of one wave at K = 256 (K/4 entries, 4 per step)
-  const int kper = K / 4, nst = kper / 4;
+  constexpr int NST = 256 / (16 * kGramKParts);  // K-steps of one wave at K = 256 (kh/4 entries, 4 per step)
+  const int kper = kh / 4, nst = kper / 4;
   const double* G = I.Gam + (size_t)(row0 + col) * K;
   double av[NST];
   T bv[NST][NCB];
 #pragma unroll
   for (int st = 0; st < NST; ++st) {
-    const int k = min(wave * kper + 4 * st + kk, K - 1);
+    const int k = kb0 + min(wave * kper + 4 * st + kk, kh - 1);
     av[st] = ldg<double>(G + k);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) bv[st][cb] = ldg<T>(F + (size_t)(1 + min(cb * 16 + col, 2 * nq - 1)) * K + k);
@@ -691,7 +695,7 @@ __device__ __forceinline__ void gram_block(const Inst<T>* __restrict__ tab, int 
     if ((p >> 4) < nq) frow[p >> 4][p & 15] = (double)fpv[q];
   }
   __syncthreads();
-  if ((int)threadIdx.x < K) {
+  if ((int)threadIdx.x < kh) {
     double v = (double)fh;
 #pragma unroll
     for (int j = 0; j < QM; ++j)
@@ -702,13 +706,14 @@ __device__ __forceinline__ void gram_block(const Inst<T>* __restrict__ tab, int 
   f64x4 acc[NCB];
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb) acc[cb] = f64x4{0.0, 0.0, 0.0, 0.0};
-  // each wave a quarter of K, 4 entries per step, in increasing k.  The y
-  // entries of the wave's steps are read from LDS in one batch and every B
-  // operand is chosen by selects; steps past K/4 (K < 256) multiply a zero
-  // A operand, which adds exact zeros, so the loop is straight-line code
+  // each wave a quarter of the block's K part, 4 entries per step, in
+  // increasing k.  The y entries of the wave's steps are read from LDS in one
+  // batch and every B operand is chosen by selects; steps past the quarter
+  // (K < 256) multiply a zero A operand, which adds exact zeros, so the loop
+  // is straight-line code
   double yv[NST];
 #pragma unroll
-  for (int st = 0; st < NST; ++st) yv[st] = y[min(wave * kper + 4 * st + kk, K - 1)];
+  for (int st = 0; st < NST; ++st) yv[st] = y[min(wave * kper + 4 * st + kk, kh - 1)];
 #pragma unroll
   for (int st = 0; st < NST; ++st) {
     const double a = st < nst ? av[st] : 0.0;
@@ -735,9 +740,9 @@ __device__ __forceinline__ void gram_block(const Inst<T>* __restrict__ tab, int 
   }
   // T_y + gam for these rows: the backprop partial after the sparse blocks
   if (threadIdx.x < 16) {
-    const double zb = tile[threadIdx.x][2 * nq] + gm;
+    const double zb = tile[threadIdx.x][2 * nq] + (kpart == 0 ? gm : 0.0);
     tile[threadIdx.x][2 * nq] = zb;
-    stg<double>(I.part_bwd + (size_t)I.n_sblk * K + row0 + threadIdx.x, zb);
+    stg<double>(I.part_bwd + (size_t)(I.n_sblk + kpart) * K + row0 + threadIdx.x, zb);
   }
   __syncthreads();
   // mass partial F_J[rows]^T T in the layout of the direct path
