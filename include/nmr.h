@@ -177,17 +177,25 @@ int cubature_force_stiffness(nmr_inst* inst, const void* u, const void* Jt, cons
  * the cubature weights of that step. */
 int reduced_newton_system(nmr_inst* inst, const double* r, double* A, double* phi);
 
-/* One implicit-Euler step with n_iters full Newton iterations starting from
- * r = rbar, then rdot = (r - rbar) / dt, rbar = r.  resid_norms_or_null:
+/* One implicit-Euler step (Sec. 3.2) of the reduced equation of motion
+ * (eq. our_equation_of_motion, Sec. 3.6) with n_iters full Newton
+ * iterations, each solving A delta = -phi with the matrix of eq. system_mat
+ * (third-order term eq. delta_j) by LU with partial pivoting, starting from
+ * r = rbar, then rdot = (r - rbar) / dt, rbar = r.  The cubature weights come
+ * from the weight net at rbar once per step (Sec. 5.2).  resid_norms_or_null:
  * host, n_iters doubles of ||phi|| per iteration (synchronizes).  A failure
  * leaves the state of the previous step in place and is returned here (if
  * synchronized) or by nmr_instance_status. */
 int reduced_newton_step(nmr_inst* inst, int n_iters, double* resid_norms_or_null);
 
 /* Advances n_inst instances (same context) n_steps steps of n_iters Newton
- * iterations each, all instances together: instances that share a decoder
- * run their decoder passes as one batched launch per layer, and every phase
- * is one launch for the whole set, captured in a HIP graph per step.  Host
+ * iterations each (the step of reduced_newton_step for every instance), all
+ * instances together.  Instances that share a decoder -- one trained net
+ * reused across identical domains, as for the strings of the multi-domain
+ * scenes of Sec. 6.8 -- run their decoder passes as one batched launch per
+ * layer, their perturbation columns stacked like the mini-batch of
+ * collective perturbations of Sec. 4.4; every phase is one launch for the
+ * whole set, captured in a HIP graph per step.  Host
  * outputs: status [n_inst] (nmr_status of each instance; a failed instance is
  * frozen at its last good state, the others continue) and step_ms_or_null
  * [n_steps] (device time of each step). */
@@ -202,13 +210,16 @@ typedef struct nmr_pool nmr_pool;
  * over all slots; instances attach to free slots and detach between steps
  * without a new capture (empty slots return at once).  Every attached
  * instance must share the first one's decoder, precision and sizes (N, n_p,
- * n_q, |C|, weight net), i.e. one request class. */
+ * n_q, |C|, weight-net widths), Newton path and decoded cubature DOFs,
+ * formulation (trimmed) and derivative scheme (fd_h), i.e. one request
+ * class. */
 int nmr_pool_create(nmr_ctx* ctx, int capacity, nmr_pool** out);
 int nmr_pool_destroy(nmr_pool* pool);
 /* Attaches `inst` to a free slot (host output *slot).  NMR_ERR_BUDGET if the
- * pool is full, NMR_ERR_ARG if the instance does not match the pool's class.
- * The instance keeps its own state and buffers; it must stay alive until it is
- * detached. */
+ * pool is full, NMR_ERR_ARG if the instance does not match the pool's class
+ * or is already attached to a pool.  The instance keeps its own state and
+ * buffers; nmr_instance_destroy of an attached instance detaches it first,
+ * and nmr_pool_destroy detaches every instance. */
 int nmr_pool_attach(nmr_pool* pool, nmr_inst* inst, int* slot);
 int nmr_pool_detach(nmr_pool* pool, int slot);
 /* One implicit-Euler step (n_iters Newton iterations) of every attached

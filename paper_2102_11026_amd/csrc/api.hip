@@ -133,6 +133,8 @@ struct nmr_inst {
   std::vector<unsigned char> host;  // host copy of the Inst<T>
   std::map<int, hipGraphExec_t> step_graphs;
   double* A_scratch = nullptr;
+  nmr_pool* pool = nullptr;  // the pool this instance is attached to, if any
+  int pool_slot = -1;
 };
 
 // ---------------------------------------------------------------------------
@@ -693,6 +695,9 @@ extern "C" int nmr_instance_destroy(nmr_inst* in) {
   nmr_ctx* c = in->ctx;
   CHK(set_device(c));
   (void)hipStreamSynchronize(c->stream);
+  // an attached instance leaves its pool first: the pool's graph must never
+  // reach the buffers freed below
+  if (in->pool) CHK(nmr_pool_detach(in->pool, in->pool_slot));
   drop_many_graphs(c, in);
   for (auto& kv : in->step_graphs) (void)hipGraphExecDestroy(kv.second);
   c->used -= in->bytes;
@@ -1234,6 +1239,11 @@ extern "C" int nmr_pool_destroy(nmr_pool* p) {
   if (!p) return fail(NMR_ERR_ARG, "null pool");
   CHK(set_device(p->ctx));
   (void)hipStreamSynchronize(p->ctx->stream);
+  for (nmr_inst* x : p->slots)
+    if (x) {
+      x->pool = nullptr;
+      x->pool_slot = -1;
+    }
   pool_drop_graphs(p);
   if (p->tab) (void)hipFree(p->tab);
   if (p->proto) decoder_unref(p->proto->dec);
@@ -1241,14 +1251,33 @@ extern "C" int nmr_pool_destroy(nmr_pool* p) {
   return NMR_OK;
 }
 
+// The pool's graph is captured from its first instance: its launch grids,
+// its Newton path (Gram-folded or direct), the decoded rows of the Gram path,
+// the formulation, the derivative scheme and the weight net's shape must
+// hold for every later member too.
+template <typename T>
+static bool same_inst_shape(const nmr_inst* a, const nmr_inst* b) {
+  const Inst<T>& x = *reinterpret_cast<const Inst<T>*>(a->host.data());
+  const Inst<T>& y = *reinterpret_cast<const Inst<T>*>(b->host.data());
+  if (x.trimmed != y.trimmed || x.fd != y.fd || x.fd_h != y.fd_h || x.wn_L != y.wn_L || x.wn_maxw != y.wn_maxw)
+    return false;
+  for (int l = 0; x.wn_L > 0 && l <= x.wn_L; ++l)
+    if (x.wn_w[l] != y.wn_w[l]) return false;
+  return true;
+}
+
 static bool same_class(const nmr_inst* a, const nmr_inst* b) {
-  return a->dec == b->dec && a->prec == b->prec && a->Cp == b->Cp && a->N == b->N && a->n_p == b->n_p &&
-         a->n_q == b->n_q &&
-         a->n_cub == b->n_cub && a->n_mblk == b->n_mblk && a->n_cblk == b->n_cblk && a->n_bblk == b->n_bblk;
+  if (!(a->dec == b->dec && a->prec == b->prec && a->Cp == b->Cp && a->Cb == b->Cb && a->Cf == b->Cf &&
+        a->N == b->N && a->n_p == b->n_p && a->n_q == b->n_q && a->n_cub == b->n_cub && a->n_mblk == b->n_mblk &&
+        a->n_cblk == b->n_cblk && a->n_bblk == b->n_bblk && a->gram == b->gram && a->n_cdofs == b->n_cdofs &&
+        a->n_sblk == b->n_sblk && a->fd == b->fd && a->cdofs == b->cdofs))
+    return false;
+  return is_f64(a) ? same_inst_shape<double>(a, b) : same_inst_shape<float>(a, b);
 }
 
 extern "C" int nmr_pool_attach(nmr_pool* p, nmr_inst* in, int* slot) {
   if (!p || !in || !slot || in->ctx != p->ctx) return fail(NMR_ERR_ARG, "bad argument");
+  if (in->pool) return fail(NMR_ERR_ARG, "instance is already attached to a pool");
   CHK(set_device(p->ctx));
   if (p->proto && !same_class(p->proto, in)) return fail(NMR_ERR_ARG, "instance does not match the pool's class");
   int s = -1;
@@ -1261,6 +1290,7 @@ extern "C" int nmr_pool_attach(nmr_pool* p, nmr_inst* in, int* slot) {
   if (!p->proto) {
     p->proto_copy = *in;
     p->proto_copy.step_graphs.clear();
+    p->proto_copy.pool = nullptr;
     p->proto = &p->proto_copy;
     p->proto->dec->refs++;  // the pool's graph references the decoder's weights
     p->isz = is_f64(in) ? sizeof(Inst<double>) : sizeof(Inst<float>);
@@ -1272,6 +1302,8 @@ extern "C" int nmr_pool_attach(nmr_pool* p, nmr_inst* in, int* slot) {
   HIPCHK(hipMemcpy(static_cast<unsigned char*>(p->tab) + s * p->isz, in->host.data(), p->isz,
                    hipMemcpyHostToDevice));
   p->slots[s] = in;
+  in->pool = p;
+  in->pool_slot = s;
   *slot = s;
   return NMR_OK;
 }
@@ -1282,6 +1314,8 @@ extern "C" int nmr_pool_detach(nmr_pool* p, int s) {
   HIPCHK(hipStreamSynchronize(p->ctx->stream));
   const int zero = 0;  // Inst<T>::active is the first member
   HIPCHK(hipMemcpy(static_cast<unsigned char*>(p->tab) + s * p->isz, &zero, sizeof(int), hipMemcpyHostToDevice));
+  p->slots[s]->pool = nullptr;
+  p->slots[s]->pool_slot = -1;
   p->slots[s] = nullptr;
   return NMR_OK;
 }

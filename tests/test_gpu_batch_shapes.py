@@ -6,14 +6,10 @@ import numpy as np
 import pytest
 
 from paper_2102_11026_amd import synth
+from parity import close, rel
 
 pytestmark = pytest.mark.gpu
 
-
-def rel(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 @pytest.fixture(scope="module")
@@ -125,7 +121,9 @@ def test_merged_cubature_blocks_match_alone(nmr, ctx, prec, tol):
         probs.append(base.replace(r0=r0))
     got, alone = batch_vs_alone(nmr, ctx, probs, prec, 4, 3)
     for k, ((r, rd, u), (ra, rda, ua)) in enumerate(zip(got, alone)):
-        assert rel(r, ra) < tol and rel(rd, rda) < tol and rel(u, ua) < tol, k
+        close(r, ra, tol, ("r", k))
+        close(rd, rda, tol, ("rdot", k))
+        close(u, ua, tol, ("u", k))
 
 
 def test_large_pool_matches_alone(nmr, ctx):
@@ -150,7 +148,7 @@ def test_large_pool_matches_alone(nmr, ctx):
             assert all(v == 0 for v in st)
         st, _ = nmr.step_many(ctx, [ref], 5, 3)
         assert st == [0]
-        assert rel(insts[0].get_state()[0], ref.get_state()[0]) < 1e-5
+        close(insts[0].get_state()[0], ref.get_state()[0], 1e-5, 'insts[0].get_state()[0]')
     finally:
         pool.close()
         for x in insts + [ref]:

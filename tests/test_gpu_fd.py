@@ -5,14 +5,10 @@ import pytest
 
 from oracle.newton import Instance as OInst
 from paper_2102_11026_amd import synth
+from parity import close, rel
 
 pytestmark = pytest.mark.gpu
 
-
-def rel(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 @pytest.fixture(scope="module")
@@ -59,14 +55,16 @@ def test_fd_mode_matches_oracle_fd(nmr, ctx, name, formulation):
         ref = oi.decode(q, dq, qd)
         JTa, B = oi.left(q, a)
         for k, kk in (("u", "m"), ("J", "J"), ("dJ", "dJ")):
-            assert rel(got[k].cpu(), ref[kk]) < 1e-6, k
+            close(got[k].cpu(), ref[kk], 1e-6, k)
         if formulation == "full":
-            assert rel(got["Hdd"].cpu(), ref["Hdd"]) < 1e-6
-        assert rel(got["JTa"].cpu(), JTa) < 1e-10 and rel(got["B"].cpu(), B) < 1e-6
+            close(got["Hdd"].cpu(), ref["Hdd"], 1e-6, "Hdd")
+        close(got["JTa"].cpu(), JTa, 1e-10, "JTa")
+        close(got["B"].cpu(), B, 1e-6, "B")
         r = p.r0 + rng.normal(size=p.R) * 0.01
         A, phi = inst.newton_system(r)
         sysd = oi.system(r, p.r0, rdot, oi.cubature_weights(p.r0))
-        assert rel(phi.cpu().numpy(), sysd["phi"]) < 1e-6 and rel(A.cpu().numpy(), sysd["A"]) < 1e-6
+        close(phi.cpu().numpy(), sysd["phi"], 1e-6, "phi")
+        close(A.cpu().numpy(), sysd["A"], 1e-6, "A")
     finally:
         inst.close()
 

@@ -11,6 +11,7 @@ import pytest
 from oracle import decoder as odec
 from oracle.newton import Instance as OInst
 from paper_2102_11026_amd import synth
+from parity import close, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -21,11 +22,6 @@ TOL = {
                  A=1e-4, phi=1e-4),
 }
 
-
-def rel(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 @pytest.fixture(scope="module")
@@ -82,12 +78,12 @@ def test_decoder_jacobian_hessian(nmr, ctx, name, prec):
         t = TOL[prec]
         print(name, prec, {k: rel(got[k].cpu().numpy(), ref[kk]) for k, kk in
                            [("u", "m"), ("J", "J"), ("dJ", "dJ"), ("Hdd", "Hdd")]})
-        assert rel(got["u"].cpu().numpy(), ref["m"]) < t["u"]
-        assert rel(got["J"].cpu().numpy(), ref["J"]) < t["J"]
-        assert rel(got["dJ"].cpu().numpy(), ref["dJ"]) < t["dJ"]
-        assert rel(got["Hdd"].cpu().numpy(), ref["Hdd"]) < t["Hdd"]
-        assert rel(got["JTa"].cpu().numpy(), JTa) < t["JTa"]
-        assert rel(got["B"].cpu().numpy(), B) < t["B"]
+        close(got["u"].cpu().numpy(), ref["m"], t["u"], "u")
+        close(got["J"].cpu().numpy(), ref["J"], t["J"], "J")
+        close(got["dJ"].cpu().numpy(), ref["dJ"], t["dJ"], "dJ")
+        close(got["Hdd"].cpu().numpy(), ref["Hdd"], t["Hdd"], "Hdd")
+        close(got["JTa"].cpu().numpy(), JTa, t["JTa"], "JTa")
+        close(got["B"].cpu().numpy(), B, t["B"], "B")
     finally:
         inst.close()
 
@@ -107,9 +103,9 @@ def test_cubature_force_stiffness(nmr, ctx, name, prec):
         oi = OInst(p)
         f_int, fr, Kr = fem.cubature_force_stiffness(p.X, p.tets, u, Jt, p.cub_ids, w, oi.Bm, oi.Ve, oi.mu, oi.lam)
         t = TOL[prec]
-        assert rel(got["f_int"].cpu().numpy(), f_int) < t["fint"]
-        assert rel(got["fr"].cpu().numpy(), fr) < t["fr"]
-        assert rel(got["Kr"].cpu().numpy(), Kr) < t["Kr"]
+        close(got["f_int"].cpu().numpy(), f_int, t["fint"], "f_int")
+        close(got["fr"].cpu().numpy(), fr, t["fr"], "fr")
+        close(got["Kr"].cpu().numpy(), Kr, t["Kr"], "Kr")
     finally:
         inst.close()
 
@@ -127,8 +123,8 @@ def test_newton_system(nmr, ctx, name, prec):
         A, phi = inst.newton_system(r)
         sysd = oi.system(r, p.r0, rdot, oi.cubature_weights(p.r0))
         t = TOL[prec]
-        assert rel(phi.cpu().numpy(), sysd["phi"]) < t["phi"]
-        assert rel(A.cpu().numpy(), sysd["A"]) < t["A"]
+        close(phi.cpu().numpy(), sysd["phi"], t["phi"], "phi")
+        close(A.cpu().numpy(), sysd["A"], t["A"], "A")
     finally:
         inst.close()
 
@@ -145,7 +141,7 @@ def test_trajectory_plain_fp64(nmr, ctx):
             norms = inst.step(p.newton_iters)
             st, onorms = oi.step(st, p.newton_iters)
             r, rd = inst.get_state()
-            assert rel(r, st.rbar) < 1e-9, s
+            close(r, st.rbar, 1e-9, s)
             # once the bar is at rest rdot = (r - rbar)/dt cancels, so compare it
             # against the velocity scale of the first step
             vscale = vscale or np.linalg.norm(st.rdot_bar)
@@ -153,6 +149,6 @@ def test_trajectory_plain_fp64(nmr, ctx):
             scale = scale or onorms[0]
             np.testing.assert_allclose(norms, onorms, rtol=1e-6, atol=1e-11 * scale)
         r, rd, u = inst.get_state(with_u=True)
-        assert rel(u, oi.displacement(st.rbar)) < 1e-9
+        close(u, oi.displacement(st.rbar), 1e-9, 'u')
     finally:
         inst.close()

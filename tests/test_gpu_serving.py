@@ -4,12 +4,9 @@ import pytest
 
 from oracle.newton import Instance as OInst
 from paper_2102_11026_amd import synth
+from parity import close, rel
 
 pytestmark = pytest.mark.gpu
-
-
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
 @pytest.fixture(scope="module")
@@ -44,7 +41,7 @@ def test_rods_batched_against_oracle(nmr, ctx):
             s = oi.initial_state()
             for _ in range(2):
                 s, _ = oi.step(s, 3)
-            assert rel(x.get_state()[0], s.rbar) < 1e-9, p.name
+            close(x.get_state()[0], s.rbar, 1e-9, p.name)
     finally:
         for x in insts:
             x.close()
@@ -115,3 +112,72 @@ def test_serve_loop_drains_and_matches_alone(nmr, ctx):
             x.close()
     finally:
         srv.close()
+
+
+def test_pool_rejects_other_classes(nmr, ctx):
+    """Instances whose Newton path, decoded cubature DOFs, formulation or
+    derivative scheme differ from the pool's first member are refused, even
+    with the same sizes and decoder (the pool's graph is captured from the
+    first member)."""
+    p = small_class(0)
+    dec = nmr.Decoder(ctx, p.weights, p.biases, p.act, "fp32")
+    pool = nmr.Pool(ctx, 4)
+    other_ids = np.sort(synth.permutation("srv/other-cub", p.tets.shape[0])[: p.cub_ids.size]).astype(np.int32)
+    variants = {
+        "direct path": (p, "direct"),
+        "other cubature tets": (p.replace(cub_ids=other_ids), "auto"),
+        "trimmed": (p.replace(formulation="trimmed"), "auto"),
+    }
+    first = nmr.Instance(ctx, p, "fp32", shared=dec)
+    made = [first]
+    try:
+        pool.attach(first)
+        with pytest.raises(nmr.NmrError) as e:
+            pool.attach(first)                       # already attached
+        assert nmr.STATUS[e.value.code] == "arg"
+        for name, (q, path) in variants.items():
+            x = nmr.Instance(ctx, q, "fp32", shared=dec, path=path)
+            made.append(x)
+            with pytest.raises(nmr.NmrError) as e:
+                pool.attach(x)
+            assert nmr.STATUS[e.value.code] == "arg", name
+        same = nmr.Instance(ctx, small_class(1), "fp32", shared=dec)
+        made.append(same)
+        pool.attach(same)                            # same class, other initial state: accepted
+    finally:
+        pool.close()
+        for x in made:
+            x.close()
+        dec.close()
+
+
+def test_destroying_an_attached_instance_detaches_it(nmr, ctx):
+    """nmr_instance_destroy of a pool member frees its slot first, so the
+    pool's next step never reaches the freed buffers; the remaining member
+    continues as if stepped alone."""
+    probs = [small_class(k) for k in range(2)]
+    dec = nmr.Decoder(ctx, probs[0].weights, probs[0].biases, probs[0].act, "fp32")
+    pool = nmr.Pool(ctx, 4)
+    a, b = (nmr.Instance(ctx, q, "fp32", shared=dec) for q in probs)
+    ref = nmr.Instance(ctx, probs[0], "fp32", shared=dec)
+    try:
+        sa = pool.attach(a)
+        sb = pool.attach(b)
+        pool.step(3)
+        b.close()                                    # destroyed while attached
+        st, _ = pool.step(3, status=True)
+        assert st[sb] == 0 and st[sa] == 0
+        c = nmr.Instance(ctx, probs[1], "fp32", shared=dec)
+        s2 = pool.attach(c)
+        assert s2 == sb                              # the freed slot is reused
+        pool.detach(s2)
+        c.close()
+        st, _ = nmr.step_many(ctx, [ref], 2, 3)
+        assert st == [0]
+        # a (two pool steps) against the same request stepped alone twice
+        close(a.get_state()[0], ref.get_state()[0], 1e-5, "r")
+    finally:
+        pool.close()
+        for x in (a, ref):
+            x.close()
+        dec.close()

@@ -7,16 +7,12 @@ import pytest
 
 from oracle.newton import Instance as OInst
 from paper_2102_11026_amd import synth
+from parity import close, rel
 
 pytestmark = pytest.mark.gpu
 
 CONFIGS = [(1, 1), (2, 1), (4, 1), (4, 2), (4, 4)]
 
-
-def rel(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 @pytest.fixture(scope="module")
@@ -89,8 +85,8 @@ def test_forced_tiles_fp32_match_oracle(nmr, n_q, q_scale):
     # the K sums differently, the same bar
     for cfg, rs in got.items():
         for k, (r, o) in enumerate(zip(rs, ref)):
-            assert rel(r, o) < 1e-4, (cfg, k, rel(r, o))
-            assert rel(r, got[(1, 1)][k]) < 1e-4, (cfg, k)
+            close(r, o, 1e-4, (cfg, k, rel(r, o)))
+            close(r, got[(1, 1)][k], 1e-4, (cfg, k))
 
 
 def test_forced_tiles_bf16_match_oracle(nmr):
@@ -101,7 +97,7 @@ def test_forced_tiles_bf16_match_oracle(nmr):
         for cfg in [(1, 1), (4, 1), (4, 2), (4, 4)]:
             rs = run(nmr, ctx, base, probs, "bf16", 2, 3, ("force",) + cfg)
             for k, (r, o) in enumerate(zip(rs, ref)):
-                assert rel(r, o) < 3e-2, (cfg, k, rel(r, o))
+                close(r, o, 3e-2, (cfg, k, rel(r, o)))
     finally:
         ctx.close()
 
@@ -130,10 +126,10 @@ def test_jet_groups_are_bitwise_the_whole_tile(nmr, n_q, prec, form):
                     if n_q <= 15:
                         np.testing.assert_array_equal(a, b)
                     else:
-                        assert rel(a, b) < 1e-4
+                        close(a, b, 1e-4, 'a')
         if prec == "fp32":
             for (r, _, _), o in zip(grouped, oracle_states(probs, 2, 3)):
-                assert rel(r, o) < 1e-4
+                close(r, o, 1e-4, 'r')
     finally:
         ctx.close()
 
@@ -152,7 +148,7 @@ def test_tall_tiles_at_headline_shape(nmr):
         for cfg in [(4, 2), (4, 4)]:
             rs = run(nmr, ctx, p, probs, "fp32", 1, p.newton_iters, ("force",) + cfg)
             for k in range(8):
-                assert rel(rs[k], rule[k]) < 1e-4, (cfg, k, rel(rs[k], rule[k]))
+                close(rs[k], rule[k], 1e-4, (cfg, k, rel(rs[k], rule[k])))
     finally:
         ctx.close()
 
@@ -169,7 +165,7 @@ def test_autotune_records_eligible_choices(nmr):
             st, _ = nmr.step_many(ctx, insts, 2, 3)
             assert st == [0] * 8
             for x, o in zip(insts, ref):
-                assert rel(x.get_state()[0], o) < 1e-4
+                close(x.get_state()[0], o, 1e-4, 'x.get_state()[0]')
         finally:
             for x in insts:
                 x.close()

@@ -6,17 +6,13 @@ import pytest
 
 from oracle.newton import Instance as OInst
 from paper_2102_11026_amd import synth
+from parity import close, rel
 
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": dict(u=1e-12, J=1e-11, dJ=1e-10, B=1e-10, JTa=1e-11, A=1e-10, phi=1e-10),
        "fp32": dict(u=1e-5, J=1e-4, dJ=1e-3, B=1e-3, JTa=1e-4, A=1e-4, phi=1e-4)}
 
-
-def rel(a, b):
-    a = np.asarray(a, np.float64)
-    b = np.asarray(b, np.float64)
-    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
 @pytest.fixture(scope="module")
@@ -64,15 +60,16 @@ def test_trimmed_decoder_and_system(nmr, ctx, name, prec):
         got = inst.decoder_jacobian_hessian(q, dq, qdot, a)
         ref = oi.decode(q, dq, qdot)
         JTa, B = oi.left(q, a)
-        assert rel(got["J"].cpu(), ref["J"]) < t["J"]
-        assert rel(got["dJ"].cpu(), ref["dJ"]) < t["dJ"]
+        close(got["J"].cpu(), ref["J"], t["J"], "J")
+        close(got["dJ"].cpu(), ref["dJ"], t["dJ"], "dJ")
         assert np.abs(got["Hdd"].cpu().numpy()).max() == 0.0
-        assert rel(got["JTa"].cpu(), JTa) < t["JTa"] and rel(got["B"].cpu(), B) < t["B"]
+        close(got["JTa"].cpu(), JTa, t["JTa"], "JTa")
+        close(got["B"].cpu(), B, t["B"], "B")
         r = p.r0 + rng.normal(size=p.R) * 0.01
         A, phi = inst.newton_system(r)
         sysd = oi.system(r, p.r0, rdot, oi.cubature_weights(p.r0))
-        assert rel(phi.cpu().numpy(), sysd["phi"]) < t["phi"]
-        assert rel(A.cpu().numpy(), sysd["A"]) < t["A"]
+        close(phi.cpu().numpy(), sysd["phi"], t["phi"], "phi")
+        close(A.cpu().numpy(), sysd["A"], t["A"], "A")
     finally:
         inst.close()
 
@@ -86,7 +83,7 @@ def test_trimmed_trajectory_fp64(nmr, ctx):
         for s in range(6):
             inst.step(p.newton_iters, resid=False)
             st, _ = oi.step(st, p.newton_iters)
-            assert rel(inst.get_state()[0], st.rbar) < 1e-9, s
+            close(inst.get_state()[0], st.rbar, 1e-9, s)
     finally:
         inst.close()
 
@@ -104,7 +101,8 @@ def test_trimmed_gram_path_equals_direct_path(nmr, ctx):
             out.append((A.cpu().numpy(), phi.cpu().numpy()))
         finally:
             inst.close()
-    assert rel(out[0][0], out[1][0]) < 1e-11 and rel(out[0][1], out[1][1]) < 1e-11
+    close(out[0][0], out[1][0], 1e-11, "A")
+    close(out[0][1], out[1][1], 1e-11, "phi")
 
 
 def test_fictitious_force_is_needed_for_consistency_in_dt(nmr, ctx):

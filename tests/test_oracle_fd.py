@@ -44,6 +44,20 @@ def test_fd_converges_to_csfd_at_second_order(act):
         assert 70 < ratio < 140, (k, errs[2e-1][k], errs[2e-2][k])
 
 
+def test_elu_decoder_values_and_jacobian_match_the_independent_passes():
+    """ELU (alpha = 1) is C^1 with a jump of its second derivative at 0, so
+    stencils that straddle a kink do not converge at second order; the value
+    and first-order channel still pin the multicomplex ELU against fd.py's
+    plain real passes (np.expm1 on the negative branch): m(q) to rounding and
+    the central-difference Jacobian at h = 1e-5 to its truncation error (a
+    multicomplex ELU without the "- 1" of its negative branch fails the
+    first check)."""
+    p, q, dq, qd, s, ex, B = setup("elu")
+    f = fd.right_contractions_fd(p.weights, p.biases, p.act, q, dq, qd, n_rows=p.N, h=1e-5)
+    assert rel(f["m"], ex["m"]) < 1e-13
+    assert rel(f["J"], ex["J"]) < 1e-8
+
+
 def test_fd_of_a_linear_decoder():
     """Identity activations: the first difference is exact and every higher
     one is zero up to the cancellation of a few ulps."""

@@ -93,3 +93,28 @@ def test_unit_squares_to_minus_one():
             ref = np.zeros(2 ** n)
             ref[0] = -1.0
             np.testing.assert_array_equal(sq, ref)
+
+
+def test_elu_closed_form_values():
+    """ELU with alpha = 1 (Sec. 3.5 activations): exp(x) - 1 for x <= 0 and x
+    for x > 0.  At x = -ln 2 the value is -1/2 and every derivative is
+    exp(-ln 2) = 1/2, so along units i1, i2, i3 of step h the tricomplex
+    components are -1/2, h/2, h^2/2 and h^3/2; dropping the "- 1" of the
+    negative branch, or branching the wrong way, fails this."""
+    h = 1e-5
+    z = mc.real(-np.log(2.0), 3)
+    z[1] = z[2] = z[4] = h          # i1, i2, i3
+    y = mc.elu(z)
+    assert y[0] == pytest.approx(-0.5, rel=1e-9)
+    for comp, k in ((1, 1), (2, 1), (4, 1), (3, 2), (5, 2), (6, 2), (7, 3)):
+        assert y[comp] == pytest.approx(0.5 * h ** k, rel=1e-9), comp
+    # positive branch: the identity, every unit passes through unchanged
+    z = mc.real(0.7, 3)
+    z[1:] = rng.normal(size=7)
+    np.testing.assert_array_equal(mc.elu(z), z)
+    # C^1 at generic parts: exp(a + bi) - 1 in library complex arithmetic
+    a, b = -np.abs(rng.normal(size=20)) - 0.1, rng.normal(size=20)
+    got = mc.elu(np.stack([a, b], axis=-1))
+    ref = np.exp(a + 1j * b) - 1.0
+    np.testing.assert_allclose(got[:, 0], ref.real, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(got[:, 1], ref.imag, rtol=1e-13, atol=1e-15)

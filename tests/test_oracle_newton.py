@@ -165,6 +165,21 @@ def test_wnet_closed_form():
     np.testing.assert_allclose(wnet_weights([W], [b], 1.7, r), 1.7 * np.log1p(np.exp(W @ r + b)), rtol=1e-14)
 
 
+def test_wnet_softplus_after_the_hidden_layer():
+    """Sec. 5.2 weight net with a softplus after every layer: a zero first
+    layer outputs softplus(0) = ln 2 whatever r is, and a second layer of
+    weight 1 maps it to softplus(ln 2) = ln(1 + 2) = ln 3.  A net that skipped
+    the hidden softplus would give softplus(0) = ln 2 instead."""
+    Ws = [np.zeros((1, 4)), np.ones((1, 1))]
+    bs = [np.zeros(1), np.zeros(1)]
+    for _ in range(3):
+        np.testing.assert_allclose(wnet_weights(Ws, bs, 0.8, rng.normal(size=4)), [0.8 * np.log(3.0)], rtol=1e-15)
+    # two hidden units, output weights (1, -1) and bias 2: softplus(ln2 - ln2 + 2)
+    Ws = [np.zeros((2, 3)), np.array([[1.0, -1.0]])]
+    bs = [np.zeros(2), np.array([2.0])]
+    np.testing.assert_allclose(wnet_weights(Ws, bs, 1.0, rng.normal(size=3)), [np.log1p(np.exp(2.0))], rtol=1e-15)
+
+
 # --------------------------------------------------------------------------
 # trimmed formulation: the fictitious force dropped (Sec. 3.3, Sec. 6)
 # --------------------------------------------------------------------------
