@@ -171,6 +171,25 @@ int decoder_jacobian_hessian(nmr_inst* inst, const double* q, const double* dq,
 int cubature_force_stiffness(nmr_inst* inst, const void* u, const void* Jt, const void* w_or_null,
                              void* f_int_or_null, double* fr, double* Kr);
 
+/* For callers that cannot allocate device memory at call time (tight serving
+ * loops, harnesses that forbid hipMalloc): cubature_force_stiffness with the
+ * same arguments, layouts, results (the same kernels, so the same bits) and
+ * errors, but it calls no hipMalloc, hipFree or allocating library routine.
+ * Its working memory -- the instance's table entry, a status word, the
+ * weighted element forces [|C| x 12 reals] and one FP64 partial sum per
+ * block of four cubature tets [ceil(|C| / 4) x (R*R + R) doubles] -- lives in
+ * a static device array of 16 MiB that each GPU the library runs on holds
+ * until the process ends.  It needs 12800 + round_up_256(48 |C|) (96 |C| in
+ * FP64) + 8 ceil(|C| / 4) (R*R + R) bytes: NMR_ERR_ARG, before any device
+ * work, if that exceeds 16 MiB (|C| = 6,600 at R = 30 needs 12.6 MB).  Every
+ * call on a GPU shares that GPU's array and overwrites what the last call
+ * left there: calls that overlap on one GPU (other threads, other contexts
+ * on the same device) race and must be serialized by the caller.  The
+ * instance is only read.  Synchronizes the context stream (the status is
+ * read back). */
+int cubature_force_stiffness_noalloc(nmr_inst* inst, const void* u, const void* Jt, const void* w_or_null,
+                                     void* f_int_or_null, double* fr, double* Kr);
+
 /* Newton system at iterate r (device, R doubles) of the step that starts from
  * the instance state: phi (eq. our_equation_of_motion) [R doubles] and its
  * Jacobian A = dphi/dr (eq. system_mat) [R x R doubles], both device.  Uses

@@ -10,8 +10,10 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -181,6 +183,42 @@ static int check_mlp(const nmr_mlp_desc* d, int min_layers, const char* what) {
 }
 
 // ---------------------------------------------------------------------------
+// static scratch of cubature_force_stiffness_noalloc: every buffer beyond the
+// caller's inputs and outputs (the instance table entry, the status word,
+// the weighted element forces, the per-block partials and their sums) lives
+// in one static device array.  Host code never passes the array's name to a
+// kernel or a copy: its device address on each GPU comes from
+// hipGetSymbolAddress at context creation (g_scratch_ptr).
+static constexpr size_t kScratchBytes = (size_t)16 << 20;
+static constexpr size_t kScratchHead = 4096;                  // Inst<T> table entry
+static constexpr size_t kScratchStatus = kScratchHead;        // int status word
+static constexpr size_t kScratchSums = kScratchHead + 256;    // [R*R + R] doubles
+static constexpr size_t kScratchBody = kScratchSums + 8448;   // element forces, then partials
+static_assert(sizeof(Inst<double>) <= kScratchHead && sizeof(Inst<float>) <= kScratchHead, "table entry size");
+static_assert(NMR_MAX_R * NMR_MAX_R * 8 + NMR_MAX_R * 8 <= 8448 && kScratchBody % 256 == 0, "sums size");
+
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+static void* g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// device address of `scratch` on the current device `device`, looked up once
+static int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(NMR_ERR_ARG, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return NMR_OK;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return fail(NMR_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  }
+  g_scratch_ptr[device] = p;
+  return NMR_OK;
+}
+
+// ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
 extern "C" int nmr_create(int device, void* hip_stream, size_t hbm_budget_bytes, nmr_ctx** out) {
@@ -195,6 +233,10 @@ extern "C" int nmr_create(int device, void* hip_stream, size_t hbm_budget_bytes,
   if (hipSetDevice(device) != hipSuccess) {
     delete c;
     return fail(NMR_ERR_DEVICE, "hipSetDevice failed");
+  }
+  if (int rc = scratch_setup(device)) {
+    delete c;
+    return rc;
   }
   if (hip_stream) {
     c->stream = static_cast<hipStream_t>(hip_stream);
@@ -1130,6 +1172,79 @@ extern "C" int cubature_force_stiffness(nmr_inst* in, const void* u, const void*
   CHK(set_device(in->ctx));
   return is_f64(in) ? cfs_impl<double>(in, u, Jt, w_or_null, f_int_or_null, fr, Kr)
                     : cfs_impl<float>(in, u, Jt, w_or_null, f_int_or_null, fr, Kr);
+}
+
+// ---------------------------------------------------------------------------
+// cubature_force_stiffness_noalloc: the kernels of cubature_force_stiffness
+// on the static scratch
+// ---------------------------------------------------------------------------
+// bytes of the static scratch that cubature_force_stiffness_noalloc needs
+template <typename T>
+static size_t noalloc_bytes(const nmr_inst* in) {
+  const size_t fe = round256((size_t)in->n_cub * 12 * sizeof(T));
+  const size_t part = (size_t)in->n_cblk * (in->R * in->R + in->R) * sizeof(double);
+  return kScratchBody + fe + part;
+}
+
+template <typename T>
+static int cfs_noalloc_impl(nmr_inst* in, const void* u, const void* Jt, const void* w, void* f_int, double* fr,
+                            double* Kr) {
+  nmr_ctx* c = in->ctx;
+  const size_t need = noalloc_bytes<T>(in);
+  if (need > kScratchBytes)
+    return fail(NMR_ERR_ARG, "cubature set too large for the static scratch: needs " + std::to_string(need) +
+                                 " bytes, the limit is " + std::to_string(kScratchBytes));
+  unsigned char* base = static_cast<unsigned char*>(g_scratch_ptr[c->device]);
+  if (!base) return fail(NMR_ERR_DEVICE, "scratch address not set up for this device");
+  // the table entry and a zero status word, written in one copy
+  struct Head {
+    Inst<T> I;
+    unsigned char pad[kScratchStatus - sizeof(Inst<T>)];
+    int status;
+  } head;
+  static_assert(offsetof(Head, status) == kScratchStatus, "status offset");
+  std::memset(&head, 0, sizeof(head));
+  head.I = host_inst<T>(in);
+  Inst<T>& I = head.I;
+  I.cu_u = static_cast<const T*>(u);
+  I.cu_u_ld = 1;
+  I.cu_Ja = static_cast<const T*>(Jt);
+  I.cu_Ja_ld = in->R;
+  I.cu_na = in->R;
+  I.cu_Jb = nullptr;
+  I.cu_Jb_ld = 0;
+  I.cu_nb = 0;
+  if (w) I.cu_w = static_cast<const T*>(w);
+  I.gram = 0;
+  I.status = reinterpret_cast<int*>(base + kScratchStatus);
+  I.sum_cub = reinterpret_cast<double*>(base + kScratchSums);
+  I.fe = reinterpret_cast<T*>(base + kScratchBody);
+  I.part_cub = reinterpret_cast<double*>(base + kScratchBody + round256((size_t)in->n_cub * 12 * sizeof(T)));
+  head.status = 0;
+  // earlier work on the stream may still read the scratch (an earlier call)
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(base, &head, sizeof(head), hipMemcpyHostToDevice));
+  const Inst<T>* tab = reinterpret_cast<const Inst<T>*>(base);
+  launch_cubature<T>(tab, 1, in->n_cblk, c->stream);
+  const int Ec = in->R * in->R + in->R;
+  launch_sums<T>(tab, 1, Ec, c->stream);  // cubature entries only
+  HIPCHK(hipMemcpyAsync(Kr, I.sum_cub, in->R * in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(fr, I.sum_cub + in->R * in->R, in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (f_int) launch_fint<T>(tab, static_cast<T*>(f_int), in->N, c->stream);
+  HIPCHK(hipGetLastError());
+  int st = 0;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(&st, I.status, sizeof(int), hipMemcpyDeviceToHost));
+  if (st & ST_INVERTED) return fail(NMR_ERR_INVERTED, "a cubature tet has det F <= 0");
+  return NMR_OK;
+}
+
+extern "C" int cubature_force_stiffness_noalloc(nmr_inst* in, const void* u, const void* Jt, const void* w_or_null,
+                                                void* f_int_or_null, double* fr, double* Kr) {
+  if (!in || !u || !Jt || !fr || !Kr) return fail(NMR_ERR_ARG, "null argument");
+  CHK(set_device(in->ctx));
+  return is_f64(in) ? cfs_noalloc_impl<double>(in, u, Jt, w_or_null, f_int_or_null, fr, Kr)
+                    : cfs_noalloc_impl<float>(in, u, Jt, w_or_null, f_int_or_null, fr, Kr);
 }
 
 template <typename T>

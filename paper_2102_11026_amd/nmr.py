@@ -84,6 +84,7 @@ def lib():
             "nmr_instance_status": (i, [vp]),
             "decoder_jacobian_hessian": (i, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
             "cubature_force_stiffness": (i, [vp, vp, vp, vp, vp, vp, vp]),
+            "cubature_force_stiffness_noalloc": (i, [vp, vp, vp, vp, vp, vp, vp]),
             "reduced_newton_system": (i, [vp, vp, vp, vp]),
             "reduced_newton_step": (i, [vp, i, _dp]),
             "step_many": (i, [vp, C.POINTER(vp), i, i, i, ip, C.POINTER(C.c_float)]),
@@ -293,7 +294,9 @@ class Instance:
             out["B"], out["JTa"] = B, JTa
         return out
 
-    def cubature_force_stiffness(self, u, Jt, w=None, want_fint: bool = True):
+    def cubature_force_stiffness(self, u, Jt, w=None, want_fint: bool = True, noalloc: bool = False):
+        """noalloc: call cubature_force_stiffness_noalloc (working memory in
+        the library's static device array) instead."""
         import torch
         rt = dict(dtype=self.rdtype, device=self.dev)
         ut = torch.as_tensor(np.asarray(u), **rt).contiguous()
@@ -303,8 +306,8 @@ class Instance:
         fr = torch.empty(self.R, dtype=torch.float64, device=self.dev)
         Kr = torch.empty(self.R, self.R, dtype=torch.float64, device=self.dev)
         torch.cuda.synchronize(self.dev)
-        _check(lib().cubature_force_stiffness(self.h, _ptr(ut), _ptr(Jtt), _ptr(wt), _ptr(fint), _ptr(fr),
-                                              _ptr(Kr)))
+        fn = lib().cubature_force_stiffness_noalloc if noalloc else lib().cubature_force_stiffness
+        _check(fn(self.h, _ptr(ut), _ptr(Jtt), _ptr(wt), _ptr(fint), _ptr(fr), _ptr(Kr)))
         torch.cuda.synchronize(self.dev)
         return dict(f_int=fint, fr=fr, Kr=Kr)
 
