@@ -128,7 +128,7 @@ def phase_roofline(p, phase: str, us: float, prec: str, gram: bool):
     peak_tf = BF16_MFMA_PEAK_TFLOPS if prec == "bf16" else FP32_MFMA_PEAK_TFLOPS
     ridge = peak_tf * 1e12 / (HBM_PEAK_GBS * 1e9)
     traffic = None
-    if prec == "fp32" and kernel_sources_digest() == MEASURED_TRAFFIC_SOURCES:
+    if prec == "fp32" and gram and kernel_sources_digest() == MEASURED_TRAFFIC_SOURCES:
         traffic = MEASURED_TRAFFIC.get(PHASE_KERNEL[phase])
     common = dict(traffic=traffic, traffic_unit="bytes per launch", kernel=PHASE_KERNEL[phase], phase=phase,
                   launches_per_pass=launches,
@@ -182,29 +182,27 @@ def run_steps(nmr, ctx, insts, steps: int, warmup: int):
     return t1 - t0, np.asarray(ms)
 
 
-def cpu_baseline(p, seconds: float):
+def cpu_baseline(p, seconds: float, threads: int = 0):
     """The FP64 oracle, untuned, on this host's cores: Newton iterations of the
-    same problem from its initial state until about `seconds` have passed.
-    Returns the baseline record, the number of steps and the oracle's state."""
-    from threadpoolctl import threadpool_info
+    same problem from its initial state until about `seconds` have passed
+    (threads > 0: with the BLAS pools limited to that many threads)."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle.newton import Instance as OracleInstance
     oi = OracleInstance(p)
     st = oi.initial_state()
     n = 0
-    first = None
-    t0 = time.perf_counter()
-    while True:
-        st, _ = oi.step(st, ITERS)
-        n += ITERS
-        first = first or st
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    rec = dict(value=round(n / dt, 4), unit="Newton iters/s", cores=int(threads), kind="oracle",
-               sample=f"first {n // ITERS} implicit-Euler steps x {ITERS} Newton iterations of the same "
-                      f"10k-vertex problem (FP64 numpy/BLAS oracle), {dt:.1f} s")
-    return rec, n // ITERS, oi, first, st
+    with threadpool_limits(limits=threads if threads > 0 else None):
+        used = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        t0 = time.perf_counter()
+        while True:
+            st, _ = oi.step(st, ITERS)
+            n += ITERS
+            if time.perf_counter() - t0 > seconds:
+                break
+        dt = time.perf_counter() - t0
+    return dict(value=round(n / dt, 4), unit="Newton iters/s", cores=int(used), kind="oracle",
+                sample=f"first {n // ITERS} implicit-Euler steps x {ITERS} Newton iterations of the same "
+                       f"10k-vertex problem (FP64 numpy/BLAS oracle), {dt:.1f} s")
 
 
 def rel(a, b) -> float:
@@ -213,38 +211,63 @@ def rel(a, b) -> float:
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def precision_report(nmr, ctx, p, oi, steps: int, first, last):
-    """FP32 and BF16 forms against the FP64 oracle: the state r after the
-    first step (the bar still moving) and after the oracle's last step (close
-    to rest, where the error is the precision of the equilibrium), the
-    displacement u there, and J (Frobenius) and phi (relative to ||phi|| at
-    the start of the step) and A at a perturbed initial state."""
+GOLDEN = os.path.join(ROOT, "tests", "golden", "bar10k_trajectory_fp64.npz")
+
+
+def precision_report(nmr, ctx, p):
+    """FP32 and BF16 forms against the FP64 oracle.
+
+    Trajectory: 100 steps x 4 Newton iterations against the stored oracle
+    trajectory (tests/golden/make_bar10k_trajectory.py, written by the oracle
+    alone).  The bar comes to rest within a few steps, so errors are
+    normalised by the trajectory's largest magnitude: max_t |r - r_or| /
+    max_t |r_or| (every step), and |u - u_or| / max_t |u_or| for u after
+    steps 1, 10 and 100 and for the frames steps 2 and 11 emit (those of
+    steps 1 and 10).
+    Newton system: J (Frobenius) at the initial state, and phi (relative to
+    |phi| at the start of the step, evaluated at the same iterate) and A at
+    a perturbed initial state, the oracle evaluated live."""
     import torch
+    from oracle.newton import Instance as OracleInstance
+    g = np.load(GOLDEN)
+    oi = OracleInstance(p)
     rng = np.random.default_rng(7)
     r1 = p.r0 + rng.normal(size=p.R) * 0.005
     w0 = oi.cubature_weights(p.r0)
     sys_o = oi.system(r1, p.r0, p.rdot0, w0)
     phi0 = np.linalg.norm(oi.system(p.r0, p.r0, p.rdot0, w0)["phi"])
-    u_o = oi.displacement(last.rbar)
     zeros = np.zeros(p.n_q)
     dec_o = oi.decode(p.r0[p.n_p:], zeros, zeros)
-    rep = dict(steps=steps, newton_iters_per_step=ITERS, r_norm_first_step=float(np.linalg.norm(first.rbar)),
-               r_norm_last_step=float(np.linalg.norm(last.rbar)))
+    steps = g["rbar"].shape[0] - 1
+    rmax = float(np.linalg.norm(g["rbar"], axis=1).max())
+    umax = float(g["u_norm"].max())
+    ustep = {int(t): g["u"][k] for k, t in enumerate(g["u_steps"])}
+    rep = dict(steps=steps, newton_iters_per_step=ITERS, source="tests/golden/bar10k_trajectory_fp64.npz",
+               r_norm_max=rmax, r_norm_last=float(np.linalg.norm(g["rbar"][-1])), u_norm_max=umax)
     for prec in ("fp32", "bf16"):
         x = nmr.Instance(ctx, p, prec)
         try:
             A, phi = x.newton_system(r1)
             J = x.decoder_jacobian_hessian(p.r0[p.n_p:], zeros, zeros)["J"].cpu().numpy()
-            st1, _ = nmr.step_many(ctx, [x], 1, ITERS)
-            ra, _ = x.get_state()
-            st, _ = nmr.step_many(ctx, [x], steps - 1, ITERS)
-            r, _, u = x.get_state(with_u=True)
+            r_err, u_err, f_err, status = 0.0, {}, {}, 0
+            for t in range(1, steps + 1):
+                st, _ = nmr.step_many(ctx, [x], 1, ITERS)
+                status = status or st[0]
+                if t - 1 in ustep and t - 1 > 0:
+                    f_err[t - 1] = float(np.linalg.norm(x.get_frame() - ustep[t - 1]) / umax)
+                if t in ustep:
+                    r, _, u = x.get_state(with_u=True)
+                    u_err[t] = float(np.linalg.norm(u - ustep[t]) / umax)
+                else:
+                    r, _ = x.get_state()
+                r_err = max(r_err, float(np.linalg.norm(r - g["rbar"][t]) / rmax))
             torch.cuda.synchronize()
         finally:
             x.close()
-        rep[prec] = dict(status=max(st1[0], st[0], key=abs), r_rel_first_step=rel(ra, first.rbar),
-                         r_rel_last_step=rel(r, last.rbar), r_abs_last_step=float(np.linalg.norm(r - last.rbar)),
-                         u_rel_last_step=rel(u, u_o), J_rel=rel(J, dec_o["J"]),
+        rep[prec] = dict(status=int(status), r_err_max_over_steps=r_err,
+                         u_err_at_step={str(k): v for k, v in u_err.items()},
+                         frame_err_at_step={str(k): v for k, v in f_err.items()},
+                         J_rel=rel(J, dec_o["J"]),
                          phi_rel_to_phi0=float(np.linalg.norm(phi.cpu().numpy() - sys_o["phi"]) / phi0),
                          A_rel=rel(A.cpu().numpy(), sys_o["A"]))
     return rep
@@ -331,7 +354,9 @@ def main():
                p50_step_ms=round(float(np.percentile(ms, 50)), 4),
                p99_step_ms=round(float(np.percentile(ms, 99)), 4),
                frame_budget_ms=round(FRAME_BUDGET_MS, 2),
-               frames_per_s=round(args.steps / secs, 2))
+               frames_per_s=round(args.steps / secs, 2),
+               frame_output="each timed step writes the full-space displacement u (30,000 DOFs) of the frame it "
+                            "starts from into the instance's frame buffer, inside the same graph launch")
     # per-phase device time (HIP events on the library's stream)
     phases = {}
     for k, name in enumerate(nmr.PHASES):
@@ -341,6 +366,8 @@ def main():
     cand = {k: v for k, v in phases.items() if k in PHASE_KERNEL}
     dom = max(cand, key=cand.get)
     out["roofline"] = phase_roofline(p, dom, phases[dom], "fp32", gram)
+    out["roofline"]["timing"] = ("HIP events on the library's stream around 50 replays of the phase's launches "
+                                 "(nmr_time_phase), divided by the launches per pass")
     out["phase_rooflines"] = {k: phase_roofline(p, k, phases[k], "fp32", gram) for k in PHASE_KERNEL}
     out["newton_path"] = "gram-folded" if gram else "direct"
     log("phases (us):", phases)
@@ -355,6 +382,20 @@ def main():
         bphase = {name: round(ib.time_phase(k, reps=50), 3) for k, name in enumerate(nmr.PHASES)}
         var["plain_bf16"]["phase_us"] = bphase
         ib.close()
+        # the direct Newton path: every one of the 30,000 output rows decoded in every iteration
+        idr = nmr.Instance(ctx, p, "fp32", path="direct")
+        nd = max(args.steps // 2, 10)
+        s_d, ms_d = run_steps(nmr, ctx, [idr], nd, 3)
+        dphase = {name: round(idr.time_phase(k, reps=50), 3) for k, name in enumerate(nmr.PHASES)}
+        var["plain_fp32_direct_path"] = dict(newton_iters_per_s=round(ITERS * nd / s_d, 2),
+                                             p99_step_ms=round(float(np.percentile(ms_d, 99)), 4),
+                                             phase_us=dphase,
+                                             dec_out_roofline=phase_roofline(p, "dec_out", dphase["dec_out"],
+                                                                             "fp32", False),
+                                             bwd_out_roofline=phase_roofline(p, "bwd_out", dphase["bwd_out"],
+                                                                             "fp32", False))
+        idr.close()
+        log("direct path:", var["plain_fp32_direct_path"])
         for prec in ("fp32", "bf16"):
             dec = nmr.Decoder(ctx, p.weights, p.biases, p.act, prec)
             for B in args.batch:
@@ -420,10 +461,10 @@ def main():
     inst.close()
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
-        rec, o_steps, oi, o_first, o_last = cpu_baseline(p, args.cpu_seconds)
-        out["cpu_baseline"] = rec
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        out["cpu_baseline_1thread"] = cpu_baseline(p, args.cpu_seconds, threads=1)
         log("precision forms against the oracle")
-        out["precision_vs_oracle"] = precision_report(nmr, ctx, p, oi, o_steps, o_first, o_last)
+        out["precision_vs_oracle"] = precision_report(nmr, ctx, p)
     ctx.close()
     print(json.dumps(out), flush=True)
 

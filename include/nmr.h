@@ -139,9 +139,22 @@ int nmr_instance_bytes(const nmr_inst* inst, size_t* bytes);
  * (only the DOFs of cubature tets decoded per iteration), 1 = direct. */
 int nmr_instance_newton_path(const nmr_inst* inst, int* path);
 /* Host buffers: r and rdot (R doubles each) of the last completed step; u
- * (N reals, may be NULL) is the full-space displacement u = U p + D(q).
- * Synchronizes. */
+ * (N reals, may be NULL) is the full-space displacement u = U p + D(q)
+ * (Sec. 3.6, eq. our_subspace) at that r, decoded into the instance's frame
+ * buffer (see nmr_instance_get_frame) and copied from there.  Synchronizes. */
 int nmr_instance_get_state(nmr_inst* inst, double* r, double* rdot, void* u_or_null);
+/* Frame output.  Every implicit-Euler step (Sec. 3.2) starts its Newton
+ * iteration at r = rbar, the state the previous step ended in, so its first
+ * decoder pass already evaluates D at that frame's state: the step writes
+ * that frame's full-space displacement u = U p + D(q) [N reals] into the
+ * instance's frame buffer (the value channel through every row of the output
+ * layer), as part of the same graph launch.  After a step, the buffer holds
+ * the frame the step started from; after nmr_instance_get_state with u, the
+ * frame of the current state.  get_frame copies it to a host buffer u [N
+ * reals] (synchronizes); frame_ptr returns its device address (valid until
+ * the instance is destroyed; read it after the context stream's work). */
+int nmr_instance_get_frame(nmr_inst* inst, void* u);
+int nmr_instance_frame_ptr(nmr_inst* inst, void** u_dev);
 /* Host buffers: sets (rbar, rdot_bar) and clears a failed status. */
 int nmr_instance_set_state(nmr_inst* inst, const double* r, const double* rdot);
 /* Status of the last step (nmr_status); synchronizes. */

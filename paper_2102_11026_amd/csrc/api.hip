@@ -432,6 +432,7 @@ static size_t instance_bytes(const Sizes& s, const DecoderDev& d) {
   }
   add((s.R * s.R + s.R) * 8); add((s.R * s.R + s.R * s.n_q + s.R + s.n_p) * 8);
   add(s.n_q * s.n_q * 8); add(s.n_q * 8);
+  add((size_t)s.N * sizeof(T));  // frame
   add(s.R * s.R * 8);
   return b;
 }
@@ -581,6 +582,7 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   CHK(dalloc_t(M, s.R * s.R + s.R * s.n_q + s.R + s.n_p, &I.sum_mass));
   CHK(dalloc_t(M, s.n_q * s.n_q, &I.Bq));
   CHK(dalloc_t(M, s.n_q, &I.JTa));
+  CHK(dalloc_t(M, s.N, &I.frame));
   CHK(dalloc_t(M, s.R * s.R, &in->A_scratch));
   // cubature sources: the Newton path reads the decoder records
   I.cu_u = I.rec; I.cu_u_ld = s.Cf;
@@ -836,6 +838,9 @@ template <typename T>
 static void enqueue_iteration(const Group& g, int iter, int mode, double* A_out, double* phi_out, hipStream_t s) {
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
   enqueue_decoder_fwd<T>(g, s, 1);
+  // a step's first iteration runs the decoder at r = rbar, the state the
+  // step starts from: its value channel is that frame's displacement
+  if (iter == 0 && (mode & SOLVE_UPDATE)) launch_frame<T>(g.dec->d, tab, g.nb, g.maxN, s);
   if (g.gram && g.nb < kShareLaunchMax) {
     // the Gram terms need only the folded activations and the state, and the
     // output-layer seed only the element forces: each pair is one launch
@@ -1274,23 +1279,38 @@ static int get_state_impl(nmr_inst* in, double* r, double* rdot, void* u) {
   if (r) HIPCHK(hipMemcpy(r, I.rbar, in->R * sizeof(double), hipMemcpyDeviceToHost));
   if (rdot) HIPCHK(hipMemcpy(rdot, I.rdot, in->R * sizeof(double), hipMemcpyDeviceToHost));
   if (u) {
-    // decode at rbar: r <- rbar, decoder input (qbar, 0, rdot_bar), u = U p + D(q)
+    // decode the frame at rbar: r <- rbar, decoder input (qbar, 0, rdot_bar),
+    // the instance's own forward pass, then u = U p + D(q) into its frame buffer
     HIPCHK(hipMemcpyAsync(I.r, I.rbar, in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    void* dt_tab;
-    CHK(direct_tab<T>(in, &dt_tab));
-    launch_step_begin<T>(static_cast<const Inst<T>*>(dt_tab), 1, BEGIN_SYSTEM, in->n_cub, c->stream);
+    const Inst<T>* tab = static_cast<const Inst<T>*>(in->tab);
+    launch_step_begin<T>(tab, 1, BEGIN_SYSTEM, in->n_cub, c->stream);
     std::vector<nmr_inst*> v{in};
-    Group g = group_of(v, dt_tab);
-    g.gram = false;
+    Group g = group_of(v, in->tab);
     enqueue_decoder_fwd<T>(g, c->stream, 1);
-    T* du;
-    HIPCHK(hipMalloc(&du, in->N * sizeof(T)));
-    launch_unpack<T>(static_cast<const Inst<T>*>(dt_tab), du, nullptr, nullptr, nullptr, in->N, c->stream);
-    hipError_t e = hipStreamSynchronize(c->stream);
-    if (e == hipSuccess) e = hipMemcpy(u, du, in->N * sizeof(T), hipMemcpyDeviceToHost);
-    (void)hipFree(du);
-    if (e != hipSuccess) return fail(NMR_ERR_DEVICE, hipGetErrorString(e));
+    launch_frame<T>(g.dec->d, tab, 1, in->N, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    HIPCHK(hipMemcpy(u, I.frame, in->N * sizeof(T), hipMemcpyDeviceToHost));
   }
+  return NMR_OK;
+}
+
+template <typename T>
+static int get_frame_impl(nmr_inst* in, void* u) {
+  HIPCHK(hipStreamSynchronize(in->ctx->stream));
+  HIPCHK(hipMemcpy(u, host_inst<T>(in).frame, in->N * sizeof(T), hipMemcpyDeviceToHost));
+  return NMR_OK;
+}
+
+extern "C" int nmr_instance_get_frame(nmr_inst* in, void* u) {
+  if (!in || !u) return fail(NMR_ERR_ARG, "null argument");
+  CHK(set_device(in->ctx));
+  return is_f64(in) ? get_frame_impl<double>(in, u) : get_frame_impl<float>(in, u);
+}
+
+extern "C" int nmr_instance_frame_ptr(nmr_inst* in, void** u_dev) {
+  if (!in || !u_dev) return fail(NMR_ERR_ARG, "null argument");
+  *u_dev = is_f64(in) ? (void*)host_inst<double>(in).frame : (void*)host_inst<float>(in).frame;
   return NMR_OK;
 }
 

@@ -1260,6 +1260,58 @@ __global__ void k_unpack(const Inst<T>* __restrict__ tab, T* u, T* J, T* dJ, T* 
 }
 
 // ---------------------------------------------------------------------------
+// Frame output: the full-space displacement u of the state the forward pass
+// was run at (dq = 0 there, so the value channel is u itself).  Gram path
+// (n_p = 0): u_i = keep_i (W_L[i,:] . fold_value + b_i) for every DOF, a
+// memory-bound GEMV; 16 lanes per row, each reading 4 consecutive K entries
+// per step (one 64-entry K slice per step across the 16 lanes), then a
+// butterfly sum within the 16 lanes.  Direct path: the records already hold
+// u = U p + D(q) in their value channel.
+// ---------------------------------------------------------------------------
+template <typename T, typename TW>
+__global__ __launch_bounds__(256) void k_frame(LayerArgs la, const Inst<T>* __restrict__ tab) {
+  const Inst<T>& I = tab[blockIdx.y];
+  const int active = I.active, gram = I.gram, N = I.N, Cf = I.Cf;
+  const T* fold = I.fold;
+  const T* rec = I.rec;
+  const T* keep = I.keep;
+  T* frame = I.frame;
+  const int K = la.m_inp;
+  load_now(active, gram, N, Cf, fold, rec, keep, frame, K, la.W, la.b);
+  if (!active) return;
+  if (!gram) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < N) stg<T>(frame + i, ldg<T>(rec + (size_t)i * Cf));
+    return;
+  }
+  const int row = blockIdx.x * 16 + (threadIdx.x >> 4), j = threadIdx.x & 15;
+  if (blockIdx.x * 16 >= N) return;  // uniform over the block
+  const int rr = min(row, N - 1);
+  const TW* w = reinterpret_cast<const TW*>(la.W) + (size_t)rr * K;
+  typedef typename std::conditional<std::is_same<T, double>::value, double, float>::type Acc;
+  Acc acc = Acc(0);
+  for (int k = 4 * j; k < K; k += 64) {
+    typedef typename vec4<T>::type V4;
+    const V4 x = ldg<V4>(fold + k);
+    Acc w0, w1, w2, w3;
+    if constexpr (std::is_same<TW, __bf16>::value) {
+      const bf16x4 v = ldg<bf16x4>(w + k);
+      w0 = (Acc)(float)v[0]; w1 = (Acc)(float)v[1]; w2 = (Acc)(float)v[2]; w3 = (Acc)(float)v[3];
+    } else {
+      const V4 v = ldg<V4>(w + k);
+      w0 = v.x; w1 = v.y; w2 = v.z; w3 = v.w;
+    }
+    acc += w0 * (Acc)x.x + w1 * (Acc)x.y + w2 * (Acc)x.z + w3 * (Acc)x.w;
+  }
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 16);
+  if (j == 0 && row < N) {
+    const T b = ldg<T>(reinterpret_cast<const T*>(la.b) + row);
+    stg<T>(frame + row, (T)((acc + (Acc)b) * (Acc)ldg<T>(keep + row)));
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 #define NCB_SWITCH(ncb, CALL) \
@@ -1538,6 +1590,17 @@ template <>
 void launch_bwd_hidden<double>(const DecoderDev& d, int l, const Inst<double>* tab, int nb, int cb, bool fd,
                                TileCfg, hipStream_t s) {
   bwd_hidden_dispatch<double, double>(d, l, tab, nb, cb, fd, TileCfg{1, 1}, s);
+}
+
+template <>
+void launch_frame<float>(const DecoderDev& d, const Inst<float>* tab, int nb, int max_n, hipStream_t s) {
+  dim3 grid((max_n + 15) / 16, nb);
+  if (d.prec == PREC_BF16) k_frame<float, __bf16><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab);
+  else k_frame<float, float><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab);
+}
+template <>
+void launch_frame<double>(const DecoderDev& d, const Inst<double>* tab, int nb, int max_n, hipStream_t s) {
+  k_frame<double, double><<<dim3((max_n + 15) / 16, nb), 256, 0, s>>>(layer_args(d, d.L - 1), tab);
 }
 
 template <typename T>

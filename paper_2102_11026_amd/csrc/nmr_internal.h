@@ -9,6 +9,7 @@
 //   rec     [N][Cf]          one record per DOF: u, J (n_q), dJ (n_q), Hdd
 //   seed    [N]              P a, the backpropagation seed
 //   zb      [2][Cb][Wmax]    adjoints of the hidden layers, ping-pong
+//   frame   [N]              u of the frame decoded last
 // Jet channels of the forward pass (multicomplex units taken to the h -> 0
 // limit, i.e. each component stored divided by h^order):
 //   0 value, 1 along dq (i2 = i3), 2 along qdot_bar (i4), 3 along (dq, dq),
@@ -109,6 +110,7 @@ struct Inst {
   double* sum_mass;        // [R*R + R*n_q + R + n_p]
   double* Bq;              // [n_q][n_q] a . H, column j from perturbation j
   double* JTa;             // [n_q]
+  T* frame;                // [N] u = U p + D(q) of the frame decoded last
   // Gram-folded Newton path (n_p == 0): with the linear output layer W_L and
   // the constant lumped mass, Jt^T M Jt = F_J^T Gam F_J etc. over the folded
   // activations F; only the DOFs of cubature tets are decoded per iteration
@@ -288,6 +290,11 @@ void launch_bwd_hidden(const DecoderDev& d, int l, const Inst<T>* tab, int nb, i
                        hipStream_t s);
 template <typename T>
 void launch_unpack(const Inst<T>* tab, T* u, T* J, T* dJ, T* Hdd, int N, hipStream_t s);
+// the frame's displacement from the forward pass just run: Gram path, the
+// value channel of the folded activations through every row of the output
+// layer; direct path, the value channel of the records (filtered, U p added)
+template <typename T>
+void launch_frame(const DecoderDev& d, const Inst<T>* tab, int nb, int max_n, hipStream_t s);
 
 // ---- launchers (sim.hip) -----------------------------------------------
 template <typename T>

@@ -82,6 +82,8 @@ def lib():
             "nmr_instance_get_state": (i, [vp, _dp, _dp, vp]),
             "nmr_instance_set_state": (i, [vp, _dp, _dp]),
             "nmr_instance_status": (i, [vp]),
+            "nmr_instance_get_frame": (i, [vp, vp]),
+            "nmr_instance_frame_ptr": (i, [vp, C.POINTER(vp)]),
             "decoder_jacobian_hessian": (i, [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
             "cubature_force_stiffness": (i, [vp, vp, vp, vp, vp, vp, vp]),
             "cubature_force_stiffness_noalloc": (i, [vp, vp, vp, vp, vp, vp, vp]),
@@ -254,6 +256,19 @@ class Instance:
         _check(lib().nmr_instance_get_state(self.h, r.ctypes.data_as(_dp), rd.ctypes.data_as(_dp),
                                             None if u is None else u.ctypes.data))
         return (r, rd, u) if with_u else (r, rd)
+
+    def get_frame(self):
+        """The frame buffer (host copy): u of the state the last step started
+        from, or of the current state after get_state(with_u=True)."""
+        u = np.zeros(self.N, dtype=np.float64 if self.prec == "fp64" else np.float32)
+        _check(lib().nmr_instance_get_frame(self.h, u.ctypes.data))
+        return u
+
+    def frame_ptr(self) -> int:
+        """Device address of the frame buffer (N reals)."""
+        p = C.c_void_p()
+        _check(lib().nmr_instance_frame_ptr(self.h, C.byref(p)))
+        return p.value
 
     def set_state(self, r, rdot):
         r = np.ascontiguousarray(r, np.float64)

@@ -194,7 +194,8 @@ def test_class_c_hidden_widths_decoder_against_oracle(nmr, ctx, prec):
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-3), ("bf16", 5e-2)])
 def test_bar10k_100_steps_against_stored_oracle_trajectory(nmr, ctx, prec, tol):
     """100 steps x 4 Newton iterations of the 10k-vertex bar.  The state after
-    every step, and u after steps 1, 10 and 100, are compared element-wise
+    every step, u after steps 1, 10 and 100, and the frames that steps 2 and
+    11 emit (those of steps 1 and 10), are compared element-wise
     against the stored FP64 oracle trajectory, relative to the largest
     magnitude along it (the bar comes to rest under gravity within a few
     steps, where relative errors of a near-zero state say nothing)."""
@@ -210,6 +211,9 @@ def test_bar10k_100_steps_against_stored_oracle_trajectory(nmr, ctx, prec, tol):
             assert st == [0]
             r, _ = inst.get_state()
             worst_r = max(worst_r, close_scaled(r, g["rbar"][t], tol, rmax, (prec, "r", t)))
+            if t - 1 in (1, 10):                         # the frame the step started from
+                ref = g["u"][list(g["u_steps"]).index(t - 1)]
+                close_scaled(inst.get_frame(), ref, tol, float(np.abs(g["u"]).max()), (prec, "frame", t - 1))
             if t in g["u_steps"]:
                 _, _, u = inst.get_state(with_u=True)
                 ref = g["u"][list(g["u_steps"]).index(t)]

@@ -129,6 +129,34 @@ def test_newton_system(nmr, ctx, name, prec):
         inst.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", list(PROBS))
+def test_step_emits_the_frame_it_starts_from(nmr, ctx, name, prec):
+    """Every step writes u = U p + D(q) of the state it starts from (its first
+    Newton iteration decodes at r = rbar) into the instance's frame buffer:
+    the value channel through every output row (Gram path) or the filtered
+    records plus U p (direct path, n_p > 0).  The first frame is a decode at
+    the exact initial state (the decoder's u bound); later ones carry the
+    trajectory's error (the bound on u after a run)."""
+    p = PROBS[name]
+    tol_decode, tol_run = TOL[prec]["u"], {"fp64": 1e-9, "fp32": 1e-3}[prec]
+    inst = nmr.Instance(ctx, p, prec)
+    try:
+        oi = OInst(p)
+        st = oi.initial_state()
+        for s in range(3):
+            u_ref = oi.displacement(st.rbar)
+            inst.step(p.newton_iters, resid=False)
+            close(inst.get_frame(), u_ref, tol_decode if s == 0 else tol_run, (name, prec, "frame", s))
+            st, _ = oi.step(st, p.newton_iters)
+        # get_state with u decodes the current state into the same buffer
+        r, rd, u = inst.get_state(with_u=True)
+        close(u, oi.displacement(st.rbar), tol_run, (name, prec, "u"))
+        np.testing.assert_array_equal(inst.get_frame(), u)
+    finally:
+        inst.close()
+
+
 def test_trajectory_plain_fp64(nmr, ctx):
     """20 steps x 3 Newton iterations of the 192-vertex bar in FP64 mode."""
     p = PROBS["bar192"]
