@@ -104,8 +104,12 @@ class Instance:
         return dec.left_contraction(p.weights, p.biases, p.act, q, s, h=self.h)
 
     # -- one Newton linearisation ------------------------------------------
-    def system(self, r, rbar, rdot_bar, w):
-        """phi(r), dphi/dr and intermediates at iterate r of the step from rbar."""
+    def system(self, r, rbar, rdot_bar, w, f_extra=None):
+        """phi(r), dphi/dr and intermediates at iterate r of the step from rbar.
+
+        f_extra (N, optional): a further internal force at the DOFs (the
+        interface force of a coupled domain, oracle/coupled.py); it enters
+        a and phi exactly as f_int does.  Its stiffness is the caller's."""
         n_p, n_q, dt = self.n_p, self.n_q, self.dt
         p_, q = r[:n_p], r[n_p:]
         dq = q - rbar[n_p:]
@@ -119,15 +123,16 @@ class Instance:
         M = self.mass
         w_r = r - rbar - dt * rdot_bar
         f_fict = M * d["Hdd"]
-        a = M * (Jt @ w_r) + f_fict + dt * dt * (f_int - self.f_ext)
-        phi = Jt.T @ (M * (Jt @ w_r)) + Jt.T @ f_fict + dt * dt * (Jt.T @ (f_int - self.f_ext))
+        f_all = f_int if f_extra is None else f_int + f_extra
+        a = M * (Jt @ w_r) + f_fict + dt * dt * (f_all - self.f_ext)
+        phi = Jt.T @ (M * (Jt @ w_r)) + Jt.T @ f_fict + dt * dt * (Jt.T @ (f_all - self.f_ext))
         A = Jt.T @ (M[:, None] * np.concatenate([U, d["J"] + d["dJ"]], axis=1)) + dt * dt * Kr
         if n_q:
             JTa, B = self.left(q, a)
             A[n_p:, n_p:] += B
         else:
             JTa, B = np.zeros(0), np.zeros((0, 0))
-        return dict(phi=phi, A=A, u=u, J=d["J"], dJ=d["dJ"], Hdd=d["Hdd"], f_int=f_int,
+        return dict(phi=phi, A=A, u=u, J=d["J"], Jt=Jt, dJ=d["dJ"], Hdd=d["Hdd"], f_int=f_int,
                     fr=fr, Kr=Kr, a=a, B=B, JTa=JTa, w=w)
 
     # -- time stepping -----------------------------------------------------

@@ -389,3 +389,152 @@ def tiny_problem(grid=(2, 2, 3), widths=(2, 4, 4, 36), act="tanh", n_p=0, n_cub=
                  q_std=0.1, name="tiny", instance=0, out_scale=1.0) -> Problem:
     return bar_problem(name, grid, list(widths), act, n_p=n_p, n_cub=n_cub, q_std=q_std,
                        instance=instance, out_scale=out_scale, stream_prefix=name + "/")
+
+
+# --------------------------------------------------------------------------
+# coupled multi-domain scenes (the puffer ball / cactus setting of Sec. 6.8)
+# --------------------------------------------------------------------------
+@dataclass
+class CoupledScene:
+    """A core domain and rods tied to it: ties[k] (4, 2) pairs (vertex of rod
+    k, vertex of the core) whose copies are joined by springs of stiffness
+    kappa [N/m]."""
+    core: Problem
+    rods: List[Problem]
+    ties: List[np.ndarray]
+    kappa: float
+    steps: int = 1
+    newton_iters: int = 1
+
+
+# outward normal and in-face axes (e1 x e2 = n) of the five free faces of a
+# grid pinned at k = 0: top, +x, -x, +y, -y
+_FACES = (
+    ("top", (0, 0, 1), (1, 0, 0), (0, 1, 0)),
+    ("+x", (1, 0, 0), (0, 1, 0), (0, 0, 1)),
+    ("-x", (-1, 0, 0), (0, 0, 1), (0, 1, 0)),
+    ("+y", (0, 1, 0), (0, 0, 1), (1, 0, 0)),
+    ("-y", (0, -1, 0), (1, 0, 0), (0, 0, 1)),
+)
+
+
+def attach_sites(grid):
+    """Unit squares of the five free faces of a grid pinned at k = 0 at which
+    a rod can be rooted, no two sharing a vertex (odd offsets, away from the
+    face edges and from the pinned face): list of (corner (i, j, k), n, e1, e2)."""
+    nx, ny, nz = grid
+    size = np.array([nx, ny, nz])
+    out = []
+    for name, n, e1, e2 in _FACES:
+        n, e1, e2 = (np.array(v) for v in (n, e1, e2))
+        base = np.where(n > 0, size - 1, 0) * np.abs(n)
+        a1, a2 = int(np.flatnonzero(e1)[0]), int(np.flatnonzero(e2)[0])
+        for s1 in range(1, size[a1] - 2, 2):
+            for s2 in range(1, size[a2] - 2, 2):
+                corner = base + s1 * e1 + s2 * e2
+                out.append((tuple(int(c) for c in corner), n, e1, e2))
+    return out
+
+
+def rod_frame_basis(X: np.ndarray, n_p: int, stream: str, seed: int = MASTER_SEED) -> np.ndarray:
+    """(3n, n_p) orthonormal basis of a free rod: its three translations and
+    three infinitesimal rotations about the centre of its root face (the first
+    four vertices), then Gaussian directions, orthonormalised by QR, so that
+    the linear subspace can follow the motion of what the rod is tied to."""
+    n = X.shape[0]
+    c = X[:4].mean(axis=0)
+    cols = []
+    for a in range(3):
+        t = np.zeros((n, 3))
+        t[:, a] = 1.0
+        cols.append(t.ravel())
+    for a in range(3):
+        ax = np.zeros(3)
+        ax[a] = 1.0
+        cols.append(np.cross(ax, X - c).ravel())
+    extra = max(n_p - 6, 0)
+    G = normal(stream, 3 * n * extra, seed).reshape(3 * n, extra)
+    M = np.column_stack(cols[: min(6, n_p)] + [G])
+    Q, _ = np.linalg.qr(M)
+    return Q[:, :n_p]
+
+
+def coupled_scene(name: str, core_grid, n_rods: int, rod_lengths, *, core_np: int, core_widths, rod_np: int,
+                  rod_widths, act: str = "tanh", kappa: float = 1.0e5, core_out_scale: float = 0.25,
+                  rod_out_scale: float = 0.25, q_std: float = 0.02, steps: int = 1, newton_iters: int = 3,
+                  seed: int = MASTER_SEED) -> CoupledScene:
+    """A core (a grid pinned at its k = 0 face, n_p linear plus a decoder of
+    its own, full quadrature) with n_rods 2 x 2 x L rods rooted on unit squares
+    of its five free faces (chosen by a seeded permutation of the sites), each
+    rod's root face a copy of the square's four core vertices tied to them by
+    springs.  Rods share one decoder (rod_widths[-1] >= 12 max L, a rod using
+    the first 12 L rows) and have their own frame basis (rod_frame_basis);
+    nothing of a rod is pinned.  Full quadrature everywhere; initial latent
+    q ~ N(0, q_std^2), linear coordinates and velocities zero."""
+    sp = name + "/"
+    nx, ny, nz = core_grid
+    Xc, tc = grid_mesh(nx, ny, nz)
+    nc = Xc.shape[0]
+    pin_c = _pins_k0(nc, nx, ny)
+    Wc, bc = xavier_mlp(core_widths, sp + "core/dec", seed)
+    Wc[-1] = Wc[-1] * core_out_scale
+    assert core_widths[-1] >= 3 * nc
+    Uc = random_orthonormal(3 * nc, core_np, np.repeat(pin_c, 3), sp + "core/U", seed)
+    nqc = core_widths[0]
+    rc0 = np.zeros(core_np + nqc)
+    rc0[core_np:] = q_std * normal(sp + "core/q0", nqc, seed)
+    mc = tc.shape[0]
+    core = Problem(name=sp + "core", X=Xc, tets=tc, pinned=pin_c, gravity=GRAVITY.copy(), dt=DT, U=Uc,
+                   weights=Wc, biases=bc, act=act, cub_ids=np.arange(mc, dtype=np.int32), cub_w=np.ones(mc),
+                   r0=rc0, rdot0=np.zeros(core_np + nqc), steps=steps, newton_iters=newton_iters,
+                   out_rows=core_widths[-1], meta=dict(grid=tuple(core_grid), widths=list(core_widths)), **MATERIAL)
+    sites = attach_sites(core_grid)
+    assert n_rods <= len(sites), (n_rods, len(sites))
+    pick = np.sort(permutation(sp + "sites", len(sites), seed)[:n_rods])
+    Ws, bs = xavier_mlp(rod_widths, sp + "rods/dec", seed)
+    Ws[-1] = Ws[-1] * rod_out_scale
+    Ls = np.asarray(rod_lengths)[raw64(sp + "rods/len", n_rods, seed) % np.uint64(len(rod_lengths))]
+    cidx = lambda v: int(v[0] + nx * (v[1] + ny * v[2]))
+    rods, ties = [], []
+    nqr = rod_widths[0]
+    for k, s in enumerate(pick):
+        corner, n, e1, e2 = sites[int(s)]
+        L = int(Ls[k])
+        X0, tr = grid_mesh(2, 2, L)
+        assert rod_widths[-1] >= X0.size
+        P0 = Xc[cidx(corner)]
+        X = P0 + X0[:, 0:1] * e1 + X0[:, 1:2] * e2 + X0[:, 2:3] * n
+        nv = X.shape[0]
+        U = rod_frame_basis(X, rod_np, sp + f"rods/U/{k}", seed)
+        r0 = np.zeros(rod_np + nqr)
+        r0[rod_np:] = q_std * normal(sp + f"rods/q0/{k}", nqr, seed)
+        m = tr.shape[0]
+        rods.append(Problem(name=sp + f"rod{k}_L{L}", X=X, tets=tr, pinned=np.zeros(nv, np.uint8),
+                            gravity=GRAVITY.copy(), dt=DT, U=U, weights=Ws, biases=bs, act=act,
+                            cub_ids=np.arange(m, dtype=np.int32), cub_w=np.ones(m), r0=r0,
+                            rdot0=np.zeros(rod_np + nqr), steps=steps, newton_iters=newton_iters,
+                            out_rows=rod_widths[-1], meta=dict(L=L, site=int(s)), **MATERIAL))
+        root = [(a, b) for b in (0, 1) for a in (0, 1)]     # rod vertices 0..3 = (a, b, 0)
+        ties.append(np.array([[a + 2 * b, cidx(np.array(corner) + a * e1 + b * e2)] for a, b in root],
+                             dtype=np.int64))
+    return CoupledScene(core=core, rods=rods, ties=ties, kappa=kappa, steps=steps, newton_iters=newton_iters)
+
+
+def config_coupled_tiny(n_rods: int = 2) -> CoupledScene:
+    """Small coupled scene for the parity tests: a 4 x 4 x 5 core (n_p = 4,
+    tanh decoder [3, 16, 16, 240]) with rods of 3 or 4 vertex layers (n_p = 6,
+    shared decoder [3, 16, 16, 48])."""
+    return coupled_scene("coupled_tiny", (4, 4, 5), n_rods, (3, 4), core_np=4, core_widths=[3, 16, 16, 240],
+                         rod_np=6, rod_widths=[3, 16, 16, 48], q_std=0.05, steps=4, newton_iters=3)
+
+
+def config_puffer(n_rods: int = 320) -> CoupledScene:
+    """Puffer-ball-like coupled scene: a 21 x 21 x 21 core (9,261 vertices,
+    40,000 tets) pinned at one face, n_p = 10 plus an n_q = 6 tanh decoder
+    [6, 32, 64, 128, 27783], and 320 rods of 2 x 2 x L vertices (L from
+    {20, 30, 40, 60}) rooted on its five free faces, each with n_p = 10 and the
+    shared n_q = 5 decoder [5, 32, 64, 128, 720]; full quadrature, tie springs
+    of 1e5 N/m, 60 steps x 3 Newton iterations."""
+    return coupled_scene("puffer", (21, 21, 21), n_rods, ROD_LENGTHS, core_np=10,
+                         core_widths=[6, 32, 64, 128, 3 * 21 ** 3], rod_np=10, rod_widths=ROD_WIDTHS,
+                         steps=60, newton_iters=3)
