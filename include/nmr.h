@@ -234,6 +234,44 @@ int reduced_newton_step(nmr_inst* inst, int n_iters, double* resid_norms_or_null
 int step_many(nmr_ctx* ctx, nmr_inst* const* insts, int n_inst, int n_steps, int n_iters,
               int* status, float* step_ms_or_null);
 
+/* ---- coupled domains (Sec. 6.8) ------------------------------------------ */
+
+typedef struct nmr_coupled nmr_coupled;
+
+/* A coupled set: a core domain and n_rods domains tied to it, the
+ * multi-domain form of the paper's substructured scenes (Sec. 6.8: strings
+ * on a ball, branches on a trunk).  The paper gives no coupling equations;
+ * here each tied vertex of a rod owns a copy of a core vertex and the two
+ * are joined by a zero-length spring of stiffness kappa [N/m]:
+ *   E_tie = kappa/2 sum |(X + u)_rod vertex - (X + u)_core vertex|^2.
+ * One coupled step (Sec. 3.2) solves the stacked reduced equations of motion
+ * (eq. our_equation_of_motion per domain, the tie force entering as internal
+ * force, so also in the a . H term of eq. system_mat) with the Newton matrix
+ * of the stacked system: each domain's own matrix plus the tie stiffness
+ * dt^2 kappa Jt_T^T Jt_T, and the core-rod blocks -dt^2 kappa Jt_core,T^T
+ * Jt_rod,T.  It is solved by static condensation onto the core (each rod's
+ * block eliminated on its own, the core's Schur complement summed over the
+ * rods in order and solved), FP64 LU with partial pivoting throughout.
+ * ties: host, n_rods x n_tie x 2 int32 (rod vertex, core vertex); every rod
+ * has n_tie <= 21 tied vertices, no core vertex is tied twice.  Members:
+ * same context, precision and time step, complex-step derivatives, not
+ * attached to a pool, each at most once; they run the direct Newton path in
+ * the set (every DOF decoded per iteration).  A member cannot be destroyed
+ * while it belongs to a set.  Charges the context budget for the set's
+ * buffers (tie forces, per-member systems, per-rod workspaces). */
+int nmr_coupled_create(nmr_ctx* ctx, nmr_inst* core, int n_rods, nmr_inst* const* rods, const int32_t* ties,
+                       int n_tie, double kappa, nmr_coupled** out);
+int nmr_coupled_destroy(nmr_coupled* set);
+/* n_steps coupled steps of n_iters Newton iterations (one graph launch per
+ * step; each step also writes every member's frame, see
+ * nmr_instance_get_frame).  A failure of any member (inverted tet, singular
+ * or non-finite system) freezes the whole set at its last good state and
+ * is reported for every member.  Host outputs: status [1 + n_rods] (core
+ * first), step_ms_or_null [n_steps].  Each member's recorded residual norms
+ * are those of its own block of the stacked residual; the core's is the
+ * norm of the whole stacked residual.  Synchronizes. */
+int nmr_coupled_step(nmr_coupled* set, int n_steps, int n_iters, int* status, float* step_ms_or_null);
+
 /* ---- served form: slot pools (continuous batching) ---------------------- */
 
 typedef struct nmr_pool nmr_pool;

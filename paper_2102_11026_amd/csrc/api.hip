@@ -137,6 +137,7 @@ struct nmr_inst {
   double* A_scratch = nullptr;
   nmr_pool* pool = nullptr;  // the pool this instance is attached to, if any
   int pool_slot = -1;
+  int coupled_refs = 0;      // coupled sets this instance is a member of
 };
 
 // ---------------------------------------------------------------------------
@@ -742,6 +743,7 @@ extern "C" int nmr_instance_destroy(nmr_inst* in) {
   // an attached instance leaves its pool first: the pool's graph must never
   // reach the buffers freed below
   if (in->pool) CHK(nmr_pool_detach(in->pool, in->pool_slot));
+  if (in->coupled_refs > 0) return fail(NMR_ERR_ARG, "instance is a member of a coupled set: destroy the set first");
   drop_many_graphs(c, in);
   for (auto& kv : in->step_graphs) (void)hipGraphExecDestroy(kv.second);
   c->used -= in->bytes;
@@ -1082,6 +1084,210 @@ extern "C" int step_many(nmr_ctx* c, nmr_inst* const* insts, int n_inst, int n_s
   for (int k = 0; k < n_inst; ++k) {
     int st;
     CHK(read_status(key[k], &st));
+    status[k] = map_status(st);
+  }
+  return NMR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// coupled sets: a core and rods tied to it (couple.hip), one graph per step
+// ---------------------------------------------------------------------------
+struct nmr_coupled {
+  nmr_ctx* ctx = nullptr;
+  std::vector<nmr_inst*> mem;  // core first
+  bool f64 = false;
+  DevMem dev;
+  CoupleDev cd{};
+  void* mem_tab = nullptr;
+  std::vector<void*> group_tabs;
+  std::vector<Group> groups;
+  std::map<int, hipGraphExec_t> graphs;
+  size_t bytes = 0;
+};
+
+template <typename T>
+static int coupled_build(nmr_coupled* cs, const int32_t* ties, int n_tie) {
+  nmr_ctx* c = cs->ctx;
+  const int m = (int)cs->mem.size() - 1;
+  const size_t isz = sizeof(Inst<T>);
+  // per-member tie force and system buffers, then the member table and the
+  // group tables (copies of the members' entries on the direct path)
+  std::vector<Inst<T>> ent;
+  for (nmr_inst* in : cs->mem) {
+    Inst<T> I = host_inst<T>(in);
+    CHK(dalloc_t(cs->dev, in->N, &I.pen));
+    CHK(dalloc_t(cs->dev, (size_t)in->R * in->R, &I.sysA));
+    CHK(dalloc_t(cs->dev, in->R, &I.sysphi));
+    I.gram = 0;
+    I.active = 1;
+    ent.push_back(I);
+  }
+  CHK(dalloc(cs->dev, ent.size() * isz, &cs->mem_tab));
+  HIPCHK(hipMemcpy(cs->mem_tab, ent.data(), ent.size() * isz, hipMemcpyHostToDevice));
+  std::vector<std::pair<nmr_decoder*, std::vector<int>>> byd;
+  for (int k = 0; k <= m; ++k) {
+    nmr_inst* in = cs->mem[k];
+    auto f = std::find_if(byd.begin(), byd.end(), [&](auto& pr) { return pr.first == in->dec; });
+    if (f == byd.end()) byd.push_back({in->dec, {k}});
+    else f->second.push_back(k);
+  }
+  for (auto& pr : byd) {
+    std::vector<Inst<T>> ge;
+    std::vector<nmr_inst*> v;
+    for (int k : pr.second) {
+      ge.push_back(ent[k]);
+      v.push_back(cs->mem[k]);
+    }
+    void* tab;
+    CHK(dalloc(cs->dev, ge.size() * isz, &tab));
+    HIPCHK(hipMemcpy(tab, ge.data(), ge.size() * isz, hipMemcpyHostToDevice));
+    cs->group_tabs.push_back(tab);
+    Group g = group_of(v, tab);
+    g.gram = false;
+    g.same_rows = false;
+    CHK(choose_tiles(c, g, false));
+    cs->groups.push_back(g);
+  }
+  // ties: DOF pairs (rod DOF, core DOF) per rod
+  const int ntd = 3 * n_tie;
+  std::vector<int> td((size_t)m * ntd * 2);
+  for (int k = 0; k < m; ++k)
+    for (int t = 0; t < n_tie; ++t)
+      for (int d = 0; d < 3; ++d) {
+        const size_t o = 2 * ((size_t)k * ntd + 3 * t + d);
+        td[o] = 3 * ties[2 * ((size_t)k * n_tie + t)] + d;
+        td[o + 1] = 3 * ties[2 * ((size_t)k * n_tie + t) + 1] + d;
+      }
+  int* dtie;
+  CHK(dalloc_t(cs->dev, td.size(), &dtie));
+  HIPCHK(hipMemcpy(dtie, td.data(), td.size() * sizeof(int), hipMemcpyHostToDevice));
+  cs->cd.n_rods = m;
+  cs->cd.n_td = ntd;
+  cs->cd.tie = dtie;
+  CHK(dalloc_t(cs->dev, (size_t)m * kCoupleWs, &cs->cd.ws));
+  CHK(dalloc_t(cs->dev, NMR_MAX_R, &cs->cd.dc));
+  CHK(dalloc_t(cs->dev, 1, &cs->cd.frozen));
+  return NMR_OK;
+}
+
+template <typename T>
+static void enqueue_coupled_step(nmr_coupled* cs, int K, hipStream_t s) {
+  const Inst<T>* mt = static_cast<const Inst<T>*>(cs->mem_tab);
+  for (const Group& g : cs->groups)
+    launch_step_begin<T>(static_cast<const Inst<T>*>(g.tab), g.nb, BEGIN_STEP, g.max_cub, s);
+  for (int it = 0; it < K; ++it) {
+    const int mode = SOLVE_UPDATE | (it == K - 1 ? SOLVE_FINISH : 0);
+    for (const Group& g : cs->groups) {
+      enqueue_decoder_fwd<T>(g, s, 1);
+      if (it == 0) launch_frame<T>(g.dec->d, static_cast<const Inst<T>*>(g.tab), g.nb, g.maxN, s);
+    }
+    launch_couple_pen<T>(mt, cs->cd, s);
+    for (const Group& g : cs->groups) {
+      const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
+      launch_cubature<T>(tab, g.nb, g.max_cblk, s);
+      launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
+      launch_sums<T>(tab, g.nb, g.max_entries, s);
+      enqueue_decoder_bwd<T>(g, s);
+      launch_solve<T>(tab, g.nb, it, SOLVE_WRITE_SYSTEM | SOLVE_WRITE_INST, nullptr, nullptr, s);
+    }
+    launch_couple_solve<T>(mt, cs->cd, it, mode, s);
+  }
+}
+
+extern "C" int nmr_coupled_create(nmr_ctx* c, nmr_inst* core, int n_rods, nmr_inst* const* rods,
+                                  const int32_t* ties, int n_tie, double kappa, nmr_coupled** out) {
+  if (!c || !core || n_rods < 1 || !rods || !ties || n_tie < 1 || !out) return fail(NMR_ERR_ARG, "bad argument");
+  if (!(kappa >= 0.0) || !std::isfinite(kappa)) return fail(NMR_ERR_ARG, "kappa must be finite and >= 0");
+  if (3 * n_tie > 64) return fail(NMR_ERR_ARG, "at most 21 tied vertices per rod");
+  *out = nullptr;
+  CHK(set_device(c));
+  std::vector<nmr_inst*> mem{core};
+  for (int k = 0; k < n_rods; ++k) mem.push_back(rods[k]);
+  for (nmr_inst* in : mem) {
+    if (!in || in->ctx != c) return fail(NMR_ERR_ARG, "instance of another context");
+    if (in->prec != core->prec) return fail(NMR_ERR_ARG, "members must share one precision");
+    if (in->fd) return fail(NMR_ERR_ARG, "coupled members take complex-step derivatives");
+    if (in->pool) return fail(NMR_ERR_ARG, "a member is attached to a pool");
+    auto dt_of = [](nmr_inst* x) { return is_f64(x) ? host_inst<double>(x).dt : host_inst<float>(x).dt; };
+    if (dt_of(in) != dt_of(core)) return fail(NMR_ERR_ARG, "members must share the time step");
+  }
+  for (size_t a = 0; a < mem.size(); ++a)
+    for (size_t b = a + 1; b < mem.size(); ++b)
+      if (mem[a] == mem[b]) return fail(NMR_ERR_ARG, "an instance appears twice");
+  std::vector<char> used(core->N, 0);
+  for (int k = 0; k < n_rods; ++k)
+    for (int t = 0; t < n_tie; ++t) {
+      const int vr = ties[2 * ((size_t)k * n_tie + t)], vc = ties[2 * ((size_t)k * n_tie + t) + 1];
+      if (vr < 0 || 3 * vr >= rods[k]->N || vc < 0 || 3 * vc >= core->N) return fail(NMR_ERR_ARG, "tie vertex out of range");
+      if (used[3 * vc]) return fail(NMR_ERR_ARG, "a core vertex is tied twice");
+      used[3 * vc] = 1;
+    }
+  nmr_coupled* cs = new nmr_coupled();
+  cs->ctx = c;
+  cs->mem = mem;
+  cs->f64 = is_f64(core);
+  cs->cd.kappa = kappa;
+  int rc = cs->f64 ? coupled_build<double>(cs, ties, n_tie) : coupled_build<float>(cs, ties, n_tie);
+  if (rc == NMR_OK && c->budget && c->used + cs->dev.bytes > c->budget) rc = fail(NMR_ERR_BUDGET, "coupled set exceeds HBM budget");
+  if (rc != NMR_OK) {
+    cs->dev.release();
+    delete cs;
+    return rc;
+  }
+  c->used += cs->dev.bytes;
+  for (nmr_inst* in : mem) in->coupled_refs++;
+  *out = cs;
+  return NMR_OK;
+}
+
+extern "C" int nmr_coupled_destroy(nmr_coupled* cs) {
+  if (!cs) return fail(NMR_ERR_ARG, "null coupled set");
+  CHK(set_device(cs->ctx));
+  (void)hipStreamSynchronize(cs->ctx->stream);
+  for (auto& kv : cs->graphs) (void)hipGraphExecDestroy(kv.second);
+  cs->ctx->used -= cs->dev.bytes;
+  cs->dev.release();
+  for (nmr_inst* in : cs->mem) in->coupled_refs--;
+  delete cs;
+  return NMR_OK;
+}
+
+extern "C" int nmr_coupled_step(nmr_coupled* cs, int n_steps, int n_iters, int* status, float* step_ms_or_null) {
+  if (!cs || n_steps < 0 || !status) return fail(NMR_ERR_ARG, "bad argument");
+  if (n_iters < 1 || n_iters > kMaxIters) return fail(NMR_ERR_ARG, "n_iters must be in [1, 64]");
+  nmr_ctx* c = cs->ctx;
+  CHK(set_device(c));
+  auto it = cs->graphs.find(n_iters);
+  if (it == cs->graphs.end()) {
+    hipGraph_t graph;
+    HIPCHK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+    if (cs->f64) enqueue_coupled_step<double>(cs, n_iters, c->cap);
+    else enqueue_coupled_step<float>(cs, n_iters, c->cap);
+    HIPCHK(hipStreamEndCapture(c->cap, &graph));
+    hipGraphExec_t ex;
+    hipError_t e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(NMR_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    it = cs->graphs.emplace(n_iters, ex).first;
+  }
+  std::vector<hipEvent_t> ev;
+  if (step_ms_or_null) {
+    ev.resize(n_steps + 1);
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipEventRecord(ev[0], c->stream));
+  }
+  for (int s = 0; s < n_steps; ++s) {
+    HIPCHK(hipGraphLaunch(it->second, c->stream));
+    if (step_ms_or_null) HIPCHK(hipEventRecord(ev[s + 1], c->stream));
+  }
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (step_ms_or_null) {
+    for (int s = 0; s < n_steps; ++s) HIPCHK(hipEventElapsedTime(&step_ms_or_null[s], ev[s], ev[s + 1]));
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+  for (size_t k = 0; k < cs->mem.size(); ++k) {
+    int st;
+    CHK(read_status(cs->mem[k], &st));
     status[k] = map_status(st);
   }
   return NMR_OK;

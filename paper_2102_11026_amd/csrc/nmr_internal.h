@@ -111,6 +111,12 @@ struct Inst {
   double* Bq;              // [n_q][n_q] a . H, column j from perturbation j
   double* JTa;             // [n_q]
   T* frame;                // [N] u = U p + D(q) of the frame decoded last
+  // coupled sets only (null elsewhere): the tie force of this domain [N],
+  // added to f_int in the residual and the backpropagation seed, and the
+  // domain's own Newton system written for the coupled solve
+  T* pen;
+  double* sysA;            // [R][R]
+  double* sysphi;          // [R]
   // Gram-folded Newton path (n_p == 0): with the linear output layer W_L and
   // the constant lumped mass, Jt^T M Jt = F_J^T Gam F_J etc. over the folded
   // activations F; only the DOFs of cubature tets are decoded per iteration
@@ -325,8 +331,45 @@ template <typename T>
 void launch_gram_setup(const void* W, int prec, int K, const T* mass, const T* keep, int N, double dt,
                        const double* g, double* Gam, double* gam, hipStream_t s);
 
-// solve modes
-enum { SOLVE_UPDATE = 1, SOLVE_FINISH = 2, SOLVE_WRITE_SYSTEM = 4 };
+// solve modes (SOLVE_WRITE_INST: the system goes to the entry's sysA / sysphi)
+enum { SOLVE_UPDATE = 1, SOLVE_FINISH = 2, SOLVE_WRITE_SYSTEM = 4, SOLVE_WRITE_INST = 8 };
+
+// ---- coupled sets (couple.hip) -----------------------------------------
+// Member 0 is the core, member 1 + k rod k; rod k's ties are n_td DOF pairs
+// (rod DOF, core DOF).  Per-rod FP64 workspace of kCoupleWs doubles, laid
+// out with row stride NMR_MAX_R:
+//   Pr [R_r][R_r]   dt^2 kappa Jt_r,T^T Jt_r,T       (rod tie stiffness)
+//   gr [R_r]        dt^2 Jt_r,T^T f_r                (rod tie force)
+//   Pc [R_c][R_c]   dt^2 kappa Jt_c,T^T Jt_c,T       (core tie stiffness)
+//   gc [R_c]        dt^2 Jt_c,T^T f_c
+//   Cc [R_c][R_r]   -dt^2 kappa Jt_c,T^T Jt_r,T      (core-rod block)
+//   X  [R_r][1+R_c] A'^-1 [phi', Cc^T]               (local solve)
+//   Sc [R_c][R_c]   Cc X[:, 1:],  sc [R_c]  Cc X[:, 0]
+//   nrm2            |phi'_r|^2
+enum {
+  CW_PR = 0,
+  CW_GR = CW_PR + NMR_MAX_R * NMR_MAX_R,
+  CW_PC = CW_GR + NMR_MAX_R,
+  CW_GC = CW_PC + NMR_MAX_R * NMR_MAX_R,
+  CW_CC = CW_GC + NMR_MAX_R,
+  CW_X = CW_CC + NMR_MAX_R * NMR_MAX_R,
+  CW_SC = CW_X + NMR_MAX_R * (NMR_MAX_R + 1),
+  CW_SCV = CW_SC + NMR_MAX_R * NMR_MAX_R,
+  CW_NRM = CW_SCV + NMR_MAX_R,
+  kCoupleWs = CW_NRM + 8
+};
+struct CoupleDev {
+  int n_rods, n_td;      // rods, tie DOFs per rod (<= 64)
+  double kappa;
+  const int* tie;        // [n_rods][n_td][2]
+  double* ws;            // [n_rods][kCoupleWs]
+  double* dc;            // [NMR_MAX_R] core update of the iteration
+  int* frozen;           // 1: a member has failed, nothing is updated
+};
+template <typename T>
+void launch_couple_pen(const Inst<T>* mem, const CoupleDev& cd, hipStream_t s);
+template <typename T>
+void launch_couple_solve(const Inst<T>* mem, const CoupleDev& cd, int iter, int mode, hipStream_t s);
 // step-begin modes
 enum { BEGIN_STEP = 0, BEGIN_SYSTEM = 1 };
 

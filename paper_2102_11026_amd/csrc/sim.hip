@@ -473,7 +473,8 @@ __global__ __launch_bounds__(256) void k_mass(const Inst<T>* __restrict__ tab) {
   const double m_i = (double)ldg<T>(I.mass + ic), keep_i = (double)ldg<T>(I.keep + ic);
   const int lr = min(t, R - 1);
   const double wrv = ldg<double>(I.r + lr) - ldg<double>(I.rbar + lr) - dt * ldg<double>(I.rdot + lr);
-  const double fi = fint_at(I, ic);
+  // a coupled domain's tie force counts as internal force
+  const double fi = fint_at(I, ic) + (I.pen ? (double)ldg<T>(I.pen + ic) : 0.0);
   if (t < R) wr[t] = wrv;
   __syncthreads();
   {
@@ -1047,6 +1048,10 @@ __global__ __launch_bounds__(64) void k_solve(const Inst<T>* __restrict__ tab, i
   load_now(I.active, I.R, I.n_p, I.n_q, I.dt, I.sum_mass, I.sum_cub, I.Bq, I.status, I.r, I.rbar, I.rdot, I.resid,
            I.dec_in);
   if (!I.active) return;
+  if (mode & SOLVE_WRITE_INST) {
+    A_out = I.sysA;
+    phi_out = I.sysphi;
+  }
   if (I.R < 16) solve_body<T, 16>(I, iter, mode, A_out, phi_out);
   else solve_body<T, 32>(I, iter, mode, A_out, phi_out);
 }

@@ -93,6 +93,10 @@ def lib():
             "nmr_time_phase": (i, [vp, i, i, C.POINTER(C.c_float)]),
             "nmr_set_tiling": (i, [vp, i, i, i]),
             "nmr_tiling_table": (i, [vp, C.POINTER(TileChoice), i, ip]),
+            "nmr_coupled_create": (i, [vp, vp, i, C.POINTER(vp), C.POINTER(C.c_int32), i, C.c_double,
+                                       C.POINTER(vp)]),
+            "nmr_coupled_destroy": (i, [vp]),
+            "nmr_coupled_step": (i, [vp, i, i, ip, C.POINTER(C.c_float)]),
             "nmr_pool_create": (i, [vp, i, C.POINTER(vp)]),
             "nmr_pool_destroy": (i, [vp]),
             "nmr_pool_attach": (i, [vp, vp, ip]),
@@ -368,6 +372,33 @@ class Pool:
     def close(self):
         if self.h:
             _check(lib().nmr_pool_destroy(self.h))
+            self.h = None
+
+
+class Coupled:
+    """A core instance and rod instances tied to it (nmr_coupled_*); ties[k]
+    is an (n_tie, 2) array of (rod vertex, core vertex) pairs of rod k."""
+
+    def __init__(self, ctx: Context, core: Instance, rods: Sequence[Instance], ties, kappa: float):
+        t = np.ascontiguousarray(np.stack([np.asarray(x) for x in ties]), dtype=np.int32)
+        arr = (C.c_void_p * len(rods))(*[r.h.value for r in rods])
+        h = C.c_void_p()
+        _check(lib().nmr_coupled_create(ctx.h, core.h, len(rods), arr, t.ctypes.data_as(C.POINTER(C.c_int32)),
+                                        t.shape[1], float(kappa), C.byref(h)))
+        self.h = h
+        self.n = 1 + len(rods)
+        self.members = [core] + list(rods)
+
+    def step(self, n_steps: int, n_iters: int, timings: bool = False):
+        """Returns (status per member, core first; device ms per step or None)."""
+        st = (C.c_int * self.n)()
+        ms = (C.c_float * max(n_steps, 1))() if timings else None
+        _check(lib().nmr_coupled_step(self.h, n_steps, n_iters, st, ms))
+        return list(st), (list(ms)[:n_steps] if timings else None)
+
+    def close(self):
+        if self.h:
+            _check(lib().nmr_coupled_destroy(self.h))
             self.h = None
 
 
