@@ -437,6 +437,29 @@ def main():
             for x in insts:
                 x.close()
             dec.close()
+        # coupled multi-domain scene: 320 rods tied to a 9,261-vertex reduced core (one coupled system)
+        scene = synth.config_puffer(320)
+        for prec in ("fp32", "bf16"):
+            core = nmr.Instance(ctx, scene.core, prec)
+            dec = nmr.Decoder(ctx, scene.rods[0].weights, scene.rods[0].biases, scene.rods[0].act, prec)
+            rods = [nmr.Instance(ctx, q, prec, shared=dec) for q in scene.rods]
+            cs = nmr.Coupled(ctx, core, rods, scene.ties, scene.kappa)
+            st, _ = cs.step(2, scene.newton_iters, timings=True)
+            st, ms_c = cs.step(20, scene.newton_iters, timings=True)
+            assert all(x == 0 for x in st), st
+            sec = float(np.sum(ms_c)) / 1000.0
+            nd = len(rods) + 1
+            var[f"coupled_puffer_{prec}"] = dict(
+                domains=nd, rods=len(rods), core_vertices=scene.core.n, rod_vertices=int(sum(q.n for q in scene.rods)),
+                domain_newton_iters_per_s=round(nd * scene.newton_iters * 20 / sec, 1),
+                coupled_steps_per_s=round(20 / sec, 2), p50_step_ms=round(float(np.percentile(ms_c, 50)), 4),
+                p99_step_ms=round(float(np.percentile(ms_c, 99)), 4), steps=20,
+                newton_iters_per_step=scene.newton_iters)
+            log(f"coupled puffer {prec}:", var[f"coupled_puffer_{prec}"])
+            cs.close()
+            for x in [core] + rods:
+                x.close()
+            dec.close()
         if args.serve_seconds > 0:
             from paper_2102_11026_amd import serve
             probs = {"A": synth.config_serve_a(), "B": synth.config_serve_b(), "C": synth.config_serve_c()}

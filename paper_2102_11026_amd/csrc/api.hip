@@ -434,6 +434,7 @@ static size_t instance_bytes(const Sizes& s, const DecoderDev& d) {
   add((s.R * s.R + s.R) * 8); add((s.R * s.R + s.R * s.n_q + s.R + s.n_p) * 8);
   add(s.n_q * s.n_q * 8); add(s.n_q * 8);
   add((size_t)s.N * sizeof(T));  // frame
+  if (s.n_p > 0) add((size_t)((s.N + 255) / 256) * s.n_p * s.Cf * 8);
   add(s.R * s.R * 8);
   return b;
 }
@@ -584,6 +585,7 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   CHK(dalloc_t(M, s.n_q * s.n_q, &I.Bq));
   CHK(dalloc_t(M, s.n_q, &I.JTa));
   CHK(dalloc_t(M, s.N, &I.frame));
+  if (s.n_p > 0) CHK(dalloc_t(M, (size_t)((s.N + 255) / 256) * s.n_p * s.Cf, &I.part_filt));
   CHK(dalloc_t(M, s.R * s.R, &in->A_scratch));
   // cubature sources: the Newton path reads the decoder records
   I.cu_u = I.rec; I.cu_u_ld = s.Cf;
@@ -817,7 +819,7 @@ static void enqueue_decoder_fwd(const Group& g, hipStream_t s, int add_up) {
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
   for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, g.tf[l], s);
   launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, g.same_rows, s);
-  if (g.any_np) launch_filter<T>(tab, g.nb, add_up, s);
+  if (g.any_np) launch_filter<T>(tab, g.nb, g.maxN, add_up, s);
 }
 
 // with_out: launch the output-layer backpropagation too (else the caller
@@ -1166,6 +1168,7 @@ static int coupled_build(nmr_coupled* cs, const int32_t* ties, int n_tie) {
   cs->cd.tie = dtie;
   CHK(dalloc_t(cs->dev, (size_t)m * kCoupleWs, &cs->cd.ws));
   CHK(dalloc_t(cs->dev, NMR_MAX_R, &cs->cd.dc));
+  CHK(dalloc_t(cs->dev, NMR_MAX_R * NMR_MAX_R + 2 * NMR_MAX_R + 1, &cs->cd.red));
   CHK(dalloc_t(cs->dev, 1, &cs->cd.frozen));
   return NMR_OK;
 }
@@ -1724,7 +1727,7 @@ static void enqueue_phase(const Group& g, int phase, hipStream_t s) {
       break;
     case NMR_PHASE_DEC_OUT:
       launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, g.same_rows, s);
-      if (g.any_np) launch_filter<T>(tab, g.nb, 1, s);
+      if (g.any_np) launch_filter<T>(tab, g.nb, g.maxN, 1, s);
       break;
     case NMR_PHASE_CUBATURE: launch_cubature<T>(tab, g.nb, g.max_cblk, s); break;
     case NMR_PHASE_MASS:

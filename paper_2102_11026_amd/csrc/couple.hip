@@ -10,7 +10,8 @@
 // by static condensation onto the core: each rod's block is eliminated on
 // its own (k_couple_local, one block per rod), the core's Schur complement
 //   S = A_c' - sum_k Cc_k A_k'^-1 Cc_k^T
-// is summed over the rods in rod order and solved (k_couple_core), and each
+// is summed over the rods in a fixed order (k_couple_sum) and solved
+// (k_couple_core), and each
 // rod back-substitutes (k_couple_back).  A_d' and phi_d' are the domain's
 // own matrix and residual plus its tie stiffness and tie force.  All
 // reduced arithmetic in FP64.  Dense elimination with partial pivoting, as
@@ -221,6 +222,45 @@ __global__ __launch_bounds__(256) void k_couple_local(const Inst<T>* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Sums over the rods of the core's terms, in fixed order: entry e of
+//   [sum_k (Pc_k - Sc_k) (R_c x R_c) | sum_k gc_k (R_c) | sum_k sc_k (R_c) |
+//    sum_k |phi'_k|^2]
+// 16 entries per block; slice s of 16 threads adds rods s, s + 16, ... and
+// the slice sums are added in slice order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_couple_sum(const Inst<T>* __restrict__ mem, CoupleDev cd) {
+  const int Rc = mem[0].R, m = cd.n_rods;
+  const int ne = Rc * Rc + 2 * Rc + 1;
+  const int kk = threadIdx.x & 15, sl = threadIdx.x >> 4;
+  const int e = blockIdx.x * 16 + kk;
+  __shared__ double part[16][17];
+  double acc = 0.0;
+  if (e < ne) {
+    for (int k = sl; k < m; k += 16) {
+      const double* w = cd.ws + (size_t)k * kCoupleWs;
+      if (e < Rc * Rc) {
+        const int a = e / Rc, b = e - a * Rc;
+        acc += ldg<double>(w + CW_PC + a * NMR_MAX_R + b) - ldg<double>(w + CW_SC + a * NMR_MAX_R + b);
+      } else if (e < Rc * Rc + Rc) {
+        acc += ldg<double>(w + CW_GC + (e - Rc * Rc));
+      } else if (e < Rc * Rc + 2 * Rc) {
+        acc += ldg<double>(w + CW_SCV + (e - Rc * Rc - Rc));
+      } else {
+        acc += ldg<double>(w + CW_NRM);
+      }
+    }
+  }
+  part[sl][kk] = acc;
+  __syncthreads();
+  if (sl == 0 && e < ne) {
+    double v = part[0][kk];
+    for (int q = 1; q < 16; ++q) v += part[q][kk];
+    stg<double>(cd.red + e, v);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Core: members' status (any failure freezes the whole set and is reported
 // by every member), S = A_c + sum_k (Pc_k - Sc_k), rhs = -(phi_c + sum_k gc_k)
 // + sum_k sc_k (rods added in rod order), S d_c = rhs, core update.  The
@@ -250,30 +290,19 @@ __global__ __launch_bounds__(256) void k_couple_core(const Inst<T>* __restrict__
   for (int e = tid; e < Rc * Rc + Rc; e += 256) {
     if (e < Rc * Rc) {
       const int a = e / Rc, b = e - a * Rc;
-      double v = ldg<double>(C.sysA + a * Rc + b);
-      for (int k = 0; k < m; ++k) {
-        const double* w = cd.ws + (size_t)k * kCoupleWs;
-        v += ldg<double>(w + CW_PC + a * NMR_MAX_R + b) - ldg<double>(w + CW_SC + a * NMR_MAX_R + b);
-      }
-      M[a][b] = v;
+      M[a][b] = ldg<double>(C.sysA + a * Rc + b) + ldg<double>(cd.red + e);
     } else {
       const int a = e - Rc * Rc;
-      double ph = ldg<double>(C.sysphi + a), s = 0.0;
-      for (int k = 0; k < m; ++k) {
-        const double* w = cd.ws + (size_t)k * kCoupleWs;
-        ph += ldg<double>(w + CW_GC + a);
-        s += ldg<double>(w + CW_SCV + a);
-      }
+      const double ph = ldg<double>(C.sysphi + a) + ldg<double>(cd.red + Rc * Rc + a);
       phic[a] = ph;
-      M[a][Rc] = -ph + s;
+      M[a][Rc] = -ph + ldg<double>(cd.red + Rc * Rc + Rc + a);
     }
   }
   __syncthreads();
   if (tid == 0) {
     double s = 0.0;
     for (int a = 0; a < Rc; ++a) s += phic[a] * phic[a];
-    for (int k = 0; k < m; ++k) s += ldg<double>(cd.ws + (size_t)k * kCoupleWs + CW_NRM);
-    snrm = sqrt(s);
+    snrm = sqrt(s + ldg<double>(cd.red + Rc * Rc + 2 * Rc));
   }
   const bool bad = gj_solve(M, Rc, Rc + 1);
   if (bad) {
@@ -317,6 +346,7 @@ void launch_couple_pen(const Inst<T>* mem, const CoupleDev& cd, hipStream_t s) {
 template <typename T>
 void launch_couple_solve(const Inst<T>* mem, const CoupleDev& cd, int iter, int mode, hipStream_t s) {
   k_couple_local<T><<<cd.n_rods, 256, 0, s>>>(mem, cd);
+  k_couple_sum<T><<<(NMR_MAX_R * NMR_MAX_R + 2 * NMR_MAX_R + 1 + 15) / 16, 256, 0, s>>>(mem, cd);
   k_couple_core<T><<<1, 256, 0, s>>>(mem, cd, iter, mode);
   k_couple_back<T><<<cd.n_rods, 64, 0, s>>>(mem, cd, iter, mode);
 }

@@ -970,29 +970,87 @@ __global__ __launch_bounds__(256) void k_fwd_out_f64(LayerArgs la, const Inst<do
 // Filter (I - U U^T) of every output channel and u += U p (n_p > 0 only).
 // One block per instance.
 // ---------------------------------------------------------------------------
+// Filter of every output channel, rec <- (I - U U^T) rec (the mask is
+// already applied and U has zero pinned rows), and u = U p + D(q) in the
+// value channel when add_up.  Two passes over 256-row blocks: k_filter_part
+// writes each block's FP64 partial of Y = U^T rec [n_p][Cf]; k_filter_apply
+// adds the partials in block order (every block the same sum) and updates
+// its rows.
+#define FILT_ROWS 256
 template <typename T>
-__global__ __launch_bounds__(256) void k_filter(const Inst<T>* __restrict__ tab, int add_up) {
+__global__ __launch_bounds__(256) void k_filter_part(const Inst<T>* __restrict__ tab) {
   const Inst<T>& I = tab[blockIdx.y];
-  if (!I.active) return;
-  const int np = I.n_p, Cf = I.Cf, N = I.N;
-  if (np == 0) return;
-  __shared__ double Y[NMR_MAX_R][64];  // U^T rec, n_p x Cf (Cf <= 64)
+  const int active = I.active, np = I.n_p, Cf = I.Cf, N = I.N;
+  load_now(active, np, Cf, N, I.U, I.rec, I.part_filt);
+  if (!active || np == 0) return;
+  const int i0 = blockIdx.x * FILT_ROWS;
+  if (i0 >= N) return;
+  const int nr = min(FILT_ROWS, N - i0);
+  // rows staged 64 at a time; thread t accumulates entries t + 256 j of
+  // [n_p][Cf] (at most 8) over the rows in order
+  constexpr int CH = 64, EPT = (NMR_MAX_R * 64 + 255) / 256;
+  __shared__ double sU[CH][NMR_MAX_R + 1];
+  __shared__ double sR[CH][65];
+  double acc[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) acc[j] = 0.0;
+  for (int r0 = 0; r0 < nr; r0 += CH) {
+    const int nc = min(CH, nr - r0);
+    for (int e = threadIdx.x; e < nc * np; e += 256) {
+      const int i = e / np, k = e - i * np;
+      sU[i][k] = (double)ldg<T>(I.U + (size_t)(i0 + r0 + i) * np + k);
+    }
+    for (int e = threadIdx.x; e < nc * Cf; e += 256) {
+      const int i = e / Cf, c = e - i * Cf;
+      sR[i][c] = (double)ldg<T>(I.rec + (size_t)(i0 + r0 + i) * Cf + c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+      const int e = threadIdx.x + 256 * j;
+      if (e < np * Cf) {
+        const int k = e / Cf, c = e - k * Cf;
+        for (int i = 0; i < nc; ++i) acc[j] = fma(sU[i][k], sR[i][c], acc[j]);
+      }
+    }
+    __syncthreads();
+  }
+  double* out = I.part_filt + (size_t)blockIdx.x * np * Cf;
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int e = threadIdx.x + 256 * j;
+    if (e < np * Cf) stg<double>(out + e, acc[j]);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_filter_apply(const Inst<T>* __restrict__ tab, int add_up) {
+  const Inst<T>& I = tab[blockIdx.y];
+  const int active = I.active, np = I.n_p, Cf = I.Cf, N = I.N;
+  load_now(active, np, Cf, N, I.U, I.rec, I.part_filt, I.r);
+  if (!active || np == 0) return;
+  const int i0 = blockIdx.x * FILT_ROWS;
+  if (i0 >= N) return;
+  const int nblk = (N + FILT_ROWS - 1) / FILT_ROWS;
+  __shared__ double Y[NMR_MAX_R][65];
   __shared__ double pv[NMR_MAX_R];
   for (int e = threadIdx.x; e < np * Cf; e += 256) {
     const int k = e / Cf, c = e - k * Cf;
     double acc = 0.0;
-    for (int i = 0; i < N; ++i) acc += (double)I.U[(size_t)i * np + k] * (double)I.rec[(size_t)i * Cf + c];
+    for (int b = 0; b < nblk; ++b) acc += ldg<double>(I.part_filt + (size_t)b * np * Cf + e);
     Y[k][c] = acc;
   }
-  if (threadIdx.x < np) pv[threadIdx.x] = I.r[threadIdx.x];
+  if (threadIdx.x < np) pv[threadIdx.x] = ldg<double>(I.r + threadIdx.x);
   __syncthreads();
-  for (int e = threadIdx.x; e < N * Cf; e += 256) {
-    const int i = e / Cf, c = e - i * Cf;
-    double v = (double)I.rec[e];
-    for (int k = 0; k < np; ++k) v -= (double)I.U[(size_t)i * np + k] * Y[k][c];
+  const int nr = min(FILT_ROWS, N - i0);
+  for (int e = threadIdx.x; e < nr * Cf; e += 256) {
+    const int i = i0 + e / Cf, c = e % Cf;
+    T* rp = I.rec + (size_t)i * Cf + c;
+    double v = (double)ldg<T>(rp);
+    for (int k = 0; k < np; ++k) v -= (double)ldg<T>(I.U + (size_t)i * np + k) * Y[k][c];
     if (c == 0 && add_up)
-      for (int k = 0; k < np; ++k) v += (double)I.U[(size_t)i * np + k] * pv[k];
-    I.rec[e] = (T)v;
+      for (int k = 0; k < np; ++k) v += (double)ldg<T>(I.U + (size_t)i * np + k) * pv[k];
+    stg<T>(rp, (T)v);
   }
 }
 
@@ -1498,11 +1556,13 @@ void launch_fwd_out<double>(const DecoderDev& d, const Inst<double>* tab, int nb
 }
 
 template <typename T>
-void launch_filter(const Inst<T>* tab, int nb, int add_up, hipStream_t s) {
-  k_filter<T><<<dim3(1, nb), 256, 0, s>>>(tab, add_up);
+void launch_filter(const Inst<T>* tab, int nb, int max_n, int add_up, hipStream_t s) {
+  const dim3 grid((max_n + FILT_ROWS - 1) / FILT_ROWS, nb);
+  k_filter_part<T><<<grid, 256, 0, s>>>(tab);
+  k_filter_apply<T><<<grid, 256, 0, s>>>(tab, add_up);
 }
-template void launch_filter<float>(const Inst<float>*, int, int, hipStream_t);
-template void launch_filter<double>(const Inst<double>*, int, int, hipStream_t);
+template void launch_filter<float>(const Inst<float>*, int, int, int, hipStream_t);
+template void launch_filter<double>(const Inst<double>*, int, int, int, hipStream_t);
 
 template <>
 void launch_bwd_out<float>(const DecoderDev& d, const Inst<float>* tab, int nb, int max_bblk, hipStream_t s) {

@@ -106,6 +106,7 @@ struct Inst {
   double* part_cub;        // [n_cblk][R*R + R]
   double* part_mass;       // [n_mblk][R*R + R*n_q + R + n_p]
   double* part_bwd;        // [n_bblk][K_last]
+  double* part_filt;       // [ceil(N / 256)][n_p][Cf] (n_p > 0): partials of U^T rec
   double* sum_cub;         // [R*R + R]
   double* sum_mass;        // [R*R + R*n_q + R + n_p]
   double* Bq;              // [n_q][n_q] a . H, column j from perturbation j
@@ -281,7 +282,7 @@ template <typename T>
 void launch_fwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_np, int max_cf, bool same_rows,
                     hipStream_t s);
 template <typename T>
-void launch_filter(const Inst<T>* tab, int nb, int add_up, hipStream_t s);
+void launch_filter(const Inst<T>* tab, int nb, int max_n, int add_up, hipStream_t s);
 template <typename T>
 void launch_bwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_bblk, hipStream_t s);
 // the partial sums and the output-layer backpropagation in one launch (Gram
@@ -364,6 +365,7 @@ struct CoupleDev {
   const int* tie;        // [n_rods][n_td][2]
   double* ws;            // [n_rods][kCoupleWs]
   double* dc;            // [NMR_MAX_R] core update of the iteration
+  double* red;           // [R_c^2 + 2 R_c + 1] sums over the rods (k_couple_sum)
   int* frozen;           // 1: a member has failed, nothing is updated
 };
 template <typename T>
