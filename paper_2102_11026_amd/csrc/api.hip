@@ -813,12 +813,21 @@ static Group group_of(const std::vector<nmr_inst*>& v, void* tab) {
   return g;
 }
 
+// Channels the per-iteration output layer decodes into the records.  On the
+// Gram-folded path the records feed only the cubature, which reads u and J:
+// the value and the n_q J channels (the mass terms come from the folded
+// activations).  The direct path decodes every channel.  The FP64 form
+// always decodes every channel.
+static int out_channels(const Group& g) {
+  return (g.gram && !g.f64) ? pad_to(1 + g.n_q, 16) : g.Cf;
+}
+
 template <typename T>
 static void enqueue_decoder_fwd(const Group& g, hipStream_t s, int add_up) {
   const DecoderDev& d = g.dec->d;
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
   for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, g.tf[l], s);
-  launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, g.same_rows, s);
+  launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, out_channels(g), g.same_rows, s);
   if (g.any_np) launch_filter<T>(tab, g.nb, g.maxN, add_up, s);
 }
 
@@ -837,6 +846,8 @@ static void enqueue_decoder_bwd(const Group& g, hipStream_t s, bool with_out = t
 // idle; from this many instances on, each runs at its own occupancy (the
 // shared grid takes the larger register and LDS footprint of the two).
 static const int kShareLaunchMax = 16;
+// frames of a Gram-path group as one GEMM over the instances from this many
+static const int kFrameBatchMin = 8;
 
 template <typename T>
 static void enqueue_iteration(const Group& g, int iter, int mode, double* A_out, double* phi_out, hipStream_t s) {
@@ -844,7 +855,10 @@ static void enqueue_iteration(const Group& g, int iter, int mode, double* A_out,
   enqueue_decoder_fwd<T>(g, s, 1);
   // a step's first iteration runs the decoder at r = rbar, the state the
   // step starts from: its value channel is that frame's displacement
-  if (iter == 0 && (mode & SOLVE_UPDATE)) launch_frame<T>(g.dec->d, tab, g.nb, g.maxN, s);
+  if (iter == 0 && (mode & SOLVE_UPDATE)) {
+    if (g.gram && g.nb >= kFrameBatchMin) launch_frame_batch<T>(g.dec->d, tab, g.nb, g.maxN, s);
+    else launch_frame<T>(g.dec->d, tab, g.nb, g.maxN, s);
+  }
   if (g.gram && g.nb < kShareLaunchMax) {
     // the Gram terms need only the folded activations and the state, and the
     // output-layer seed only the element forces: each pair is one launch
@@ -1726,7 +1740,7 @@ static void enqueue_phase(const Group& g, int phase, hipStream_t s) {
       for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, g.tf[l], s);
       break;
     case NMR_PHASE_DEC_OUT:
-      launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, g.Cf, g.same_rows, s);
+      launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, out_channels(g), g.same_rows, s);
       if (g.any_np) launch_filter<T>(tab, g.nb, g.maxN, 1, s);
       break;
     case NMR_PHASE_CUBATURE: launch_cubature<T>(tab, g.nb, g.max_cblk, s); break;

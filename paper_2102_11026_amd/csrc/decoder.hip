@@ -766,7 +766,10 @@ __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out(LayerArgs la, const 
 #pragma unroll
     for (int i = 0; i < 4; ++i) red[wave][cb * 16 + rA][4 * g + i] = acc[cb][i];
   __syncthreads();
-  for (int p = threadIdx.x; p < 16 * Cf; p += 64 * OUT_SPLIT) {
+  // the launch may decode fewer channels than the record holds (the Gram
+  // path needs the value and J only)
+  const int nc = min(Cf, NCB * 16);
+  for (int p = threadIdx.x; p < 16 * nc; p += 64 * OUT_SPLIT) {
     const int c = p >> 4, r = p & 15;
     if (row0 + r < nrows) {
       float v = red[0][c][r];
@@ -1369,6 +1372,88 @@ __global__ __launch_bounds__(256) void k_frame(LayerArgs la, const Inst<T>* __re
   }
 }
 
+// Frames of many instances sharing a decoder (Gram path): one GEMM with the
+// instances as columns, U = W_L [F_0 ... F_nb] for the value channels F_j of
+// the folded activations, so every weight row is read once for all of them.
+// A block takes 256 rows (four waves of four 16-row tiles) and 32 instance
+// columns, whose value channels it stages in LDS (zeros for a slot not in
+// use, whose pointers are never read).  u_j[i] = keep_j[i] (acc + b_i) for
+// rows i < N_j.
+#define FRAME_COLS 32
+template <typename TW>
+__global__ __launch_bounds__(256) void k_frame_batch(LayerArgs la, const Inst<float>* __restrict__ tab, int nb) {
+  constexpr int NCB = FRAME_COLS / 16;
+  const int K = la.m_inp;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rA = lane & 15, g = lane >> 4;
+  const int c0 = blockIdx.y * FRAME_COLS;
+  __shared__ __align__(16) float Fs[FRAME_COLS][OUT_KMAX + 4];
+  __shared__ int s_act[FRAME_COLS], s_n[FRAME_COLS];
+  if (threadIdx.x < FRAME_COLS) {
+    const int j = c0 + threadIdx.x;
+    const int act = j < nb ? tab[j].active : 0;
+    s_act[threadIdx.x] = act && tab[j].gram;
+    s_n[threadIdx.x] = act ? tab[j].N : 0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < FRAME_COLS * (K / 4); e += 256) {
+    const int c = e / (K / 4), k = 4 * (e - c * (K / 4));
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (s_act[c]) v = ldg<float4>(tab[c0 + c].fold + k);
+    *reinterpret_cast<float4*>(&Fs[c][k]) = v;
+  }
+  __syncthreads();
+  const TW* W = reinterpret_cast<const TW*>(la.W);
+  const float* bias = reinterpret_cast<const float*>(la.b);
+  const int m_out = la.m_out;
+  for (int t = 0; t < 4; ++t) {
+    const int row0 = blockIdx.x * 256 + wave * 64 + t * 16;
+    if (row0 >= m_out) break;  // uniform over the wave
+    const int wrow = min(row0 + rA, m_out - 1);
+    f32x4 acc[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if constexpr (std::is_same<TW, float>::value) {
+      for (int k = 0; k < K; k += 16) {
+        const float4 a = ldg<float4>(W + (size_t)wrow * K + k + 4 * g);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const float4 b = *reinterpret_cast<const float4*>(&Fs[cb * 16 + rA][k + 4 * g]);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc[cb], 0, 0, 0);
+        }
+      }
+    } else {
+      for (int k = 0; k < K; k += 32) {
+        const bf16x8 a = ldg<bf16x8>(W + (size_t)wrow * K + k + 8 * g);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const float4 b0 = *reinterpret_cast<const float4*>(&Fs[cb * 16 + rA][k + 8 * g]);
+          const float4 b1 = *reinterpret_cast<const float4*>(&Fs[cb * 16 + rA][k + 8 * g + 4]);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, to_bf16x8(b0, b1), acc[cb], 0, 0, 0);
+        }
+      }
+    }
+    // item i of lane l is D[4 (l/16) + i][l % 16]: row row0 + 4 g + i of
+    // instance c0 + cb * 16 + rA
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int c = cb * 16 + rA;
+      if (!s_act[c]) continue;
+      const Inst<float>& I = tab[c0 + c];
+      float* frame = I.frame;
+      const float* keep = I.keep;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = row0 + 4 * g + i;
+        if (row < s_n[c]) stg<float>(frame + row, (acc[cb][i] + ldg<float>(bias + row)) * ldg<float>(keep + row));
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
@@ -1659,8 +1744,18 @@ void launch_frame<float>(const DecoderDev& d, const Inst<float>* tab, int nb, in
   else k_frame<float, float><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab);
 }
 template <>
+void launch_frame_batch<float>(const DecoderDev& d, const Inst<float>* tab, int nb, int max_n, hipStream_t s) {
+  dim3 grid((max_n + 255) / 256, (nb + FRAME_COLS - 1) / FRAME_COLS);
+  if (d.prec == PREC_BF16) k_frame_batch<__bf16><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab, nb);
+  else k_frame_batch<float><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab, nb);
+}
+template <>
 void launch_frame<double>(const DecoderDev& d, const Inst<double>* tab, int nb, int max_n, hipStream_t s) {
   k_frame<double, double><<<dim3((max_n + 15) / 16, nb), 256, 0, s>>>(layer_args(d, d.L - 1), tab);
+}
+template <>
+void launch_frame_batch<double>(const DecoderDev& d, const Inst<double>* tab, int nb, int max_n, hipStream_t s) {
+  launch_frame<double>(d, tab, nb, max_n, s);
 }
 
 template <typename T>

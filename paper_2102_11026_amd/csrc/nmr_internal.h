@@ -302,6 +302,10 @@ void launch_unpack(const Inst<T>* tab, T* u, T* J, T* dJ, T* Hdd, int N, hipStre
 // layer; direct path, the value channel of the records (filtered, U p added)
 template <typename T>
 void launch_frame(const DecoderDev& d, const Inst<T>* tab, int nb, int max_n, hipStream_t s);
+// the same for a group whose every member runs the Gram path, as one GEMM
+// with the instances as columns (FP32 / BF16; FP64 falls back to the above)
+template <typename T>
+void launch_frame_batch(const DecoderDev& d, const Inst<T>* tab, int nb, int max_n, hipStream_t s);
 
 // ---- launchers (sim.hip) -----------------------------------------------
 template <typename T>

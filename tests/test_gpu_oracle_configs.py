@@ -131,7 +131,8 @@ def test_128_shared_decoder_instances_against_oracle(nmr, ctx, bar10k_two_starts
     the default launch rule: at this count the hidden layers take four-row
     tall tiles with four instances per block and the output layer the wide
     kernel with two instances per block.  After one step every instance
-    matches the oracle of its initial state."""
+    matches the oracle of its initial state, and every frame (u of the start
+    state, decoded for all 128 instances by one GEMM) the oracle's."""
     tol = TOL[prec]
     base = bar10k_two_starts[0][0]
     ctx.set_tiling("rule")
@@ -146,6 +147,10 @@ def test_128_shared_decoder_instances_against_oracle(nmr, ctx, bar10k_two_starts
             r, rd = x.get_state()
             worst = max(worst, close_scaled(r, s1.rbar, tol, rmax, (prec, k)))
         print(prec, "128 instances, worst max |r - r_oracle| / max |r|:", f"{worst:.2e}")
+        # the frames of the step (its start state), all 128 from one batched GEMM
+        u0 = [bar10k_two_starts[k][1].displacement(bar10k_two_starts[k][0].r0) for k in (0, 1)]
+        for k, x in enumerate(insts):
+            close(x.get_frame(), u0[k % 2], tol, (prec, "frame", k))
         for k in (0, 1):                                  # the displacement of one instance per start
             p, oi, s1, rmax = bar10k_two_starts[k]
             _, _, u = insts[k].get_state(with_u=True)
