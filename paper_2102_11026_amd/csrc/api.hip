@@ -866,7 +866,7 @@ static void enqueue_iteration(const Group& g, int iter, int mode, double* A_out,
     launch_sums_bwd_out<T>(g.dec->d, tab, g.nb, g.max_entries, g.max_sblk, s);
     enqueue_decoder_bwd<T>(g, s, false);
   } else {
-    launch_cubature<T>(tab, g.nb, g.max_cblk, s);
+    launch_cubature<T>(tab, g.nb, g.max_cblk, g.maxR, s);
     if (g.gram) launch_gram<T>(tab, g.nb, g.n_gblk, g.K, g.n_q, s);
     else launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
     launch_sums<T>(tab, g.nb, g.max_entries, s);
@@ -1201,7 +1201,7 @@ static void enqueue_coupled_step(nmr_coupled* cs, int K, hipStream_t s) {
     launch_couple_pen<T>(mt, cs->cd, s);
     for (const Group& g : cs->groups) {
       const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
-      launch_cubature<T>(tab, g.nb, g.max_cblk, s);
+      launch_cubature<T>(tab, g.nb, g.max_cblk, g.maxR, s);
       launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
       launch_sums<T>(tab, g.nb, g.max_entries, s);
       enqueue_decoder_bwd<T>(g, s);
@@ -1377,7 +1377,7 @@ static int cfs_impl(nmr_inst* in, const void* u, const void* Jt, const void* w, 
   I.gram = 0;
   HIPCHK(hipMemcpy(in->api_tab, &I, sizeof(Inst<T>), hipMemcpyHostToDevice));
   const Inst<T>* tab = static_cast<const Inst<T>*>(in->api_tab);
-  launch_cubature<T>(tab, 1, in->n_cblk, c->stream);
+  launch_cubature<T>(tab, 1, in->n_cblk, in->R, c->stream);
   std::vector<nmr_inst*> v{in};
   Group g = group_of(v, in->api_tab);
   launch_sums<T>(tab, 1, g.max_entries, c->stream);
@@ -1453,7 +1453,7 @@ static int cfs_noalloc_impl(nmr_inst* in, const void* u, const void* Jt, const v
   HIPCHK(hipStreamSynchronize(c->stream));
   HIPCHK(hipMemcpy(base, &head, sizeof(head), hipMemcpyHostToDevice));
   const Inst<T>* tab = reinterpret_cast<const Inst<T>*>(base);
-  launch_cubature<T>(tab, 1, in->n_cblk, c->stream);
+  launch_cubature<T>(tab, 1, in->n_cblk, in->R, c->stream);
   const int Ec = in->R * in->R + in->R;
   launch_sums<T>(tab, 1, Ec, c->stream);  // cubature entries only
   HIPCHK(hipMemcpyAsync(Kr, I.sum_cub, in->R * in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1743,7 +1743,7 @@ static void enqueue_phase(const Group& g, int phase, hipStream_t s) {
       launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, out_channels(g), g.same_rows, s);
       if (g.any_np) launch_filter<T>(tab, g.nb, g.maxN, 1, s);
       break;
-    case NMR_PHASE_CUBATURE: launch_cubature<T>(tab, g.nb, g.max_cblk, s); break;
+    case NMR_PHASE_CUBATURE: launch_cubature<T>(tab, g.nb, g.max_cblk, g.maxR, s); break;
     case NMR_PHASE_MASS:
       if (g.gram) launch_gram<T>(tab, g.nb, g.n_gblk, g.K, g.n_q, s);
       else launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);

@@ -314,8 +314,9 @@ void launch_rest_shape(const double* X, const int* tets, int m, const int* cub_i
                        T* cub_Bm, T* cub_Ve, T* mass, double* Ve_tmp, hipStream_t s);
 template <typename T>
 void launch_step_begin(const Inst<T>* tab, int nb, int mode, int max_cub, hipStream_t s);
+// max_r: the largest R in the launch (sizes the kernel's per-tet work)
 template <typename T>
-void launch_cubature(const Inst<T>* tab, int nb, int max_cblk, hipStream_t s);
+void launch_cubature(const Inst<T>* tab, int nb, int max_cblk, int max_r, hipStream_t s);
 // the cubature pass and the Gram kernel in one launch (Gram path)
 template <typename T>
 void launch_cub_gram(const Inst<T>* tab, int nb, int max_cblk, int max_gblk, int K, int nq, hipStream_t s);

@@ -169,7 +169,7 @@ template void launch_step_begin<double>(const Inst<double>*, int, int, int, hipS
 // ---------------------------------------------------------------------------
 #define CUB_WAVES 4
 
-template <typename T>
+template <typename T, int RB>
 __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, int bx, int by, int m) {
   const Inst<T>& I = tab[by];
   load_now(I.active, I.n_cblk, I.R, I.cu_na, I.mu, I.lam, I.cub_per_blk, I.n_cub, I.cub_v, I.cub_Bm, I.cu_w, I.cub_Ve,
@@ -181,14 +181,14 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
   const int na = I.cu_na;
   const T mu = (T)I.mu, lam = (T)I.lam;
   __shared__ T xs[CUB_WAVES][12];
-  __shared__ T J12[CUB_WAVES][12][NMR_MAX_R + 1];
-  __shared__ T dFs[CUB_WAVES][NMR_MAX_R][9];
-  __shared__ T dPs[CUB_WAVES][NMR_MAX_R][9];
-  __shared__ double red[NMR_MAX_R * NMR_MAX_R + NMR_MAX_R];
+  __shared__ T J12[CUB_WAVES][12][RB + 1];
+  __shared__ T dFs[CUB_WAVES][RB][9];
+  __shared__ T dPs[CUB_WAVES][RB][9];
+  __shared__ double red[RB * RB + RB];
   // the R x R stiffness sums in 2 x 2 blocks: lane l owns blocks l + 64 t,
   // block b covering rows 2 (b / nb2) + {0, 1} and columns 2 (b % nb2) + {0, 1}
   // (each entry the same 9-term dot product in the same order as unblocked)
-  constexpr int BT = ((NMR_MAX_R + 1) / 2 * ((NMR_MAX_R + 1) / 2) + 63) / 64;
+  constexpr int BT = ((RB + 1) / 2 * ((RB + 1) / 2) + 63) / 64;
   const int nb2 = (R + 1) / 2;
   double kacc[BT][4];
 #pragma unroll
@@ -198,7 +198,7 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
   double facc = 0.0;
   const int e0 = bx * m * I.cub_per_blk;
   const int e1 = min(e0 + m * I.cub_per_blk, I.n_cub);
-  constexpr int JT = (12 * NMR_MAX_R + 63) / 64;
+  constexpr int JT = (12 * RB + 63) / 64;
   // first round trip of tet e: its vertices, B_m, weight and volume (none
   // depends on another load)
   auto load_r1 = [&](int e, int4& tv, T (&Bmv)[9], T& wV) {
@@ -393,18 +393,21 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
   for (int p = threadIdx.x; p < E; p += 256) stg<double>(out + p, red[p]);
 }
 
-template <typename T>
+template <typename T, int RB>
 __global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ tab, int m) {
-  cubature_block<T>(tab, blockIdx.x, blockIdx.y, m);
+  cubature_block<T, RB>(tab, blockIdx.x, blockIdx.y, m);
 }
 
 template <typename T>
-void launch_cubature(const Inst<T>* tab, int nb, int max_cblk, hipStream_t s) {
+void launch_cubature(const Inst<T>* tab, int nb, int max_cblk, int max_r, hipStream_t s) {
   const int m = cubature_merge(nb);
-  k_cubature<T><<<dim3((max_cblk + m - 1) / m, nb), 64 * CUB_WAVES, 0, s>>>(tab, m);
+  const dim3 grid((max_cblk + m - 1) / m, nb);
+  if (max_r <= 8) k_cubature<T, 8><<<grid, 64 * CUB_WAVES, 0, s>>>(tab, m);
+  else if (max_r <= 16) k_cubature<T, 16><<<grid, 64 * CUB_WAVES, 0, s>>>(tab, m);
+  else k_cubature<T, NMR_MAX_R><<<grid, 64 * CUB_WAVES, 0, s>>>(tab, m);
 }
-template void launch_cubature<float>(const Inst<float>*, int, int, hipStream_t);
-template void launch_cubature<double>(const Inst<double>*, int, int, hipStream_t);
+template void launch_cubature<float>(const Inst<float>*, int, int, int, hipStream_t);
+template void launch_cubature<double>(const Inst<double>*, int, int, int, hipStream_t);
 
 
 template <typename T>
@@ -776,9 +779,9 @@ __global__ __launch_bounds__(256) void k_gram(const Inst<T>* __restrict__ tab, i
 // The cubature pass and the Gram kernel in one launch (the Gram terms need
 // only the folded activations and the state, not the decoded rows): blocks
 // below n_cub_blocks run the cubature, the rest the Gram rows.
-template <typename T, int NCB>
+template <typename T, int NCB, int RB>
 __global__ __launch_bounds__(256) void k_cub_gram(const Inst<T>* __restrict__ tab, int m, int K, int n_cub_blocks) {
-  if ((int)blockIdx.x < n_cub_blocks) cubature_block<T>(tab, blockIdx.x, blockIdx.y, m);
+  if ((int)blockIdx.x < n_cub_blocks) cubature_block<T, RB>(tab, blockIdx.x, blockIdx.y, m);
   else gram_block<T, NCB>(tab, blockIdx.x - n_cub_blocks, blockIdx.y, K);
 }
 
@@ -795,16 +798,24 @@ void launch_gram(const Inst<T>* tab, int nb, int max_gblk, int K, int nq, hipStr
 template void launch_gram<float>(const Inst<float>*, int, int, int, int, hipStream_t);
 template void launch_gram<double>(const Inst<double>*, int, int, int, int, hipStream_t);
 
+template <typename T, int RB>
+static void cub_gram_ncb(const Inst<T>* tab, int nb, int m, int ncb, int max_gblk, int K, int nq, hipStream_t s) {
+  const dim3 grid(ncb + max_gblk, nb);
+  switch ((2 * nq + 1 + 15) / 16) {
+    case 1: k_cub_gram<T, 1, RB><<<grid, 256, 0, s>>>(tab, m, K, ncb); break;
+    case 2: k_cub_gram<T, 2, RB><<<grid, 256, 0, s>>>(tab, m, K, ncb); break;
+    case 3: k_cub_gram<T, 3, RB><<<grid, 256, 0, s>>>(tab, m, K, ncb); break;
+    default: k_cub_gram<T, 4, RB><<<grid, 256, 0, s>>>(tab, m, K, ncb); break;
+  }
+}
+
 template <typename T>
 void launch_cub_gram(const Inst<T>* tab, int nb, int max_cblk, int max_gblk, int K, int nq, hipStream_t s) {
   const int m = cubature_merge(nb), ncb = (max_cblk + m - 1) / m;
-  const dim3 grid(ncb + max_gblk, nb);
-  switch ((2 * nq + 1 + 15) / 16) {
-    case 1: k_cub_gram<T, 1><<<grid, 256, 0, s>>>(tab, m, K, ncb); break;
-    case 2: k_cub_gram<T, 2><<<grid, 256, 0, s>>>(tab, m, K, ncb); break;
-    case 3: k_cub_gram<T, 3><<<grid, 256, 0, s>>>(tab, m, K, ncb); break;
-    default: k_cub_gram<T, 4><<<grid, 256, 0, s>>>(tab, m, K, ncb); break;
-  }
+  // the Gram path has no linear subspace: R = n_q
+  if (nq <= 8) cub_gram_ncb<T, 8>(tab, nb, m, ncb, max_gblk, K, nq, s);
+  else if (nq <= 16) cub_gram_ncb<T, 16>(tab, nb, m, ncb, max_gblk, K, nq, s);
+  else cub_gram_ncb<T, NMR_MAX_R>(tab, nb, m, ncb, max_gblk, K, nq, s);
 }
 template void launch_cub_gram<float>(const Inst<float>*, int, int, int, int, int, hipStream_t);
 template void launch_cub_gram<double>(const Inst<double>*, int, int, int, int, int, hipStream_t);
