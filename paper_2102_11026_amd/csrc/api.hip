@@ -781,6 +781,8 @@ struct Group {
   int max_cdofs, max_sblk, n_gblk, K;
   TileCfg tf[NMR_MAX_LAYERS], tb[NMR_MAX_LAYERS];  // hidden-layer tiles (ib == 0: the rule)
   bool same_rows;  // every member decodes the same output rows (checked exactly)
+  const int* rows = nullptr;  // Gram path: the decoded rows every member shares (device), or null
+  int n_rows = 0;
 };
 
 static Group group_of(const std::vector<nmr_inst*>& v, void* tab) {
@@ -810,6 +812,10 @@ static Group group_of(const std::vector<nmr_inst*>& v, void* tab) {
   g.same_rows = true;
   for (nmr_inst* in : v)
     g.same_rows = g.same_rows && (g.gram ? in->cdofs == v[0]->cdofs : in->N == v[0]->N);
+  if (g.gram && g.same_rows) {
+    g.rows = g.f64 ? host_inst<double>(v[0]).cdofs : host_inst<float>(v[0]).cdofs;
+    g.n_rows = v[0]->n_cdofs;
+  }
   return g;
 }
 
@@ -837,7 +843,10 @@ template <typename T>
 static void enqueue_decoder_bwd(const Group& g, hipStream_t s, bool with_out = true) {
   const DecoderDev& d = g.dec->d;
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
-  if (with_out) launch_bwd_out<T>(d, tab, g.nb, g.gram ? g.max_sblk : g.max_bblk, s);
+  if (with_out) {
+    if (g.gram && g.rows && !g.f64 && g.nb >= 2) launch_bwd_out_batch<T>(d, tab, g.nb, g.rows, g.n_rows, s);
+    else launch_bwd_out<T>(d, tab, g.nb, g.gram ? g.max_sblk : g.max_bblk, s);
+  }
   launch_bwd_reduce<T>(d, tab, g.nb, s);
   for (int l = d.L - 2; l >= 0; --l) launch_bwd_hidden<T>(d, l, tab, g.nb, g.Cb, g.fd, g.tb[l], s);
 }
@@ -1575,6 +1584,7 @@ struct nmr_pool {
   size_t isz = 0;
   std::map<int, hipGraphExec_t> graphs;
   int tile_epoch = 0;  // the context's tiling epoch the graphs were captured in
+  int* rows = nullptr;  // Gram path: the class's decoded rows (device copy; every member shares them)
 };
 
 extern "C" int nmr_pool_create(nmr_ctx* c, int capacity, nmr_pool** out) {
@@ -1604,6 +1614,7 @@ extern "C" int nmr_pool_destroy(nmr_pool* p) {
     }
   pool_drop_graphs(p);
   if (p->tab) (void)hipFree(p->tab);
+  if (p->rows) (void)hipFree(p->rows);
   if (p->proto) decoder_unref(p->proto->dec);
   delete p;
   return NMR_OK;
@@ -1655,6 +1666,10 @@ extern "C" int nmr_pool_attach(nmr_pool* p, nmr_inst* in, int* slot) {
     std::vector<unsigned char> zero(p->isz * p->capacity, 0);  // active = 0 everywhere
     HIPCHK(hipMalloc(&p->tab, zero.size()));
     HIPCHK(hipMemcpy(p->tab, zero.data(), zero.size(), hipMemcpyHostToDevice));
+    if (in->gram && in->n_cdofs > 0) {
+      HIPCHK(hipMalloc(&p->rows, in->cdofs.size() * sizeof(int)));
+      HIPCHK(hipMemcpy(p->rows, in->cdofs.data(), in->cdofs.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
   }
   HIPCHK(hipStreamSynchronize(p->ctx->stream));
   HIPCHK(hipMemcpy(static_cast<unsigned char*>(p->tab) + s * p->isz, in->host.data(), p->isz,
@@ -1692,7 +1707,13 @@ extern "C" int nmr_pool_step(nmr_pool* p, int n_iters, int* status, float* ms) {
   if (it == p->graphs.end()) {
     Group g = group_of({p->proto}, p->tab);
     g.nb = p->capacity;
-    g.same_rows = false;  // later members need not share the first one's rows
+    // every member shares the class's rows (nmr_pool_attach checks them), but a
+    // table entry of an empty slot may be stale: only kernels that take the
+    // rows from the pool's own copy and never read an empty slot's pointers
+    // use them (the batched output-layer backpropagation)
+    g.same_rows = false;
+    g.rows = p->proto->gram ? p->rows : nullptr;
+    g.n_rows = p->proto->n_cdofs;
     int live = 0;
     for (nmr_inst* x : p->slots) live += x != nullptr;
     CHK(choose_tiles(c, g, 2 * live >= p->capacity));

@@ -1141,6 +1141,74 @@ __global__ __launch_bounds__(256) void k_bwd_out(LayerArgs la, const Inst<T>* __
   bwd_out_block<T, TW>(la, tab, blockIdx.x, blockIdx.y);
 }
 
+// The Gram path's output-layer backpropagation for instances that decode the
+// same rows (`rows`, shared by every member of the launch): a block takes
+// 128 rows and BWD_NJ instances, so every weight row it loads serves all of
+// them.  Each instance's partial is the same sum in the same order as in
+// bwd_out_block (slice sl adds rows i0 + sl, i0 + sl + 4, ...; slices
+// combined in order), so the results are the same bits.  Slots not in use
+// contribute nothing and their pointers are never read.
+#define BWD_NJ 8
+template <typename TW>
+__global__ __launch_bounds__(256) void k_bwd_out_batch(LayerArgs la, const Inst<float>* __restrict__ tab, int nb,
+                                                       const int* __restrict__ rows, int nrows) {
+  const int bx = blockIdx.x, j0 = blockIdx.y * BWD_NJ, tid = threadIdx.x;
+  const int K = la.m_inp;
+  const int i0 = bx * BWD_ROWS;
+  if (i0 >= nrows) return;
+  const int i1 = min(i0 + BWD_ROWS, nrows), ni = i1 - i0;
+  __shared__ double s[BWD_NJ][BWD_ROWS];
+  __shared__ int srow[BWD_ROWS];
+  __shared__ int sact[BWD_NJ];
+  __shared__ double red[4][256];
+  if (tid < BWD_NJ) {
+    const int j = j0 + tid;
+    sact[tid] = (j < nb && tab[j].active && tab[j].gram) ? 1 : 0;
+  }
+  for (int i = tid; i < ni; i += 256) srow[i] = ldg<int>(rows + i0 + i);
+  __syncthreads();
+  for (int e = tid; e < BWD_NJ * ni; e += 256) {
+    const int jj = e / ni, ii = e - jj * ni;
+    double v = 0.0;
+    if (sact[jj]) {
+      const Inst<float>& I = tab[j0 + jj];
+      const int row = srow[ii];
+      v = I.dt * I.dt * (double)ldg<float>(I.keep + row) * fint_at(I, row);
+    }
+    s[jj][ii] = v;
+  }
+  __syncthreads();
+  const TW* W = reinterpret_cast<const TW*>(la.W);
+  const int cg = tid & 63, sl = tid >> 6, col = 4 * cg;
+  double acc[BWD_NJ][4];
+#pragma unroll
+  for (int jj = 0; jj < BWD_NJ; ++jj)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[jj][t] = 0.0;
+  if (col < K) {
+#pragma unroll 4
+    for (int i = i0 + sl; i < i1; i += 4) {
+      double w[4];
+      load4(W + (size_t)srow[i - i0] * K + col, w);
+#pragma unroll
+      for (int jj = 0; jj < BWD_NJ; ++jj) {
+        const double si = s[jj][i - i0];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[jj][t] = fma(w[t], si, acc[jj][t]);
+      }
+    }
+  }
+#pragma unroll
+  for (int jj = 0; jj < BWD_NJ; ++jj) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) red[sl][4 * cg + t] = acc[jj][t];
+    __syncthreads();
+    if (sact[jj] && tid < K)
+      stg<double>(tab[j0 + jj].part_bwd + (size_t)bx * K + tid, ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid]);
+    __syncthreads();
+  }
+}
+
 // The partial sums and the output-layer backpropagation in one launch (Gram
 // path: the seed dt^2 P f_int needs the element forces, not the sums):
 // blocks below n_sum run the sums, the rest the output-layer rows.
@@ -1660,6 +1728,16 @@ void launch_bwd_out<double>(const DecoderDev& d, const Inst<double>* tab, int nb
   dim3 grid(max_bblk, nb);
   k_bwd_out<double, double><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab);
 }
+
+template <>
+void launch_bwd_out_batch<float>(const DecoderDev& d, const Inst<float>* tab, int nb, const int* rows, int nrows,
+                                 hipStream_t s) {
+  dim3 grid((nrows + BWD_ROWS - 1) / BWD_ROWS, (nb + BWD_NJ - 1) / BWD_NJ);
+  if (d.prec == PREC_BF16) k_bwd_out_batch<__bf16><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab, nb, rows, nrows);
+  else k_bwd_out_batch<float><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab, nb, rows, nrows);
+}
+template <>
+void launch_bwd_out_batch<double>(const DecoderDev&, const Inst<double>*, int, const int*, int, hipStream_t) {}
 
 template <>
 void launch_sums_bwd_out<float>(const DecoderDev& d, const Inst<float>* tab, int nb, int max_entries, int max_sblk,

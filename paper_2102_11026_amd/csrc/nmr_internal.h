@@ -290,6 +290,12 @@ void launch_bwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_bbl
 template <typename T>
 void launch_sums_bwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_entries, int max_sblk,
                          hipStream_t s);
+// the Gram path's output-layer backpropagation of instances that all decode
+// `rows` (device, nrows ids), batched so each weight row serves several
+// (FP32 / BF16; same bits as launch_bwd_out)
+template <typename T>
+void launch_bwd_out_batch(const DecoderDev& d, const Inst<T>* tab, int nb, const int* rows, int nrows,
+                          hipStream_t s);
 template <typename T>
 void launch_bwd_reduce(const DecoderDev& d, const Inst<T>* tab, int nb, hipStream_t s);
 template <typename T>
