@@ -73,6 +73,13 @@ __device__ inline void act_d12(int act, T x, T& d1, T& d2) {
   act_jet(act, x, y, d1, d2, d3);
 }
 
+template <typename V>
+__device__ inline V zero_of() {
+  V v;
+  __builtin_memset(&v, 0, sizeof(V));
+  return v;
+}
+
 template <typename T> struct vec4;
 template <> struct vec4<float> { typedef float4 type; };
 template <> struct vec4<double> { typedef double4 type; };
@@ -86,6 +93,7 @@ struct LayerArgs {
   const void* WT;  // W_l^T, [m_inp][m_outp] (hidden layers only)
   int l, L, act;
   int m_in, m_inp, m_out, m_outp;  // true and padded input / output widths
+  int bf16;                        // BF16 decoder: activations and adjoints stored as BF16
 };
 
 static LayerArgs layer_args(const DecoderDev& d, int l) {
@@ -100,6 +108,7 @@ static LayerArgs layer_args(const DecoderDev& d, int l) {
   a.m_inp = d.wp[l];
   a.m_out = d.w[l + 1];
   a.m_outp = d.wp[l + 1];
+  a.bf16 = d.prec == PREC_BF16 ? 1 : 0;
   return a;
 }
 
@@ -158,6 +167,16 @@ __device__ inline bf16x8 to_bf16x8(float4 lo, float4 hi) {
   return b;
 }
 
+// K entries k .. k + 7 of B column c as a BF16 fragment: loaded as they are
+// from a BF16 operand (a BF16 decoder's hidden activations and adjoints are
+// stored rounded), or rounded here from two FP32 loads (the decoder input).
+// Either way each value is rounded once, from the same FP32 value.
+template <typename BL>
+__device__ inline bf16x8 bfrag(BL& bload, int c, int k) {
+  if constexpr (std::is_same<decltype(bload(c, k)), bf16x8>::value) return bload(c, k);
+  else return to_bf16x8(bload(c, k), bload(c, k + 4));
+}
+
 template <int NCB, typename BL>
 __device__ inline void mfma_range(const __bf16* __restrict__ A, int lda, int kb, int ke, BL bload,
                                   f32x4 (&acc)[NCB]) {
@@ -174,8 +193,7 @@ __device__ inline void mfma_range(const __bf16* __restrict__ A, int lda, int kb,
       if (k < ke) {
         a[t] = ldg<bf16x8>(ap + k);
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-          b[t][cb] = to_bf16x8(bload(cb * 16 + rA, k + 8 * g), bload(cb * 16 + rA, k + 8 * g + 4));
+        for (int cb = 0; cb < NCB; ++cb) b[t][cb] = bfrag(bload, cb * 16 + rA, k + 8 * g);
       } else {
         const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
         a[t] = to_bf16x8(z, z);
@@ -336,25 +354,20 @@ __device__ inline void mfma_tall(const __bf16* __restrict__ A, int lda, int K, B
   const int rA = lane & 15, g = lane >> 4;
   const __bf16* ap = A + (size_t)rA * lda + 8 * g;
   bf16x8 a0[MR], a1[MR];
-  float4 b0[NCB][2], b1[NCB][2];
+  bf16x8 b0[NCB], b1[NCB];
   // unconditional loads of whole K-steps, as in the FP32 form
-  auto load = [&](int k, bf16x8(&a)[MR], float4(&b)[NCB][2]) {
+  auto load = [&](int k, bf16x8(&a)[MR], bf16x8(&b)[NCB]) {
     const int kc = min(k, K - 32);
 #pragma unroll
     for (int m = 0; m < MR; ++m) a[m] = ldg<bf16x8>(ap + (size_t)16 * m * lda + kc);
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      b[cb][0] = bload(cb * 16 + rA, kc + 8 * g);
-      b[cb][1] = bload(cb * 16 + rA, kc + 8 * g + 4);
-    }
+    for (int cb = 0; cb < NCB; ++cb) b[cb] = bfrag(bload, cb * 16 + rA, kc + 8 * g);
   };
-  auto mma = [&](const bf16x8(&a)[MR], const float4(&b)[NCB][2]) {
+  auto mma = [&](const bf16x8(&a)[MR], const bf16x8(&b)[NCB]) {
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      const bf16x8 bb = to_bf16x8(b[cb][0], b[cb][1]);
+    for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-      for (int m = 0; m < MR; ++m) acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], bb, acc[m][cb], 0, 0, 0);
-    }
+      for (int m = 0; m < MR; ++m) acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[cb], acc[m][cb], 0, 0, 0);
   };
   const int nbat = K / 32;
   load(0, a0, b0);
@@ -497,7 +510,13 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
     }
     return V4{v[0], v[1], v[2], v[3]};
   };
-  auto bload_x = [&](int c, int k) -> V4 { return ldg<V4>(X + (size_t)c * m_inp + k); };
+  // a BF16 decoder's hidden activations are stored as BF16 (the MFMA operand
+  // they become); complex-step jets only
+  constexpr bool BFX = std::is_same<TW, __bf16>::value && !FD;
+  auto bload_x = [&](int c, int k) {
+    if constexpr (BFX) return ldg<bf16x8>(reinterpret_cast<const __bf16*>(X) + (size_t)c * m_inp + k);
+    else return ldg<V4>(X + (size_t)c * m_inp + k);
+  };
   // jet channel of local column c of a jet group (-1: past n_q)
   auto gcol = [&](int c) -> int {
     if (c < 4) return c;
@@ -507,10 +526,10 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
   };
   auto gemm = [&](auto bload) {
     if constexpr (JG > 0) {
-      auto bload_g = [&](int c, int k) -> V4 {
+      auto bload_g = [&](int c, int k) {
         const int gc = gcol(c);
-        const V4 v = bload(max(gc, 0), k);
-        return gc >= 0 ? v : V4{T(0), T(0), T(0), T(0)};
+        const auto v = bload(max(gc, 0), k);
+        return gc >= 0 ? v : zero_of<std::remove_const_t<decltype(v)>>();
       };
       gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload_g, S, red);
     } else if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload, S, red);
@@ -581,14 +600,18 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
     if constexpr (JG > 0) {
       for (int p = tg; p < 16 * 16; p += NG) {
         const int c = p >> 4, r = p & 15, gc = gcol(c);
-        if (gc >= 0 && (c >= 4 || grp == 0)) stg<T>(outp + (size_t)gc * m_outp + row0 + r, Ss[c][r]);
+        if (gc >= 0 && (c >= 4 || grp == 0)) {
+          if constexpr (BFX) stg<__bf16>(reinterpret_cast<__bf16*>(outp) + (size_t)gc * m_outp + row0 + r, (__bf16)Ss[c][r]);
+          else stg<T>(outp + (size_t)gc * m_outp + row0 + r, Ss[c][r]);
+        }
       }
       return;
     }
     const int C = fd ? 14 * nq + 3 : 4 + 4 * nq;
     for (int p = tg; p < C * ROWS; p += NG) {
       const int c = p / ROWS, r = p & (ROWS - 1);
-      stg<T>(outp + (size_t)c * m_outp + row0 + r, Ss[c][r]);
+      if constexpr (BFX) stg<__bf16>(reinterpret_cast<__bf16*>(outp) + (size_t)c * m_outp + row0 + r, (__bf16)Ss[c][r]);
+      else stg<T>(outp + (size_t)c * m_outp + row0 + r, Ss[c][r]);
     }
   } else {
     // last hidden layer: fold into the output channels (the output layer is
@@ -677,12 +700,6 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
 #define OUT_SPLIT 4
 #define OUT_KMAX 256  // last hidden layer: K <= 256
 
-template <typename V>
-__device__ inline V zero_of() {
-  V v;
-  __builtin_memset(&v, 0, sizeof(V));
-  return v;
-}
 
 template <typename TW, int NCB>
 __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out(LayerArgs la, const Inst<float>* __restrict__ tab) {
@@ -1272,7 +1289,8 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(LayerArgs la, const Inst<T>*
       act_d12(la.act, x0, d1, d2);
       v = c == 0 ? (T)(d1 * zb0) : (T)(d2 * xc * zb0);
     }
-    stg<T>(xb + (size_t)c * K + k, in ? v : T(0));
+    if (la.bf16 && !I.fd) stg<__bf16>(reinterpret_cast<__bf16*>(xb) + (size_t)c * K + k, (__bf16)(float)(in ? v : T(0)));
+    else stg<T>(xb + (size_t)c * K + k, in ? v : T(0));
   }
 }
 
@@ -1318,7 +1336,12 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_bwd_hidden(LayerArgs
   __shared__ T S[IB][NCB * 16][ROWS + 1];
   __shared__ T red[MR == 1 ? NW : 1][NCB * 16][16];
   typedef typename vec4<T>::type V4;
-  auto bload = [&](int c, int k) -> V4 { return ldg<V4>(xb + (size_t)c * K + k); };
+  // a BF16 decoder's adjoints are stored as BF16 (complex-step BP only)
+  constexpr bool BFX = std::is_same<TW, __bf16>::value && !FD;
+  auto bload = [&](int c, int k) {
+    if constexpr (BFX) return ldg<bf16x8>(reinterpret_cast<const __bf16*>(xb) + (size_t)c * K + k);
+    else return ldg<V4>(xb + (size_t)c * K + k);
+  };
   // pre-activations of layer l-1 used by the epilogue, loaded before the GEMM
   constexpr int PP = (ROWS * 32 + NG - 1) / NG;  // items per thread: ROWS rows x (1 + n_q <= 32) channels
   T px0[PP], px1[PP];
@@ -1354,7 +1377,9 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_bwd_hidden(LayerArgs
           if (c == 0) v = d1 * Ss[0][r];
           else v = d1 * Ss[c][r] + d2 * px1[t] * Ss[0][r];
         }
-        stg<T>(xb_out + (size_t)c * m_inp + row, (row < m_in) ? v : T(0));
+        if constexpr (BFX)
+          stg<__bf16>(reinterpret_cast<__bf16*>(xb_out) + (size_t)c * m_inp + row, (__bf16)((row < m_in) ? v : T(0)));
+        else stg<T>(xb_out + (size_t)c * m_inp + row, (row < m_in) ? v : T(0));
       }
     }
   } else {

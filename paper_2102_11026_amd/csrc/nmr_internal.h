@@ -188,7 +188,7 @@ __device__ inline V ldg(const T* p) {
 }
 template <typename V, typename T>
 __device__ inline void stg(T* p, V v) {
-  if constexpr (std::is_scalar<V>::value) {
+  if constexpr (std::is_scalar<V>::value || sizeof(V) < 4) {  // scalars, and 2-byte types such as __bf16
     static_assert(std::is_same<V, T>::value, "scalar stores take the pointee type");
     *(NMR_GLOBAL V*)p = v;
   } else {
