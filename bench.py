@@ -40,8 +40,8 @@ PHASE_KERNEL = dict(dec_hidden="k_fwd_hidden", dec_out="k_fwd_out", bwd_out="k_b
 # factors a plain 512 MiB device copy gives), averaged over one pass of the
 # phase; see profiles/k_fwd_hidden_bar10k_fp32_pmc.md.  They hold only for the
 # kernel sources they were taken on: with any other sources traffic is null.
-MEASURED_TRAFFIC = dict(k_fwd_hidden=1644704, k_bwd_hidden=972633, k_fwd_out=6702327, k_bwd_out=5785349)
-MEASURED_TRAFFIC_SOURCES = "bb31dfa6c087bc12"
+MEASURED_TRAFFIC = dict(k_fwd_hidden=1649209, k_bwd_hidden=978848, k_fwd_out=6220032, k_bwd_out=5785600)
+MEASURED_TRAFFIC_SOURCES = "c549fa81e3b55b4a"
 KERNEL_SOURCES = ("paper_2102_11026_amd/csrc/decoder.hip", "paper_2102_11026_amd/csrc/nmr_internal.h")
 
 
@@ -294,7 +294,62 @@ def main():
     ap.add_argument("--profile-batch", type=int, default=0, metavar="B",
                     help="only step B instances of the 10k-vertex problem sharing one decoder (for a "
                          "profiler) and exit")
+    ap.add_argument("--profile-coupled", type=int, default=0, metavar="RODS",
+                    help="only step the coupled scene with RODS rods tied to the 21^3 core (for a profiler) "
+                         "and exit")
+    ap.add_argument("--profile-pools", type=int, default=0, metavar="SLOTS",
+                    help="only tick full slot pools of the three serving classes, SLOTS each (for a "
+                         "profiler), and exit")
     args = ap.parse_args()
+    if args.profile_coupled:
+        from paper_2102_11026_amd import nmr, synth
+        scene = synth.config_puffer(args.profile_coupled)
+        ctx = nmr.Context(0)
+        core = nmr.Instance(ctx, scene.core, args.precision)
+        dec = nmr.Decoder(ctx, scene.rods[0].weights, scene.rods[0].biases, scene.rods[0].act, args.precision)
+        rods = [nmr.Instance(ctx, q, args.precision, shared=dec) for q in scene.rods]
+        cs = nmr.Coupled(ctx, core, rods, scene.ties, scene.kappa)
+        cs.step(args.warmup, scene.newton_iters)
+        st, ms = cs.step(args.steps, scene.newton_iters, timings=True)
+        print(json.dumps(dict(rods=len(rods), precision=args.precision, steps=args.steps, status=sorted(set(st)),
+                              p50_step_ms=round(float(np.median(ms)), 4))))
+        cs.close()
+        for x in [core] + rods:
+            x.close()
+        dec.close()
+        ctx.close()
+        return
+    if args.profile_pools:
+        from paper_2102_11026_amd import nmr, synth
+        ctx = nmr.Context(0)
+        probs = {"A": synth.config_serve_a(), "B": synth.config_serve_b(), "C": synth.config_serve_c()}
+        pools, keep = {}, []
+        for name, q in probs.items():
+            dec = nmr.Decoder(ctx, q.weights, q.biases, q.act, args.precision)
+            pool = nmr.Pool(ctx, args.profile_pools)
+            for k in range(args.profile_pools):
+                r0 = np.zeros(q.R)
+                r0[q.n_p:] = 0.1 * synth.normal(f"serve/q0/{1000 + k}", q.n_q)
+                x = nmr.Instance(ctx, q.replace(r0=r0), args.precision, shared=dec)
+                pool.attach(x)
+                keep.append(x)
+            pools[name] = pool
+            keep.append(dec)
+        for _ in range(args.warmup):
+            for pool in pools.values():
+                pool.step(ITERS)
+        ticks = {k: [] for k in pools}
+        for _ in range(args.steps):
+            for name, pool in pools.items():
+                ticks[name].append(pool.step(ITERS, timing=True)[1])
+        print(json.dumps(dict(slots=args.profile_pools, precision=args.precision,
+                              median_pool_step_ms={k: round(float(np.median(v)), 3) for k, v in ticks.items()})))
+        for pool in pools.values():
+            pool.close()
+        for x in keep:
+            x.close()
+        ctx.close()
+        return
     if args.profile_batch:
         import torch
         from paper_2102_11026_amd import nmr, synth
