@@ -117,6 +117,10 @@ struct nmr_decoder {
   DevMem mem;
   int refs = 1;  // the creator's reference
   bool charged = false;
+  // Gram matrices of the output layer (Gram-folded path) by mesh: instances of
+  // one decoder on the same mesh, mass, pins, time step and gravity share them
+  std::map<uint64_t, std::pair<double*, double*>> gram_cache;
+  DevMem gram_mem;
 };
 
 struct nmr_inst {
@@ -369,9 +373,32 @@ static int decoder_build(nmr_ctx* ctx, const nmr_mlp_desc* desc, int prec, nmr_d
 static void decoder_unref(nmr_decoder* d) {
   if (--d->refs == 0) {
     if (d->charged) d->ctx->used -= d->mem.bytes;
+    d->ctx->used -= d->gram_mem.bytes;
     d->mem.release();
+    d->gram_mem.release();
     delete d;
   }
+}
+
+// key of the output layer's Gram matrices: everything they depend on besides
+// the decoder (FNV-1a over the mesh, pins, density, time step, gravity, the
+// element type)
+static uint64_t gram_key(const nmr_problem* p, int real_bytes) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* data, size_t n) {
+    const unsigned char* b = static_cast<const unsigned char*>(data);
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  };
+  mix(&p->n_vertices, sizeof(int));
+  mix(&p->n_tets, sizeof(int));
+  mix(&real_bytes, sizeof(int));
+  mix(&p->rho, sizeof(double));
+  mix(&p->dt, sizeof(double));
+  mix(p->gravity, 3 * sizeof(double));
+  mix(p->X, (size_t)p->n_vertices * 3 * sizeof(double));
+  mix(p->tets, (size_t)p->n_tets * 4 * sizeof(int32_t));
+  mix(p->pinned, (size_t)p->n_vertices);
+  return h;
 }
 
 extern "C" int nmr_decoder_create(nmr_ctx* ctx, const nmr_mlp_desc* desc, int prec, nmr_decoder** out) {
@@ -569,16 +596,29 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   I.n_gblk = s.n_gblk;
   I.n_cdofs = s.n_cdofs;
   I.n_sblk = s.n_sblk;
+  bool gram_new = false;
+  uint64_t gkey = 0;
   if (s.gram) {
     int* cd;
-    double *Gm, *gm;
     CHK(dalloc_t(M, s.n_cdofs, &cd));
-    CHK(dalloc_t(M, (size_t)s.K * s.K, &Gm));
-    CHK(dalloc_t(M, s.K, &gm));
     HIPCHK(hipMemcpy(cd, s.cdofs.data(), s.n_cdofs * sizeof(int), hipMemcpyHostToDevice));
     I.cdofs = cd;
-    I.Gam = Gm;
-    I.gam = gm;
+    gkey = gram_key(p, (int)sizeof(T));
+    auto it = dec->gram_cache.find(gkey);
+    if (it != dec->gram_cache.end()) {
+      I.Gam = it->second.first;
+      I.gam = it->second.second;
+    } else {
+      // computed below, after the lumped mass, and cached once that succeeded
+      double *Gm, *gm;
+      const size_t before = dec->gram_mem.bytes;
+      CHK(dalloc_t(dec->gram_mem, (size_t)s.K * s.K, &Gm));
+      CHK(dalloc_t(dec->gram_mem, s.K, &gm));
+      ctx->used += dec->gram_mem.bytes - before;
+      I.Gam = Gm;
+      I.gam = gm;
+      gram_new = true;
+    }
   }
   CHK(dalloc_t(M, s.R * s.R + s.R, &I.sum_cub));
   CHK(dalloc_t(M, s.R * s.R + s.R * s.n_q + s.R + s.n_p, &I.sum_mass));
@@ -679,13 +719,14 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
     (void)hipMemcpy(dvp, vcnt.data(), 4 * (size_t)(s.n + 1), hipMemcpyHostToDevice);
     (void)hipMemcpy(dve, vent.data(), 4 * (size_t)(4 * s.m), hipMemcpyHostToDevice);
     launch_rest_shape<T>(dX, dT, s.m, dcub, s.n_cub, dvp, dve, s.n, p->rho, Bm, Ve, mass, dVe, ctx->stream);
-    if (s.gram)
+    if (gram_new)
       launch_gram_setup<T>(d.W[d.L - 1], d.prec, s.K, mass, keep, s.N, p->dt, p->gravity, const_cast<double*>(I.Gam),
                            const_cast<double*>(I.gam), ctx->stream);
     hipError_t e1 = hipGetLastError();
     hipError_t e2 = hipStreamSynchronize(ctx->stream);
     tmp.release();
     if (e1 != hipSuccess || e2 != hipSuccess) return fail(NMR_ERR_DEVICE, "rest-shape setup failed");
+    if (gram_new) dec->gram_cache.emplace(gkey, std::make_pair(const_cast<double*>(I.Gam), const_cast<double*>(I.gam)));
   }
   // device copies of the instance table
   CHK(dalloc(M, sizeof(Inst<T>), &in->tab));
