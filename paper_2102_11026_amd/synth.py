@@ -538,3 +538,76 @@ def config_puffer(n_rods: int = 320) -> CoupledScene:
     return coupled_scene("puffer", (21, 21, 21), n_rods, ROD_LENGTHS, core_np=10,
                          core_widths=[6, 32, 64, 128, 3 * 21 ** 3], rod_np=10, rod_widths=ROD_WIDTHS,
                          steps=60, newton_iters=3)
+
+
+# --------------------------------------------------------------------------
+# neural cubature training sets (Sec. 5)
+# --------------------------------------------------------------------------
+@dataclass
+class CubatureTraining:
+    """Poses and initial networks of one neural cubature training run.
+
+    ``prob`` gives the mesh, material, U and decoder; ``poses`` (P x R) stand
+    in for the simulated training poses of Sec. 5 (normal draws at the
+    magnitudes the simulator visits).  The weight net has widths
+    [R, *hidden, c_max] (Xavier, zero biases) with c_max = n_c0 + K *
+    alternations rows in its last layer, one per element C will hold; scale =
+    (m / c_max) / ln 2.  ``theta`` holds the selection net's 170 parameters in
+    the order G0 (3 x 8), G1 (8 x 8), A1 (8 x 8), a1 (8), A2 (8), a2, c: the
+    matrices Xavier-normal, the rest zero."""
+    prob: Problem
+    poses: np.ndarray
+    wnet_weights: List[np.ndarray]
+    wnet_biases: List[np.ndarray]
+    scale: float
+    theta: np.ndarray
+    n_c0: int
+    K: int
+    alternations: int
+    epochs: int
+    lr: float = 1.0e-3
+
+    @property
+    def c_max(self) -> int:
+        return self.n_c0 + self.K * self.alternations
+
+
+def cubature_training(prob: Problem, n_poses: int, n_c0: int, K: int, alternations: int, epochs: int,
+                      hidden=(64, 64), p_std: float = 0.02, q_std: float = 0.1, name: str = "cubtrain",
+                      seed: int = MASTER_SEED) -> CubatureTraining:
+    R, n_p = prob.R, prob.n_p
+    z = normal(f"{name}/poses", n_poses * R, seed).reshape(n_poses, R)
+    poses = np.concatenate([p_std * z[:, :n_p], q_std * z[:, n_p:]], axis=1)
+    c_max = n_c0 + K * alternations
+    Ws, bs = xavier_mlp([R, *hidden, c_max], f"{name}/wnet", seed)
+    m = prob.tets.shape[0]
+    scale = (m / c_max) / np.log(2.0)
+    parts = []
+    for k, (fi, fo) in enumerate([(3, 8), (8, 8), (8, 8)]):
+        parts.append(normal(f"{name}/snet/{k}", fi * fo, seed) * np.sqrt(2.0 / (fi + fo)))
+    parts.append(np.zeros(8))
+    parts.append(normal(f"{name}/snet/3", 8, seed) * np.sqrt(2.0 / 9.0))
+    parts.append(np.zeros(2))
+    theta = np.concatenate(parts)
+    return CubatureTraining(prob=prob, poses=poses, wnet_weights=Ws, wnet_biases=bs, scale=scale, theta=theta,
+                            n_c0=n_c0, K=K, alternations=alternations, epochs=epochs)
+
+
+def config_cubature_tiny() -> CubatureTraining:
+    """Small training run for the parity tests: a 3 x 3 x 4 bar (36 vertices,
+    60 tets), n_p = 2 plus a tanh decoder [3, 8, 8, 108] (output layer scaled
+    by 0.05); 12 poses, C from 4
+    samples plus 4 per alternation over 3 alternations of 4 epochs, weight net
+    [5, 16, 16, 16]."""
+    p = tiny_problem(grid=(3, 3, 4), widths=(3, 8, 8, 108), act="tanh", n_p=2, name="cubtiny", out_scale=0.05)
+    return cubature_training(p, 12, 4, 4, 3, 4, hidden=(16, 16), q_std=0.3, name="cubtiny")
+
+
+def config_cubature_bar10k(n_poses: int = 1024) -> CubatureTraining:
+    """Training run on the 10,000-vertex bar (43,320 tets, r = 15, the ELU
+    decoder of the headline problem): n_poses poses, C from 20 Voronoi samples
+    plus 20 per alternation up to 500 elements, weight net 15 -> 64 -> 64 ->
+    500, 15 epochs per net per alternation (Sec. 5)."""
+    p = config_single_10k().replace(cub_ids=np.arange(43320, dtype=np.int32), cub_w=np.ones(43320),
+                                   wnet_weights=None, wnet_biases=None, wnet_scale=1.0)
+    return cubature_training(p, n_poses, 20, 20, 24, 15, name="cubbar10k")
