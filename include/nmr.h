@@ -352,6 +352,83 @@ typedef struct {
  * and that number to *n. */
 int nmr_tiling_table(nmr_ctx* ctx, nmr_tile_choice* out, int cap, int* n);
 
+/* ---- neural cubature training (Sec. 5) --------------------------------- */
+
+/* Reduced force of every element at pose r (Sec. 5.1, the training data of
+ * the cubature networks): with u = U p + D(q) and Jt = [U, J] at r,
+ * F[e] = Jt_e^T f_e(u) for every tet e, f_e its neo-Hookean force.  Device
+ * input r [R doubles]; device outputs F [n_tets x R doubles], f_or_null [R
+ * doubles] = sum_e F[e] (the full-quadrature reduced force, tets in index
+ * order), u_or_null [N doubles].  Decoder derivatives as in
+ * decoder_jacobian_hessian in the instance's precision, element arithmetic in
+ * FP64.  Allocates its working memory; NMR_ERR_INVERTED if a tet has
+ * det F <= 0 (its row of F is then zero).  The instance state is unchanged.
+ * Synchronizes. */
+int nmr_element_forces(nmr_inst* inst, const double* r, double* F, double* f_or_null, double* u_or_null);
+
+typedef struct nmr_trainer nmr_trainer; /* one neural cubature training run */
+
+/* A training run (host pointers, read only during nmr_trainer_create). */
+typedef struct {
+  int n_poses;               /* P >= 1                                          */
+  const double* poses;       /* P x R training poses r_p                        */
+  int c_max;                 /* elements the cubature set may hold, < n_tets    */
+  int n_c0;                  /* initial set size, 1 <= n_c0 <= c_max            */
+  const int32_t* c0;         /* n_c0 distinct tet ids, or NULL: n_c0            */
+                             /* farthest-point samples of the tet centroids     */
+                             /* from tet 0 (the Voronoi samples of Sec. 5.2)    */
+  int K;                     /* elements added per alternation (Sec. 5.1)       */
+  int epochs;                /* Adam steps per net per alternation              */
+  double lr, beta1, beta2, eps;  /* Adam (the paper: lr = 1e-3)                 */
+  const nmr_mlp_desc* wnet;  /* weight net R -> ... -> c_max, softplus after    */
+                             /* every layer, hidden widths <= 1024; row j of    */
+                             /* its last layer serves the j-th element to join  */
+  double wnet_scale;         /* w = wnet_scale * wnet(r) (> 0)                  */
+  const double* snet;        /* 170 selection-net parameters: G0 [3][8] and     */
+                             /* G1 [8][8] (graph convolutions, [in][out]), A1   */
+                             /* [8][8] ([out][in]), a1 [8], A2 [8], a2, c       */
+} nmr_cubature_train_desc;
+
+/* Neural cubature training (Sec. 5) on the instance's mesh, decoder and U:
+ * computes the training data of every pose (nmr_element_forces) into device
+ * memory (P x n_tets x R doubles of element forces, the run's largest
+ * buffer), copies both nets and picks the initial set.  The trainer keeps no
+ * reference to the instance.  NMR_ERR_INVERTED if a pose inverts a tet;
+ * NMR_ERR_BUDGET beyond the context's HBM budget.  Synchronizes. */
+int nmr_trainer_create(nmr_inst* inst, const nmr_cubature_train_desc* desc, nmr_trainer** out);
+int nmr_trainer_destroy(nmr_trainer* tr);
+
+/* n_alternations alternations of Sec. 5: `epochs` full-batch Adam steps of
+ * the weight net on L_W = mean_p |f_p - sum_{j<|C|} w_j(r_p) F_p[C_j]|^2 /
+ * |f_p|^2; the residual forces fb_p of the trained weights (eq. of the
+ * residual force); `epochs` Adam steps of the selection net -- two graph
+ * convolutions h' = sin(sum over the one-ring (self included) of
+ * h_j Gamma / sqrt(d_i d_j)) of the vertex displacements, element feature =
+ * mean of its vertices, sin(A1 g + a1), logit A2 . y + a2, scores e^c times
+ * the softmax over the elements outside C -- on L_S = mean_p |fb_p -
+ * sum_{e not in C} s_e F_p[e]|^2 / |fb_p|^2; then the K elements outside C
+ * with the largest score averaged over the poses (ties to the lower id) join
+ * C.  Each net keeps its Adam state across alternations; rows of the weight
+ * net's last layer beyond |C| stay as given until their element joins.
+ * Host outputs (each may be NULL): loss_w and loss_s [n_alternations x
+ * epochs], each net's loss before each of its steps; added [n_alternations x
+ * K]; ms_or_null: device time of the whole call.  NMR_ERR_ARG if |C| would
+ * exceed c_max.  Every sum runs in a fixed order: a run is bitwise repeatable.
+ * Synchronizes. */
+int nmr_trainer_run(nmr_trainer* tr, int n_alternations, double* loss_w, double* loss_s, int* added,
+                    float* ms_or_null);
+
+/* The current set and nets (host outputs, each but n_c may be NULL): n_c =
+ * |C|, C [|C|] in joining order, the weight net's parameters [W_0 (row-major),
+ * b_0, ..., W_{L-1} (c_max rows), b_{L-1}] and the 170 selection-net
+ * parameters.  The first |C| rows of the last layer with scale wnet_scale
+ * form the run-time weight net of an instance whose cubature set is C. */
+int nmr_trainer_get(nmr_trainer* tr, int* n_c, int32_t* C_or_null, double* wnet_or_null, double* snet_or_null);
+
+/* Training data of pose p (host outputs, each may be NULL): F [n_tets x R],
+ * f [R], u [N]. */
+int nmr_trainer_pose(nmr_trainer* tr, int p, double* F_or_null, double* f_or_null, double* u_or_null);
+
 /* ---- measurement -------------------------------------------------------- */
 
 /* Phases of one Newton iteration, in launch order. */

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libnmr.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "decoder.hip", "sim.hip", "couple.hip"]
+SOURCES = ["api.hip", "decoder.hip", "sim.hip", "couple.hip", "train.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -142,6 +142,9 @@ struct nmr_inst {
   nmr_pool* pool = nullptr;  // the pool this instance is attached to, if any
   int pool_slot = -1;
   int coupled_refs = 0;      // coupled sets this instance is a member of
+  int m = 0;                 // tets of the mesh
+  std::vector<double> Xh;    // host copies of the rest positions and tets
+  std::vector<int32_t> tets_h;  // (the training data covers every tet)
 };
 
 // ---------------------------------------------------------------------------
@@ -545,6 +548,9 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   in->gram = s.gram; in->n_cdofs = s.n_cdofs; in->n_sblk = s.n_sblk;
   in->cdofs = s.cdofs;
   in->fd = p->fd_h > 0 ? 1 : 0;
+  in->m = s.m;
+  in->Xh.assign(p->X, p->X + 3 * (size_t)s.n);
+  in->tets_h.assign(p->tets, p->tets + 4 * (size_t)s.m);
   in->host.assign(sizeof(Inst<T>), 0);
   Inst<T>& I = host_inst<T>(in);
   I.active = 1;
@@ -1856,4 +1862,424 @@ extern "C" int nmr_time_phase(nmr_inst* in, int phase, int reps, float* avg_us) 
   if (!in || !avg_us || phase < 0 || phase >= NMR_PHASE_COUNT || reps < 1) return fail(NMR_ERR_ARG, "bad argument");
   CHK(set_device(in->ctx));
   return is_f64(in) ? time_phase_impl<double>(in, phase, reps, avg_us) : time_phase_impl<float>(in, phase, reps, avg_us);
+}
+
+// ---------------------------------------------------------------------------
+// neural cubature training (Sec. 5): training data from the instance's
+// decoder and mesh, then the alternation of the weight and selection nets
+// ---------------------------------------------------------------------------
+namespace {
+
+// every tet of the instance's mesh in FP64, rest shape on the device
+int mesh_build(nmr_inst* in, DevMem& M, TrainMesh* tm) {
+  tm->n = in->n;
+  tm->N = in->N;
+  tm->m = in->m;
+  if (is_f64(in)) {
+    tm->mu = host_inst<double>(in).mu;
+    tm->lam = host_inst<double>(in).lam;
+  } else {
+    tm->mu = host_inst<float>(in).mu;
+    tm->lam = host_inst<float>(in).lam;
+  }
+  double *X, *Bm, *Ve;
+  int* tets;
+  CHK(dalloc_t(M, 3 * (size_t)in->n, &X));
+  CHK(dalloc_t(M, 4 * (size_t)in->m, &tets));
+  CHK(dalloc_t(M, 9 * (size_t)in->m, &Bm));
+  CHK(dalloc_t(M, (size_t)in->m, &Ve));
+  HIPCHK(hipMemcpy(X, in->Xh.data(), 3 * (size_t)in->n * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(tets, in->tets_h.data(), 4 * (size_t)in->m * sizeof(int), hipMemcpyHostToDevice));
+  launch_rest_all(X, tets, in->m, Bm, Ve, in->ctx->stream);
+  HIPCHK(hipGetLastError());
+  tm->X = X;
+  tm->tets = tets;
+  tm->Bm = Bm;
+  tm->Ve = Ve;
+  return NMR_OK;
+}
+
+// F[p] (m x R), u[p] (N) for poses r[p] (device, P x R), p < P; then f[p] = sum_e F[p][e]
+template <typename T>
+int pose_forces(nmr_inst* in, const TrainMesh& tm, const double* r, int P, double* u, double* F, double* f) {
+  nmr_ctx* c = in->ctx;
+  hipStream_t s = c->stream;
+  Inst<T>& I = host_inst<T>(in);
+  const int N = in->N, nq = in->n_q, np = in->n_p, R = in->R;
+  DevMem tmp;
+  T *uD, *J, *dJ, *Hdd;
+  int* st;
+  std::vector<double> save(3 * nq);
+  int rc = NMR_OK;
+  auto body = [&]() -> int {
+    CHK(dalloc_t(tmp, N, &uD));
+    CHK(dalloc_t(tmp, (size_t)N * nq, &J));
+    CHK(dalloc_t(tmp, (size_t)N * nq, &dJ));
+    CHK(dalloc_t(tmp, N, &Hdd));
+    CHK(dalloc_t(tmp, 1, &st));
+    // the decoder input buffer is the instance's: kept and put back
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(save.data(), I.dec_in, 3 * nq * sizeof(double), hipMemcpyDeviceToHost));
+    void* dt_tab;
+    CHK(direct_tab<T>(in, &dt_tab));
+    const Inst<T>* tab = static_cast<const Inst<T>*>(dt_tab);
+    std::vector<nmr_inst*> v{in};
+    Group g = group_of(v, dt_tab);
+    g.gram = false;
+    for (int p = 0; p < P; ++p) {
+      const double* rp = r + (size_t)p * R;
+      HIPCHK(hipMemcpyAsync(I.dec_in, rp + np, nq * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemsetAsync(I.dec_in + nq, 0, 2 * nq * sizeof(double), s));
+      enqueue_decoder_fwd<T>(g, s, 0);
+      launch_unpack<T>(tab, uD, J, dJ, Hdd, N, s);
+      launch_elem_forces<T>(tm, I.U, np, rp, uD, J, nq, u + (size_t)p * N, F + (size_t)p * tm.m * R, st, s);
+    }
+    if (f) launch_force_sum(F, P, tm.m, R, f, s);
+    HIPCHK(hipGetLastError());
+    int hst = 0;
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipMemcpy(&hst, st, sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(I.dec_in, save.data(), 3 * nq * sizeof(double), hipMemcpyHostToDevice));
+    if (hst & ST_INVERTED) return fail(NMR_ERR_INVERTED, "a tet has det F <= 0 at a training pose");
+    return NMR_OK;
+  };
+  rc = body();
+  (void)hipStreamSynchronize(s);
+  tmp.release();
+  return rc;
+}
+
+}  // namespace
+
+extern "C" int nmr_element_forces(nmr_inst* in, const double* r, double* F, double* f_or_null, double* u_or_null) {
+  if (!in || !r || !F) return fail(NMR_ERR_ARG, "null argument");
+  CHK(set_device(in->ctx));
+  DevMem M;
+  TrainMesh tm{};
+  double* u = u_or_null;
+  int rc = mesh_build(in, M, &tm);
+  if (rc == NMR_OK && !u) rc = dalloc_t(M, (size_t)in->N, &u);
+  if (rc == NMR_OK)
+    rc = is_f64(in) ? pose_forces<double>(in, tm, r, 1, u, F, f_or_null)
+                    : pose_forces<float>(in, tm, r, 1, u, F, f_or_null);
+  (void)hipStreamSynchronize(in->ctx->stream);
+  M.release();
+  return rc;
+}
+
+struct nmr_trainer {
+  nmr_ctx* ctx = nullptr;
+  DevMem dev;
+  int P = 0, R = 0, n = 0, N = 0, m = 0;
+  int K = 0, epochs = 0, c_max = 0, nC = 0;
+  double lr = 1e-3, b1 = 0.9, b2 = 0.999, eps = 1e-8;
+  long long tw = 0, ts = 0;  // Adam steps taken by each net
+  size_t n_w = 0;            // weight-net parameter count
+  TrainMesh tm{};
+  TrainData td{};
+  WNetDev w{};
+  SNetDev sd{};
+  double *wm = nullptr, *wv = nullptr, *sm = nullptr, *sv = nullptr;
+  double* theta = nullptr;
+  double* mean = nullptr;    // [m] averaged scores (also the sampling distances)
+  int* C = nullptr;
+  int* inC = nullptr;
+  double* losses = nullptr;  // [2 epochs] one alternation's loss history
+  std::vector<int> Ch;       // host copy of C
+  int broken = 0;            // 1 after a selection found no finite score
+};
+
+namespace {
+
+int trainer_build(nmr_inst* in, const nmr_cubature_train_desc* d, nmr_trainer* tr) {
+  DevMem& M = tr->dev;
+  const int P = d->n_poses, R = in->R, n = in->n, N = in->N, m = in->m;
+  tr->P = P;
+  tr->R = R;
+  tr->n = n;
+  tr->N = N;
+  tr->m = m;
+  tr->K = d->K;
+  tr->epochs = d->epochs;
+  tr->c_max = d->c_max;
+  tr->lr = d->lr;
+  tr->b1 = d->beta1;
+  tr->b2 = d->beta2;
+  tr->eps = d->eps;
+  CHK(mesh_build(in, M, &tr->tm));
+  // training data
+  double *r, *F, *f, *fb, *u, *loss_p;
+  CHK(dalloc_t(M, (size_t)P * R, &r));
+  CHK(dalloc_t(M, (size_t)P * m * R, &F));
+  CHK(dalloc_t(M, (size_t)P * R, &f));
+  CHK(dalloc_t(M, (size_t)P * R, &fb));
+  CHK(dalloc_t(M, (size_t)P * N, &u));
+  CHK(dalloc_t(M, (size_t)P, &loss_p));
+  CHK(dalloc_t(M, (size_t)d->c_max, &tr->C));
+  CHK(dalloc_t(M, (size_t)m, &tr->inC));
+  CHK(dalloc_t(M, (size_t)m, &tr->mean));
+  CHK(dalloc_t(M, 2 * (size_t)d->epochs, &tr->losses));
+  HIPCHK(hipMemcpy(r, d->poses, (size_t)P * R * sizeof(double), hipMemcpyHostToDevice));
+  CHK(is_f64(in) ? pose_forces<double>(in, tr->tm, r, P, u, F, f) : pose_forces<float>(in, tr->tm, r, P, u, F, f));
+  tr->td = TrainData{P, R, m, r, F, f, fb, tr->C, loss_p};
+  // weight net
+  const nmr_mlp_desc* wd = d->wnet;
+  WNetDev& w = tr->w;
+  w.L = wd->n_layers;
+  w.scale = d->wnet_scale;
+  size_t off = 0;
+  for (int l = 0; l <= w.L; ++l) w.width[l] = wd->widths[l];
+  for (int l = 0; l < w.L; ++l) {
+    w.Woff[l] = off;
+    off += (size_t)w.width[l + 1] * w.width[l];
+    w.boff[l] = off;
+    off += (size_t)w.width[l + 1];
+  }
+  tr->n_w = off;
+  CHK(dalloc_t(M, off, &w.x));
+  CHK(dalloc_t(M, off, &w.g));
+  CHK(dalloc_t(M, off, &tr->wm));
+  CHK(dalloc_t(M, off, &tr->wv));
+  {
+    std::vector<double> hx(off);
+    for (int l = 0; l < w.L; ++l) {
+      std::copy(wd->W[l], wd->W[l] + (size_t)w.width[l + 1] * w.width[l], hx.begin() + w.Woff[l]);
+      std::copy(wd->b[l], wd->b[l] + w.width[l + 1], hx.begin() + w.boff[l]);
+    }
+    HIPCHK(hipMemcpy(w.x, hx.data(), off * sizeof(double), hipMemcpyHostToDevice));
+  }
+  for (int l = 0; l < w.L; ++l) {
+    CHK(dalloc_t(M, (size_t)P * w.width[l + 1], &w.a[l]));
+    CHK(dalloc_t(M, (size_t)P * w.width[l + 1], &w.z[l]));
+    CHK(dalloc_t(M, (size_t)P * w.width[l + 1], &w.d[l]));
+  }
+  // selection net: one-ring graph (self included) and vertex -> tet lists
+  std::vector<std::vector<int>> ring(n);
+  for (int e = 0; e < m; ++e)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) ring[in->tets_h[4 * e + a]].push_back(in->tets_h[4 * e + b]);
+  std::vector<int> gptr(n + 1, 0), gidx;
+  std::vector<double> gval;
+  for (int i = 0; i < n; ++i) {
+    std::sort(ring[i].begin(), ring[i].end());
+    ring[i].erase(std::unique(ring[i].begin(), ring[i].end()), ring[i].end());
+    gptr[i + 1] = gptr[i] + (int)ring[i].size();
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j : ring[i]) {
+      gidx.push_back(j);
+      gval.push_back(1.0 / std::sqrt((double)ring[i].size() * (double)ring[j].size()));
+    }
+  std::vector<int> vptr(n + 1, 0), vtet(4 * (size_t)m);
+  for (int e = 0; e < m; ++e)
+    for (int a = 0; a < 4; ++a) vptr[in->tets_h[4 * e + a] + 1]++;
+  for (int i = 0; i < n; ++i) vptr[i + 1] += vptr[i];
+  {
+    std::vector<int> fill(vptr.begin(), vptr.end() - 1);
+    for (int e = 0; e < m; ++e)
+      for (int a = 0; a < 4; ++a) vtet[fill[in->tets_h[4 * e + a]]++] = e;
+  }
+  SNetDev& sd = tr->sd;
+  sd.n = n;
+  sd.m = m;
+  sd.R = R;
+  sd.P = P;
+  sd.nbv = (n + 255) / 256;
+  sd.nbe = (m + 255) / 256;
+  sd.u = u;
+  int *g_ptr, *g_idx, *vt_ptr, *vt_tet;
+  double* g_val;
+  CHK(dalloc_t(M, (size_t)n + 1, &g_ptr));
+  CHK(dalloc_t(M, gidx.size(), &g_idx));
+  CHK(dalloc_t(M, gval.size(), &g_val));
+  CHK(dalloc_t(M, (size_t)n + 1, &vt_ptr));
+  CHK(dalloc_t(M, vtet.size(), &vt_tet));
+  HIPCHK(hipMemcpy(g_ptr, gptr.data(), gptr.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(g_idx, gidx.data(), gidx.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(g_val, gval.data(), gval.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(vt_ptr, vptr.data(), vptr.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(vt_tet, vtet.data(), vtet.size() * sizeof(int), hipMemcpyHostToDevice));
+  sd.g_ptr = g_ptr;
+  sd.g_idx = g_idx;
+  sd.g_val = g_val;
+  sd.vt_ptr = vt_ptr;
+  sd.vt_tet = vt_tet;
+  sd.tets = tr->tm.tets;
+  sd.inC = tr->inC;
+  CHK(dalloc_t(M, 170, &tr->theta));
+  CHK(dalloc_t(M, 170, &tr->sm));
+  CHK(dalloc_t(M, 170, &tr->sv));
+  HIPCHK(hipMemcpy(tr->theta, d->snet, 170 * sizeof(double), hipMemcpyHostToDevice));
+  sd.theta = tr->theta;
+  sd.F = F;
+  sd.fb = fb;
+  const size_t Pn = (size_t)P * n;
+  CHK(dalloc_t(M, 3 * Pn, &sd.H0));
+  CHK(dalloc_t(M, 8 * Pn, &sd.P1));
+  CHK(dalloc_t(M, 8 * Pn, &sd.X1));
+  CHK(dalloc_t(M, 8 * Pn, &sd.H1));
+  CHK(dalloc_t(M, 8 * Pn, &sd.P2));
+  CHK(dalloc_t(M, 8 * Pn, &sd.X2));
+  CHK(dalloc_t(M, 8 * Pn, &sd.T2));
+  CHK(dalloc_t(M, (size_t)P * m, &sd.z));
+  CHK(dalloc_t(M, (size_t)P * sd.nbe * (R + 2), &sd.pf));
+  CHK(dalloc_t(M, (size_t)P * 8, &sd.pstat));
+  CHK(dalloc_t(M, (size_t)P * R, &sd.res));
+  sd.loss_p = loss_p;
+  CHK(dalloc_t(M, (size_t)P * m * 8, &sd.dg));
+  CHK(dalloc_t(M, (size_t)P * sd.nbe * 81, &sd.pe));
+  CHK(dalloc_t(M, (size_t)P * sd.nbv * 64, &sd.pv2));
+  CHK(dalloc_t(M, (size_t)P * sd.nbv * 24, &sd.pv1));
+  CHK(dalloc_t(M, (size_t)P * 170, &sd.gpose));
+  CHK(dalloc_t(M, 170, &sd.grad));
+  // initial cubature set: the caller's, or farthest-point samples
+  if (d->c0) {
+    std::vector<int> hin(m, 0);
+    for (int k = 0; k < d->n_c0; ++k) {
+      const int e = d->c0[k];
+      if (e < 0 || e >= m) return fail(NMR_ERR_ARG, "initial cubature id out of range");
+      if (hin[e]) return fail(NMR_ERR_ARG, "initial cubature ids must be distinct");
+      hin[e] = 1;
+    }
+    HIPCHK(hipMemcpy(tr->C, d->c0, d->n_c0 * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(tr->inC, hin.data(), m * sizeof(int), hipMemcpyHostToDevice));
+  } else {
+    launch_fps(tr->tm.X, tr->tm.tets, m, d->n_c0, tr->mean, tr->C, tr->inC, in->ctx->stream);
+    HIPCHK(hipGetLastError());
+  }
+  tr->nC = d->n_c0;
+  tr->Ch.resize(d->c_max);
+  HIPCHK(hipStreamSynchronize(in->ctx->stream));
+  HIPCHK(hipMemcpy(tr->Ch.data(), tr->C, d->n_c0 * sizeof(int), hipMemcpyDeviceToHost));
+  for (int k = 0; k < d->n_c0; ++k)
+    if (tr->Ch[k] < 0) return fail(NMR_ERR_NONFINITE, "non-finite tet centroids");
+  return NMR_OK;
+}
+
+int trainer_alternation(nmr_trainer* tr, double* lw, double* ls, int* added) {
+  hipStream_t s = tr->ctx->stream;
+  const int E = tr->epochs;
+  for (int ep = 0; ep < E; ++ep) {
+    WNetDev w = tr->w;
+    w.loss_out = tr->losses + ep;
+    launch_wnet_epoch(w, tr->td, tr->nC, 0, s);
+    ++tr->tw;
+    launch_adam(tr->w.x, tr->w.g, tr->wm, tr->wv, (long long)tr->n_w, tr->lr, tr->b1, tr->b2, tr->eps,
+                1.0 - std::pow(tr->b1, (double)tr->tw), 1.0 - std::pow(tr->b2, (double)tr->tw), s);
+  }
+  launch_wnet_epoch(tr->w, tr->td, tr->nC, 1, s);  // residual forces fb with the trained weights
+  for (int ep = 0; ep < E; ++ep) {
+    SNetDev sd = tr->sd;
+    sd.loss_out = tr->losses + E + ep;
+    launch_snet_epoch(sd, s);
+    ++tr->ts;
+    launch_adam(tr->theta, tr->sd.grad, tr->sm, tr->sv, 170, tr->lr, tr->b1, tr->b2, tr->eps,
+                1.0 - std::pow(tr->b1, (double)tr->ts), 1.0 - std::pow(tr->b2, (double)tr->ts), s);
+  }
+  launch_snet_forward(tr->sd, s);  // scores with the trained selection net
+  launch_select(tr->sd, tr->mean, tr->K, tr->inC, tr->C, tr->nC, s);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(s));
+  if (lw) HIPCHK(hipMemcpy(lw, tr->losses, E * sizeof(double), hipMemcpyDeviceToHost));
+  if (ls) HIPCHK(hipMemcpy(ls, tr->losses + E, E * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(tr->Ch.data() + tr->nC, tr->C + tr->nC, tr->K * sizeof(int), hipMemcpyDeviceToHost));
+  if (added) std::copy(tr->Ch.begin() + tr->nC, tr->Ch.begin() + tr->nC + tr->K, added);
+  for (int k = 0; k < tr->K; ++k)
+    if (tr->Ch[tr->nC + k] < 0) {
+      tr->broken = 1;
+      return fail(NMR_ERR_NONFINITE, "no finite candidate score: the trainer is left unusable");
+    }
+  tr->nC += tr->K;
+  return NMR_OK;
+}
+
+}  // namespace
+
+extern "C" int nmr_trainer_create(nmr_inst* in, const nmr_cubature_train_desc* d, nmr_trainer** out) {
+  if (!in || !d || !out) return fail(NMR_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (d->n_poses < 1 || !d->poses) return fail(NMR_ERR_ARG, "need at least one pose");
+  if (d->K < 1 || d->epochs < 1) return fail(NMR_ERR_ARG, "K and epochs must be >= 1");
+  if (!(d->lr > 0.0) || !(d->beta1 >= 0.0 && d->beta1 < 1.0) || !(d->beta2 >= 0.0 && d->beta2 < 1.0) ||
+      !(d->eps > 0.0))
+    return fail(NMR_ERR_ARG, "Adam needs lr > 0, 0 <= beta < 1, eps > 0");
+  if (!d->snet) return fail(NMR_ERR_ARG, "missing selection-net parameters");
+  CHK(check_mlp(d->wnet, 1, "weight net"));
+  const nmr_mlp_desc* wd = d->wnet;
+  if (wd->widths[0] != in->R) return fail(NMR_ERR_ARG, "weight net input must be R");
+  if (wd->widths[wd->n_layers] != d->c_max) return fail(NMR_ERR_ARG, "weight net output must be c_max");
+  for (int l = 1; l < wd->n_layers; ++l)
+    if (wd->widths[l] > 1024) return fail(NMR_ERR_ARG, "weight-net hidden widths must be <= 1024");
+  if (d->n_c0 < 1 || d->n_c0 > d->c_max) return fail(NMR_ERR_ARG, "need 1 <= n_c0 <= c_max");
+  if (d->c_max >= in->m) return fail(NMR_ERR_ARG, "c_max must be below the tet count");
+  if (!(d->wnet_scale > 0.0)) return fail(NMR_ERR_ARG, "wnet_scale must be > 0");
+  CHK(set_device(in->ctx));
+  nmr_trainer* tr = new nmr_trainer();
+  tr->ctx = in->ctx;
+  int rc = trainer_build(in, d, tr);
+  nmr_ctx* c = in->ctx;
+  if (rc == NMR_OK && c->budget && c->used + tr->dev.bytes > c->budget) rc = fail(NMR_ERR_BUDGET, "trainer exceeds HBM budget");
+  if (rc != NMR_OK) {
+    (void)hipStreamSynchronize(c->stream);
+    tr->dev.release();
+    delete tr;
+    return rc;
+  }
+  c->used += tr->dev.bytes;
+  *out = tr;
+  return NMR_OK;
+}
+
+extern "C" int nmr_trainer_destroy(nmr_trainer* tr) {
+  if (!tr) return fail(NMR_ERR_ARG, "null trainer");
+  CHK(set_device(tr->ctx));
+  (void)hipStreamSynchronize(tr->ctx->stream);
+  tr->ctx->used -= tr->dev.bytes;
+  tr->dev.release();
+  delete tr;
+  return NMR_OK;
+}
+
+extern "C" int nmr_trainer_run(nmr_trainer* tr, int n_alternations, double* loss_w, double* loss_s, int* added,
+                               float* ms_or_null) {
+  if (!tr || n_alternations < 0) return fail(NMR_ERR_ARG, "bad argument");
+  if (tr->broken) return fail(NMR_ERR_NONFINITE, "an earlier selection failed");
+  if (tr->nC + (long long)n_alternations * tr->K > tr->c_max)
+    return fail(NMR_ERR_ARG, "the cubature set would exceed c_max");
+  CHK(set_device(tr->ctx));
+  nmr_ctx* c = tr->ctx;
+  HIPCHK(hipEventRecord(c->ev[0], c->stream));
+  for (int a = 0; a < n_alternations; ++a)
+    CHK(trainer_alternation(tr, loss_w ? loss_w + (size_t)a * tr->epochs : nullptr,
+                            loss_s ? loss_s + (size_t)a * tr->epochs : nullptr,
+                            added ? added + (size_t)a * tr->K : nullptr));
+  HIPCHK(hipEventRecord(c->ev[1], c->stream));
+  HIPCHK(hipEventSynchronize(c->ev[1]));
+  if (ms_or_null) HIPCHK(hipEventElapsedTime(ms_or_null, c->ev[0], c->ev[1]));
+  return NMR_OK;
+}
+
+extern "C" int nmr_trainer_get(nmr_trainer* tr, int* n_c, int32_t* C_or_null, double* wnet_or_null,
+                               double* snet_or_null) {
+  if (!tr || !n_c) return fail(NMR_ERR_ARG, "null argument");
+  CHK(set_device(tr->ctx));
+  HIPCHK(hipStreamSynchronize(tr->ctx->stream));
+  *n_c = tr->nC;
+  if (C_or_null) std::copy(tr->Ch.begin(), tr->Ch.begin() + tr->nC, C_or_null);
+  if (wnet_or_null) HIPCHK(hipMemcpy(wnet_or_null, tr->w.x, tr->n_w * sizeof(double), hipMemcpyDeviceToHost));
+  if (snet_or_null) HIPCHK(hipMemcpy(snet_or_null, tr->theta, 170 * sizeof(double), hipMemcpyDeviceToHost));
+  return NMR_OK;
+}
+
+extern "C" int nmr_trainer_pose(nmr_trainer* tr, int p, double* F_or_null, double* f_or_null, double* u_or_null) {
+  if (!tr || p < 0 || p >= tr->P) return fail(NMR_ERR_ARG, "bad argument");
+  CHK(set_device(tr->ctx));
+  HIPCHK(hipStreamSynchronize(tr->ctx->stream));
+  const size_t mR = (size_t)tr->m * tr->R;
+  if (F_or_null) HIPCHK(hipMemcpy(F_or_null, tr->td.F + p * mR, mR * sizeof(double), hipMemcpyDeviceToHost));
+  if (f_or_null)
+    HIPCHK(hipMemcpy(f_or_null, tr->td.f + (size_t)p * tr->R, tr->R * sizeof(double), hipMemcpyDeviceToHost));
+  if (u_or_null)
+    HIPCHK(hipMemcpy(u_or_null, tr->sd.u + (size_t)p * tr->N, tr->N * sizeof(double), hipMemcpyDeviceToHost));
+  return NMR_OK;
 }

@@ -52,6 +52,13 @@ class TileChoice(C.Structure):
 TILING = {"rule": 0, "autotune": 1, "force": 2}
 
 
+class TrainDesc(C.Structure):
+    _fields_ = [("n_poses", C.c_int), ("poses", _dp), ("c_max", C.c_int), ("n_c0", C.c_int),
+                ("c0", C.POINTER(C.c_int32)), ("K", C.c_int), ("epochs", C.c_int), ("lr", C.c_double),
+                ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double), ("wnet", C.POINTER(MlpDesc)),
+                ("wnet_scale", C.c_double), ("snet", _dp)]
+
+
 class NmrError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -102,6 +109,12 @@ def lib():
             "nmr_pool_attach": (i, [vp, vp, ip]),
             "nmr_pool_detach": (i, [vp, i]),
             "nmr_pool_step": (i, [vp, i, ip, C.POINTER(C.c_float)]),
+            "nmr_element_forces": (i, [vp, vp, vp, vp, vp]),
+            "nmr_trainer_create": (i, [vp, C.POINTER(TrainDesc), C.POINTER(vp)]),
+            "nmr_trainer_destroy": (i, [vp]),
+            "nmr_trainer_run": (i, [vp, i, _dp, _dp, ip, C.POINTER(C.c_float)]),
+            "nmr_trainer_get": (i, [vp, ip, C.POINTER(C.c_int32), _dp, _dp]),
+            "nmr_trainer_pose": (i, [vp, i, _dp, _dp, _dp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -346,6 +359,18 @@ class Instance:
         torch.cuda.synchronize(self.dev)
         return A, phi
 
+    def element_forces(self, r):
+        """(F [n_tets, R], f [R], u [N]) at pose r, device FP64 tensors."""
+        import torch
+        f64 = dict(dtype=torch.float64, device=self.dev)
+        rt = torch.as_tensor(np.asarray(r, np.float64), **f64).contiguous()
+        F = torch.empty(int(self.prob.tets.shape[0]), self.R, **f64)
+        f = torch.empty(self.R, **f64)
+        u = torch.empty(self.N, **f64)
+        torch.cuda.synchronize(self.dev)
+        _check(lib().nmr_element_forces(self.h, _ptr(rt), _ptr(F), _ptr(f), _ptr(u)))
+        return F, f, u
+
 
 class Pool:
     """Fixed-capacity slot pool stepped by one captured graph (served form)."""
@@ -399,6 +424,75 @@ class Coupled:
     def close(self):
         if self.h:
             _check(lib().nmr_coupled_destroy(self.h))
+            self.h = None
+
+
+class Trainer:
+    """Neural cubature training (nmr_trainer_*) on an instance's mesh and
+    decoder; `run` returns the loss histories and the elements added."""
+
+    def __init__(self, inst: Instance, poses, wnet_weights, wnet_biases, wnet_scale: float, snet, n_c0: int, K: int,
+                 epochs: int, c0=None, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8):
+        self.poses = np.ascontiguousarray(poses, np.float64)
+        self.P, self.R = self.poses.shape
+        self.m = int(inst.prob.tets.shape[0])
+        self.N = inst.N
+        self.K, self.epochs = K, epochs
+        self.mlp = _Mlp(wnet_weights, wnet_biases, "identity")
+        self.c_max = int(self.mlp.W[-1].shape[0])
+        self.snet = np.ascontiguousarray(snet, np.float64)
+        assert self.snet.size == 170
+        self.c0 = None if c0 is None else np.ascontiguousarray(c0, np.int32)
+        d = TrainDesc()
+        d.n_poses, d.poses, d.c_max, d.n_c0 = self.P, self.poses.ctypes.data_as(_dp), self.c_max, n_c0
+        d.c0 = None if self.c0 is None else self.c0.ctypes.data_as(C.POINTER(C.c_int32))
+        d.K, d.epochs, d.lr, d.beta1, d.beta2, d.eps = K, epochs, lr, beta1, beta2, eps
+        d.wnet, d.wnet_scale, d.snet = C.pointer(self.mlp.desc), wnet_scale, self.snet.ctypes.data_as(_dp)
+        h = C.c_void_p()
+        _check(lib().nmr_trainer_create(inst.h, C.byref(d), C.byref(h)))
+        self.h = h
+        self.shapes = [W.shape for W in self.mlp.W]
+
+    def run(self, n_alternations: int):
+        """Returns (loss_w, loss_s [n_alt, epochs], added [n_alt, K], device ms)."""
+        E, K = self.epochs, self.K
+        lw = np.zeros((max(n_alternations, 1), E))
+        ls = np.zeros((max(n_alternations, 1), E))
+        add = np.zeros((max(n_alternations, 1), K), np.int32)
+        ms = C.c_float()
+        _check(lib().nmr_trainer_run(self.h, n_alternations, lw.ctypes.data_as(_dp), ls.ctypes.data_as(_dp),
+                                     add.ctypes.data_as(C.POINTER(C.c_int)), C.byref(ms)))
+        return lw[:n_alternations], ls[:n_alternations], add[:n_alternations], ms.value
+
+    def get(self):
+        """(C, weight-net Ws, bs, selection-net parameters)."""
+        n = C.c_int()
+        Cs = np.zeros(self.c_max, np.int32)
+        nw = sum(a * b + a for a, b in self.shapes)
+        wx = np.zeros(nw)
+        th = np.zeros(170)
+        _check(lib().nmr_trainer_get(self.h, C.byref(n), Cs.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     wx.ctypes.data_as(_dp), th.ctypes.data_as(_dp)))
+        Ws, bs, o = [], [], 0
+        for a, b in self.shapes:
+            Ws.append(wx[o:o + a * b].reshape(a, b))
+            o += a * b
+            bs.append(wx[o:o + a].copy())
+            o += a
+        return Cs[:n.value].tolist(), Ws, bs, th
+
+    def pose(self, p: int):
+        """(F [n_tets, R], f [R], u [N]) of training pose p."""
+        F = np.zeros((self.m, self.R))
+        f = np.zeros(self.R)
+        u = np.zeros(self.N)
+        _check(lib().nmr_trainer_pose(self.h, p, F.ctypes.data_as(_dp), f.ctypes.data_as(_dp), u.ctypes.data_as(_dp)))
+        return F, f, u
+
+    def close(self):
+        if self.h:
+            _check(lib().nmr_trainer_destroy(self.h))
             self.h = None
 
 

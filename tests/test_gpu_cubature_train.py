@@ -1,0 +1,200 @@
+"""Neural cubature training on the GPU (nmr_element_forces, nmr_trainer_*,
+through the C ABI) against the FP64 oracle (oracle/cubature_train.py): the
+training data of every pose, the loss histories of both nets, the elements
+each alternation adds, the trained parameters, the farthest-point initial
+set, and bitwise repeatability."""
+import numpy as np
+import pytest
+
+from oracle import cubature_train as ct
+from oracle.newton import Instance as OInstance
+from paper_2102_11026_amd import synth
+from parity import close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nmr():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2102_11026_amd import nmr as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(nmr):
+    c = nmr.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    t = synth.config_cubature_tiny()
+    oi = OInstance(t.prob)
+    data = [ct.element_forces(oi, r) for r in t.poses]
+    C0 = ct.voronoi_samples(t.prob.X, t.prob.tets, t.n_c0)
+    res = ct.train(oi, t.poses, t.wnet_weights, t.wnet_biases, t.scale, t.theta, C0, t.K, t.alternations,
+                   t.epochs, data=data)
+    # every selection is decided by a clear margin, so both sides must take it
+    for cand, mean in res.mean_scores:
+        srt = np.sort(mean)[::-1]
+        assert srt[t.K - 1] - srt[t.K] > 1e-6 * srt[0]
+    return t, oi, data, C0, res
+
+
+def trainer(nmr, ctx, t, prec, c0):
+    inst = nmr.Instance(ctx, t.prob, prec)
+    tr = nmr.Trainer(inst, t.poses, t.wnet_weights, t.wnet_biases, t.scale, t.theta, t.n_c0, t.K, t.epochs, c0=c0,
+                     lr=t.lr)
+    return inst, tr
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
+def test_element_forces_against_oracle(nmr, ctx, tiny, prec, tol):
+    t, oi, data, _, _ = tiny
+    inst = nmr.Instance(ctx, t.prob, prec)
+    try:
+        for p in (0, 7):
+            F, f, u = inst.element_forces(t.poses[p])
+            Fo, fo, uo = data[p]
+            close(F, Fo, tol, (prec, "F", p))
+            close(f, fo, tol, (prec, "f", p))
+            close(u, uo, tol, (prec, "u", p))
+    finally:
+        inst.close()
+
+
+def test_training_run_against_oracle_fp64(nmr, ctx, tiny):
+    t, oi, data, C0, res = tiny
+    inst, tr = trainer(nmr, ctx, t, "fp64", C0)
+    try:
+        for p in (0, 5, 11):
+            F, f, u = tr.pose(p)
+            close(F, data[p][0], 1e-10, ("F", p))
+            close(f, data[p][1], 1e-10, ("f", p))
+        lw, ls, added, ms = tr.run(t.alternations)
+        assert ms > 0
+        for a in range(t.alternations):
+            close(lw[a], res.loss_w[a], 1e-9, ("L_W", a))
+            close(ls[a], res.loss_s[a], 1e-9, ("L_S", a))
+            assert list(added[a]) == res.added[a], (a, list(added[a]), res.added[a])
+        C, Ws, bs, theta = tr.get()
+        assert C == res.C
+        for l in range(len(Ws)):
+            close(Ws[l], res.Ws[l], 1e-8, ("W", l))
+            close(bs[l], res.bs[l], 1e-8, ("b", l))
+        close(theta, res.theta, 1e-8, "theta")
+    finally:
+        tr.close()
+        inst.close()
+
+
+def test_training_is_bitwise_repeatable(nmr, ctx, tiny):
+    t, _, _, C0, _ = tiny
+    runs = []
+    for _ in range(2):
+        inst, tr = trainer(nmr, ctx, t, "fp64", C0)
+        try:
+            lw, ls, added, _ = tr.run(2)
+            C, Ws, bs, theta = tr.get()
+            runs.append((lw, ls, added, C, Ws, theta))
+        finally:
+            tr.close()
+            inst.close()
+    a, b = runs
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    np.testing.assert_array_equal(a[2], b[2])
+    assert a[3] == b[3]
+    for x, y in zip(a[4], b[4]):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(a[5], b[5])
+
+
+def test_farthest_point_initial_set(nmr, ctx, tiny):
+    """c0 = NULL: the library's Voronoi samples equal the oracle's (same
+    arithmetic order, ties to the lower id) on a grid mesh full of ties."""
+    t, _, _, C0, _ = tiny
+    inst, tr = trainer(nmr, ctx, t, "fp64", None)
+    try:
+        C, _, _, _ = tr.get()
+        assert C == C0
+        big = ct.voronoi_samples(t.prob.X, t.prob.tets, 16)
+    finally:
+        tr.close()
+        inst.close()
+    t16 = synth.cubature_training(t.prob, 2, 16, 1, 1, 1, hidden=(8,), name="cubtiny16")
+    inst = nmr.Instance(ctx, t16.prob, "fp64")
+    tr = nmr.Trainer(inst, t16.poses * 0.0, t16.wnet_weights, t16.wnet_biases, t16.scale, t16.theta, 16, 1, 1)
+    try:
+        assert tr.get()[0] == big
+    finally:
+        tr.close()
+        inst.close()
+
+
+def test_fp32_decoder_training_follows_the_oracle(nmr, ctx, tiny):
+    """FP32 decoder derivatives (training arithmetic still FP64): the first
+    alternation's losses and selection agree with the oracle's."""
+    t, _, _, C0, res = tiny
+    inst, tr = trainer(nmr, ctx, t, "fp32", C0)
+    try:
+        lw, ls, added, _ = tr.run(1)
+        close(lw[0], res.loss_w[0], 1e-3, "L_W fp32")
+        close(ls[0], res.loss_s[0], 1e-3, "L_S fp32")
+        assert list(added[0]) == res.added[0]
+    finally:
+        tr.close()
+        inst.close()
+
+
+def test_trainer_argument_checks(nmr, ctx, tiny):
+    t, _, _, C0, _ = tiny
+    inst = nmr.Instance(ctx, t.prob, "fp64")
+    try:
+        with pytest.raises(nmr.NmrError):       # duplicate initial ids
+            nmr.Trainer(inst, t.poses, t.wnet_weights, t.wnet_biases, t.scale, t.theta, 2, t.K, t.epochs,
+                        c0=[3, 3])
+        with pytest.raises(nmr.NmrError):       # weight net input is not R
+            nmr.Trainer(inst, t.poses, [t.wnet_weights[0][:, :-1]] + t.wnet_weights[1:], t.wnet_biases, t.scale,
+                        t.theta, t.n_c0, t.K, t.epochs)
+        tr = nmr.Trainer(inst, t.poses, t.wnet_weights, t.wnet_biases, t.scale, t.theta, t.n_c0, t.K, t.epochs,
+                         c0=C0)
+        try:
+            with pytest.raises(nmr.NmrError):   # past c_max
+                tr.run(t.alternations + 1)
+            assert tr.get()[0] == C0            # nothing ran
+        finally:
+            tr.close()
+    finally:
+        inst.close()
+
+
+def test_full_size_training_data_sample_fp32(nmr, ctx):
+    """The 10,000-vertex bar (43,320 tets, FP32 decoder): training pose 0's
+    element forces against the oracle, and one alternation on 16 poses keeps
+    both losses finite and adds distinct new elements."""
+    t = synth.config_cubature_bar10k(16)
+    oi = OInstance(t.prob)
+    Fo, fo, uo = ct.element_forces(oi, t.poses[0])
+    inst = nmr.Instance(ctx, t.prob, "fp32")
+    try:
+        tr = nmr.Trainer(inst, t.poses, t.wnet_weights, t.wnet_biases, t.scale, t.theta, t.n_c0, t.K, t.epochs)
+        try:
+            F, f, u = tr.pose(0)
+            close(F, Fo, 2e-3, "F")
+            close(f, fo, 2e-3, "f")
+            close(u, uo, 1e-4, "u")
+            lw, ls, added, _ = tr.run(1)
+            assert np.isfinite(lw).all() and np.isfinite(ls).all()
+            assert lw[0, -1] < lw[0, 0] and ls[0, -1] < ls[0, 0]
+            C, _, _, _ = tr.get()
+            assert len(set(C)) == len(C) == t.n_c0 + t.K
+        finally:
+            tr.close()
+    finally:
+        inst.close()
