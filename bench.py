@@ -214,6 +214,45 @@ def rel(a, b) -> float:
 GOLDEN = os.path.join(ROOT, "tests", "golden", "bar10k_trajectory_fp64.npz")
 
 
+def training_report(nmr, ctx, n_poses: int):
+    """Neural cubature training (Sec. 5) on the 10,000-vertex bar: training
+    data of n_poses poses (FP32 decoder derivatives, FP64 element forces), then
+    alternations of 15 epochs per net (FP64).  The dominant kernel is the
+    selection net's element backward pass; its algorithmic bytes per launch
+    are the element forces F (P m R doubles), the stored logits (P m), the
+    element adjoints it writes (P m 8) and the vertex features it gathers
+    (P n 8)."""
+    import torch
+    from paper_2102_11026_amd import synth
+    t = synth.config_cubature_bar10k(n_poses)
+    inst = nmr.Instance(ctx, t.prob, "fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr = nmr.Trainer(inst, t.poses, t.wnet_weights, t.wnet_biases, t.scale, t.theta, t.n_c0, t.K, t.epochs)
+    create_s = time.perf_counter() - t0
+    lw0, ls0, _, _ = tr.run(1)
+    lw, ls, added, ms = tr.run(2)
+    alt_ms = ms / 2
+    ph = {k: tr.time_phase(k, 3) for k in nmr.TRAIN_PHASES}
+    P, m, n, R = n_poses, int(t.prob.tets.shape[0]), t.prob.n, t.prob.R
+    bwd_bytes = 8.0 * P * (m * R + m + 8 * m + 8 * n)
+    achieved = bwd_bytes / (ph["s_elem_bwd"] * 1e-6) / 1e9
+    C, _, _, _ = tr.get()
+    out = dict(poses=P, tets=m, R=R, epochs_per_net=t.epochs, K=t.K, cubature_elements=len(C),
+               training_data_s=round(create_s, 3), training_data_gb=round(8.0 * P * m * R / 1e9, 3),
+               alternation_ms=round(alt_ms, 2), pose_epochs_per_s=round(P * 2 * t.epochs / (alt_ms / 1e3), 1),
+               s_epoch_ms=round(ph["s_epoch"] / 1e3, 3), w_epoch_ms=round(ph["w_epoch"] / 1e3, 3),
+               s_elem_fwd_ms=round(ph["s_elem_fwd"] / 1e3, 3), s_elem_bwd_ms=round(ph["s_elem_bwd"] / 1e3, 3),
+               loss_w_first_last=[round(float(lw0[0][0]), 5), round(float(lw[-1][-1]), 5)],
+               loss_s_first_last=[round(float(ls0[0][0]), 5), round(float(ls[-1][-1]), 5)],
+               paper_scale_projection_s=round(alt_ms / 1e3 * (20000 / P) * 24, 1),
+               roofline=dict(kernel="k_sbwd_elem", bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                             unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), algorithmic_bytes=int(bwd_bytes)))
+    tr.close()
+    inst.close()
+    return out
+
+
 def precision_report(nmr, ctx, p):
     """FP32 and BF16 forms against the FP64 oracle.
 
@@ -300,7 +339,24 @@ def main():
     ap.add_argument("--profile-pools", type=int, default=0, metavar="SLOTS",
                     help="only tick full slot pools of the three serving classes, SLOTS each (for a "
                          "profiler), and exit")
+    ap.add_argument("--train-poses", type=int, default=1024, help="poses of the cubature-training variant (0: skip)")
+    ap.add_argument("--profile-training", type=int, default=0, metavar="P",
+                    help="only build the training data of P poses of the 10,000-vertex bar and run one "
+                         "alternation (for a profiler), and exit")
     args = ap.parse_args()
+    if args.profile_training:
+        from paper_2102_11026_amd import nmr, synth
+        t = synth.config_cubature_bar10k(args.profile_training)
+        ctx = nmr.Context(0)
+        inst = nmr.Instance(ctx, t.prob, "fp32")
+        tr = nmr.Trainer(inst, t.poses, t.wnet_weights, t.wnet_biases, t.scale, t.theta, t.n_c0, t.K, t.epochs)
+        lw, ls, added, ms = tr.run(1)
+        print(json.dumps(dict(poses=args.profile_training, alternation_ms=round(ms, 2),
+                              loss_w=[float(lw[0][0]), float(lw[0][-1])], loss_s=[float(ls[0][0]), float(ls[0][-1])])))
+        tr.close()
+        inst.close()
+        ctx.close()
+        return
     if args.profile_coupled:
         from paper_2102_11026_amd import nmr, synth
         scene = synth.config_puffer(args.profile_coupled)
@@ -530,6 +586,10 @@ def main():
                              budget_gb=200, slots_per_class=args.serve_slots)
                 var[f"served_{prec}"] = stats
                 log(f"served {prec}:", stats)
+        # NEXT row: neural cubature training (Sec. 5)
+        if args.train_poses > 0:
+            var["cubature_training_bar10k"] = training_report(nmr, ctx, args.train_poses)
+            log("cubature training:", var["cubature_training_bar10k"])
         # NEXT row: the fictitious force and consistency in dt (FP64, through the C ABI)
         from paper_2102_11026_amd import experiments
         var["experiment_fictitious_force"] = experiments.consistency_in_dt(nmr, ctx, "fp64")

@@ -387,6 +387,10 @@ typedef struct {
   const double* snet;        /* 170 selection-net parameters: G0 [3][8] and     */
                              /* G1 [8][8] (graph convolutions, [in][out]), A1   */
                              /* [8][8] ([out][in]), a1 [8], A2 [8], a2, c       */
+  int pose_chunk;            /* poses per selection-net launch (its per-pose    */
+                             /* intermediates take (51 n + 8 n_tets) doubles    */
+                             /* each); 0: automatic, every pose up to 4 GiB of  */
+                             /* them.  Results do not depend on it              */
 } nmr_cubature_train_desc;
 
 /* Neural cubature training (Sec. 5) on the instance's mesh, decoder and U:
@@ -428,6 +432,22 @@ int nmr_trainer_get(nmr_trainer* tr, int* n_c, int32_t* C_or_null, double* wnet_
 /* Training data of pose p (host outputs, each may be NULL): F [n_tets x R],
  * f [R], u [N]. */
 int nmr_trainer_pose(nmr_trainer* tr, int p, double* F_or_null, double* f_or_null, double* u_or_null);
+
+/* Pieces of an alternation, for measurement. */
+typedef enum {
+  NMR_TRAIN_PHASE_S_EPOCH = 0,    /* one selection-net epoch without its Adam step */
+  NMR_TRAIN_PHASE_W_EPOCH = 1,    /* one weight-net epoch without its Adam step    */
+  NMR_TRAIN_PHASE_S_ELEM_FWD = 2, /* the selection net's element forward pass      */
+  NMR_TRAIN_PHASE_S_ELEM_BWD = 3, /* the selection net's element backward pass     */
+  NMR_TRAIN_PHASE_COUNT = 4
+} nmr_train_phase;
+
+/* Replays one phase `reps` times on the context stream between two HIP
+ * events (after the residual forces and a forward pass that give it valid
+ * inputs, and one untimed replay) and writes the mean device time per replay
+ * in microseconds to *avg_us (host).  Only intermediates are written: the
+ * nets, their Adam states and the cubature set are unchanged.  Synchronizes. */
+int nmr_trainer_time_phase(nmr_trainer* tr, int phase, int reps, float* avg_us);
 
 /* ---- measurement -------------------------------------------------------- */
 

@@ -2113,7 +2113,13 @@ int trainer_build(nmr_inst* in, const nmr_cubature_train_desc* d, nmr_trainer* t
   sd.theta = tr->theta;
   sd.F = F;
   sd.fb = fb;
-  const size_t Pn = (size_t)P * n;
+  // poses per chunk: every pose at once up to 4 GiB of per-pose intermediates
+  const size_t per_pose = (51 * (size_t)n + 8 * (size_t)m) * sizeof(double);
+  sd.nc = d->pose_chunk > 0 ? std::min(d->pose_chunk, P)
+                            : (int)std::max<size_t>(1, std::min<size_t>(P, (size_t(4) << 30) / per_pose));
+  sd.p0 = 0;
+  const int nc = sd.nc;
+  const size_t Pn = (size_t)nc * n;
   CHK(dalloc_t(M, 3 * Pn, &sd.H0));
   CHK(dalloc_t(M, 8 * Pn, &sd.P1));
   CHK(dalloc_t(M, 8 * Pn, &sd.X1));
@@ -2122,14 +2128,14 @@ int trainer_build(nmr_inst* in, const nmr_cubature_train_desc* d, nmr_trainer* t
   CHK(dalloc_t(M, 8 * Pn, &sd.X2));
   CHK(dalloc_t(M, 8 * Pn, &sd.T2));
   CHK(dalloc_t(M, (size_t)P * m, &sd.z));
-  CHK(dalloc_t(M, (size_t)P * sd.nbe * (R + 2), &sd.pf));
+  CHK(dalloc_t(M, (size_t)nc * sd.nbe * (R + 2), &sd.pf));
   CHK(dalloc_t(M, (size_t)P * 8, &sd.pstat));
   CHK(dalloc_t(M, (size_t)P * R, &sd.res));
   sd.loss_p = loss_p;
-  CHK(dalloc_t(M, (size_t)P * m * 8, &sd.dg));
-  CHK(dalloc_t(M, (size_t)P * sd.nbe * 81, &sd.pe));
-  CHK(dalloc_t(M, (size_t)P * sd.nbv * 64, &sd.pv2));
-  CHK(dalloc_t(M, (size_t)P * sd.nbv * 24, &sd.pv1));
+  CHK(dalloc_t(M, (size_t)nc * m * 8, &sd.dg));
+  CHK(dalloc_t(M, (size_t)nc * sd.nbe * 81, &sd.pe));
+  CHK(dalloc_t(M, (size_t)nc * sd.nbv * 64, &sd.pv2));
+  CHK(dalloc_t(M, (size_t)nc * sd.nbv * 24, &sd.pv1));
   CHK(dalloc_t(M, (size_t)P * 170, &sd.gpose));
   CHK(dalloc_t(M, 170, &sd.grad));
   // initial cubature set: the caller's, or farthest-point samples
@@ -2213,6 +2219,7 @@ extern "C" int nmr_trainer_create(nmr_inst* in, const nmr_cubature_train_desc* d
   if (d->n_c0 < 1 || d->n_c0 > d->c_max) return fail(NMR_ERR_ARG, "need 1 <= n_c0 <= c_max");
   if (d->c_max >= in->m) return fail(NMR_ERR_ARG, "c_max must be below the tet count");
   if (!(d->wnet_scale > 0.0)) return fail(NMR_ERR_ARG, "wnet_scale must be > 0");
+  if (d->pose_chunk < 0) return fail(NMR_ERR_ARG, "pose_chunk must be >= 0");
   CHK(set_device(in->ctx));
   nmr_trainer* tr = new nmr_trainer();
   tr->ctx = in->ctx;
@@ -2281,5 +2288,39 @@ extern "C" int nmr_trainer_pose(nmr_trainer* tr, int p, double* F_or_null, doubl
     HIPCHK(hipMemcpy(f_or_null, tr->td.f + (size_t)p * tr->R, tr->R * sizeof(double), hipMemcpyDeviceToHost));
   if (u_or_null)
     HIPCHK(hipMemcpy(u_or_null, tr->sd.u + (size_t)p * tr->N, tr->N * sizeof(double), hipMemcpyDeviceToHost));
+  return NMR_OK;
+}
+
+extern "C" int nmr_trainer_time_phase(nmr_trainer* tr, int phase, int reps, float* avg_us) {
+  if (!tr || !avg_us || reps < 1 || phase < 0 || phase >= NMR_TRAIN_PHASE_COUNT) return fail(NMR_ERR_ARG, "bad argument");
+  if (tr->broken) return fail(NMR_ERR_NONFINITE, "an earlier selection failed");
+  CHK(set_device(tr->ctx));
+  nmr_ctx* c = tr->ctx;
+  hipStream_t s = c->stream;
+  // valid inputs for every phase: residual forces of the current weights and
+  // a selection-net forward pass (intermediates only; no parameter changes)
+  launch_wnet_epoch(tr->w, tr->td, tr->nC, 1, s);
+  launch_snet_forward(tr->sd, s);
+  auto once = [&]() {
+    WNetDev w = tr->w;
+    SNetDev sd = tr->sd;
+    w.loss_out = tr->losses;
+    sd.loss_out = tr->losses + tr->epochs;
+    switch (phase) {
+      case NMR_TRAIN_PHASE_S_EPOCH: launch_snet_epoch(sd, s); break;
+      case NMR_TRAIN_PHASE_W_EPOCH: launch_wnet_epoch(w, tr->td, tr->nC, 0, s); break;
+      case NMR_TRAIN_PHASE_S_ELEM_FWD: launch_snet_elem(sd, 0, s); break;
+      default: launch_snet_elem(sd, 1, s); break;
+    }
+  };
+  once();
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(c->ev[0], s));
+  for (int k = 0; k < reps; ++k) once();
+  HIPCHK(hipEventRecord(c->ev[1], s));
+  HIPCHK(hipEventSynchronize(c->ev[1]));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev[0], c->ev[1]));
+  *avg_us = 1000.f * ms / reps;
   return NMR_OK;
 }

@@ -420,9 +420,11 @@ struct WNetDev {
   double* d[NMR_MAX_LAYERS];  // [P][width[l + 1]] adjoints of the pre-activations
   double* loss_out;           // where the epoch's loss is written
 };
-// Selection net under training (all per-pose arrays [P][...]).
+// Selection net under training.  Poses run in chunks of nc starting at p0:
+// arrays marked "chunk" hold the poses of one chunk, the others every pose.
 struct SNetDev {
   int n, m, R, P, nbv, nbe;
+  int p0, nc;
   const double* u;                     // [P][n][3]
   const int *g_ptr, *g_idx;            // one-ring CSR, self included
   const double* g_val;                 // 1 / sqrt(d_i d_j)
@@ -432,14 +434,14 @@ struct SNetDev {
   const double* theta;                 // [170]
   const double* F;                     // [P][m][R]
   const double* fb;                    // [P][R]
-  double *H0, *P1, *X1, *H1, *P2, *X2, *T2;  // [P][n][3 or 8]
+  double *H0, *P1, *X1, *H1, *P2, *X2, *T2;  // chunk [nc][n][3 or 8]
   double* z;                           // [P][m] logits
-  double* pf;                          // [P][nbe][R + 2] forward partials
+  double* pf;                          // chunk [nc][nbe][R + 2] forward partials
   double* pstat;                       // [P][8]: M, S, coef, qbar, dL/dc
   double* res;                         // [P][R]
   double* loss_p;                      // [P]
-  double* dg;                          // [P][m][8]
-  double *pe, *pv2, *pv1;              // gradient partials [P][nbe][81], [P][nbv][64], [P][nbv][24]
+  double* dg;                          // chunk [nc][m][8]
+  double *pe, *pv2, *pv1;              // chunk gradient partials [nc][nbe][81], [nc][nbv][64], [nc][nbv][24]
   double* gpose;                       // [P][170]
   double* grad;                        // [170]
   double* loss_out;
@@ -454,6 +456,7 @@ void launch_adam(double* x, const double* g, double* m, double* v, long long n, 
                  double eps, double c1, double c2, hipStream_t s);
 void launch_snet_forward(const SNetDev& sd, hipStream_t s);
 void launch_snet_epoch(const SNetDev& sd, hipStream_t s);
+void launch_snet_elem(const SNetDev& sd, int backward, hipStream_t s);  // the element pass alone
 void launch_select(const SNetDev& sd, double* mean, int K, int* inC, int* C, int nC, hipStream_t s);
 void launch_fps(const double* X, const int* tets, int m, int k, double* dist, int* C, int* inC, hipStream_t s);
 

@@ -348,11 +348,30 @@ void launch_adam(double* x, const double* g, double* m, double* v, long long n, 
 // ---------------------------------------------------------------------------
 #define SB 256  // vertices or elements per block
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  Renumbered so that each XCD takes a contiguous run of logical blocks,
+// neighbouring vertex and element blocks (which gather each other's
+// features) share an L2.  (b, pc) = (vertex or element block, pose of the chunk).
+__device__ inline void xcd_block(int& b, int& pc) {
+  const int total = gridDim.x * gridDim.y, lin = blockIdx.y * gridDim.x + blockIdx.x;
+  const int per = total / 8, rem = total % 8, x = lin % 8, i = lin / 8;
+  const int L = x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+  b = L % gridDim.x;
+  pc = L / gridDim.x;
+}
+
+// the 8 channels of one vertex or element, stored back to back
+__device__ inline void store8(double* dst, const double (&v)[8]) {
+  for (int k = 0; k < 4; ++k) stg<double2>(dst + 2 * k, make_double2(v[2 * k], v[2 * k + 1]));
+}
+
 // first convolution: H0 = sum_j A_ij u_j (3), P1 = H0 G0, X1 = sin P1
 __global__ __launch_bounds__(SB) void k_gcn1(SNetDev sd) {
-  const int v = blockIdx.x * SB + threadIdx.x, p = blockIdx.y;
+  int b, pc;
+  xcd_block(b, pc);
+  const int v = b * SB + threadIdx.x;
   if (v >= sd.n) return;
-  const double* u = sd.u + (size_t)p * 3 * sd.n;
+  const double* u = sd.u + (size_t)(sd.p0 + pc) * 3 * sd.n;
   double h[3] = {0.0, 0.0, 0.0};
   const int j0 = ldg<int>(sd.g_ptr + v), j1 = ldg<int>(sd.g_ptr + v + 1);
   for (int k = j0; k < j1; ++k) {
@@ -360,22 +379,27 @@ __global__ __launch_bounds__(SB) void k_gcn1(SNetDev sd) {
     const double a = ldg<double>(sd.g_val + k);
     for (int c = 0; c < 3; ++c) h[c] += a * ldg<double>(u + 3 * j + c);
   }
-  const size_t vi = (size_t)p * sd.n + v;
+  const size_t vi = (size_t)pc * sd.n + v;
   for (int c = 0; c < 3; ++c) stg<double>(sd.H0 + 3 * vi + c, h[c]);
   const double* G0 = sd.theta;
+  double P[8], X[8];
   for (int o = 0; o < 8; ++o) {
     double acc = 0.0;
     for (int c = 0; c < 3; ++c) acc += h[c] * ldg<double>(G0 + 8 * c + o);
-    stg<double>(sd.P1 + 8 * vi + o, acc);
-    stg<double>(sd.X1 + 8 * vi + o, sin(acc));
+    P[o] = acc;
+    X[o] = sin(acc);
   }
+  store8(sd.P1 + 8 * vi, P);
+  store8(sd.X1 + 8 * vi, X);
 }
 
 // second convolution: H1 = sum_j A_ij X1_j (8), P2 = H1 G1, X2 = sin P2
 __global__ __launch_bounds__(SB) void k_gcn2(SNetDev sd) {
-  const int v = blockIdx.x * SB + threadIdx.x, p = blockIdx.y;
+  int b, pc;
+  xcd_block(b, pc);
+  const int v = b * SB + threadIdx.x;
   if (v >= sd.n) return;
-  const double* X1 = sd.X1 + (size_t)p * 8 * sd.n;
+  const double* X1 = sd.X1 + (size_t)pc * 8 * sd.n;
   double h[8];
   for (int c = 0; c < 8; ++c) h[c] = 0.0;
   const int j0 = ldg<int>(sd.g_ptr + v), j1 = ldg<int>(sd.g_ptr + v + 1);
@@ -384,20 +408,23 @@ __global__ __launch_bounds__(SB) void k_gcn2(SNetDev sd) {
     const double a = ldg<double>(sd.g_val + k);
     for (int c = 0; c < 8; ++c) h[c] += a * ldg<double>(X1 + 8 * j + c);
   }
-  const size_t vi = (size_t)p * sd.n + v;
-  for (int c = 0; c < 8; ++c) stg<double>(sd.H1 + 8 * vi + c, h[c]);
+  const size_t vi = (size_t)pc * sd.n + v;
+  store8(sd.H1 + 8 * vi, h);
   const double* G1 = sd.theta + 24;
+  double P[8], X[8];
   for (int o = 0; o < 8; ++o) {
     double acc = 0.0;
     for (int c = 0; c < 8; ++c) acc += h[c] * ldg<double>(G1 + 8 * c + o);
-    stg<double>(sd.P2 + 8 * vi + o, acc);
-    stg<double>(sd.X2 + 8 * vi + o, sin(acc));
+    P[o] = acc;
+    X[o] = sin(acc);
   }
+  store8(sd.P2 + 8 * vi, P);
+  store8(sd.X2 + 8 * vi, X);
 }
 
 // element head: g = mean of the 4 vertices' X2, Q = A1 g + a1, Y = sin Q, z = A2 . Y + a2
-__device__ inline double elem_head(const SNetDev& sd, int p, int e, double (&g)[8], double (&Q)[8], double (&Y)[8]) {
-  const double* X2 = sd.X2 + (size_t)p * 8 * sd.n;
+__device__ inline double elem_head(const SNetDev& sd, int pc, int e, double (&g)[8], double (&Q)[8], double (&Y)[8]) {
+  const double* X2 = sd.X2 + (size_t)pc * 8 * sd.n;
   for (int c = 0; c < 8; ++c) g[c] = 0.0;
   for (int a = 0; a < 4; ++a) {
     const int v = ldg<int>(sd.tets + 4 * e + a);
@@ -418,14 +445,18 @@ __device__ inline double elem_head(const SNetDev& sd, int p, int e, double (&g)[
   return z + ldg<double>(sd.theta + 168);
 }
 
-// Stage the block's F rows [SB][R] in LDS with coalesced loads.
+// LDS row stride of an F tile: R + 1 columns (R forces and one more value),
+// rounded up to an odd number of doubles so that rows fall in different banks
+__device__ __host__ inline int tile_ld(int R) { return (R + 1) | 1; }
+
+// Stage the block's F rows [SB][R] of pose p in LDS with coalesced loads.
 __device__ inline void load_F_tile(const SNetDev& sd, int p, int e0, double* tile) {
-  const int R = sd.R;
+  const int R = sd.R, ld = tile_ld(R);
   const int ne = min(SB, sd.m - e0);
   const double* src = sd.F + ((size_t)p * sd.m + e0) * R;
   for (int k = threadIdx.x; k < ne * R; k += SB) {
     const int e = k / R;
-    tile[e * (R + 1) + (k - e * R)] = ldg<double>(src + k);
+    tile[e * ld + (k - e * R)] = ldg<double>(src + k);
   }
 }
 
@@ -434,9 +465,11 @@ __device__ inline void load_F_tile(const SNetDev& sd, int p, int e0, double* til
 // V_b = sum w_e F[p][e]; partial layout [P][nbe][R + 2] = (V_b, S_b, M_b).
 __global__ __launch_bounds__(SB) void k_sfwd_elem(SNetDev sd) {
   extern __shared__ double lds[];
-  const int b = blockIdx.x, p = blockIdx.y, t = threadIdx.x, R = sd.R;
+  int b, pc;
+  xcd_block(b, pc);
+  const int p = sd.p0 + pc, t = threadIdx.x, R = sd.R, ld = tile_ld(R);
   const int e0 = b * SB, e = e0 + t;
-  double* tile = lds;                    // [SB][R + 1], column R = w
+  double* tile = lds;                    // [SB][ld], column R = w
   __shared__ double red[SB];
   __shared__ double part[8][NMR_MAX_R + 2];
   load_F_tile(sd, p, e0, tile);
@@ -444,7 +477,7 @@ __global__ __launch_bounds__(SB) void k_sfwd_elem(SNetDev sd) {
   double z = -INFINITY;
   if (e < sd.m) {
     double g[8], Q[8], Y[8];
-    z = elem_head(sd, p, e, g, Q, Y);
+    z = elem_head(sd, pc, e, g, Q, Y);
     stg<double>(sd.z + (size_t)p * sd.m + e, z);
     cand = ldg<int>(sd.inC + e) == 0;
   }
@@ -456,7 +489,7 @@ __global__ __launch_bounds__(SB) void k_sfwd_elem(SNetDev sd) {
   }
   const double Mb = red[0];
   const double w = cand ? exp(z - Mb) : 0.0;
-  tile[t * (R + 1) + R] = w;
+  tile[t * ld + R] = w;
   __syncthreads();
   // 8 slices of 32 elements: thread (slice, col) sums its column
   const int col = t % 32, sl = t / 32;
@@ -464,8 +497,8 @@ __global__ __launch_bounds__(SB) void k_sfwd_elem(SNetDev sd) {
     const int ne = min(SB, sd.m - e0);
     double acc = 0.0;
     for (int k = sl * 32; k < min(ne, sl * 32 + 32); ++k) {
-      const double wk = tile[k * (R + 1) + R];
-      acc += col == R ? wk : wk * tile[k * (R + 1) + col];
+      const double wk = tile[k * ld + R];
+      acc += col == R ? wk : wk * tile[k * ld + col];
     }
     part[sl][col] = acc;
   }
@@ -473,32 +506,44 @@ __global__ __launch_bounds__(SB) void k_sfwd_elem(SNetDev sd) {
   if (t <= R) {
     double s = 0.0;
     for (int k = 0; k < 8; ++k) s += part[k][t];
-    stg<double>(sd.pf + ((size_t)p * sd.nbe + b) * (R + 2) + t, s);
+    stg<double>(sd.pf + ((size_t)pc * sd.nbe + b) * (R + 2) + t, s);
   }
-  if (t == 0) stg<double>(sd.pf + ((size_t)p * sd.nbe + b) * (R + 2) + R + 1, Mb);
+  if (t == 0) stg<double>(sd.pf + ((size_t)pc * sd.nbe + b) * (R + 2) + R + 1, Mb);
 }
 
 // Per pose: M = max M_b, S = sum S_b e^{M_b - M}, V likewise; res = fb - e^c V / S,
 // loss_p = |res|^2 / |fb|^2 / P, coef = -2 / (P |fb|^2), qbar = coef (V / S) . res.
-__global__ __launch_bounds__(64) void k_scombine(SNetDev sd) {
-  const int p = blockIdx.x, t = threadIdx.x, R = sd.R;
+// 256 threads: 8 slices of the blocks per column, slice sums added in order.
+__global__ __launch_bounds__(256) void k_scombine(SNetDev sd) {
+  const int pc = blockIdx.x, p = sd.p0 + pc, t = threadIdx.x, R = sd.R;
+  __shared__ double part[8][NMR_MAX_R + 1];
   __shared__ double col[NMR_MAX_R + 1];
-  __shared__ double Msh;
-  const double* pf = sd.pf + (size_t)p * sd.nbe * (R + 2);
-  if (t == 0) {
-    double M = -INFINITY;
-    for (int b = 0; b < sd.nbe; ++b) M = fmax(M, ldg<double>(pf + (size_t)b * (R + 2) + R + 1));
-    Msh = M;
-  }
+  __shared__ double red[256];
+  const double* pf = sd.pf + (size_t)pc * sd.nbe * (R + 2);
+  double M = -INFINITY;
+  for (int b = t; b < sd.nbe; b += 256) M = fmax(M, ldg<double>(pf + (size_t)b * (R + 2) + R + 1));
+  red[t] = M;
   __syncthreads();
-  const double M = Msh;
-  if (t <= R) {
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] = fmax(red[t], red[t + h]);
+    __syncthreads();
+  }
+  M = red[0];
+  const int c = t % 32, sl = t / 32;
+  if (c <= R) {
+    const int per = (sd.nbe + 7) / 8;
     double s = 0.0;
-    for (int b = 0; b < sd.nbe; ++b) {
+    for (int b = sl * per; b < min(sd.nbe, sl * per + per); ++b) {
       const double Mb = ldg<double>(pf + (size_t)b * (R + 2) + R + 1);
       if (Mb == -INFINITY) continue;
-      s += ldg<double>(pf + (size_t)b * (R + 2) + t) * exp(Mb - M);
+      s += ldg<double>(pf + (size_t)b * (R + 2) + c) * exp(Mb - M);
     }
+    part[sl][c] = s;
+  }
+  __syncthreads();
+  if (t <= R) {
+    double s = 0.0;
+    for (int k = 0; k < 8; ++k) s += part[k][t];
     col[t] = s;
   }
   __syncthreads();
@@ -532,19 +577,34 @@ __global__ __launch_bounds__(64) void k_scombine(SNetDev sd) {
 // gradients, layout [P][nbe][81] = (A1 [8][8], a1, A2, a2) in theta order.
 __global__ __launch_bounds__(SB) void k_sbwd_elem(SNetDev sd) {
   extern __shared__ double lds[];
-  const int b = blockIdx.x, p = blockIdx.y, t = threadIdx.x, R = sd.R;
+  int b, pc;
+  xcd_block(b, pc);
+  const int p = sd.p0 + pc, t = threadIdx.x, R = sd.R, ld = tile_ld(R);
   const int e0 = b * SB, e = e0 + t;
-  double* tile = lds;                        // [SB][R + 1]
+  double* tile = lds;                        // [SB][ld]
   double(*sv)[25] = (double(*)[25])lds;      // after the dot products: dz, dQ (8), g (8), Y (8)
   __shared__ double part[3][81];
   __shared__ double res[NMR_MAX_R];
   load_F_tile(sd, p, e0, tile);
   if (t < R) res[t] = ldg<double>(sd.res + (size_t)p * R + t);
   __syncthreads();
-  double dz = 0.0, dQ[8], g[8], Q[8], Y[8];
+  double dz = 0.0, dQ[8], g[8], Y[8];
   for (int c = 0; c < 8; ++c) dQ[c] = g[c] = Y[c] = 0.0;
   if (e < sd.m) {
-    const double z = elem_head(sd, p, e, g, Q, Y);
+    // the head again, without the logit (the forward pass stored it)
+    const double* X2 = sd.X2 + (size_t)pc * 8 * sd.n;
+    for (int a = 0; a < 4; ++a) {
+      const int v = ldg<int>(sd.tets + 4 * e + a);
+      for (int c = 0; c < 8; ++c) g[c] += ldg<double>(X2 + 8 * v + c);
+    }
+    for (int c = 0; c < 8; ++c) g[c] = g[c] / 4.0;
+    double cQ[8];
+    for (int o = 0; o < 8; ++o) {
+      double acc = 0.0;
+      for (int i = 0; i < 8; ++i) acc += ldg<double>(sd.theta + 88 + 8 * o + i) * g[i];
+      sincos(acc + ldg<double>(sd.theta + 152 + o), &Y[o], &cQ[o]);
+    }
+    const double z = ldg<double>(sd.z + (size_t)p * sd.m + e);
     const double* ps = sd.pstat + (size_t)p * 8;
     double dg[8];
     for (int c = 0; c < 8; ++c) dg[c] = 0.0;
@@ -553,19 +613,18 @@ __global__ __launch_bounds__(SB) void k_sbwd_elem(SNetDev sd) {
                    qbar = ldg<double>(ps + 3);
       const double s = exp(ldg<double>(sd.theta + 169)) * (exp(z - M) / S);
       double dot = 0.0;
-      for (int r = 0; r < R; ++r) dot += tile[t * (R + 1) + r] * res[r];
+      for (int r = 0; r < R; ++r) dot += tile[t * ld + r] * res[r];
       dz = s * (coef * dot - qbar);
       const double* A1 = sd.theta + 88;
       const double* A2 = sd.theta + 160;
-      for (int o = 0; o < 8; ++o) dQ[o] = dz * ldg<double>(A2 + o) * cos(Q[o]);
+      for (int o = 0; o < 8; ++o) dQ[o] = dz * ldg<double>(A2 + o) * cQ[o];
       for (int i = 0; i < 8; ++i) {
         double acc = 0.0;
         for (int o = 0; o < 8; ++o) acc += dQ[o] * ldg<double>(A1 + 8 * o + i);
         dg[i] = acc;
       }
     }
-    double* out = sd.dg + ((size_t)p * sd.m + e) * 8;
-    for (int c = 0; c < 8; ++c) stg<double>(out + c, dg[c]);
+    store8(sd.dg + ((size_t)pc * sd.m + e) * 8, dg);
   }
   __syncthreads();  // every dot product has read the tile
   sv[t][0] = dz;
@@ -594,16 +653,18 @@ __global__ __launch_bounds__(SB) void k_sbwd_elem(SNetDev sd) {
   }
   __syncthreads();
   if (t < 81)
-    stg<double>(sd.pe + ((size_t)p * sd.nbe + b) * 81 + t, (part[0][t] + part[1][t]) + part[2][t]);
+    stg<double>(sd.pe + ((size_t)pc * sd.nbe + b) * 81 + t, (part[0][t] + part[1][t]) + part[2][t]);
 }
 
 // Second convolution backward, per vertex: dX2 = sum over incident tets of
 // dg / 4, dP2 = dX2 cos P2, T2 = dP2 G1^T (stored); partials of
 // dG1[i][o] = sum_v H1_i dP2_o, layout [P][nbv][64].
 __global__ __launch_bounds__(SB) void k_sbwd_v2(SNetDev sd) {
-  const int b = blockIdx.x, p = blockIdx.y, t = threadIdx.x;
+  int b, p;  // p: pose of the chunk
+  xcd_block(b, p);
+  const int t = threadIdx.x;
   const int v = b * SB + t;
-  __shared__ double sv[SB][16];  // H1 (8), dP2 (8)
+  __shared__ double sv[SB][17];  // H1 (8), dP2 (8), padded
   __shared__ double part[4][64];
   double h[8], d[8];
   for (int c = 0; c < 8; ++c) h[c] = d[c] = 0.0;
@@ -622,11 +683,13 @@ __global__ __launch_bounds__(SB) void k_sbwd_v2(SNetDev sd) {
       d[c] = dx[c] * cos(ldg<double>(sd.P2 + 8 * vi + c));
     }
     const double* G1 = sd.theta + 24;
+    double T[8];
     for (int i = 0; i < 8; ++i) {
       double acc = 0.0;
       for (int o = 0; o < 8; ++o) acc += d[o] * ldg<double>(G1 + 8 * i + o);
-      stg<double>(sd.T2 + 8 * vi + i, acc);
+      T[i] = acc;
     }
+    store8(sd.T2 + 8 * vi, T);
   }
   for (int c = 0; c < 8; ++c) {
     sv[t][c] = h[c];
@@ -647,7 +710,9 @@ __global__ __launch_bounds__(SB) void k_sbwd_v2(SNetDev sd) {
 // First convolution backward, per vertex: dX1 = sum_j A_ij T2_j,
 // dP1 = dX1 cos P1; partials of dG0[c][o] = sum_v H0_c dP1_o, [P][nbv][24].
 __global__ __launch_bounds__(SB) void k_sbwd_v1(SNetDev sd) {
-  const int b = blockIdx.x, p = blockIdx.y, t = threadIdx.x;
+  int b, p;  // p: pose of the chunk
+  xcd_block(b, p);
+  const int t = threadIdx.x;
   const int v = b * SB + t;
   __shared__ double sv[SB][11];  // H0 (3), dP1 (8)
   __shared__ double part[8][24];
@@ -684,21 +749,30 @@ __global__ __launch_bounds__(SB) void k_sbwd_v1(SNetDev sd) {
   }
 }
 
-// Per pose: the 170 gradient entries from the block partials (blocks in order).
-__global__ __launch_bounds__(256) void k_sred_pose(SNetDev sd) {
-  const int p = blockIdx.x, k = threadIdx.x;
-  if (k >= 170) return;
-  double s = 0.0;
-  if (k < 24) {
-    for (int b = 0; b < sd.nbv; ++b) s += ldg<double>(sd.pv1 + ((size_t)p * sd.nbv + b) * 24 + k);
-  } else if (k < 88) {
-    for (int b = 0; b < sd.nbv; ++b) s += ldg<double>(sd.pv2 + ((size_t)p * sd.nbv + b) * 64 + (k - 24));
-  } else if (k < 169) {
-    for (int b = 0; b < sd.nbe; ++b) s += ldg<double>(sd.pe + ((size_t)p * sd.nbe + b) * 81 + (k - 88));
-  } else {
-    s = ldg<double>(sd.pstat + (size_t)p * 8 + 4);
+// Per pose: the 170 gradient entries from the block partials: 4 slices of
+// the blocks per entry (blocks in order within a slice, slices in order).
+__global__ __launch_bounds__(1024) void k_sred_pose(SNetDev sd) {
+  const int pc = blockIdx.x, p = sd.p0 + pc, t = threadIdx.x;
+  const int k = t % 256, sl = t / 256;
+  __shared__ double part[4][170];
+  if (k < 170) {
+    double s = 0.0;
+    if (k < 169) {
+      const bool vert = k < 88;
+      const int nb = vert ? sd.nbv : sd.nbe;
+      const int per = (nb + 3) / 4, b0 = sl * per, b1 = min(nb, b0 + per);
+      const double* src = k < 24 ? sd.pv1 + (size_t)pc * sd.nbv * 24 + k
+                        : k < 88 ? sd.pv2 + (size_t)pc * sd.nbv * 64 + (k - 24)
+                                 : sd.pe + (size_t)pc * sd.nbe * 81 + (k - 88);
+      const int ld = k < 24 ? 24 : k < 88 ? 64 : 81;
+      for (int b = b0; b < b1; ++b) s += ldg<double>(src + (size_t)b * ld);
+    } else if (sl == 0) {
+      s = ldg<double>(sd.pstat + (size_t)p * 8 + 4);
+    }
+    part[sl][k] = s;
   }
-  stg<double>(sd.gpose + (size_t)p * 170 + k, s);
+  __syncthreads();
+  if (t < 170) stg<double>(sd.gpose + (size_t)p * 170 + t, ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t]);
 }
 
 // grad = sum_p gpose[p] (poses in order); thread 170 sums the losses
@@ -715,25 +789,55 @@ __global__ __launch_bounds__(256) void k_sred_all(SNetDev sd) {
   }
 }
 
-static size_t tile_bytes(int R) { return (size_t)SB * (R + 1) * sizeof(double); }
+static size_t tile_bytes(int R) { return (size_t)SB * tile_ld(R) * sizeof(double); }
 static size_t bwd_bytes(int R) { return std::max(tile_bytes(R), (size_t)SB * 25 * sizeof(double)); }
 
+// Poses go through in chunks of sd.nc (the last one shorter): the per-pose
+// intermediates of a chunk ([nc][n][8] features, [nc][m][8] adjoints) stay
+// small enough to be re-read from the caches rather than from HBM.
+static void forward_chunk(SNetDev c, hipStream_t s) {
+  dim3 gv(c.nbv, c.nc), ge(c.nbe, c.nc);
+  k_gcn1<<<gv, SB, 0, s>>>(c);
+  k_gcn2<<<gv, SB, 0, s>>>(c);
+  k_sfwd_elem<<<ge, SB, tile_bytes(c.R), s>>>(c);
+  k_scombine<<<c.nc, 256, 0, s>>>(c);
+}
+
 void launch_snet_forward(const SNetDev& sd, hipStream_t s) {
-  dim3 gv(sd.nbv, sd.P), ge(sd.nbe, sd.P);
-  k_gcn1<<<gv, SB, 0, s>>>(sd);
-  k_gcn2<<<gv, SB, 0, s>>>(sd);
-  k_sfwd_elem<<<ge, SB, tile_bytes(sd.R), s>>>(sd);
-  k_scombine<<<sd.P, 64, 0, s>>>(sd);
+  for (int p0 = 0; p0 < sd.P; p0 += sd.nc) {
+    SNetDev c = sd;
+    c.p0 = p0;
+    c.nc = std::min(sd.nc, sd.P - p0);
+    forward_chunk(c, s);
+  }
 }
 
 void launch_snet_epoch(const SNetDev& sd, hipStream_t s) {
-  launch_snet_forward(sd, s);
-  dim3 gv(sd.nbv, sd.P), ge(sd.nbe, sd.P);
-  k_sbwd_elem<<<ge, SB, bwd_bytes(sd.R), s>>>(sd);
-  k_sbwd_v2<<<gv, SB, 0, s>>>(sd);
-  k_sbwd_v1<<<gv, SB, 0, s>>>(sd);
-  k_sred_pose<<<sd.P, 256, 0, s>>>(sd);
+  for (int p0 = 0; p0 < sd.P; p0 += sd.nc) {
+    SNetDev c = sd;
+    c.p0 = p0;
+    c.nc = std::min(sd.nc, sd.P - p0);
+    forward_chunk(c, s);
+    dim3 gv(c.nbv, c.nc), ge(c.nbe, c.nc);
+    k_sbwd_elem<<<ge, SB, bwd_bytes(c.R), s>>>(c);
+    k_sbwd_v2<<<gv, SB, 0, s>>>(c);
+    k_sbwd_v1<<<gv, SB, 0, s>>>(c);
+    k_sred_pose<<<c.nc, 1024, 0, s>>>(c);
+  }
   k_sred_all<<<1, 256, 0, s>>>(sd);
+}
+
+void launch_snet_elem(const SNetDev& sd, int backward, hipStream_t s) {
+  for (int p0 = 0; p0 < sd.P; p0 += sd.nc) {
+    SNetDev c = sd;
+    c.p0 = p0;
+    c.nc = std::min(sd.nc, sd.P - p0);
+    dim3 ge(c.nbe, c.nc);
+    if (backward)
+      k_sbwd_elem<<<ge, SB, bwd_bytes(c.R), s>>>(c);
+    else
+      k_sfwd_elem<<<ge, SB, tile_bytes(c.R), s>>>(c);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -17,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libnmr.so")
 
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+TRAIN_PHASES = ["s_epoch", "w_epoch", "s_elem_fwd", "s_elem_bwd"]
 PHASES = ["dec_hidden", "dec_out", "cubature", "mass", "sums", "bwd_out", "bwd_hidden", "solve"]
 # kernels of each phase, as rocprofv3 names them
 PHASE_KERNELS = {"dec_hidden": "k_fwd_hidden", "dec_out": "k_fwd_out", "cubature": "k_cubature", "mass": "k_mass",
@@ -56,7 +57,7 @@ class TrainDesc(C.Structure):
     _fields_ = [("n_poses", C.c_int), ("poses", _dp), ("c_max", C.c_int), ("n_c0", C.c_int),
                 ("c0", C.POINTER(C.c_int32)), ("K", C.c_int), ("epochs", C.c_int), ("lr", C.c_double),
                 ("beta1", C.c_double), ("beta2", C.c_double), ("eps", C.c_double), ("wnet", C.POINTER(MlpDesc)),
-                ("wnet_scale", C.c_double), ("snet", _dp)]
+                ("wnet_scale", C.c_double), ("snet", _dp), ("pose_chunk", C.c_int)]
 
 
 class NmrError(RuntimeError):
@@ -115,6 +116,7 @@ def lib():
             "nmr_trainer_run": (i, [vp, i, _dp, _dp, ip, C.POINTER(C.c_float)]),
             "nmr_trainer_get": (i, [vp, ip, C.POINTER(C.c_int32), _dp, _dp]),
             "nmr_trainer_pose": (i, [vp, i, _dp, _dp, _dp]),
+            "nmr_trainer_time_phase": (i, [vp, i, i, C.POINTER(C.c_float)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -433,7 +435,7 @@ class Trainer:
 
     def __init__(self, inst: Instance, poses, wnet_weights, wnet_biases, wnet_scale: float, snet, n_c0: int, K: int,
                  epochs: int, c0=None, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
-                 eps: float = 1e-8):
+                 eps: float = 1e-8, pose_chunk: int = 0):
         self.poses = np.ascontiguousarray(poses, np.float64)
         self.P, self.R = self.poses.shape
         self.m = int(inst.prob.tets.shape[0])
@@ -449,6 +451,7 @@ class Trainer:
         d.c0 = None if self.c0 is None else self.c0.ctypes.data_as(C.POINTER(C.c_int32))
         d.K, d.epochs, d.lr, d.beta1, d.beta2, d.eps = K, epochs, lr, beta1, beta2, eps
         d.wnet, d.wnet_scale, d.snet = C.pointer(self.mlp.desc), wnet_scale, self.snet.ctypes.data_as(_dp)
+        d.pose_chunk = pose_chunk
         h = C.c_void_p()
         _check(lib().nmr_trainer_create(inst.h, C.byref(d), C.byref(h)))
         self.h = h
@@ -489,6 +492,12 @@ class Trainer:
         u = np.zeros(self.N)
         _check(lib().nmr_trainer_pose(self.h, p, F.ctypes.data_as(_dp), f.ctypes.data_as(_dp), u.ctypes.data_as(_dp)))
         return F, f, u
+
+    def time_phase(self, phase: str, reps: int = 5) -> float:
+        """Mean device microseconds of one phase (TRAIN_PHASES)."""
+        us = C.c_float()
+        _check(lib().nmr_trainer_time_phase(self.h, TRAIN_PHASES.index(phase), reps, C.byref(us)))
+        return us.value
 
     def close(self):
         if self.h:

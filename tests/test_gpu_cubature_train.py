@@ -94,10 +94,14 @@ def test_training_run_against_oracle_fp64(nmr, ctx, tiny):
 
 
 def test_training_is_bitwise_repeatable(nmr, ctx, tiny):
+    """Two runs, the second with the selection net's poses in chunks of 5
+    (5 + 5 + 2 launches): the same bits."""
     t, _, _, C0, _ = tiny
     runs = []
-    for _ in range(2):
-        inst, tr = trainer(nmr, ctx, t, "fp64", C0)
+    for chunk in (0, 5):
+        inst = nmr.Instance(ctx, t.prob, "fp64")
+        tr = nmr.Trainer(inst, t.poses, t.wnet_weights, t.wnet_biases, t.scale, t.theta, t.n_c0, t.K, t.epochs,
+                         c0=C0, lr=t.lr, pose_chunk=chunk)
         try:
             lw, ls, added, _ = tr.run(2)
             C, Ws, bs, theta = tr.get()
