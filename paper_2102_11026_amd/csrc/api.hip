@@ -5,6 +5,7 @@
 // (instance set, Newton iteration count) and replayed with one
 // hipGraphLaunch per step.
 #include "nmr_internal.h"
+#include "train_internal.h"
 #include "nmr.h"
 
 #include <algorithm>

@@ -21,7 +21,7 @@
 // vertex features [P][n][8] (H0 [P][n][3]); element adjoints dg [P][m][8];
 // parameter vector theta (170): G0 [3][8] (in, out), G1 [8][8] (in, out),
 // A1 [8][8] (out, in), a1 [8], A2 [8], a2, c.
-#include "nmr_internal.h"
+#include "train_internal.h"
 
 #include <algorithm>
 
