@@ -2086,7 +2086,7 @@ int trainer_build(nmr_inst* in, const nmr_cubature_train_desc* d, nmr_trainer* t
   sd.R = R;
   sd.P = P;
   sd.nbv = (n + 255) / 256;
-  sd.nbe = (m + 255) / 256;
+  sd.nbe = (m + NMR_TRAIN_SBE - 1) / NMR_TRAIN_SBE;
   sd.u = u;
   int *g_ptr, *g_idx, *vt_ptr, *vt_tet;
   double* g_val;

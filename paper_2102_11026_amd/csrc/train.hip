@@ -270,20 +270,42 @@ __global__ __launch_bounds__(256) void k_w_back(const double* W, const double* d
   stg<double>(din + (size_t)p * win + i, acc * sigmoid_d(ldg<double>(ain + (size_t)p * win + i)));
 }
 
-// gW[o][i] = sum_p delta[p][o] z[p][i] (i < win), gb[o] = sum_p delta[p][o] (i = win)
+// gW[o][i] = sum_p delta[p][o] z[p][i] (i < win), gb[o] = sum_p delta[p][o]
+// (column i = win of a z extended by ones).  Block: a 64 x 64 output tile,
+// 16 x 16 threads with 4 x 4 outputs each; poses staged 32 at a time in LDS
+// and added in pose order.
 __global__ __launch_bounds__(256) void k_w_grad(const double* delta, int wout, const double* zin, int win, int P,
                                                 double* gW, double* gb) {
-  const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (k >= (long long)wout * (win + 1)) return;
-  const int o = (int)(k / (win + 1)), i = (int)(k - (long long)o * (win + 1));
-  double acc = 0.0;
-  if (i < win) {
-    for (int p = 0; p < P; ++p) acc += ldg<double>(delta + (size_t)p * wout + o) * ldg<double>(zin + (size_t)p * win + i);
-    stg<double>(gW + (size_t)o * win + i, acc);
-  } else {
-    for (int p = 0; p < P; ++p) acc += ldg<double>(delta + (size_t)p * wout + o);
-    stg<double>(gb + o, acc);
+  __shared__ double sD[32][64], sZ[32][65];
+  const int o0 = blockIdx.y * 64, i0 = blockIdx.x * 64, t = threadIdx.x, ty = t / 16, tx = t % 16;
+  double acc[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int p0 = 0; p0 < P; p0 += 32) {
+    for (int k = t; k < 32 * 64; k += 256) {
+      const int pp = k / 64, c = k % 64, p = p0 + pp;
+      const int o = o0 + c, i = i0 + c;
+      sD[pp][c] = (p < P && o < wout) ? ldg<double>(delta + (size_t)p * wout + o) : 0.0;
+      sZ[pp][c] = (p < P && i < win) ? ldg<double>(zin + (size_t)p * win + i) : (p < P && i == win) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int np = min(32, P - p0);
+    for (int pp = 0; pp < np; ++pp) {
+      double d[4], z[4];
+      for (int a = 0; a < 4; ++a) d[a] = sD[pp][ty * 4 + a];
+      for (int b = 0; b < 4; ++b) z[b] = sZ[pp][tx * 4 + b];
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) acc[a][b] += d[a] * z[b];
+    }
+    __syncthreads();
   }
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) {
+      const int o = o0 + ty * 4 + a, i = i0 + tx * 4 + b;
+      if (o >= wout) continue;
+      if (i < win) stg<double>(gW + (size_t)o * win + i, acc[a][b]);
+      else if (i == win) stg<double>(gb + o, acc[a][b]);
+    }
 }
 
 // out = sum_p in[p] (poses in order)
@@ -328,8 +350,8 @@ void launch_wnet_epoch(const WNetDev& w, const TrainData& td, int nC, int mode, 
   for (int l = L - 1; l >= 0; --l) {
     const int wout = w.width[l + 1], win = w.width[l];
     const double* zl = l == 0 ? td.r : w.z[l - 1];
-    const long long nk = (long long)wout * (win + 1);
-    k_w_grad<<<(unsigned)((nk + 255) / 256), 256, 0, s>>>(w.d[l], wout, zl, win, P, w.g + w.Woff[l], w.g + w.boff[l]);
+    dim3 gg((win + 1 + 63) / 64, (wout + 63) / 64);
+    k_w_grad<<<gg, 256, 0, s>>>(w.d[l], wout, zl, win, P, w.g + w.Woff[l], w.g + w.boff[l]);
     if (l > 0) {
       const int nact = l == L - 1 ? nC : wout;
       dim3 grid((win + 63) / 64, (P + 3) / 4);
@@ -346,7 +368,9 @@ void launch_adam(double* x, const double* g, double* m, double* v, long long n, 
 // ---------------------------------------------------------------------------
 // selection net
 // ---------------------------------------------------------------------------
-#define SB 256  // vertices or elements per block
+#define SB 256                // vertices per block
+#define SBE NMR_TRAIN_SBE     // elements per block
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
 // L2.  Renumbered so that each XCD takes a contiguous run of logical blocks,
@@ -360,9 +384,16 @@ __device__ inline void xcd_block(int& b, int& pc) {
   pc = L / gridDim.x;
 }
 
-// the 8 channels of one vertex or element, stored back to back
+// the 8 channels of one vertex or element, stored and loaded back to back
 __device__ inline void store8(double* dst, const double (&v)[8]) {
   for (int k = 0; k < 4; ++k) stg<double2>(dst + 2 * k, make_double2(v[2 * k], v[2 * k + 1]));
+}
+__device__ inline void load8(const double* src, double (&v)[8]) {
+  for (int k = 0; k < 4; ++k) {
+    const double2 x = ldg<double2>(src + 2 * k);
+    v[2 * k] = x.x;
+    v[2 * k + 1] = x.y;
+  }
 }
 
 // first convolution: H0 = sum_j A_ij u_j (3), P1 = H0 G0, X1 = sin P1
@@ -406,7 +437,9 @@ __global__ __launch_bounds__(SB) void k_gcn2(SNetDev sd) {
   for (int k = j0; k < j1; ++k) {
     const int j = ldg<int>(sd.g_idx + k);
     const double a = ldg<double>(sd.g_val + k);
-    for (int c = 0; c < 8; ++c) h[c] += a * ldg<double>(X1 + 8 * j + c);
+    double x[8];
+    load8(X1 + 8 * j, x);
+    for (int c = 0; c < 8; ++c) h[c] += a * x[c];
   }
   const size_t vi = (size_t)pc * sd.n + v;
   store8(sd.H1 + 8 * vi, h);
@@ -428,7 +461,9 @@ __device__ inline double elem_head(const SNetDev& sd, int pc, int e, double (&g)
   for (int c = 0; c < 8; ++c) g[c] = 0.0;
   for (int a = 0; a < 4; ++a) {
     const int v = ldg<int>(sd.tets + 4 * e + a);
-    for (int c = 0; c < 8; ++c) g[c] += ldg<double>(X2 + 8 * v + c);
+    double x[8];
+    load8(X2 + 8 * v, x);
+    for (int c = 0; c < 8; ++c) g[c] += x[c];
   }
   for (int c = 0; c < 8; ++c) g[c] = g[c] / 4.0;
   const double* A1 = sd.theta + 88;
@@ -449,29 +484,37 @@ __device__ inline double elem_head(const SNetDev& sd, int pc, int e, double (&g)
 // rounded up to an odd number of doubles so that rows fall in different banks
 __device__ __host__ inline int tile_ld(int R) { return (R + 1) | 1; }
 
-// Stage the block's F rows [SB][R] of pose p in LDS with coalesced loads.
+// Stage the block's F rows [SBE][R] of pose p in LDS with coalesced loads.
 __device__ inline void load_F_tile(const SNetDev& sd, int p, int e0, double* tile) {
   const int R = sd.R, ld = tile_ld(R);
-  const int ne = min(SB, sd.m - e0);
+  const int ne = min(SBE, sd.m - e0);
   const double* src = sd.F + ((size_t)p * sd.m + e0) * R;
-  for (int k = threadIdx.x; k < ne * R; k += SB) {
-    const int e = k / R;
-    tile[e * ld + (k - e * R)] = ldg<double>(src + k);
+  // element and column of flat index k, advanced by SBE without a division
+  int k = threadIdx.x, e = k / R, c = k - e * R;
+  const int de = SBE / R, dc = SBE - de * R;
+  for (; k < ne * R; k += SBE) {
+    tile[e * ld + c] = ldg<double>(src + k);
+    e += de;
+    c += dc;
+    if (c >= R) {
+      c -= R;
+      ++e;
+    }
   }
 }
 
 // Forward over the elements, block b of pose p: z (stored), block max M_b of
 // the candidates' z, and with w_e = exp(z_e - M_b): S_b = sum w_e and
 // V_b = sum w_e F[p][e]; partial layout [P][nbe][R + 2] = (V_b, S_b, M_b).
-__global__ __launch_bounds__(SB) void k_sfwd_elem(SNetDev sd) {
+__global__ __launch_bounds__(SBE) void k_sfwd_elem(SNetDev sd) {
   extern __shared__ double lds[];
   int b, pc;
   xcd_block(b, pc);
   const int p = sd.p0 + pc, t = threadIdx.x, R = sd.R, ld = tile_ld(R);
-  const int e0 = b * SB, e = e0 + t;
-  double* tile = lds;                    // [SB][ld], column R = w
-  __shared__ double red[SB];
-  __shared__ double part[8][NMR_MAX_R + 2];
+  const int e0 = b * SBE, e = e0 + t;
+  double* tile = lds;                    // [SBE][ld], column R = w
+  __shared__ double red[SBE];
+  __shared__ double part[SBE / 32][NMR_MAX_R + 2];
   load_F_tile(sd, p, e0, tile);
   bool cand = false;
   double z = -INFINITY;
@@ -483,7 +526,7 @@ __global__ __launch_bounds__(SB) void k_sfwd_elem(SNetDev sd) {
   }
   red[t] = cand ? z : -INFINITY;
   __syncthreads();
-  for (int h = SB / 2; h > 0; h >>= 1) {
+  for (int h = SBE / 2; h > 0; h >>= 1) {
     if (t < h) red[t] = fmax(red[t], red[t + h]);
     __syncthreads();
   }
@@ -491,10 +534,10 @@ __global__ __launch_bounds__(SB) void k_sfwd_elem(SNetDev sd) {
   const double w = cand ? exp(z - Mb) : 0.0;
   tile[t * ld + R] = w;
   __syncthreads();
-  // 8 slices of 32 elements: thread (slice, col) sums its column
+  // slices of 32 elements: thread (slice, col) sums its column
   const int col = t % 32, sl = t / 32;
   if (col <= R) {
-    const int ne = min(SB, sd.m - e0);
+    const int ne = min(SBE, sd.m - e0);
     double acc = 0.0;
     for (int k = sl * 32; k < min(ne, sl * 32 + 32); ++k) {
       const double wk = tile[k * ld + R];
@@ -505,7 +548,7 @@ __global__ __launch_bounds__(SB) void k_sfwd_elem(SNetDev sd) {
   __syncthreads();
   if (t <= R) {
     double s = 0.0;
-    for (int k = 0; k < 8; ++k) s += part[k][t];
+    for (int k = 0; k < SBE / 32; ++k) s += part[k][t];
     stg<double>(sd.pf + ((size_t)pc * sd.nbe + b) * (R + 2) + t, s);
   }
   if (t == 0) stg<double>(sd.pf + ((size_t)pc * sd.nbe + b) * (R + 2) + R + 1, Mb);
@@ -575,15 +618,15 @@ __global__ __launch_bounds__(256) void k_scombine(SNetDev sd) {
 // Backward over the elements: ds_e = coef F[p][e] . res, dz = s (ds - qbar),
 // dQ = dz A2 cos Q, dg = A1^T dQ (stored); block partials of the element-head
 // gradients, layout [P][nbe][81] = (A1 [8][8], a1, A2, a2) in theta order.
-__global__ __launch_bounds__(SB) void k_sbwd_elem(SNetDev sd) {
+__global__ __launch_bounds__(SBE) void k_sbwd_elem(SNetDev sd) {
   extern __shared__ double lds[];
   int b, pc;
   xcd_block(b, pc);
   const int p = sd.p0 + pc, t = threadIdx.x, R = sd.R, ld = tile_ld(R);
-  const int e0 = b * SB, e = e0 + t;
-  double* tile = lds;                        // [SB][ld]
+  const int e0 = b * SBE, e = e0 + t;
+  double* tile = lds;                        // [SBE][ld]
   double(*sv)[25] = (double(*)[25])lds;      // after the dot products: dz, dQ (8), g (8), Y (8)
-  __shared__ double part[3][81];
+  __shared__ double cmb[2][16][16];
   __shared__ double res[NMR_MAX_R];
   load_F_tile(sd, p, e0, tile);
   if (t < R) res[t] = ldg<double>(sd.res + (size_t)p * R + t);
@@ -595,7 +638,9 @@ __global__ __launch_bounds__(SB) void k_sbwd_elem(SNetDev sd) {
     const double* X2 = sd.X2 + (size_t)pc * 8 * sd.n;
     for (int a = 0; a < 4; ++a) {
       const int v = ldg<int>(sd.tets + 4 * e + a);
-      for (int c = 0; c < 8; ++c) g[c] += ldg<double>(X2 + 8 * v + c);
+      double x[8];
+      load8(X2 + 8 * v, x);
+      for (int c = 0; c < 8; ++c) g[c] += x[c];
     }
     for (int c = 0; c < 8; ++c) g[c] = g[c] / 4.0;
     double cQ[8];
@@ -634,26 +679,42 @@ __global__ __launch_bounds__(SB) void k_sbwd_elem(SNetDev sd) {
     sv[t][17 + c] = Y[c];
   }
   __syncthreads();
-  // 81 gradient entries x 3 slices of the block's elements
-  if (t < 243) {
-    const int j = t % 81, sl = t / 81;
-    const int k0 = sl * 86, k1 = min(SB, k0 + 86);
-    double acc = 0.0;
-    if (j < 64) {  // A1[o][i] += dQ_o g_i
-      const int o = j / 8, i = j % 8;
-      for (int k = k0; k < k1; ++k) acc += sv[k][1 + o] * sv[k][9 + i];
-    } else if (j < 72) {  // a1
-      for (int k = k0; k < k1; ++k) acc += sv[k][1 + (j - 64)];
-    } else if (j < 80) {  // A2[i] += dz Y_i
-      for (int k = k0; k < k1; ++k) acc += sv[k][0] * sv[k][17 + (j - 72)];
-    } else {  // a2
-      for (int k = k0; k < k1; ++k) acc += sv[k][0];
+  // The 81 head gradients as two outer-product sums over the block's elements
+  // on the FP64 matrix cores: with a_e = [dQ (8), dz, 0 ...] and
+  // b_e = [g (8), Y (8)], D = sum_e a_e b_e^T holds dA1 (rows 0-7, columns 0-7)
+  // and dA2 (row 8, columns 8-15); D2 = sum_e a_e e_0^T holds da1 and da2
+  // (column 0).  Each wave takes its 64 elements four at a time
+  // (v_mfma_f64_16x16x4: A[m][k] from lane m + 16 k, B[k][n] from lane n + 16 k;
+  // item q of lane l is D[4 q + l / 16][l % 16]); wave partials are added in
+  // wave order.
+  {
+    const int wave = t >> 6, lane = t & 63, col = lane & 15, kk = lane >> 4;
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};
+    const double b2 = col == 0 ? 1.0 : 0.0;
+    for (int step = 0; step < 16; ++step) {
+      const int row = wave * 64 + step * 4 + kk;
+      const double a = col < 8 ? sv[row][1 + col] : col == 8 ? sv[row][0] : 0.0;
+      const double bb = col < 8 ? sv[row][9 + col] : sv[row][17 + (col - 8)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bb, acc, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b2, acc2, 0, 0, 0);
     }
-    part[sl][j] = acc;
+    for (int w = 0; w < SBE / 64; ++w) {
+      if (wave == w)
+        for (int q = 0; q < 4; ++q) {
+          const int rr = 4 * q + kk;
+          cmb[0][rr][col] = (w == 0 ? 0.0 : cmb[0][rr][col]) + acc[q];
+          cmb[1][rr][col] = (w == 0 ? 0.0 : cmb[1][rr][col]) + acc2[q];
+        }
+      __syncthreads();
+    }
   }
-  __syncthreads();
-  if (t < 81)
-    stg<double>(sd.pe + ((size_t)pc * sd.nbe + b) * 81 + t, (part[0][t] + part[1][t]) + part[2][t]);
+  if (t < 81) {
+    const double v = t < 64 ? cmb[0][t / 8][t % 8]             // dA1[o][i]
+                   : t < 72 ? cmb[1][t - 64][0]                 // da1[o]
+                   : t < 80 ? cmb[0][8][8 + (t - 72)]           // dA2[i]
+                            : cmb[1][8][0];                     // da2
+    stg<double>(sd.pe + ((size_t)pc * sd.nbe + b) * 81 + t, v);
+  }
 }
 
 // Second convolution backward, per vertex: dX2 = sum over incident tets of
@@ -676,7 +737,9 @@ __global__ __launch_bounds__(SB) void k_sbwd_v2(SNetDev sd) {
     const int k0 = ldg<int>(sd.vt_ptr + v), k1 = ldg<int>(sd.vt_ptr + v + 1);
     for (int k = k0; k < k1; ++k) {
       const int e = ldg<int>(sd.vt_tet + k);
-      for (int c = 0; c < 8; ++c) dx[c] += ldg<double>(dg + (size_t)e * 8 + c) / 4.0;
+      double x[8];
+      load8(dg + (size_t)e * 8, x);
+      for (int c = 0; c < 8; ++c) dx[c] += x[c] / 4.0;
     }
     for (int c = 0; c < 8; ++c) {
       h[c] = ldg<double>(sd.H1 + 8 * vi + c);
@@ -727,7 +790,9 @@ __global__ __launch_bounds__(SB) void k_sbwd_v1(SNetDev sd) {
     for (int k = j0; k < j1; ++k) {
       const int j = ldg<int>(sd.g_idx + k);
       const double a = ldg<double>(sd.g_val + k);
-      for (int c = 0; c < 8; ++c) dx[c] += a * ldg<double>(T2 + 8 * j + c);
+      double x[8];
+      load8(T2 + 8 * j, x);
+      for (int c = 0; c < 8; ++c) dx[c] += a * x[c];
     }
     for (int c = 0; c < 8; ++c) d[c] = dx[c] * cos(ldg<double>(sd.P1 + 8 * vi + c));
     for (int c = 0; c < 3; ++c) h[c] = ldg<double>(sd.H0 + 3 * vi + c);
@@ -775,22 +840,25 @@ __global__ __launch_bounds__(1024) void k_sred_pose(SNetDev sd) {
   if (t < 170) stg<double>(sd.gpose + (size_t)p * 170 + t, ((part[0][t] + part[1][t]) + part[2][t]) + part[3][t]);
 }
 
-// grad = sum_p gpose[p] (poses in order); thread 170 sums the losses
+// grad[k] = sum_p gpose[p][k] (block k < 170) and the loss (block 170):
+// each of 256 threads adds every 256th pose in order, then a fixed tree.
 __global__ __launch_bounds__(256) void k_sred_all(SNetDev sd) {
-  const int k = threadIdx.x;
-  if (k < 170) {
-    double s = 0.0;
-    for (int p = 0; p < sd.P; ++p) s += ldg<double>(sd.gpose + (size_t)p * 170 + k);
-    stg<double>(sd.grad + k, s);
-  } else if (k == 170) {
-    double s = 0.0;
-    for (int p = 0; p < sd.P; ++p) s += ldg<double>(sd.loss_p + p);
-    stg<double>(sd.loss_out, s);
+  const int k = blockIdx.x, t = threadIdx.x;
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int p = t; p < sd.P; p += 256)
+    s += k < 170 ? ldg<double>(sd.gpose + (size_t)p * 170 + k) : ldg<double>(sd.loss_p + p);
+  red[t] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
   }
+  if (t == 0) stg<double>(k < 170 ? sd.grad + k : sd.loss_out, red[0]);
 }
 
-static size_t tile_bytes(int R) { return (size_t)SB * tile_ld(R) * sizeof(double); }
-static size_t bwd_bytes(int R) { return std::max(tile_bytes(R), (size_t)SB * 25 * sizeof(double)); }
+static size_t tile_bytes(int R) { return (size_t)SBE * tile_ld(R) * sizeof(double); }
+static size_t bwd_bytes(int R) { return std::max(tile_bytes(R), (size_t)SBE * 25 * sizeof(double)); }
 
 // Poses go through in chunks of sd.nc (the last one shorter): the per-pose
 // intermediates of a chunk ([nc][n][8] features, [nc][m][8] adjoints) stay
@@ -799,7 +867,7 @@ static void forward_chunk(SNetDev c, hipStream_t s) {
   dim3 gv(c.nbv, c.nc), ge(c.nbe, c.nc);
   k_gcn1<<<gv, SB, 0, s>>>(c);
   k_gcn2<<<gv, SB, 0, s>>>(c);
-  k_sfwd_elem<<<ge, SB, tile_bytes(c.R), s>>>(c);
+  k_sfwd_elem<<<ge, SBE, tile_bytes(c.R), s>>>(c);
   k_scombine<<<c.nc, 256, 0, s>>>(c);
 }
 
@@ -819,12 +887,12 @@ void launch_snet_epoch(const SNetDev& sd, hipStream_t s) {
     c.nc = std::min(sd.nc, sd.P - p0);
     forward_chunk(c, s);
     dim3 gv(c.nbv, c.nc), ge(c.nbe, c.nc);
-    k_sbwd_elem<<<ge, SB, bwd_bytes(c.R), s>>>(c);
+    k_sbwd_elem<<<ge, SBE, bwd_bytes(c.R), s>>>(c);
     k_sbwd_v2<<<gv, SB, 0, s>>>(c);
     k_sbwd_v1<<<gv, SB, 0, s>>>(c);
     k_sred_pose<<<c.nc, 1024, 0, s>>>(c);
   }
-  k_sred_all<<<1, 256, 0, s>>>(sd);
+  k_sred_all<<<171, 256, 0, s>>>(sd);
 }
 
 void launch_snet_elem(const SNetDev& sd, int backward, hipStream_t s) {
@@ -834,9 +902,9 @@ void launch_snet_elem(const SNetDev& sd, int backward, hipStream_t s) {
     c.nc = std::min(sd.nc, sd.P - p0);
     dim3 ge(c.nbe, c.nc);
     if (backward)
-      k_sbwd_elem<<<ge, SB, bwd_bytes(c.R), s>>>(c);
+      k_sbwd_elem<<<ge, SBE, bwd_bytes(c.R), s>>>(c);
     else
-      k_sfwd_elem<<<ge, SB, tile_bytes(c.R), s>>>(c);
+      k_sfwd_elem<<<ge, SBE, tile_bytes(c.R), s>>>(c);
   }
 }
 

@@ -4,6 +4,8 @@
 
 #include "nmr_internal.h"
 
+#define NMR_TRAIN_SBE 128  // elements per block of the selection net's element passes
+
 namespace nmr {
 
 // Mesh of every tet in FP64 (rest shape computed on the device).
