@@ -214,7 +214,7 @@ def rel(a, b) -> float:
 GOLDEN = os.path.join(ROOT, "tests", "golden", "bar10k_trajectory_fp64.npz")
 
 
-def training_report(nmr, ctx, n_poses: int):
+def training_report(nmr, ctx, n_poses: int, cpu: bool = True):
     """Neural cubature training (Sec. 5) on the 10,000-vertex bar: training
     data of n_poses poses (FP32 decoder derivatives, FP64 element forces), then
     alternations of 15 epochs per net (FP64).  The dominant kernel is the
@@ -250,7 +250,40 @@ def training_report(nmr, ctx, n_poses: int):
                              unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), algorithmic_bytes=int(bwd_bytes)))
     tr.close()
     inst.close()
+    if cpu:
+        out["cpu_baseline"] = training_cpu_baseline(t)
     return out
+
+
+def training_cpu_baseline(t, n_poses: int = 2):
+    """The FP64 oracle of neural cubature training, untuned, on this host's
+    cores: the training data of the first n_poses poses, then one epoch of each
+    net's loss and gradient over them (C = the first n_c0 elements of a
+    uniform stride, the selection net over every other element)."""
+    from threadpoolctl import threadpool_info
+    from oracle import cubature_train as ct
+    from oracle.newton import Instance as OracleInstance
+    oi = OracleInstance(t.prob)
+    used = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    t0 = time.perf_counter()
+    data = [ct.element_forces(oi, r) for r in t.poses[:n_poses]]
+    t1 = time.perf_counter()
+    m = int(t.prob.tets.shape[0])
+    C0 = list(range(0, m, m // t.n_c0))[:t.n_c0]
+    ct.loss_W(t.wnet_weights, t.wnet_biases, t.scale, C0, [(r, F, f) for r, (F, f, _) in zip(t.poses, data)])
+    t2 = time.perf_counter()
+    A = ct.mesh_graph(t.prob.tets, t.prob.n)
+    inC = np.zeros(m, bool)
+    inC[C0] = True
+    t3 = time.perf_counter()
+    ct.loss_S(t.theta, A, t.prob.tets, np.flatnonzero(~inC), [(u, F, f) for (F, f, u) in data])
+    t4 = time.perf_counter()
+    per_pose_epochs = (t2 - t1 + t4 - t3) / n_poses   # one W and one S epoch of one pose
+    return dict(value=round(2.0 / per_pose_epochs, 3), unit="pose-epochs/s", cores=int(used), kind="oracle",
+                training_data_s_per_pose=round((t1 - t0) / n_poses, 3),
+                sample=f"training data of {n_poses} poses of the 10k-vertex bar, then one weight-net and one "
+                       f"selection-net epoch over them (FP64 numpy/BLAS oracle, dense graph), "
+                       f"{t4 - t0:.1f} s")
 
 
 def precision_report(nmr, ctx, p):
@@ -588,7 +621,8 @@ def main():
                 log(f"served {prec}:", stats)
         # NEXT row: neural cubature training (Sec. 5)
         if args.train_poses > 0:
-            var["cubature_training_bar10k"] = training_report(nmr, ctx, args.train_poses)
+            var["cubature_training_bar10k"] = training_report(nmr, ctx, args.train_poses,
+                                                              cpu=not args.no_cpu_baseline)
             log("cubature training:", var["cubature_training_bar10k"])
         # NEXT row: the fictitious force and consistency in dt (FP64, through the C ABI)
         from paper_2102_11026_amd import experiments
