@@ -491,7 +491,7 @@ static int build_instance(nmr_ctx* ctx, const nmr_problem* p, int prec, nmr_deco
   s.Cf = pad_to(2 + 2 * s.n_q, 16);
   s.Wmax = 0;
   for (int l = 1; l < d.L; ++l) s.Wmax = std::max(s.Wmax, d.wp[l]);
-  s.cub_per_blk = 4;  // one tet per wave of a 4-wave block
+  s.cub_per_blk = 4;  // four virtual waves of one tet (a 4-wave block, or four lane groups of one wave)
   s.n_mblk = (s.N + 255) / 256;
   s.n_cblk = (s.n_cub + s.cub_per_blk - 1) / s.cub_per_blk;
   s.n_bblk = (s.N + 127) / 128;

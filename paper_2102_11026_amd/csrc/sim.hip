@@ -153,24 +153,33 @@ template void launch_step_begin<float>(const Inst<float>*, int, int, int, hipStr
 template void launch_step_begin<double>(const Inst<double>*, int, int, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
-// Cubature: 4 waves per block, each wave takes every fourth tet of the
-// block's range.  Per tet e with deformation gradient F = D_s B_m, first Piola
-// stress P and its tangent dP:
+// Cubature: a block of 4 cubature tets (times the merge factor m) is split
+// over 4 "virtual waves", virtual wave v taking the tets e0 + v + 4k.  A
+// virtual wave is a real wave of a 4-wave block (W = 4: one tet per wave at a
+// time, the latency-bound form of small launches) or a 16-lane group of a
+// 1-wave block (W = 1: four tets per wave at once, the throughput form of
+// large launches with R <= 16).  Per tet e with deformation gradient
+// F = D_s B_m, first Piola stress P and its tangent dP:
 //   dF_r = dF/dr_r = sum_a Jt_{a,r} (x) g_a,   g_a = gradient of hat fn a,
 //   fr_r += w V P : dF_r,   Kr_rs += w V dP[dF_r] : dF_s,
 //   f_a   = w V P g_a (element force, gathered per DOF later),
 // which equals Jt_e^T f_e and Jt_e^T K_e Jt_e without forming the 12 x 12
 // K_e.  Neo-Hookean: P = mu (F - F^-T) + lam ln J F^-T,
 //   dP[dF] = mu dF + (mu - lam ln J) F^-T dF^T F^-T + lam tr(F^-1 dF) F^-T.
-// Element math in T, accumulation in FP64; the four wave sums are added in
-// wave order.  Launches of many instances merge m = cubature_merge(nb)
-// consecutive blocks of tets into one (partial b then covers blocks b m ..
-// b m + m - 1).
+// F and P are computed by every lane of a tet's lane group, dF_r and dP[dF_r]
+// by its lane r, the stiffness blocks by all 64 lanes of the wave.  Element
+// math in T, accumulation in FP64, one accumulator set per virtual wave, the
+// virtual waves' sums added in order: both forms give the same bits.
+// Launches of many instances merge m = cubature_merge(nb) consecutive blocks
+// of tets into one (partial b then covers blocks b m .. b m + m - 1).
 // ---------------------------------------------------------------------------
-#define CUB_WAVES 4
+#define CUB_VWAVES 4
 
-template <typename T, int RB>
+template <typename T, int RB, int W>
 __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, int bx, int by, int m) {
+  constexpr int G = CUB_VWAVES / W;  // tets per wave at once (lane groups)
+  constexpr int LG = 64 / G;         // lanes per group
+  static_assert(G == 1 || RB <= LG, "a lane group must hold R lanes");
   const Inst<T>& I = tab[by];
   load_now(I.active, I.n_cblk, I.R, I.cu_na, I.mu, I.lam, I.cub_per_blk, I.n_cub, I.cub_v, I.cub_Bm, I.cu_w, I.cub_Ve,
            I.X, I.cu_u, I.cu_u_ld, I.cu_Ja, I.cu_Ja_ld, I.cu_Jb, I.cu_Jb_ld, I.status, I.fe, I.part_cub);
@@ -178,27 +187,33 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
   if (bx * m >= I.n_cblk) return;
   const int R = I.R;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int grp = lane / LG, gl = lane % LG;  // lane group (tet of the round) and lane within it
   const int na = I.cu_na;
   const T mu = (T)I.mu, lam = (T)I.lam;
-  __shared__ T xs[CUB_WAVES][12];
-  __shared__ T J12[CUB_WAVES][12][RB + 1];
-  __shared__ T dFs[CUB_WAVES][RB][9];
-  __shared__ T dPs[CUB_WAVES][RB][9];
+  __shared__ T xs[W][G][12];
+  __shared__ T J12[W][G][12][RB + 1];
+  __shared__ T dFs[W][G][RB][9];
+  __shared__ T dPs[W][G][RB][9];
+  __shared__ T sw[W][G];     // w V of the round's tets
+  __shared__ int sok[W][G];  // 1: the group's tet is in the range
+  __shared__ double sfa[W][64];
   __shared__ double red[RB * RB + RB];
   // the R x R stiffness sums in 2 x 2 blocks: lane l owns blocks l + 64 t,
   // block b covering rows 2 (b / nb2) + {0, 1} and columns 2 (b % nb2) + {0, 1}
   // (each entry the same 9-term dot product in the same order as unblocked)
   constexpr int BT = ((RB + 1) / 2 * ((RB + 1) / 2) + 63) / 64;
   const int nb2 = (R + 1) / 2;
-  double kacc[BT][4];
+  double kacc[G][BT][4];
 #pragma unroll
-  for (int t = 0; t < BT; ++t)
+  for (int g = 0; g < G; ++g)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) kacc[t][q] = 0.0;
+    for (int t = 0; t < BT; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) kacc[g][t][q] = 0.0;
   double facc = 0.0;
   const int e0 = bx * m * I.cub_per_blk;
   const int e1 = min(e0 + m * I.cub_per_blk, I.n_cub);
-  constexpr int JT = (12 * RB + 63) / 64;
+  constexpr int JT = (12 * RB + LG - 1) / LG;
   // first round trip of tet e: its vertices, B_m, weight and volume (none
   // depends on another load)
   auto load_r1 = [&](int e, int4& tv, T (&Bmv)[9], T& wV) {
@@ -215,11 +230,11 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
       const int v = a == 0 ? tv.x : a == 1 ? tv.y : a == 2 ? tv.z : tv.w;
       return 3 * v + (ac - 3 * a);
     };
-    const int dx = dof_of(min(lane, 11));
+    const int dx = dof_of(min(gl, 11));
     xv = ldg<T>(I.X + dx) + ldg<T>(I.cu_u + (size_t)dx * I.cu_u_ld);
 #pragma unroll
     for (int t = 0; t < JT; ++t) {
-      const int p = min(lane + 64 * t, 12 * R - 1);
+      const int p = min(gl + LG * t, 12 * R - 1);
       const int ac = p / R, r = p - ac * R;
       const int dof = dof_of(ac);
       const T* src = (r < na) ? I.cu_Ja + (size_t)dof * I.cu_Ja_ld + r : I.cu_Jb + (size_t)dof * I.cu_Jb_ld + (r - na);
@@ -232,35 +247,39 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
     __builtin_amdgcn_wave_barrier();
   };
-  // tet e from its loaded operands
-  auto tet = [&](int e, const T (&Bmv)[9], const T wV, const T xv, const T (&jv)[JT]) {
-    if (lane < 12) xs[wave][lane] = xv;
+  // the round's G tets from their loaded operands (ok: this lane's tet is in range)
+  auto tets = [&](int e, bool ok, const T (&Bmv)[9], const T wV, const T xv, const T (&jv)[JT]) {
+    if (gl < 12) xs[wave][grp][gl] = xv;
 #pragma unroll
     for (int t = 0; t < JT; ++t) {
-      const int p = lane + 64 * t;
+      const int p = gl + LG * t;
       if (p < 12 * R) {
         const int ac = p / R, r = p - ac * R;
-        J12[wave][ac][r] = jv[t];
+        J12[wave][grp][ac][r] = jv[t];
       }
     }
+    if (gl == 0) {
+      sw[wave][grp] = wV;
+      sok[wave][grp] = ok ? 1 : 0;
+    }
     lds_fence();
-    T G[4][3];
+    T G3[4][3];
     for (int j = 0; j < 3; ++j) {
-      G[1][j] = Bmv[0 * 3 + j];
-      G[2][j] = Bmv[1 * 3 + j];
-      G[3][j] = Bmv[2 * 3 + j];
-      G[0][j] = -(G[1][j] + G[2][j] + G[3][j]);
+      G3[1][j] = Bmv[0 * 3 + j];
+      G3[2][j] = Bmv[1 * 3 + j];
+      G3[3][j] = Bmv[2 * 3 + j];
+      G3[0][j] = -(G3[1][j] + G3[2][j] + G3[3][j]);
     }
     T F[3][3];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
         T acc = T(0);
-        for (int a = 1; a < 4; ++a) acc += (xs[wave][3 * a + i] - xs[wave][i]) * G[a][j];
+        for (int a = 1; a < 4; ++a) acc += (xs[wave][grp][3 * a + i] - xs[wave][grp][i]) * G3[a][j];
         F[i][j] = acc;
       }
     const T det = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
                   F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
-    if (det <= T(0) && lane == 0) atomicOr(I.status, ST_INVERTED);
+    if (ok && det <= T(0) && gl == 0) atomicOr(I.status, ST_INVERTED);
     const T id = T(1) / det;
     T A[3][3];  // F^-T
     A[0][0] = (F[1][1] * F[2][2] - F[1][2] * F[2][1]) * id;
@@ -277,13 +296,13 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) P[i][j] = mu * (F[i][j] - A[i][j]) + lam * lnJ * A[i][j];
     const T c2 = mu - lam * lnJ;
-    if (lane < R) {
-      const int r = lane;
+    if (gl < R) {
+      const int r = gl;
       T dF[3][3];
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
           T acc = T(0);
-          for (int a = 0; a < 4; ++a) acc += J12[wave][3 * a + i][r] * G[a][j];
+          for (int a = 0; a < 4; ++a) acc += J12[wave][grp][3 * a + i][r] * G3[a][j];
           dF[i][j] = acc;
         }
       T tr = T(0);
@@ -296,66 +315,74 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
           const T ADA = A[i][0] * M[0][j] + A[i][1] * M[1][j] + A[i][2] * M[2][j];
-          dPs[wave][r][3 * i + j] = mu * dF[i][j] + c2 * ADA + lam * tr * A[i][j];
-          dFs[wave][r][3 * i + j] = dF[i][j];
+          dPs[wave][grp][r][3 * i + j] = mu * dF[i][j] + c2 * ADA + lam * tr * A[i][j];
+          dFs[wave][grp][r][3 * i + j] = dF[i][j];
           fr += P[i][j] * dF[i][j];
         }
-      facc += (double)wV * (double)fr;
+      if (ok) facc += (double)wV * (double)fr;
     }
-    if (lane < 12) {
-      const int a = lane / 3, i = lane % 3;
+    if (ok && gl < 12) {
+      const int a = gl / 3, i = gl % 3;
       T f = T(0);
-      for (int j = 0; j < 3; ++j) f += P[i][j] * G[a][j];
-      stg<T>(I.fe + (size_t)e * 12 + lane, wV * f);
+      for (int j = 0; j < 3; ++j) f += P[i][j] * G3[a][j];
+      stg<T>(I.fe + (size_t)e * 12 + gl, wV * f);
     }
     lds_fence();
 #pragma unroll
-    for (int t = 0; t < BT; ++t) {
-      const int b = lane + 64 * t;
-      if (b < nb2 * nb2) {
-        const int r0 = 2 * (b / nb2), s0 = 2 * (b % nb2);
-        const int r1 = min(r0 + 1, R - 1), s1 = min(s0 + 1, R - 1);
-        T a00 = T(0), a01 = T(0), a10 = T(0), a11 = T(0);
+    for (int g = 0; g < G; ++g) {
+      if (!sok[wave][g]) continue;
+      const double wg = (double)sw[wave][g];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) {
-          const T p0 = dPs[wave][r0][k], p1 = dPs[wave][r1][k];
-          const T f0 = dFs[wave][s0][k], f1 = dFs[wave][s1][k];
-          a00 += p0 * f0;
-          a01 += p0 * f1;
-          a10 += p1 * f0;
-          a11 += p1 * f1;
+      for (int t = 0; t < BT; ++t) {
+        const int b = lane + 64 * t;
+        if (b < nb2 * nb2) {
+          const int r0 = 2 * (b / nb2), s0 = 2 * (b % nb2);
+          const int r1 = min(r0 + 1, R - 1), s1 = min(s0 + 1, R - 1);
+          T a00 = T(0), a01 = T(0), a10 = T(0), a11 = T(0);
+#pragma unroll
+          for (int k = 0; k < 9; ++k) {
+            const T p0 = dPs[wave][g][r0][k], p1 = dPs[wave][g][r1][k];
+            const T f0 = dFs[wave][g][s0][k], f1 = dFs[wave][g][s1][k];
+            a00 += p0 * f0;
+            a01 += p0 * f1;
+            a10 += p1 * f0;
+            a11 += p1 * f1;
+          }
+          kacc[g][t][0] += wg * (double)a00;
+          kacc[g][t][1] += wg * (double)a01;
+          kacc[g][t][2] += wg * (double)a10;
+          kacc[g][t][3] += wg * (double)a11;
         }
-        kacc[t][0] += (double)wV * (double)a00;
-        kacc[t][1] += (double)wV * (double)a01;
-        kacc[t][2] += (double)wV * (double)a10;
-        kacc[t][3] += (double)wV * (double)a11;
       }
     }
     lds_fence();
   };
-  int e = e0 + wave;
-  if (e1 - e0 <= CUB_WAVES) {
-    // at most one tet per wave: nothing to overlap
-    if (e < e1) {
+  // round k of this wave covers tets eb + 4 k .. eb + 4 k + G - 1
+  constexpr int S = CUB_VWAVES;
+  int eb = e0 + wave * G;
+  if (e1 - e0 <= S) {
+    // one round: nothing to overlap
+    if (eb < e1) {
+      const int e = min(eb + grp, e1 - 1);
       int4 tv;
       T Bmv[9], wV, xv, jv[JT];
       load_r1(e, tv, Bmv, wV);
       load_r2(tv, xv, jv);
-      tet(e, Bmv, wV, xv, jv);
+      tets(e, eb + grp < e1, Bmv, wV, xv, jv);
     }
-  } else if (e < e1) {
-    // three-stage pipeline: while tet e is computed, the second round trip
-    // of the next tet and the first of the one after are in flight (indices
+  } else if (eb < e1) {
+    // three-stage pipeline: while round k is computed, the second round trip
+    // of round k + 1 and the first of round k + 2 are in flight (indices
     // clamped to the last tet of the range; past it the loads go unused)
     int4 tv1, tv2;
     T Bm0[9], Bm1[9], Bm2[9], wV0, wV1, wV2, xv0, xv1, jv0[JT], jv1[JT];
-    load_r1(e, tv2, Bm0, wV0);
-    load_r1(min(e + CUB_WAVES, e1 - 1), tv1, Bm1, wV1);
+    load_r1(min(eb + grp, e1 - 1), tv2, Bm0, wV0);
+    load_r1(min(eb + S + grp, e1 - 1), tv1, Bm1, wV1);
     load_r2(tv2, xv0, jv0);
-    for (; e < e1; e += CUB_WAVES) {
-      load_r1(min(e + 2 * CUB_WAVES, e1 - 1), tv2, Bm2, wV2);
+    for (; eb < e1; eb += S) {
+      load_r1(min(eb + 2 * S + grp, e1 - 1), tv2, Bm2, wV2);
       load_r2(tv1, xv1, jv1);
-      tet(e, Bm0, wV0, xv0, jv0);
+      tets(min(eb + grp, e1 - 1), eb + grp < e1, Bm0, wV0, xv0, jv0);
       tv1 = tv2;
       wV0 = wV1;
       wV1 = wV2;
@@ -369,9 +396,11 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
       for (int t = 0; t < JT; ++t) jv0[t] = jv1[t];
     }
   }
-  // wave sums added in wave order
+  // the virtual waves' sums added in virtual-wave order (wave, then group)
+  sfa[wave][lane] = facc;
+  __syncthreads();
   const int E = R * R + R;
-  for (int w = 0; w < CUB_WAVES; ++w) {
+  for (int w = 0; w < W; ++w) {
     if (wave == w) {
 #pragma unroll
       for (int t = 0; t < BT; ++t) {
@@ -381,30 +410,54 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int r = r0 + (q >> 1), c = s0 + (q & 1);
-            if (r < R && c < R) red[r * R + c] = (w == 0 ? 0.0 : red[r * R + c]) + kacc[t][q];
+            if (r < R && c < R) {
+              double v = w == 0 ? 0.0 : red[r * R + c];
+#pragma unroll
+              for (int g = 0; g < G; ++g) v += kacc[g][t][q];
+              red[r * R + c] = v;
+            }
           }
         }
       }
-      if (lane < R) red[R * R + lane] = (w == 0 ? 0.0 : red[R * R + lane]) + facc;
+      if (lane < R) {
+        double v = w == 0 ? 0.0 : red[R * R + lane];
+        for (int g = 0; g < G; ++g) v += sfa[w][g * LG + lane];
+        red[R * R + lane] = v;
+      }
     }
     __syncthreads();
   }
   double* out = I.part_cub + (size_t)bx * E;
-  for (int p = threadIdx.x; p < E; p += 256) stg<double>(out + p, red[p]);
+  for (int p = threadIdx.x; p < E; p += 64 * W) stg<double>(out + p, red[p]);
 }
 
-template <typename T, int RB>
-__global__ __launch_bounds__(256) void k_cubature(const Inst<T>* __restrict__ tab, int m) {
-  cubature_block<T, RB>(tab, blockIdx.x, blockIdx.y, m);
+template <typename T, int RB, int W>
+__global__ __launch_bounds__(64 * W) void k_cubature(const Inst<T>* __restrict__ tab, int m) {
+  cubature_block<T, RB, W>(tab, blockIdx.x, blockIdx.y, m);
 }
+
+// Launches of at least kCubPackBlocks blocks of tets (batched instances,
+// large meshes) with R <= 16 take the packed form, one wave of four lane
+// groups; smaller launches and larger R the 4-wave form.  Both give the same
+// bits.
+static const int kCubPackBlocks = 1024;
 
 template <typename T>
 void launch_cubature(const Inst<T>* tab, int nb, int max_cblk, int max_r, hipStream_t s) {
   const int m = cubature_merge(nb);
   const dim3 grid((max_cblk + m - 1) / m, nb);
-  if (max_r <= 8) k_cubature<T, 8><<<grid, 64 * CUB_WAVES, 0, s>>>(tab, m);
-  else if (max_r <= 16) k_cubature<T, 16><<<grid, 64 * CUB_WAVES, 0, s>>>(tab, m);
-  else k_cubature<T, NMR_MAX_R><<<grid, 64 * CUB_WAVES, 0, s>>>(tab, m);
+  const bool pack = (long long)nb * max_cblk >= kCubPackBlocks;
+  if (max_r <= 8) {
+    if (pack) k_cubature<T, 8, 1><<<grid, 64, 0, s>>>(tab, m);
+    else k_cubature<T, 8, 4><<<grid, 256, 0, s>>>(tab, m);
+  } else if (max_r <= 16) {
+    if (pack) k_cubature<T, 16, 1><<<grid, 64, 0, s>>>(tab, m);
+    else k_cubature<T, 16, 4><<<grid, 256, 0, s>>>(tab, m);
+  } else {
+    // R > 16: a packed form needs two accumulator sets of 16 FP64 values per
+    // lane (270 registers, one wave per SIMD) and measured slower
+    k_cubature<T, NMR_MAX_R, 4><<<grid, 256, 0, s>>>(tab, m);
+  }
 }
 template void launch_cubature<float>(const Inst<float>*, int, int, int, hipStream_t);
 template void launch_cubature<double>(const Inst<double>*, int, int, int, hipStream_t);
@@ -781,7 +834,7 @@ __global__ __launch_bounds__(256) void k_gram(const Inst<T>* __restrict__ tab, i
 // below n_cub_blocks run the cubature, the rest the Gram rows.
 template <typename T, int NCB, int RB>
 __global__ __launch_bounds__(256) void k_cub_gram(const Inst<T>* __restrict__ tab, int m, int K, int n_cub_blocks) {
-  if ((int)blockIdx.x < n_cub_blocks) cubature_block<T, RB>(tab, blockIdx.x, blockIdx.y, m);
+  if ((int)blockIdx.x < n_cub_blocks) cubature_block<T, RB, 4>(tab, blockIdx.x, blockIdx.y, m);
   else gram_block<T, NCB>(tab, blockIdx.x - n_cub_blocks, blockIdx.y, K);
 }
 

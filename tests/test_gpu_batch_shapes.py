@@ -154,3 +154,26 @@ def test_large_pool_matches_alone(nmr, ctx):
         for x in insts + [ref]:
             x.close()
         dec.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("n_p,n_q", [(3, 4), (3, 12), (11, 12)])
+def test_packed_cubature_is_bitwise_the_four_wave_form(nmr, ctx, prec, n_p, n_q):
+    """Four instances of 1,375 tets each (R = 7, 15 and 23, direct path): the
+    batched launch has 1,376 blocks of tets and takes the packed form for
+    R <= 16 (one wave of four 16-lane groups, one FP64 accumulator set per
+    virtual wave; R = 23 stays four-wave), each instance alone the four-wave
+    form; the same merge factor (one), so the same bits."""
+    base = synth.tiny_problem(grid=(6, 6, 12), widths=(n_q, 16, 32, 1296), act="tanh", n_p=n_p,
+                              name=f"pack{n_p}_{n_q}", q_std=0.3, out_scale=0.1)
+    assert base.tets.shape[0] == 1375 and base.R == n_p + n_q
+    probs = []
+    for k in range(4):
+        r0 = np.zeros(base.R)
+        r0[base.n_p:] = 0.2 * synth.normal(f"pack/q0/{k}", base.n_q)
+        probs.append(base.replace(r0=r0))
+    got, alone = batch_vs_alone(nmr, ctx, probs, prec, 2, 3)
+    for (r, rd, u), (ra, rda, ua) in zip(got, alone):
+        np.testing.assert_array_equal(r, ra)
+        np.testing.assert_array_equal(rd, rda)
+        np.testing.assert_array_equal(u, ua)
