@@ -198,18 +198,20 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
   __shared__ int sok[W][G];  // 1: the group's tet is in the range
   __shared__ double sfa[W][64];
   __shared__ double red[RB * RB + RB];
-  // the R x R stiffness sums in 2 x 2 blocks: lane l owns blocks l + 64 t,
-  // block b covering rows 2 (b / nb2) + {0, 1} and columns 2 (b % nb2) + {0, 1}
-  // (each entry the same 9-term dot product in the same order as unblocked)
-  constexpr int BT = ((RB + 1) / 2 * ((RB + 1) / 2) + 63) / 64;
-  const int nb2 = (R + 1) / 2;
-  double kacc[G][BT][4];
+  // the R x R stiffness sums in BS x BS blocks (BS = 2, or 4 when R > 16:
+  // fewer LDS reads per entry): lane l owns blocks l + 64 t, block b covering
+  // rows BS (b / nbs) + [0, BS) and columns BS (b % nbs) + [0, BS) (each entry
+  // the same 9-term dot product in the same order as unblocked)
+  constexpr int BS = RB > 16 ? 4 : 2;
+  constexpr int BT = ((RB + BS - 1) / BS * ((RB + BS - 1) / BS) + 63) / 64;
+  const int nbs = (R + BS - 1) / BS;
+  double kacc[G][BT][BS * BS];
 #pragma unroll
   for (int g = 0; g < G; ++g)
 #pragma unroll
     for (int t = 0; t < BT; ++t)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) kacc[g][t][q] = 0.0;
+      for (int q = 0; q < BS * BS; ++q) kacc[g][t][q] = 0.0;
   double facc = 0.0;
   const int e0 = bx * m * I.cub_per_blk;
   const int e1 = min(e0 + m * I.cub_per_blk, I.n_cub);
@@ -335,23 +337,36 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
 #pragma unroll
       for (int t = 0; t < BT; ++t) {
         const int b = lane + 64 * t;
-        if (b < nb2 * nb2) {
-          const int r0 = 2 * (b / nb2), s0 = 2 * (b % nb2);
-          const int r1 = min(r0 + 1, R - 1), s1 = min(s0 + 1, R - 1);
-          T a00 = T(0), a01 = T(0), a10 = T(0), a11 = T(0);
+        if (b < nbs * nbs) {
+          const int r0 = BS * (b / nbs), s0 = BS * (b % nbs);
+          int rr[BS], ss[BS];
+#pragma unroll
+          for (int i = 0; i < BS; ++i) {
+            rr[i] = min(r0 + i, R - 1);
+            ss[i] = min(s0 + i, R - 1);
+          }
+          T a[BS][BS];
+#pragma unroll
+          for (int i = 0; i < BS; ++i)
+#pragma unroll
+            for (int j = 0; j < BS; ++j) a[i][j] = T(0);
 #pragma unroll
           for (int k = 0; k < 9; ++k) {
-            const T p0 = dPs[wave][g][r0][k], p1 = dPs[wave][g][r1][k];
-            const T f0 = dFs[wave][g][s0][k], f1 = dFs[wave][g][s1][k];
-            a00 += p0 * f0;
-            a01 += p0 * f1;
-            a10 += p1 * f0;
-            a11 += p1 * f1;
+            T pv[BS], fv[BS];
+#pragma unroll
+            for (int i = 0; i < BS; ++i) {
+              pv[i] = dPs[wave][g][rr[i]][k];
+              fv[i] = dFs[wave][g][ss[i]][k];
+            }
+#pragma unroll
+            for (int i = 0; i < BS; ++i)
+#pragma unroll
+              for (int j = 0; j < BS; ++j) a[i][j] += pv[i] * fv[j];
           }
-          kacc[g][t][0] += wg * (double)a00;
-          kacc[g][t][1] += wg * (double)a01;
-          kacc[g][t][2] += wg * (double)a10;
-          kacc[g][t][3] += wg * (double)a11;
+#pragma unroll
+          for (int i = 0; i < BS; ++i)
+#pragma unroll
+            for (int j = 0; j < BS; ++j) kacc[g][t][BS * i + j] += wg * (double)a[i][j];
         }
       }
     }
@@ -405,11 +420,11 @@ __device__ __forceinline__ void cubature_block(const Inst<T>* __restrict__ tab, 
 #pragma unroll
       for (int t = 0; t < BT; ++t) {
         const int b = lane + 64 * t;
-        if (b < nb2 * nb2) {
-          const int r0 = 2 * (b / nb2), s0 = 2 * (b % nb2);
+        if (b < nbs * nbs) {
+          const int r0 = BS * (b / nbs), s0 = BS * (b % nbs);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int r = r0 + (q >> 1), c = s0 + (q & 1);
+          for (int q = 0; q < BS * BS; ++q) {
+            const int r = r0 + q / BS, c = s0 + q % BS;
             if (r < R && c < R) {
               double v = w == 0 ? 0.0 : red[r * R + c];
 #pragma unroll
