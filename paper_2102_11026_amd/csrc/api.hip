@@ -881,7 +881,8 @@ static void enqueue_decoder_fwd(const Group& g, hipStream_t s, int add_up) {
   const DecoderDev& d = g.dec->d;
   const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
   for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, g.tf[l], s);
-  launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, out_channels(g), g.same_rows, s);
+  launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, out_channels(g), g.same_rows, g.gram ? g.rows : nullptr,
+                    s);
   if (g.any_np) launch_filter<T>(tab, g.nb, g.maxN, add_up, s);
 }
 
@@ -1757,8 +1758,9 @@ extern "C" int nmr_pool_step(nmr_pool* p, int n_iters, int* status, float* ms) {
     g.nb = p->capacity;
     // every member shares the class's rows (nmr_pool_attach checks them), but a
     // table entry of an empty slot may be stale: only kernels that take the
-    // rows from the pool's own copy and never read an empty slot's pointers
-    // use them (the batched output-layer backpropagation)
+    // rows from the pool's own copy and never follow an empty slot's pointers
+    // use them (the paired output layer, the batched output-layer
+    // backpropagation)
     g.same_rows = false;
     g.rows = p->proto->gram ? p->rows : nullptr;
     g.n_rows = p->proto->n_cdofs;
@@ -1809,7 +1811,8 @@ static void enqueue_phase(const Group& g, int phase, hipStream_t s) {
       for (int l = 0; l < d.L - 1; ++l) launch_fwd_hidden<T>(d, l, tab, g.nb, g.Cp, g.fd, g.tf[l], s);
       break;
     case NMR_PHASE_DEC_OUT:
-      launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, out_channels(g), g.same_rows, s);
+      launch_fwd_out<T>(d, tab, g.nb, g.gram ? g.max_cdofs : g.maxN, out_channels(g), g.same_rows,
+                        g.gram ? g.rows : nullptr, s);
       if (g.any_np) launch_filter<T>(tab, g.nb, g.maxN, 1, s);
       break;
     case NMR_PHASE_CUBATURE: launch_cubature<T>(tab, g.nb, g.max_cblk, g.maxR, s); break;

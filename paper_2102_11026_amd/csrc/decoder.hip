@@ -809,12 +809,16 @@ __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out(LayerArgs la, const 
 #define OUT_TILES 2
 template <typename TW, int NCB, int NI>
 __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out_wide(LayerArgs la, const Inst<float>* __restrict__ tab,
-                                                                 int nb) {
+                                                                 int nb, const int* __restrict__ rows) {
   const int i0 = blockIdx.y * NI;
-  const Inst<float>& I = tab[i0];                       // the row set of the block
+  const Inst<float>& I = tab[i0];
   const Inst<float>& I1 = tab[min(i0 + NI - 1, nb - 1)];  // the second instance (NI = 2)
-  const int act0 = I.active, act1 = I1.active, gram = I.gram, n_cd = I.n_cdofs, N = I.N, Cf = I.Cf;
-  const int* cdofs = I.cdofs;
+  // The row set and sizes come from an instance in use (the entry of an
+  // empty pool slot may be zero or left by a destroyed instance: its
+  // pointers are never followed); a pool passes its own copy of the rows.
+  const Inst<float>& Ir = (NI == 1 || I.active) ? I : I1;
+  const int act0 = I.active, act1 = I1.active, gram = Ir.gram, n_cd = Ir.n_cdofs, N = Ir.N, Cf = Ir.Cf;
+  const int* cdofs = rows ? rows : Ir.cdofs;
   const float* fold0 = I.fold;
   const float* fold1 = I1.fold;
   float* rec0 = I.rec;
@@ -893,8 +897,8 @@ __global__ __launch_bounds__(64 * OUT_SPLIT) void k_fwd_out_wide(LayerArgs la, c
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       t.b[i] = ldg<float>(bias + t.orow[i]);
-      t.m[0][i] = ldg<float>(keep0 + t.orow[i]);
-      if constexpr (NI > 1) t.m[1][i] = ldg<float>(keep1 + t.orow[i]);
+      t.m[0][i] = use[0] ? ldg<float>(keep0 + t.orow[i]) : 0.f;
+      if constexpr (NI > 1) t.m[1][i] = use[1] ? ldg<float>(keep1 + t.orow[i]) : 0.f;
     }
   };
   auto run_tile = [&](int row0, const Tile& t) {
@@ -1699,16 +1703,16 @@ static bool fwd_out_wide(int max_n, int nb) { return nb >= 8 && ((max_n + 127) /
 
 template <typename TW>
 static void fwd_out_dispatch(const DecoderDev& d, const Inst<float>* tab, int nb, int max_n, int cf, bool same_rows,
-                             hipStream_t s) {
+                             const int* rows, hipStream_t s) {
   const bool wide = fwd_out_wide(max_n, nb);
-  const bool pair = wide && same_rows && ((max_n + 127) / 128) * ((nb + 1) / 2) >= 1024;
+  const bool pair = wide && (same_rows || rows) && ((max_n + 127) / 128) * ((nb + 1) / 2) >= 1024;
   const int n_rg = (max_n + 16 * OUT_SPLIT * OUT_TILES - 1) / (16 * OUT_SPLIT * OUT_TILES);
   const dim3 grid((max_n + 15) / 16, nb), gridw(n_rg, nb), gridp(n_rg, (nb + 1) / 2);
   const LayerArgs la = layer_args(d, d.L - 1);
 #define FWD_O(n)                                                                       \
   do {                                                                                 \
-    if (pair) k_fwd_out_wide<TW, n, 2><<<gridp, OUT_SPLIT * 64, 0, s>>>(la, tab, nb);  \
-    else if (wide) k_fwd_out_wide<TW, n, 1><<<gridw, OUT_SPLIT * 64, 0, s>>>(la, tab, nb); \
+    if (pair) k_fwd_out_wide<TW, n, 2><<<gridp, OUT_SPLIT * 64, 0, s>>>(la, tab, nb, rows);  \
+    else if (wide) k_fwd_out_wide<TW, n, 1><<<gridw, OUT_SPLIT * 64, 0, s>>>(la, tab, nb, rows); \
     else k_fwd_out<TW, n><<<grid, OUT_SPLIT * 64, 0, s>>>(la, tab);                     \
   } while (0)
   switch (cf / 16) {
@@ -1723,13 +1727,13 @@ static void fwd_out_dispatch(const DecoderDev& d, const Inst<float>* tab, int nb
 
 template <>
 void launch_fwd_out<float>(const DecoderDev& d, const Inst<float>* tab, int nb, int max_n, int cf, bool same_rows,
-                           hipStream_t s) {
-  if (d.prec == PREC_BF16) fwd_out_dispatch<__bf16>(d, tab, nb, max_n, cf, same_rows, s);
-  else fwd_out_dispatch<float>(d, tab, nb, max_n, cf, same_rows, s);
+                           const int* rows, hipStream_t s) {
+  if (d.prec == PREC_BF16) fwd_out_dispatch<__bf16>(d, tab, nb, max_n, cf, same_rows, rows, s);
+  else fwd_out_dispatch<float>(d, tab, nb, max_n, cf, same_rows, rows, s);
 }
 template <>
 void launch_fwd_out<double>(const DecoderDev& d, const Inst<double>* tab, int nb, int max_n, int cf, bool,
-                            hipStream_t s) {
+                            const int*, hipStream_t s) {
   k_fwd_out_f64<<<dim3((max_n + 15) / 16, nb), 256, 0, s>>>(layer_args(d, d.L - 1), tab);
 }
 

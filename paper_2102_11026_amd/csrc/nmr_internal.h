@@ -280,7 +280,7 @@ void launch_fwd_hidden(const DecoderDev& d, int l, const Inst<T>* tab, int nb, i
 // cubature DOFs on the Gram path, or all N rows of one N)
 template <typename T>
 void launch_fwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_np, int max_cf, bool same_rows,
-                    hipStream_t s);
+                    const int* rows, hipStream_t s);
 template <typename T>
 void launch_filter(const Inst<T>* tab, int nb, int max_n, int add_up, hipStream_t s);
 template <typename T>

@@ -177,3 +177,48 @@ def test_packed_cubature_is_bitwise_the_four_wave_form(nmr, ctx, prec, n_p, n_q)
         np.testing.assert_array_equal(r, ra)
         np.testing.assert_array_equal(rd, rda)
         np.testing.assert_array_equal(u, ua)
+
+
+def test_paired_output_layer_in_a_pool_with_a_stale_slot(nmr, ctx):
+    """A 64-slot pool of 10k-vertex instances (Gram path, 5,710 decoded rows)
+    runs the output layer two instances per block, rows from the pool's own
+    copy.  Slot 0's instance is destroyed after attaching, so the pair
+    (0, 1) has a stale first entry: slot 1's request must be bitwise the one
+    of a pool whose slot 0 stays live, and match the request alone (to FP32
+    rounding: the pool's tiles and merged cubature blocks sum in other
+    orders)."""
+    p = synth.config_single_10k()
+    probs = [p.replace(r0=p.r0 + 0.01 * synth.normal(f"pairpool/q0/{k}", p.R)) for k in range(3)]
+    dec = nmr.Decoder(ctx, p.weights, p.biases, p.act, "fp32")
+
+    def run(stale):
+        pool = nmr.Pool(ctx, 64)
+        insts = [nmr.Instance(ctx, q, "fp32", shared=dec) for q in probs]
+        try:
+            slots = [pool.attach(x) for x in insts]
+            assert slots == [0, 1, 2]
+            if stale:
+                insts[0].close()             # detached and freed: slot 0 keeps a stale entry
+            for _ in range(2):
+                st, _ = pool.step(p.newton_iters, status=True)
+                assert st[1] == 0 and st[2] == 0
+            return [insts[k].get_state(with_u=True) for k in (1, 2)]
+        finally:
+            pool.close()
+            for x in insts[(1 if stale else 0):]:
+                x.close()
+
+    live, stale = run(False), run(True)
+    for a, b in zip(live, stale):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+    ref = nmr.Instance(ctx, probs[1], "fp32", shared=dec)
+    try:
+        st, _ = nmr.step_many(ctx, [ref], 2, p.newton_iters)
+        assert st == [0]
+        ra, rda, ua = ref.get_state(with_u=True)
+        close(stale[0][0], ra, 1e-4, "r")
+        close(stale[0][2], ua, 1e-4, "u")
+    finally:
+        ref.close()
+        dec.close()

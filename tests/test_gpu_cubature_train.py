@@ -202,3 +202,29 @@ def test_full_size_training_data_sample_fp32(nmr, ctx):
             tr.close()
     finally:
         inst.close()
+
+
+def test_phase_timing_leaves_the_training_unchanged(nmr, ctx, tiny):
+    """nmr_trainer_time_phase replays pieces of an alternation on the
+    trainer's buffers: the next alternation is bitwise the one of a trainer
+    that was never timed."""
+    t, _, _, C0, _ = tiny
+    runs = []
+    for timed in (False, True):
+        inst, tr = trainer(nmr, ctx, t, "fp64", C0)
+        try:
+            tr.run(1)
+            if timed:
+                for ph in nmr.TRAIN_PHASES:
+                    assert tr.time_phase(ph, 2) > 0
+            lw, ls, added, _ = tr.run(1)
+            runs.append((lw, ls, added, tr.get()))
+        finally:
+            tr.close()
+            inst.close()
+    (a_lw, a_ls, a_add, a_get), (b_lw, b_ls, b_add, b_get) = runs
+    np.testing.assert_array_equal(a_lw, b_lw)
+    np.testing.assert_array_equal(a_ls, b_ls)
+    np.testing.assert_array_equal(a_add, b_add)
+    assert a_get[0] == b_get[0]
+    np.testing.assert_array_equal(a_get[3], b_get[3])
