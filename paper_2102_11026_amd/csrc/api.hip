@@ -921,13 +921,13 @@ static void enqueue_iteration(const Group& g, int iter, int mode, double* A_out,
     // the Gram terms need only the folded activations and the state, and the
     // output-layer seed only the element forces: each pair is one launch
     launch_cub_gram<T>(tab, g.nb, g.max_cblk, g.n_gblk, g.K, g.n_q, s);
-    launch_sums_bwd_out<T>(g.dec->d, tab, g.nb, g.max_entries, g.max_sblk, s);
+    launch_sums_bwd_out<T>(g.dec->d, tab, g.nb, g.max_entries, g.max_sblk, g.max_cblk, s);
     enqueue_decoder_bwd<T>(g, s, false);
   } else {
     launch_cubature<T>(tab, g.nb, g.max_cblk, g.maxR, s);
     if (g.gram) launch_gram<T>(tab, g.nb, g.n_gblk, g.K, g.n_q, s);
     else launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
-    launch_sums<T>(tab, g.nb, g.max_entries, s);
+    launch_sums<T>(tab, g.nb, g.max_entries, g.max_cblk, s);
     enqueue_decoder_bwd<T>(g, s);
   }
   launch_solve<T>(tab, g.nb, iter, mode, A_out, phi_out, s);
@@ -1261,7 +1261,7 @@ static void enqueue_coupled_step(nmr_coupled* cs, int K, hipStream_t s) {
       const Inst<T>* tab = static_cast<const Inst<T>*>(g.tab);
       launch_cubature<T>(tab, g.nb, g.max_cblk, g.maxR, s);
       launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
-      launch_sums<T>(tab, g.nb, g.max_entries, s);
+      launch_sums<T>(tab, g.nb, g.max_entries, g.max_cblk, s);
       enqueue_decoder_bwd<T>(g, s);
       launch_solve<T>(tab, g.nb, it, SOLVE_WRITE_SYSTEM | SOLVE_WRITE_INST, nullptr, nullptr, s);
     }
@@ -1399,7 +1399,7 @@ static int djh_impl(nmr_inst* in, const double* q, const double* dq, const doubl
   launch_unpack<T>(tab, (T*)u, (T*)J, (T*)dJ, (T*)Hdd, in->N, c->stream);
   if (a) {
     launch_seed_from_a<T>(tab, static_cast<const T*>(a), 1, in->n_mblk, c->stream);
-    launch_sums<T>(tab, 1, g.max_entries, c->stream);
+    launch_sums<T>(tab, 1, g.max_entries, g.max_cblk, c->stream);
     enqueue_decoder_bwd<T>(g, c->stream);
     if (B) HIPCHK(hipMemcpyAsync(B, I.Bq, in->n_q * nqb, hipMemcpyDeviceToDevice, c->stream));
     if (JTa) HIPCHK(hipMemcpyAsync(JTa, I.JTa, nqb, hipMemcpyDeviceToDevice, c->stream));
@@ -1438,7 +1438,7 @@ static int cfs_impl(nmr_inst* in, const void* u, const void* Jt, const void* w, 
   launch_cubature<T>(tab, 1, in->n_cblk, in->R, c->stream);
   std::vector<nmr_inst*> v{in};
   Group g = group_of(v, in->api_tab);
-  launch_sums<T>(tab, 1, g.max_entries, c->stream);
+  launch_sums<T>(tab, 1, g.max_entries, g.max_cblk, c->stream);
   HIPCHK(hipMemcpyAsync(Kr, I.sum_cub, in->R * in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(fr, I.sum_cub + in->R * in->R, in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if (f_int) launch_fint<T>(tab, static_cast<T*>(f_int), in->N, c->stream);
@@ -1513,7 +1513,7 @@ static int cfs_noalloc_impl(nmr_inst* in, const void* u, const void* Jt, const v
   const Inst<T>* tab = reinterpret_cast<const Inst<T>*>(base);
   launch_cubature<T>(tab, 1, in->n_cblk, in->R, c->stream);
   const int Ec = in->R * in->R + in->R;
-  launch_sums<T>(tab, 1, Ec, c->stream);  // cubature entries only
+  launch_sums<T>(tab, 1, Ec, in->n_cblk, c->stream);  // cubature entries only
   HIPCHK(hipMemcpyAsync(Kr, I.sum_cub, in->R * in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(fr, I.sum_cub + in->R * in->R, in->R * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if (f_int) launch_fint<T>(tab, static_cast<T*>(f_int), in->N, c->stream);
@@ -1820,7 +1820,7 @@ static void enqueue_phase(const Group& g, int phase, hipStream_t s) {
       if (g.gram) launch_gram<T>(tab, g.nb, g.n_gblk, g.K, g.n_q, s);
       else launch_mass<T>(tab, g.nb, g.max_mblk, g.maxR, g.n_q, s);
       break;
-    case NMR_PHASE_SUMS: launch_sums<T>(tab, g.nb, g.max_entries, s); break;
+    case NMR_PHASE_SUMS: launch_sums<T>(tab, g.nb, g.max_entries, g.max_cblk, s); break;
     case NMR_PHASE_BWD_OUT: launch_bwd_out<T>(d, tab, g.nb, g.gram ? g.max_sblk : g.max_bblk, s); break;
     case NMR_PHASE_BWD_HIDDEN:
       launch_bwd_reduce<T>(d, tab, g.nb, s);

@@ -1770,19 +1770,20 @@ void launch_bwd_out_batch<double>(const DecoderDev&, const Inst<double>*, int, c
 
 template <>
 void launch_sums_bwd_out<float>(const DecoderDev& d, const Inst<float>* tab, int nb, int max_entries, int max_sblk,
-                                hipStream_t s) {
+                                int max_cblk, hipStream_t s) {
   const int n_sum = (max_entries + 15) / 16;
   dim3 grid(n_sum + max_sblk, nb);
+  const int m = cubature_merge(nb, max_cblk);
   if (d.prec == PREC_BF16)
-    k_sums_bwd_out<float, __bf16><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab, cubature_merge(nb), n_sum);
-  else k_sums_bwd_out<float, float><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab, cubature_merge(nb), n_sum);
+    k_sums_bwd_out<float, __bf16><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab, m, n_sum);
+  else k_sums_bwd_out<float, float><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab, m, n_sum);
 }
 template <>
 void launch_sums_bwd_out<double>(const DecoderDev& d, const Inst<double>* tab, int nb, int max_entries, int max_sblk,
-                                 hipStream_t s) {
+                                 int max_cblk, hipStream_t s) {
   const int n_sum = (max_entries + 15) / 16;
   dim3 grid(n_sum + max_sblk, nb);
-  k_sums_bwd_out<double, double><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab, cubature_merge(nb), n_sum);
+  k_sums_bwd_out<double, double><<<grid, 256, 0, s>>>(layer_args(d, d.L - 1), tab, cubature_merge(nb, max_cblk), n_sum);
 }
 
 template <typename T>

@@ -216,7 +216,9 @@ __device__ inline double fint_at(const Inst<T>& I, int i) {
 // Launches of many instances merge m consecutive blocks of tets into one
 // cubature block (fewer, longer blocks); the sums read ceil(n_cblk / m)
 // cubature partials.
-inline int cubature_merge(int nb) { return nb >= 64 ? 8 : nb >= 16 ? 4 : 1; }
+// (and 8 for a launch of few instances with at least 4096 blocks of tets: a
+// large mesh, whose sums would otherwise read thousands of partials)
+inline int cubature_merge(int nb, int max_cblk) { return nb >= 64 ? 8 : nb >= 16 ? 4 : max_cblk >= 4096 ? 8 : 1; }
 
 // Block bx of instance by takes 16 entries; 16 slices of 16 threads add every
 // sixteenth partial, then the 16 slice sums are added in slice order.
@@ -289,7 +291,7 @@ void launch_bwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_bbl
 // path, where the seed needs only the element forces)
 template <typename T>
 void launch_sums_bwd_out(const DecoderDev& d, const Inst<T>* tab, int nb, int max_entries, int max_sblk,
-                         hipStream_t s);
+                         int max_cblk, hipStream_t s);
 // the Gram path's output-layer backpropagation of instances that all decode
 // `rows` (device, nrows ids), batched so each weight row serves several
 // (FP32 / BF16; same bits as launch_bwd_out)
@@ -331,7 +333,7 @@ void launch_mass(const Inst<T>* tab, int nb, int max_mblk, int R, int nq, hipStr
 template <typename T>
 void launch_seed_from_a(const Inst<T>* tab, const T* a, int nb, int max_mblk, hipStream_t s);
 template <typename T>
-void launch_sums(const Inst<T>* tab, int nb, int max_entries, hipStream_t s);
+void launch_sums(const Inst<T>* tab, int nb, int max_entries, int max_cblk, hipStream_t s);
 template <typename T>
 void launch_solve(const Inst<T>* tab, int nb, int iter, int mode, double* A_out, double* phi_out,
                   hipStream_t s);

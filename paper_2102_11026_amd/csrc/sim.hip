@@ -170,8 +170,9 @@ template void launch_step_begin<double>(const Inst<double>*, int, int, int, hipS
 // by its lane r, the stiffness blocks by all 64 lanes of the wave.  Element
 // math in T, accumulation in FP64, one accumulator set per virtual wave, the
 // virtual waves' sums added in order: both forms give the same bits.
-// Launches of many instances merge m = cubature_merge(nb) consecutive blocks
-// of tets into one (partial b then covers blocks b m .. b m + m - 1).
+// Launches of many instances or of a large mesh merge m = cubature_merge(nb,
+// max_cblk) consecutive blocks of tets into one (partial b then covers blocks
+// b m .. b m + m - 1).
 // ---------------------------------------------------------------------------
 #define CUB_VWAVES 4
 
@@ -459,7 +460,7 @@ static const int kCubPackBlocks = 1024;
 
 template <typename T>
 void launch_cubature(const Inst<T>* tab, int nb, int max_cblk, int max_r, hipStream_t s) {
-  const int m = cubature_merge(nb);
+  const int m = cubature_merge(nb, max_cblk);
   const dim3 grid((max_cblk + m - 1) / m, nb);
   const bool pack = (long long)nb * max_cblk >= kCubPackBlocks;
   if (max_r <= 8) {
@@ -879,7 +880,7 @@ static void cub_gram_ncb(const Inst<T>* tab, int nb, int m, int ncb, int max_gbl
 
 template <typename T>
 void launch_cub_gram(const Inst<T>* tab, int nb, int max_cblk, int max_gblk, int K, int nq, hipStream_t s) {
-  const int m = cubature_merge(nb), ncb = (max_cblk + m - 1) / m;
+  const int m = cubature_merge(nb, max_cblk), ncb = (max_cblk + m - 1) / m;
   // the Gram path has no linear subspace: R = n_q
   if (nq <= 8) cub_gram_ncb<T, 8>(tab, nb, m, ncb, max_gblk, K, nq, s);
   else if (nq <= 16) cub_gram_ncb<T, 16>(tab, nb, m, ncb, max_gblk, K, nq, s);
@@ -940,11 +941,11 @@ __global__ __launch_bounds__(256) void k_sums(const Inst<T>* __restrict__ tab, i
 }
 
 template <typename T>
-void launch_sums(const Inst<T>* tab, int nb, int max_entries, hipStream_t s) {
-  k_sums<T><<<dim3((max_entries + 15) / 16, nb), 256, 0, s>>>(tab, cubature_merge(nb));
+void launch_sums(const Inst<T>* tab, int nb, int max_entries, int max_cblk, hipStream_t s) {
+  k_sums<T><<<dim3((max_entries + 15) / 16, nb), 256, 0, s>>>(tab, cubature_merge(nb, max_cblk));
 }
-template void launch_sums<float>(const Inst<float>*, int, int, hipStream_t);
-template void launch_sums<double>(const Inst<double>*, int, int, hipStream_t);
+template void launch_sums<float>(const Inst<float>*, int, int, int, hipStream_t);
+template void launch_sums<double>(const Inst<double>*, int, int, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Assemble A = Jt^T M [U, J + dJ] + dt^2 Kr + diag(0, a . H) and
