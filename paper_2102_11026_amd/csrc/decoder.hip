@@ -383,26 +383,168 @@ __device__ inline void mfma_tall(const __bf16* __restrict__ A, int lda, int K, B
   if (i < nbat) mma(a0, b0);
 }
 
-// Tall tile of every instance slot (wave w = slot w) into S[slot][c][r],
-// r < 16 MR; a slot not in use writes zeros.  Ends with a barrier.
-template <typename TW, int NCB, int MR, typename BL>
+// K-split of the tall tiles: waves per instance slot.  A BF16 wave's MFMAs
+// take a sixteenth of an FP32 wave's time, so its serial chain of K-step
+// loads bounds it: two waves take half of K each.  FP32 keeps one.
+template <typename TW>
+struct tall_ks {
+  static constexpr int v = 1;
+};
+template <>
+struct tall_ks<__bf16> {
+  static constexpr int v = 2;
+};
+
+// Tall tile of every instance slot (waves KS s .. KS s + KS - 1 = slot s,
+// wave h of a slot taking the h-th part of K in 32-wide steps) into
+// S[slot][c][r], r < 16 MR, the parts added in order; a slot not in use
+// writes zeros.  Ends with a barrier.
+template <typename TW, int NCB, int MR, int KS, typename BL>
 __device__ inline void gemm_tall(const TW* __restrict__ A, int lda, int K, bool use, BL bload,
                                  float (*S)[NCB * 16][16 * MR + 1]) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int slot = wave / KS, part = wave - slot * KS;
+  const int nst = K / 32;
+  const int k0 = 32 * ((nst * part) / KS), k1 = 32 * ((nst * (part + 1)) / KS);
   f32x4 acc[MR][NCB];
 #pragma unroll
   for (int m = 0; m < MR; ++m)
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[m][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-  if (use) mfma_tall<MR, NCB>(A, lda, K, bload, acc);
+  if (use && k1 > k0) {
+    auto bpart = [&](int c, int k) { return bload(c, k0 + k); };
+    mfma_tall<MR, NCB>(A + k0, lda, k1 - k0, bpart, acc);
+  }
   const int rA = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int h = 0; h < KS; ++h) {
+    if (part == h)
+#pragma unroll
+      for (int m = 0; m < MR; ++m)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float& d = S[slot][cb * 16 + rA][16 * m + 4 * g + i];
+            d = (h == 0 ? 0.f : d) + acc[m][cb][i];
+          }
+    __syncthreads();
+  }
+}
+
+// LDS staging of the BF16 tall tiles.  Read straight from global memory,
+// an MFMA operand fragment puts the 16 lanes of each quarter-wave on 16
+// different rows, so every lane's 16 bytes are a request of their own and
+// the address unit takes about a cycle per lane: it, not the MFMAs, bounds a
+// BF16 wave.  Here the block copies each K-chunk of the weight tile (which
+// its instance slots share) and of every slot's B tile into LDS with loads
+// in which consecutive lanes read consecutive 16 bytes, and the waves read
+// their fragments from LDS rows padded by 16 bytes, which puts the 16 rows of
+// a quarter-wave's reads on disjoint banks.  Two chunk buffers: the next
+// chunk's global loads are in flight during the current chunk's MFMAs.  The
+// KS waves of a slot take the 32-wide sub-chunks of each chunk in turn.
+template <typename TW, int NCB, int MR, int IB, int KS>
+struct tall_stage {
+  static constexpr int KC = 32 * KS;            // K per chunk
+  static constexpr int LD = 2 * KC + 16;        // bytes per staged row
+  static constexpr int AROWS = 16 * MR, BROWS = IB * NCB * 16;
+  static constexpr int BYTES = 2 * (AROWS + BROWS) * LD;
+  // BF16 only, and within a third of the 160 KB of LDS beside the epilogue's
+  static constexpr bool on = std::is_same<TW, __bf16>::value && MR > 1 && BYTES <= 96 * 1024;
+};
+
+template <int NCB, int MR, int IB, int KS, typename BL>
+__device__ inline void gemm_tall_lds(const __bf16* __restrict__ A, int lda, int K, bool use, BL bload,
+                                     float (*S)[NCB * 16][16 * MR + 1], unsigned char* stage) {
+  using G = tall_stage<__bf16, NCB, MR, IB, KS>;
+  constexpr int NT = 64 * IB * KS, NG = 64 * KS;
+  constexpr int PR = G::KC / 8;  // 16-byte pieces of a staged row
+  constexpr int NA = G::AROWS * PR;
+  constexpr int PA = (NA + NT - 1) / NT, PB = NCB * 16 * PR / NG;
+  static_assert(NCB * 16 * PR % NG == 0, "B pieces split evenly over a slot's threads");
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int slot = wave / KS, part = wave - slot * KS, tg = tid - slot * NG;
+  const int nch = (K + G::KC - 1) / G::KC;
+  bf16x8 ra[PA], rb[PB];
+  // chunk ch into registers; pieces past K (a half chunk at the end) are
+  // zeros, loaded from a clamped index so that no load sits under a branch
+  auto gload = [&](int ch) {
+    const int k0 = ch * G::KC;
+#pragma unroll
+    for (int i = 0; i < PA; ++i) {
+      const int q = min(tid + i * NT, NA - 1), k = k0 + 8 * (q % PR);
+      const bf16x8 v = ldg<bf16x8>(A + (size_t)(q / PR) * lda + min(k, K - 8));
+      ra[i] = k < K ? v : zero_of<bf16x8>();
+    }
+    if (use) {  // uniform over the slot's waves
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        const int q = tg + i * NG, k = k0 + 8 * (q % PR);
+        const bf16x8 v = bfrag(bload, q / PR, min(k, K - 8));
+        rb[i] = k < K ? v : zero_of<bf16x8>();
+      }
+    }
+  };
+  auto lstore = [&](int buf) {
+    unsigned char* base = stage + buf * (G::AROWS + G::BROWS) * G::LD;
+#pragma unroll
+    for (int i = 0; i < PA; ++i) {
+      const int q = tid + i * NT;
+      if (q < NA) *reinterpret_cast<bf16x8*>(base + (q / PR) * G::LD + 16 * (q % PR)) = ra[i];
+    }
+    if (use) {
+      unsigned char* bb = base + (G::AROWS + slot * NCB * 16) * G::LD;
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        const int q = tg + i * NG;
+        *reinterpret_cast<bf16x8*>(bb + (q / PR) * G::LD + 16 * (q % PR)) = rb[i];
+      }
+    }
+  };
+  f32x4 acc[MR][NCB];
 #pragma unroll
   for (int m = 0; m < MR; ++m)
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) S[wave][cb * 16 + rA][16 * m + 4 * g + i] = acc[m][cb][i];
+    for (int cb = 0; cb < NCB; ++cb) acc[m][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const int rA = lane & 15, g = lane >> 4;
+  gload(0);
+  lstore(0);
   __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) gload(ch + 1);
+    const int kk = ch * G::KC + 32 * part;
+    if (use && kk < K) {  // uniform over the wave
+      const unsigned char* base = stage + buf * (G::AROWS + G::BROWS) * G::LD + 2 * (32 * part + 8 * g);
+      const unsigned char* bb = base + (G::AROWS + slot * NCB * 16) * G::LD;
+      bf16x8 a[MR], b[NCB];
+#pragma unroll
+      for (int m = 0; m < MR; ++m) a[m] = *reinterpret_cast<const bf16x8*>(base + (16 * m + rA) * G::LD);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const bf16x8*>(bb + (16 * cb + rA) * G::LD);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int m = 0; m < MR; ++m) acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[cb], acc[m][cb], 0, 0, 0);
+    }
+    if (ch + 1 < nch) lstore(buf ^ 1);
+    __syncthreads();
+  }
+  // S may share the staging buffers: every wave has passed the last barrier
+#pragma unroll
+  for (int h = 0; h < KS; ++h) {
+    if (part == h)
+#pragma unroll
+      for (int m = 0; m < MR; ++m)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float& d = S[slot][cb * 16 + rA][16 * m + 4 * g + i];
+            d = (h == 0 ? 0.f : d) + acc[m][cb][i];
+          }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -439,19 +581,25 @@ __device__ inline T fd_input(int c, int k, int nq, T q, T dq, T qd, T h) {
 // K sum, so the results are the same bits.  The base channels, which every
 // group needs for its activation derivatives, are stored by group 0 only.
 template <typename T, typename TW, int NCB, int IB, bool FD, int MR, int JG = 0>
-__global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab, int nb) {
+__global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_fwd_hidden(LayerArgs la,
+                                                                                       const Inst<T>* __restrict__ tab,
+                                                                                       int nb) {
   static_assert(MR == 1 || (!FD && std::is_same<T, float>::value), "tall tiles: complex-step FP32 jets only");
   static_assert(JG == 0 || (NCB == 1 && IB == 1 && MR == 1 && !FD && 4 + 4 * JG == 16), "jet groups: one column block");
   constexpr int ROWS = 16 * MR;  // output rows of a block
-  constexpr int NW = MR > 1 ? IB : splitk_waves<T, NCB>::v;
+  constexpr int NW = MR > 1 ? IB * tall_ks<TW>::v : splitk_waves<T, NCB>::v;
   constexpr int KSPL = NW / IB;
   constexpr int NG = KSPL * 64;  // threads of one instance slot
   const int l = la.l;
   const int tid = threadIdx.x, wave = tid >> 6;
   const int slot = wave / KSPL, tg = tid - slot * NG;
+  // several instances: each XCD takes whole instance groups, whose
+  // activations every row tile reads, so they stay in one L2
+  int bx = blockIdx.x, by = blockIdx.y;
+  if (!JG && gridDim.y > 1) xcd_block(bx, by);
   const int ngrp = JG ? gridDim.y / nb : 1;
-  const int inst = JG ? blockIdx.y / ngrp : blockIdx.y * IB + slot;
-  const int grp = JG ? blockIdx.y - inst * ngrp : 0;
+  const int inst = JG ? by / ngrp : by * IB + slot;
+  const int grp = JG ? by - inst * ngrp : 0;
   const Inst<T>& I = tab[min(inst, nb - 1)];
   // the table entry's fields are read before any test so that their scalar
   // loads leave together
@@ -467,11 +615,14 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
   load_now(active, nq, trimmed, X, outp, pre, fold, din, dt64, fdh64, m_inp, m_out, m_outp, la.W, la.b, la.act, la.L);
   const bool use = inst < nb && active;
   const T dtT = (T)dt64;
-  const int row0 = blockIdx.x * ROWS;
+  const int row0 = bx * ROWS;
   if (row0 >= m_outp || (IB == 1 && !use)) return;  // uniform over the block
   const TW* W = reinterpret_cast<const TW*>(la.W) + (size_t)row0 * m_inp;
   const T* bias = reinterpret_cast<const T*>(la.b);
-  __shared__ T S[IB][NCB * 16][ROWS + 1];
+  using STG = tall_stage<TW, NCB, MR, IB, tall_ks<TW>::v>;
+  constexpr int SB = (int)sizeof(T) * IB * NCB * 16 * (ROWS + 1), GB = STG::on ? STG::BYTES : 0;
+  __shared__ __align__(16) unsigned char lds_s[SB > GB ? SB : GB];  // S, or the GEMM's staging before it
+  T(*S)[NCB * 16][ROWS + 1] = reinterpret_cast<T(*)[NCB * 16][ROWS + 1]>(lds_s);
   __shared__ T red[MR == 1 ? NW : 1][NCB * 16][16];
   __shared__ T sd1[IB][ROWS], sd2[IB][ROWS], sd3[IB][ROWS], sx2[IB][ROWS], sx4[IB][ROWS], sx23[IB][ROWS];
   typedef typename vec4<T>::type V4;
@@ -533,7 +684,8 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_fwd_hidden(LayerArgs
       };
       gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload_g, S, red);
     } else if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload, S, red);
-    else gemm_tall<TW, NCB, MR>(W, m_inp, m_inp, use, bload, S);
+    else if constexpr (STG::on) gemm_tall_lds<NCB, MR, IB, tall_ks<TW>::v>(W, m_inp, m_inp, use, bload, S, lds_s);
+    else gemm_tall<TW, NCB, MR, tall_ks<TW>::v>(W, m_inp, m_inp, use, bload, S);
   };
   if (l == 0) gemm(bload_in);  // uniform over the block
   else gemm(bload_x);
@@ -1304,18 +1456,21 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(LayerArgs la, const Inst<T>*
 // at the input, J^T a and a . H.
 // ---------------------------------------------------------------------------
 template <typename T, typename TW, int NCB, int IB, bool FD, int MR>
-__global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_bwd_hidden(LayerArgs la, const Inst<T>* __restrict__ tab,
-                                                                     int nb) {
+__global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_bwd_hidden(LayerArgs la,
+                                                                                       const Inst<T>* __restrict__ tab,
+                                                                                       int nb) {
   static_assert(MR == 1 || (!FD && std::is_same<T, float>::value), "tall tiles: complex-step FP32 jets only");
   constexpr int ROWS = 16 * MR;  // rows (layer inputs) of a block
-  constexpr int NW = MR > 1 ? IB : splitk_waves<T, NCB>::v;
+  constexpr int NW = MR > 1 ? IB * tall_ks<TW>::v : splitk_waves<T, NCB>::v;
   constexpr int KSPL = NW / IB;
   constexpr int NG = KSPL * 64;  // threads of one instance slot
   const int l = la.l;
   const int step = la.L - 2 - l;  // 0 for the last hidden layer
   const int tid = threadIdx.x, wave = tid >> 6;
   const int slot = wave / KSPL, tg = tid - slot * NG;
-  const int inst = blockIdx.y * IB + slot;
+  int bx = blockIdx.x, by = blockIdx.y;  // whole instance groups per XCD
+  if (gridDim.y > 1) xcd_block(bx, by);
+  const int inst = by * IB + slot;
   const Inst<T>& I = tab[min(inst, nb - 1)];
   // the table entry's fields are read before any test so that their scalar
   // loads leave together
@@ -1334,10 +1489,13 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_bwd_hidden(LayerArgs
   // q +- h e_j stencil columns (central differences)
   const int nch = fd ? 1 + 2 * nq : 1 + nq;
   const bool use = inst < nb && active;
-  const int row0 = blockIdx.x * ROWS;
+  const int row0 = bx * ROWS;
   if (row0 >= m_inp || (IB == 1 && !use)) return;  // uniform over the block
   const TW* WT = reinterpret_cast<const TW*>(la.WT) + (size_t)row0 * K;
-  __shared__ T S[IB][NCB * 16][ROWS + 1];
+  using STG = tall_stage<TW, NCB, MR, IB, tall_ks<TW>::v>;
+  constexpr int SB = (int)sizeof(T) * IB * NCB * 16 * (ROWS + 1), GB = STG::on ? STG::BYTES : 0;
+  __shared__ __align__(16) unsigned char lds_s[SB > GB ? SB : GB];  // S, or the GEMM's staging before it
+  T(*S)[NCB * 16][ROWS + 1] = reinterpret_cast<T(*)[NCB * 16][ROWS + 1]>(lds_s);
   __shared__ T red[MR == 1 ? NW : 1][NCB * 16][16];
   typedef typename vec4<T>::type V4;
   // a BF16 decoder's adjoints are stored as BF16 (complex-step BP only)
@@ -1360,7 +1518,8 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB : 512) void k_bwd_hidden(LayerArgs
     }
   }
   if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(WT, K, K, use, bload, S, red);
-  else gemm_tall<TW, NCB, MR>(WT, K, K, use, bload, S);
+  else if constexpr (STG::on) gemm_tall_lds<NCB, MR, IB, tall_ks<TW>::v>(WT, K, K, use, bload, S, lds_s);
+  else gemm_tall<TW, NCB, MR, tall_ks<TW>::v>(WT, K, K, use, bload, S);
   if (!use) return;
   T(*Ss)[ROWS + 1] = S[slot];
   if (l > 0) {
@@ -1635,13 +1794,13 @@ static void fwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb
   }
   if constexpr (std::is_same<T, float>::value && NCB <= 4) {
     if (cfg.mr == 4) {
-      k_fwd_hidden<T, TW, NCB, 4, false, 4><<<dim3(rows / 64, (nb + 3) / 4), 256, 0, s>>>(la, tab, nb);
+      k_fwd_hidden<T, TW, NCB, 4, false, 4><<<dim3(rows / 64, (nb + 3) / 4), 256 * tall_ks<TW>::v, 0, s>>>(la, tab, nb);
       return;
     }
   }
   if constexpr (std::is_same<T, float>::value && NCB <= 8) {
     if (cfg.mr == 2) {
-      k_fwd_hidden<T, TW, NCB, 4, false, 2><<<dim3(rows / 32, (nb + 3) / 4), 256, 0, s>>>(la, tab, nb);
+      k_fwd_hidden<T, TW, NCB, 4, false, 2><<<dim3(rows / 32, (nb + 3) / 4), 256 * tall_ks<TW>::v, 0, s>>>(la, tab, nb);
       return;
     }
   }
@@ -1806,11 +1965,13 @@ static void bwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb
   }
   if constexpr (std::is_same<T, float>::value && NCB <= 2) {
     if (cfg.mr == 4) {
-      k_bwd_hidden<T, TW, NCB, 4, false, 4><<<dim3(d.wp[l] / 64, (nb + 3) / 4), 256, 0, s>>>(la, tab, nb);
+      k_bwd_hidden<T, TW, NCB, 4, false, 4><<<dim3(d.wp[l] / 64, (nb + 3) / 4), 256 * tall_ks<TW>::v, 0, s>>>(la, tab,
+                                                                                                            nb);
       return;
     }
     if (cfg.mr == 2) {
-      k_bwd_hidden<T, TW, NCB, 4, false, 2><<<dim3(d.wp[l] / 32, (nb + 3) / 4), 256, 0, s>>>(la, tab, nb);
+      k_bwd_hidden<T, TW, NCB, 4, false, 2><<<dim3(d.wp[l] / 32, (nb + 3) / 4), 256 * tall_ks<TW>::v, 0, s>>>(la, tab,
+                                                                                                            nb);
       return;
     }
   }

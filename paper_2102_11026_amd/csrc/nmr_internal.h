@@ -199,6 +199,18 @@ __device__ inline void stg(T* p, V v) {
   }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2.  The block (x, y) of a 2-D grid is renumbered so that each XCD takes a
+// contiguous run of the logical blocks b + gridDim.x pc, i.e. whole rows of
+// the grid: (b, pc) = the logical block's (x, y).
+__device__ inline void xcd_block(int& b, int& pc) {
+  const int total = gridDim.x * gridDim.y, lin = blockIdx.y * gridDim.x + blockIdx.x;
+  const int per = total / 8, rem = total % 8, x = lin % 8, i = lin / 8;
+  const int L = x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+  b = L % gridDim.x;
+  pc = L / gridDim.x;
+}
+
 // f_int[i] = sum of the weighted element forces at DOF i (fixed CSR order)
 template <typename T>
 __device__ inline double fint_at(const Inst<T>& I, int i) {

@@ -372,17 +372,9 @@ void launch_adam(double* x, const double* g, double* m, double* v, long long n, 
 #define SBE NMR_TRAIN_SBE     // elements per block
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-// L2.  Renumbered so that each XCD takes a contiguous run of logical blocks,
-// neighbouring vertex and element blocks (which gather each other's
-// features) share an L2.  (b, pc) = (vertex or element block, pose of the chunk).
-__device__ inline void xcd_block(int& b, int& pc) {
-  const int total = gridDim.x * gridDim.y, lin = blockIdx.y * gridDim.x + blockIdx.x;
-  const int per = total / 8, rem = total % 8, x = lin % 8, i = lin / 8;
-  const int L = x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
-  b = L % gridDim.x;
-  pc = L / gridDim.x;
-}
+// Blocks renumbered per XCD (xcd_block): neighbouring vertex and element
+// blocks, which gather each other's features, share an L2.
+// (b, pc) = (vertex or element block, pose of the chunk).
 
 // the 8 channels of one vertex or element, stored and loaded back to back
 __device__ inline void store8(double* dst, const double (&v)[8]) {
