@@ -759,11 +759,23 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_fwd
       }
       return;
     }
+    // tall tiles: 8 BF16 or 4 FP32 rows of a column per store (with 16-row
+    // tiles the wider items leave too many threads idle)
     const int C = fd ? 14 * nq + 3 : 4 + 4 * nq;
-    for (int p = tg; p < C * ROWS; p += NG) {
-      const int c = p / ROWS, r = p & (ROWS - 1);
-      if constexpr (BFX) stg<__bf16>(reinterpret_cast<__bf16*>(outp) + (size_t)c * m_outp + row0 + r, (__bf16)Ss[c][r]);
-      else stg<T>(outp + (size_t)c * m_outp + row0 + r, Ss[c][r]);
+    constexpr int VG = MR == 1 ? 1 : BFX ? 8 : 4, RG = ROWS / VG;
+    for (int p = tg; p < C * RG; p += NG) {
+      const int c = p / RG, r = VG * (p - c * RG);
+      if constexpr (VG == 1) {
+        if constexpr (BFX) stg<__bf16>(reinterpret_cast<__bf16*>(outp) + (size_t)c * m_outp + row0 + r, (__bf16)Ss[c][r]);
+        else stg<T>(outp + (size_t)c * m_outp + row0 + r, Ss[c][r]);
+      } else if constexpr (BFX) {
+        bf16x8 o;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = (__bf16)Ss[c][r + i];
+        stg<bf16x8>(reinterpret_cast<__bf16*>(outp) + (size_t)c * m_outp + row0 + r, o);
+      } else {
+        stg<V4>(outp + (size_t)c * m_outp + row0 + r, V4{Ss[c][r], Ss[c][r + 1], Ss[c][r + 2], Ss[c][r + 3]});
+      }
     }
   } else {
     // last hidden layer: fold into the output channels (the output layer is
@@ -1505,16 +1517,30 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_bwd
     else return ldg<V4>(xb + (size_t)c * K + k);
   };
   // pre-activations of layer l-1 used by the epilogue, loaded before the GEMM
-  constexpr int PP = (ROWS * 32 + NG - 1) / NG;  // items per thread: ROWS rows x (1 + n_q <= 32) channels
-  T px0[PP], px1[PP];
+  // (an item: VG consecutive rows of a channel; tall tiles store 16 bytes)
+  constexpr int VG = MR == 1 ? 1 : BFX ? 8 : 4, RG = ROWS / VG;
+  constexpr int PP = (RG * 32 + NG - 1) / NG;  // items per thread: RG row groups x (nch <= 32) channels
+  T px0[PP][VG], px1[PP][VG];
 #pragma unroll
   for (int t = 0; t < PP; ++t) {
     const int p = tg + t * NG;
-    px0[t] = px1[t] = T(0);
-    if (use && l > 0 && p < ROWS * nch) {
-      const int r = p & (ROWS - 1), c = p / ROWS;
-      px0[t] = ldg<T>(pre + row0 + r);
-      if (c > 0) px1[t] = ldg<T>(pre + (size_t)c * m_inp + row0 + r);
+#pragma unroll
+    for (int i = 0; i < VG; ++i) px0[t][i] = px1[t][i] = T(0);
+    if (use && l > 0 && p < RG * nch) {
+      const int c = p / RG, r = VG * (p - c * RG);
+      if constexpr (VG == 1) {
+        px0[t][0] = ldg<T>(pre + row0 + r);
+        if (c > 0) px1[t][0] = ldg<T>(pre + (size_t)c * m_inp + row0 + r);
+      } else
+#pragma unroll
+      for (int h = 0; h < VG; h += 4) {
+        const V4 a = ldg<V4>(pre + row0 + r + h);
+        px0[t][h] = a.x; px0[t][h + 1] = a.y; px0[t][h + 2] = a.z; px0[t][h + 3] = a.w;
+        if (c > 0) {
+          const V4 b = ldg<V4>(pre + (size_t)c * m_inp + row0 + r + h);
+          px1[t][h] = b.x; px1[t][h + 1] = b.y; px1[t][h + 2] = b.z; px1[t][h + 3] = b.w;
+        }
+      }
     }
   }
   if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(WT, K, K, use, bload, S, red);
@@ -1526,23 +1552,33 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_bwd
 #pragma unroll
     for (int t = 0; t < PP; ++t) {
       const int p = tg + t * NG;
-      if (p < ROWS * nch) {
-        const int r = p & (ROWS - 1), c = p / ROWS;
-        const int row = row0 + r;
-        T v;
-        if constexpr (FD) {  // each column through sigma' of its own pre-activation
+      if (p < RG * nch) {
+        const int c = p / RG, r = VG * (p - c * RG);
+        T v[VG];
+#pragma unroll
+        for (int i = 0; i < VG; ++i) {
           T d1, d2;
-          act_d12(la.act, c == 0 ? px0[t] : px1[t], d1, d2);
-          v = d1 * Ss[c][r];
-        } else {
-          T d1, d2;
-          act_d12(la.act, px0[t], d1, d2);
-          if (c == 0) v = d1 * Ss[0][r];
-          else v = d1 * Ss[c][r] + d2 * px1[t] * Ss[0][r];
+          if constexpr (FD) {  // each column through sigma' of its own pre-activation
+            act_d12(la.act, c == 0 ? px0[t][i] : px1[t][i], d1, d2);
+            v[i] = d1 * Ss[c][r + i];
+          } else {
+            act_d12(la.act, px0[t][i], d1, d2);
+            if (c == 0) v[i] = d1 * Ss[0][r + i];
+            else v[i] = d1 * Ss[c][r + i] + d2 * px1[t][i] * Ss[0][r + i];
+          }
+          v[i] = (row0 + r + i < m_in) ? v[i] : T(0);
         }
-        if constexpr (BFX)
-          stg<__bf16>(reinterpret_cast<__bf16*>(xb_out) + (size_t)c * m_inp + row, (__bf16)((row < m_in) ? v : T(0)));
-        else stg<T>(xb_out + (size_t)c * m_inp + row, (row < m_in) ? v : T(0));
+        if constexpr (VG == 1) {
+          if constexpr (BFX) stg<__bf16>(reinterpret_cast<__bf16*>(xb_out) + (size_t)c * m_inp + row0 + r, (__bf16)v[0]);
+          else stg<T>(xb_out + (size_t)c * m_inp + row0 + r, v[0]);
+        } else if constexpr (BFX) {
+          bf16x8 o;
+#pragma unroll
+          for (int i = 0; i < 8; ++i) o[i] = (__bf16)v[i];
+          stg<bf16x8>(reinterpret_cast<__bf16*>(xb_out) + (size_t)c * m_inp + row0 + r, o);
+        } else {
+          stg<V4>(xb_out + (size_t)c * m_inp + row0 + r, V4{v[0], v[1], v[2], v[3]});
+        }
       }
     }
   } else {
