@@ -443,6 +443,9 @@ __device__ inline void gemm_tall(const TW* __restrict__ A, int lda, int K, bool 
 // a quarter-wave's reads on disjoint banks.  Two chunk buffers: the next
 // chunk's global loads are in flight during the current chunk's MFMAs.  The
 // KS waves of a slot take the 32-wide sub-chunks of each chunk in turn.
+#ifndef TALL_CHUNKS_IN_FLIGHT
+#define TALL_CHUNKS_IN_FLIGHT 2
+#endif
 template <typename TW, int NCB, int MR, int IB, int KS>
 struct tall_stage {
   static constexpr int KC = 32 * KS;            // K per chunk
@@ -453,52 +456,55 @@ struct tall_stage {
   static constexpr bool on = std::is_same<TW, __bf16>::value && MR > 1 && BYTES <= 96 * 1024;
 };
 
-template <int NCB, int MR, int IB, int KS, typename BL>
-__device__ inline void gemm_tall_lds(const __bf16* __restrict__ A, int lda, int K, bool use, BL bload,
-                                     float (*S)[NCB * 16][16 * MR + 1], unsigned char* stage) {
+// B is the slot's BF16 operand, column c at B + c ldb (K contiguous).
+template <int NCB, int MR, int IB, int KS>
+__device__ inline void gemm_tall_lds(const __bf16* __restrict__ A, int lda, int K, bool use,
+                                     const __bf16* __restrict__ B, int ldb, float (*S)[NCB * 16][16 * MR + 1],
+                                     unsigned char* stage) {
   using G = tall_stage<__bf16, NCB, MR, IB, KS>;
   constexpr int NT = 64 * IB * KS, NG = 64 * KS;
   constexpr int PR = G::KC / 8;  // 16-byte pieces of a staged row
   constexpr int NA = G::AROWS * PR;
   constexpr int PA = (NA + NT - 1) / NT, PB = NCB * 16 * PR / NG;
+  constexpr int D = TALL_CHUNKS_IN_FLIGHT;  // register sets: chunks loaded ahead
   static_assert(NCB * 16 * PR % NG == 0, "B pieces split evenly over a slot's threads");
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int slot = wave / KS, part = wave - slot * KS, tg = tid - slot * NG;
   const int nch = (K + G::KC - 1) / G::KC;
-  bf16x8 ra[PA], rb[PB];
-  // chunk ch into registers; pieces past K (a half chunk at the end) are
-  // zeros, loaded from a clamped index so that no load sits under a branch
-  auto gload = [&](int ch) {
+  // chunk ch into registers, nothing applied to the loaded values (an
+  // operation on them would wait for the load right there).  Pieces past K
+  // (the second half of a last chunk) are loaded from a clamped index and
+  // never multiplied: K is a multiple of 32, so a wave's sub-chunk lies
+  // wholly inside or past K.  A slot not in use loads the same number of
+  // pieces, from the weight tile: its table entry may be an empty pool
+  // slot's, whose pointers are null or stale.
+  const __bf16* Bs = use ? B : A;
+  const int lds_b = use ? ldb : lda, cmod = use ? NCB * 16 : G::AROWS;
+  auto gload = [&](int ch, bf16x8(&ra)[PA], bf16x8(&rb)[PB]) {
     const int k0 = ch * G::KC;
 #pragma unroll
     for (int i = 0; i < PA; ++i) {
-      const int q = min(tid + i * NT, NA - 1), k = k0 + 8 * (q % PR);
-      const bf16x8 v = ldg<bf16x8>(A + (size_t)(q / PR) * lda + min(k, K - 8));
-      ra[i] = k < K ? v : zero_of<bf16x8>();
+      const int q = min(tid + i * NT, NA - 1);
+      ra[i] = ldg<bf16x8>(A + (size_t)(q / PR) * lda + min(k0 + 8 * (q % PR), K - 8));
     }
-    if (use) {  // uniform over the slot's waves
 #pragma unroll
-      for (int i = 0; i < PB; ++i) {
-        const int q = tg + i * NG, k = k0 + 8 * (q % PR);
-        const bf16x8 v = bfrag(bload, q / PR, min(k, K - 8));
-        rb[i] = k < K ? v : zero_of<bf16x8>();
-      }
+    for (int i = 0; i < PB; ++i) {
+      const int q = tg + i * NG;
+      rb[i] = ldg<bf16x8>(Bs + (size_t)((q / PR) % cmod) * lds_b + min(k0 + 8 * (q % PR), K - 8));
     }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int buf, const bf16x8(&ra)[PA], const bf16x8(&rb)[PB]) {
     unsigned char* base = stage + buf * (G::AROWS + G::BROWS) * G::LD;
 #pragma unroll
     for (int i = 0; i < PA; ++i) {
       const int q = tid + i * NT;
       if (q < NA) *reinterpret_cast<bf16x8*>(base + (q / PR) * G::LD + 16 * (q % PR)) = ra[i];
     }
-    if (use) {
-      unsigned char* bb = base + (G::AROWS + slot * NCB * 16) * G::LD;
+    unsigned char* bb = base + (G::AROWS + slot * NCB * 16) * G::LD;
 #pragma unroll
-      for (int i = 0; i < PB; ++i) {
-        const int q = tg + i * NG;
-        *reinterpret_cast<bf16x8*>(bb + (q / PR) * G::LD + 16 * (q % PR)) = rb[i];
-      }
+    for (int i = 0; i < PB; ++i) {
+      const int q = tg + i * NG;
+      *reinterpret_cast<bf16x8*>(bb + (q / PR) * G::LD + 16 * (q % PR)) = rb[i];
     }
   };
   f32x4 acc[MR][NCB];
@@ -507,15 +513,11 @@ __device__ inline void gemm_tall_lds(const __bf16* __restrict__ A, int lda, int 
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[m][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int rA = lane & 15, g = lane >> 4;
-  gload(0);
-  lstore(0);
-  __syncthreads();
-  for (int ch = 0; ch < nch; ++ch) {
-    const int buf = ch & 1;
-    if (ch + 1 < nch) gload(ch + 1);
+  // this wave's 32-wide sub-chunk of chunk ch, from LDS buffer ch & 1
+  auto mma = [&](int ch) {
     const int kk = ch * G::KC + 32 * part;
     if (use && kk < K) {  // uniform over the wave
-      const unsigned char* base = stage + buf * (G::AROWS + G::BROWS) * G::LD + 2 * (32 * part + 8 * g);
+      const unsigned char* base = stage + (ch & 1) * (G::AROWS + G::BROWS) * G::LD + 2 * (32 * part + 8 * g);
       const unsigned char* bb = base + (G::AROWS + slot * NCB * 16) * G::LD;
       bf16x8 a[MR], b[NCB];
 #pragma unroll
@@ -527,8 +529,29 @@ __device__ inline void gemm_tall_lds(const __bf16* __restrict__ A, int lda, int 
 #pragma unroll
         for (int m = 0; m < MR; ++m) acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[cb], acc[m][cb], 0, 0, 0);
     }
-    if (ch + 1 < nch) lstore(buf ^ 1);
-    __syncthreads();
+  };
+  // register set d holds chunk ch = d (mod D).  Step ch: refill set d with
+  // chunk ch + D (chunk ch is in LDS already), multiply chunk ch, store
+  // chunk ch + 1 into the other LDS buffer, barrier.  A chunk's loads have
+  // D - 1 steps to land before its LDS store waits for them.  No load sits
+  // under a branch, so that each wait counts only the loads it needs: the
+  // steps run in whole rounds of D, loads past the last chunk re-read it
+  // (clamped), and steps past it multiply nothing.
+  const int nst = (nch + D - 1) / D * D;
+  bf16x8 ra[D][PA], rb[D][PB];
+#pragma unroll
+  for (int d = 0; d < D; ++d) gload(min(d, nch - 1), ra[d], rb[d]);
+  lstore(0, ra[0], rb[0]);
+  __syncthreads();
+  for (int ch0 = 0; ch0 < nst; ch0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int ch = ch0 + d;
+      gload(min(ch + D, nch - 1), ra[d], rb[d]);
+      mma(ch);
+      lstore((ch + 1) & 1, ra[(d + 1) % D], rb[(d + 1) % D]);
+      __syncthreads();
+    }
   }
   // S may share the staging buffers: every wave has passed the last barrier
 #pragma unroll
@@ -684,7 +707,9 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_fwd
       };
       gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload_g, S, red);
     } else if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload, S, red);
-    else if constexpr (STG::on) gemm_tall_lds<NCB, MR, IB, tall_ks<TW>::v>(W, m_inp, m_inp, use, bload, S, lds_s);
+    else if constexpr (STG::on && std::is_same<decltype(bload(0, 0)), bf16x8>::value)
+      gemm_tall_lds<NCB, MR, IB, tall_ks<TW>::v>(reinterpret_cast<const __bf16*>(W), m_inp, m_inp, use,
+                                                 reinterpret_cast<const __bf16*>(X), m_inp, S, lds_s);
     else gemm_tall<TW, NCB, MR, tall_ks<TW>::v>(W, m_inp, m_inp, use, bload, S);
   };
   if (l == 0) gemm(bload_in);  // uniform over the block
@@ -1544,7 +1569,8 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_bwd
     }
   }
   if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(WT, K, K, use, bload, S, red);
-  else if constexpr (STG::on) gemm_tall_lds<NCB, MR, IB, tall_ks<TW>::v>(WT, K, K, use, bload, S, lds_s);
+  else if constexpr (STG::on)
+    gemm_tall_lds<NCB, MR, IB, tall_ks<TW>::v>(WT, K, K, use, reinterpret_cast<const __bf16*>(xb), K, S, lds_s);
   else gemm_tall<TW, NCB, MR, tall_ks<TW>::v>(WT, K, K, use, bload, S);
   if (!use) return;
   T(*Ss)[ROWS + 1] = S[slot];

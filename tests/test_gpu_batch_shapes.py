@@ -179,21 +179,27 @@ def test_packed_cubature_is_bitwise_the_four_wave_form(nmr, ctx, prec, n_p, n_q)
         np.testing.assert_array_equal(u, ua)
 
 
-def test_paired_output_layer_in_a_pool_with_a_stale_slot(nmr, ctx):
+@pytest.mark.parametrize("prec,tiles,tol", [("fp32", None, 1e-4), ("bf16", None, 3e-2), ("bf16", (4, 4), 3e-2)])
+def test_paired_output_layer_in_a_pool_with_a_stale_slot(nmr, ctx, prec, tiles, tol):
     """A 64-slot pool of 10k-vertex instances (Gram path, 5,710 decoded rows)
     runs the output layer two instances per block, rows from the pool's own
-    copy.  Slot 0's instance is destroyed after attaching, so the pair
-    (0, 1) has a stale first entry: slot 1's request must be bitwise the one
-    of a pool whose slot 0 stays live, and match the request alone (to FP32
+    copy, and its 512-wide hidden layers in tall tiles (BF16: staged through
+    LDS; tiles=(4, 4) forces four 16-row blocks).  Slot 0's instance is
+    destroyed after attaching, so the pair (0, 1) has a stale first entry and
+    61 slots were never filled (null pointers): no kernel may follow an empty
+    slot's pointers, slot 1's request must be bitwise the one of a pool whose
+    slot 0 stays live, and match the request alone (to the precision's
     rounding: the pool's tiles and merged cubature blocks sum in other
     orders)."""
     p = synth.config_single_10k()
     probs = [p.replace(r0=p.r0 + 0.01 * synth.normal(f"pairpool/q0/{k}", p.R)) for k in range(3)]
-    dec = nmr.Decoder(ctx, p.weights, p.biases, p.act, "fp32")
+    dec = nmr.Decoder(ctx, p.weights, p.biases, p.act, prec)
+    if tiles:
+        ctx.set_tiling("force", *tiles)
 
     def run(stale):
         pool = nmr.Pool(ctx, 64)
-        insts = [nmr.Instance(ctx, q, "fp32", shared=dec) for q in probs]
+        insts = [nmr.Instance(ctx, q, prec, shared=dec) for q in probs]
         try:
             slots = [pool.attach(x) for x in insts]
             assert slots == [0, 1, 2]
@@ -208,17 +214,20 @@ def test_paired_output_layer_in_a_pool_with_a_stale_slot(nmr, ctx):
             for x in insts[(1 if stale else 0):]:
                 x.close()
 
-    live, stale = run(False), run(True)
+    try:
+        live, stale = run(False), run(True)
+    finally:
+        ctx.set_tiling("rule")
     for a, b in zip(live, stale):
         for x, y in zip(a, b):
             np.testing.assert_array_equal(x, y)
-    ref = nmr.Instance(ctx, probs[1], "fp32", shared=dec)
+    ref = nmr.Instance(ctx, probs[1], prec, shared=dec)
     try:
         st, _ = nmr.step_many(ctx, [ref], 2, p.newton_iters)
         assert st == [0]
         ra, rda, ua = ref.get_state(with_u=True)
-        close(stale[0][0], ra, 1e-4, "r")
-        close(stale[0][2], ua, 1e-4, "u")
+        close(stale[0][0], ra, tol, "r")
+        close(stale[0][2], ua, tol, "u")
     finally:
         ref.close()
         dec.close()
