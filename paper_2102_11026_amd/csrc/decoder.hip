@@ -383,18 +383,6 @@ __device__ inline void mfma_tall(const __bf16* __restrict__ A, int lda, int K, B
   if (i < nbat) mma(a0, b0);
 }
 
-// K-split of the tall tiles: waves per instance slot.  A BF16 wave's MFMAs
-// take a sixteenth of an FP32 wave's time, so its serial chain of K-step
-// loads bounds it: two waves take half of K each.  FP32 keeps one.
-template <typename TW>
-struct tall_ks {
-  static constexpr int v = 1;
-};
-template <>
-struct tall_ks<__bf16> {
-  static constexpr int v = 2;
-};
-
 // Tall tile of every instance slot (waves KS s .. KS s + KS - 1 = slot s,
 // wave h of a slot taking the h-th part of K in 32-wide steps) into
 // S[slot][c][r], r < 16 MR, the parts added in order; a slot not in use
@@ -432,38 +420,56 @@ __device__ inline void gemm_tall(const TW* __restrict__ A, int lda, int K, bool 
   }
 }
 
-// LDS staging of the BF16 tall tiles.  Read straight from global memory,
-// an MFMA operand fragment puts the 16 lanes of each quarter-wave on 16
-// different rows, so every lane's 16 bytes are a request of their own and
-// the address unit takes about a cycle per lane: it, not the MFMAs, bounds a
-// BF16 wave.  Here the block copies each K-chunk of the weight tile (which
-// its instance slots share) and of every slot's B tile into LDS with loads
-// in which consecutive lanes read consecutive 16 bytes, and the waves read
-// their fragments from LDS rows padded by 16 bytes, which puts the 16 rows of
-// a quarter-wave's reads on disjoint banks.  Two chunk buffers: the next
-// chunk's global loads are in flight during the current chunk's MFMAs.  The
-// KS waves of a slot take the 32-wide sub-chunks of each chunk in turn.
+// LDS staging of the tall tiles.  Read straight from global memory, an MFMA
+// operand fragment puts the 16 lanes of each quarter-wave on 16 different
+// rows, so every lane's 16 bytes are a request of their own and the address
+// unit takes about a cycle per lane: in BF16 it, not the MFMAs, bounds a
+// wave, and in FP32 it takes about as long as the MFMAs.  Here the block
+// copies each K-chunk of the weight tile (which its instance slots share)
+// and of every slot's B tile into LDS with loads in which consecutive lanes
+// read consecutive 16 bytes, and the waves read their fragments from LDS
+// rows padded by 16 bytes, which puts the 16 rows of a quarter-wave's reads
+// on disjoint banks.  A sub-chunk is 64 bytes of a row (32 BF16 or 16 FP32
+// K entries: one BF16 MFMA step, four FP32 ones); a chunk is KS sub-chunks,
+// which the KS waves of a slot take in turn.  Two LDS buffers, and register
+// sets that load chunks ahead of the one being multiplied.
 #ifndef TALL_CHUNKS_IN_FLIGHT
 #define TALL_CHUNKS_IN_FLIGHT 2
 #endif
 template <typename TW, int NCB, int MR, int IB, int KS>
 struct tall_stage {
-  static constexpr int KC = 32 * KS;            // K per chunk
-  static constexpr int LD = 2 * KC + 16;        // bytes per staged row
+  static constexpr int SW = 64 / (int)sizeof(TW);  // K entries of a sub-chunk
+  static constexpr int KC = SW * KS;              // K per chunk
+  static constexpr int LD = 64 * KS + 16;         // bytes per staged row
   static constexpr int AROWS = 16 * MR, BROWS = IB * NCB * 16;
   static constexpr int BYTES = 2 * (AROWS + BROWS) * LD;
-  // BF16 only, and within a third of the 160 KB of LDS beside the epilogue's
-  static constexpr bool on = std::is_same<TW, __bf16>::value && MR > 1 && BYTES <= 96 * 1024;
+  // two waves per slot, within about a third of the 160 KB of LDS beside
+  // the epilogue's
+  static constexpr bool on = (std::is_same<TW, __bf16>::value || std::is_same<TW, float>::value) && MR > 1 &&
+                             KS == 2 && BYTES <= 96 * 1024;
 };
 
-// B is the slot's BF16 operand, column c at B + c ldb (K contiguous).
-template <int NCB, int MR, int IB, int KS>
-__device__ inline void gemm_tall_lds(const __bf16* __restrict__ A, int lda, int K, bool use,
-                                     const __bf16* __restrict__ B, int ldb, float (*S)[NCB * 16][16 * MR + 1],
-                                     unsigned char* stage) {
-  using G = tall_stage<__bf16, NCB, MR, IB, KS>;
+// K-split of the tall tiles: waves per instance slot.  With one block per CU
+// a single wave per SIMD leaves the MFMAs idle through every wait for LDS
+// and every barrier, so two waves per slot take alternate parts of K.  A
+// BF16 wave's MFMAs take a sixteenth of an FP32 wave's time, so BF16 splits
+// K in the direct form too; FP32 splits only the staged form (a direct
+// FP32 tile with 128 jet columns was slower split).
+template <typename TW, int NCB, int MR>
+struct tall_ks {
+  static constexpr int v = std::is_same<TW, __bf16>::value || tall_stage<TW, NCB, MR, 4, 2>::on ? 2 : 1;
+};
+
+// B is the slot's operand, column c at B + c ldb (K contiguous), in the
+// weights' type.
+template <typename TW, int NCB, int MR, int IB, int KS>
+__device__ inline void gemm_tall_lds(const TW* __restrict__ A, int lda, int K, bool use, const TW* __restrict__ B,
+                                     int ldb, float (*S)[NCB * 16][16 * MR + 1], unsigned char* stage) {
+  using G = tall_stage<TW, NCB, MR, IB, KS>;
+  typedef typename std::conditional<std::is_same<TW, float>::value, float4, bf16x8>::type P;  // 16 bytes
+  constexpr int PE = 16 / (int)sizeof(TW);  // K entries of a piece
   constexpr int NT = 64 * IB * KS, NG = 64 * KS;
-  constexpr int PR = G::KC / 8;  // 16-byte pieces of a staged row
+  constexpr int PR = G::KC / PE;  // 16-byte pieces of a staged row
   constexpr int NA = G::AROWS * PR;
   constexpr int PA = (NA + NT - 1) / NT, PB = NCB * 16 * PR / NG;
   constexpr int D = TALL_CHUNKS_IN_FLIGHT;  // register sets: chunks loaded ahead
@@ -478,33 +484,33 @@ __device__ inline void gemm_tall_lds(const __bf16* __restrict__ A, int lda, int 
   // wholly inside or past K.  A slot not in use loads the same number of
   // pieces, from the weight tile: its table entry may be an empty pool
   // slot's, whose pointers are null or stale.
-  const __bf16* Bs = use ? B : A;
+  const TW* Bs = use ? B : A;
   const int lds_b = use ? ldb : lda, cmod = use ? NCB * 16 : G::AROWS;
-  auto gload = [&](int ch, bf16x8(&ra)[PA], bf16x8(&rb)[PB]) {
+  auto gload = [&](int ch, P(&ra)[PA], P(&rb)[PB]) {
     const int k0 = ch * G::KC;
 #pragma unroll
     for (int i = 0; i < PA; ++i) {
       const int q = min(tid + i * NT, NA - 1);
-      ra[i] = ldg<bf16x8>(A + (size_t)(q / PR) * lda + min(k0 + 8 * (q % PR), K - 8));
+      ra[i] = ldg<P>(A + (size_t)(q / PR) * lda + min(k0 + PE * (q % PR), K - PE));
     }
 #pragma unroll
     for (int i = 0; i < PB; ++i) {
       const int q = tg + i * NG;
-      rb[i] = ldg<bf16x8>(Bs + (size_t)((q / PR) % cmod) * lds_b + min(k0 + 8 * (q % PR), K - 8));
+      rb[i] = ldg<P>(Bs + (size_t)((q / PR) % cmod) * lds_b + min(k0 + PE * (q % PR), K - PE));
     }
   };
-  auto lstore = [&](int buf, const bf16x8(&ra)[PA], const bf16x8(&rb)[PB]) {
+  auto lstore = [&](int buf, const P(&ra)[PA], const P(&rb)[PB]) {
     unsigned char* base = stage + buf * (G::AROWS + G::BROWS) * G::LD;
 #pragma unroll
     for (int i = 0; i < PA; ++i) {
       const int q = tid + i * NT;
-      if (q < NA) *reinterpret_cast<bf16x8*>(base + (q / PR) * G::LD + 16 * (q % PR)) = ra[i];
+      if (q < NA) *reinterpret_cast<P*>(base + (q / PR) * G::LD + 16 * (q % PR)) = ra[i];
     }
     unsigned char* bb = base + (G::AROWS + slot * NCB * 16) * G::LD;
 #pragma unroll
     for (int i = 0; i < PB; ++i) {
       const int q = tg + i * NG;
-      *reinterpret_cast<bf16x8*>(bb + (q / PR) * G::LD + 16 * (q % PR)) = rb[i];
+      *reinterpret_cast<P*>(bb + (q / PR) * G::LD + 16 * (q % PR)) = rb[i];
     }
   };
   f32x4 acc[MR][NCB];
@@ -514,20 +520,37 @@ __device__ inline void gemm_tall_lds(const __bf16* __restrict__ A, int lda, int 
     for (int cb = 0; cb < NCB; ++cb) acc[m][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int rA = lane & 15, g = lane >> 4;
   // this wave's 32-wide sub-chunk of chunk ch, from LDS buffer ch & 1
+  // (lane group g holds the sub-chunk's g-th 16 bytes of its row: BF16 one
+  // 32-deep MFMA step; FP32 four 4-deep ones, entry j of every group in step j)
   auto mma = [&](int ch) {
-    const int kk = ch * G::KC + 32 * part;
+    const int kk = ch * G::KC + G::SW * part;
     if (use && kk < K) {  // uniform over the wave
-      const unsigned char* base = stage + (ch & 1) * (G::AROWS + G::BROWS) * G::LD + 2 * (32 * part + 8 * g);
+      const unsigned char* base = stage + (ch & 1) * (G::AROWS + G::BROWS) * G::LD + 64 * part + 16 * g;
       const unsigned char* bb = base + (G::AROWS + slot * NCB * 16) * G::LD;
-      bf16x8 a[MR], b[NCB];
+      P a[MR], b[NCB];
 #pragma unroll
-      for (int m = 0; m < MR; ++m) a[m] = *reinterpret_cast<const bf16x8*>(base + (16 * m + rA) * G::LD);
+      for (int m = 0; m < MR; ++m) a[m] = *reinterpret_cast<const P*>(base + (16 * m + rA) * G::LD);
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const bf16x8*>(bb + (16 * cb + rA) * G::LD);
+      for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const P*>(bb + (16 * cb + rA) * G::LD);
+      if constexpr (std::is_same<TW, float>::value) {
+        // the MR NCB independent tiles between two steps on one accumulator
+        auto step = [&](auto pick) {
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
+          for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-        for (int m = 0; m < MR; ++m) acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[cb], acc[m][cb], 0, 0, 0);
+            for (int m = 0; m < MR; ++m)
+              acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(pick(a[m]), pick(b[cb]), acc[m][cb], 0, 0, 0);
+        };
+        step([](const float4& v) { return v.x; });
+        step([](const float4& v) { return v.y; });
+        step([](const float4& v) { return v.z; });
+        step([](const float4& v) { return v.w; });
+      } else {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+          for (int m = 0; m < MR; ++m) acc[m][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[cb], acc[m][cb], 0, 0, 0);
+      }
     }
   };
   // register set d holds chunk ch = d (mod D).  Step ch: refill set d with
@@ -538,7 +561,7 @@ __device__ inline void gemm_tall_lds(const __bf16* __restrict__ A, int lda, int 
   // steps run in whole rounds of D, loads past the last chunk re-read it
   // (clamped), and steps past it multiply nothing.
   const int nst = (nch + D - 1) / D * D;
-  bf16x8 ra[D][PA], rb[D][PB];
+  P ra[D][PA], rb[D][PB];
 #pragma unroll
   for (int d = 0; d < D; ++d) gload(min(d, nch - 1), ra[d], rb[d]);
   lstore(0, ra[0], rb[0]);
@@ -604,13 +627,13 @@ __device__ inline T fd_input(int c, int k, int nq, T q, T dq, T qd, T h) {
 // K sum, so the results are the same bits.  The base channels, which every
 // group needs for its activation derivatives, are stored by group 0 only.
 template <typename T, typename TW, int NCB, int IB, bool FD, int MR, int JG = 0>
-__global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_fwd_hidden(LayerArgs la,
+__global__ __launch_bounds__(MR > 1 ? 64 * IB * (tall_ks<TW, NCB, MR>::v) : 512) void k_fwd_hidden(LayerArgs la,
                                                                                        const Inst<T>* __restrict__ tab,
                                                                                        int nb) {
   static_assert(MR == 1 || (!FD && std::is_same<T, float>::value), "tall tiles: complex-step FP32 jets only");
   static_assert(JG == 0 || (NCB == 1 && IB == 1 && MR == 1 && !FD && 4 + 4 * JG == 16), "jet groups: one column block");
   constexpr int ROWS = 16 * MR;  // output rows of a block
-  constexpr int NW = MR > 1 ? IB * tall_ks<TW>::v : splitk_waves<T, NCB>::v;
+  constexpr int NW = MR > 1 ? IB * tall_ks<TW, NCB, MR>::v : splitk_waves<T, NCB>::v;
   constexpr int KSPL = NW / IB;
   constexpr int NG = KSPL * 64;  // threads of one instance slot
   const int l = la.l;
@@ -642,7 +665,7 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_fwd
   if (row0 >= m_outp || (IB == 1 && !use)) return;  // uniform over the block
   const TW* W = reinterpret_cast<const TW*>(la.W) + (size_t)row0 * m_inp;
   const T* bias = reinterpret_cast<const T*>(la.b);
-  using STG = tall_stage<TW, NCB, MR, IB, tall_ks<TW>::v>;
+  using STG = tall_stage<TW, NCB, MR, IB, tall_ks<TW, NCB, MR>::v>;
   constexpr int SB = (int)sizeof(T) * IB * NCB * 16 * (ROWS + 1), GB = STG::on ? STG::BYTES : 0;
   __shared__ __align__(16) unsigned char lds_s[SB > GB ? SB : GB];  // S, or the GEMM's staging before it
   T(*S)[NCB * 16][ROWS + 1] = reinterpret_cast<T(*)[NCB * 16][ROWS + 1]>(lds_s);
@@ -698,7 +721,7 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_fwd
     const int role = (c - 4) / jg, j = grp * jg + (c - 4 - role * jg);
     return j < nq ? 4 + role * nq + j : -1;
   };
-  auto gemm = [&](auto bload) {
+  auto gemm = [&](auto bload, auto x_operand) {
     if constexpr (JG > 0) {
       auto bload_g = [&](int c, int k) {
         const int gc = gcol(c);
@@ -707,13 +730,13 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_fwd
       };
       gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload_g, S, red);
     } else if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(W, m_inp, m_inp, use, bload, S, red);
-    else if constexpr (STG::on && std::is_same<decltype(bload(0, 0)), bf16x8>::value)
-      gemm_tall_lds<NCB, MR, IB, tall_ks<TW>::v>(reinterpret_cast<const __bf16*>(W), m_inp, m_inp, use,
-                                                 reinterpret_cast<const __bf16*>(X), m_inp, S, lds_s);
-    else gemm_tall<TW, NCB, MR, tall_ks<TW>::v>(W, m_inp, m_inp, use, bload, S);
+    else if constexpr (STG::on && decltype(x_operand)::value)  // the previous layer's activations, stored as TW
+      gemm_tall_lds<TW, NCB, MR, IB, tall_ks<TW, NCB, MR>::v>(W, m_inp, m_inp, use, reinterpret_cast<const TW*>(X), m_inp, S,
+                                                     lds_s);
+    else gemm_tall<TW, NCB, MR, tall_ks<TW, NCB, MR>::v>(W, m_inp, m_inp, use, bload, S);
   };
-  if (l == 0) gemm(bload_in);  // uniform over the block
-  else gemm(bload_x);
+  if (l == 0) gemm(bload_in, std::false_type());  // uniform over the block
+  else gemm(bload_x, std::true_type());
 
   T(*Ss)[ROWS + 1] = S[slot];
   if constexpr (FD) {
@@ -1493,12 +1516,12 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(LayerArgs la, const Inst<T>*
 // at the input, J^T a and a . H.
 // ---------------------------------------------------------------------------
 template <typename T, typename TW, int NCB, int IB, bool FD, int MR>
-__global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_bwd_hidden(LayerArgs la,
+__global__ __launch_bounds__(MR > 1 ? 64 * IB * (tall_ks<TW, NCB, MR>::v) : 512) void k_bwd_hidden(LayerArgs la,
                                                                                        const Inst<T>* __restrict__ tab,
                                                                                        int nb) {
   static_assert(MR == 1 || (!FD && std::is_same<T, float>::value), "tall tiles: complex-step FP32 jets only");
   constexpr int ROWS = 16 * MR;  // rows (layer inputs) of a block
-  constexpr int NW = MR > 1 ? IB * tall_ks<TW>::v : splitk_waves<T, NCB>::v;
+  constexpr int NW = MR > 1 ? IB * tall_ks<TW, NCB, MR>::v : splitk_waves<T, NCB>::v;
   constexpr int KSPL = NW / IB;
   constexpr int NG = KSPL * 64;  // threads of one instance slot
   const int l = la.l;
@@ -1529,7 +1552,7 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_bwd
   const int row0 = bx * ROWS;
   if (row0 >= m_inp || (IB == 1 && !use)) return;  // uniform over the block
   const TW* WT = reinterpret_cast<const TW*>(la.WT) + (size_t)row0 * K;
-  using STG = tall_stage<TW, NCB, MR, IB, tall_ks<TW>::v>;
+  using STG = tall_stage<TW, NCB, MR, IB, tall_ks<TW, NCB, MR>::v>;
   constexpr int SB = (int)sizeof(T) * IB * NCB * 16 * (ROWS + 1), GB = STG::on ? STG::BYTES : 0;
   __shared__ __align__(16) unsigned char lds_s[SB > GB ? SB : GB];  // S, or the GEMM's staging before it
   T(*S)[NCB * 16][ROWS + 1] = reinterpret_cast<T(*)[NCB * 16][ROWS + 1]>(lds_s);
@@ -1570,8 +1593,8 @@ __global__ __launch_bounds__(MR > 1 ? 64 * IB * tall_ks<TW>::v : 512) void k_bwd
   }
   if constexpr (MR == 1) gemm_splitk<T, TW, NCB, NW, IB>(WT, K, K, use, bload, S, red);
   else if constexpr (STG::on)
-    gemm_tall_lds<NCB, MR, IB, tall_ks<TW>::v>(WT, K, K, use, reinterpret_cast<const __bf16*>(xb), K, S, lds_s);
-  else gemm_tall<TW, NCB, MR, tall_ks<TW>::v>(WT, K, K, use, bload, S);
+    gemm_tall_lds<TW, NCB, MR, IB, tall_ks<TW, NCB, MR>::v>(WT, K, K, use, reinterpret_cast<const TW*>(xb), K, S, lds_s);
+  else gemm_tall<TW, NCB, MR, tall_ks<TW, NCB, MR>::v>(WT, K, K, use, bload, S);
   if (!use) return;
   T(*Ss)[ROWS + 1] = S[slot];
   if (l > 0) {
@@ -1856,13 +1879,13 @@ static void fwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb
   }
   if constexpr (std::is_same<T, float>::value && NCB <= 4) {
     if (cfg.mr == 4) {
-      k_fwd_hidden<T, TW, NCB, 4, false, 4><<<dim3(rows / 64, (nb + 3) / 4), 256 * tall_ks<TW>::v, 0, s>>>(la, tab, nb);
+      k_fwd_hidden<T, TW, NCB, 4, false, 4><<<dim3(rows / 64, (nb + 3) / 4), 256 * tall_ks<TW, NCB, 4>::v, 0, s>>>(la, tab, nb);
       return;
     }
   }
   if constexpr (std::is_same<T, float>::value && NCB <= 8) {
     if (cfg.mr == 2) {
-      k_fwd_hidden<T, TW, NCB, 4, false, 2><<<dim3(rows / 32, (nb + 3) / 4), 256 * tall_ks<TW>::v, 0, s>>>(la, tab, nb);
+      k_fwd_hidden<T, TW, NCB, 4, false, 2><<<dim3(rows / 32, (nb + 3) / 4), 256 * tall_ks<TW, NCB, 2>::v, 0, s>>>(la, tab, nb);
       return;
     }
   }
@@ -2027,12 +2050,12 @@ static void bwd_hidden_ib(const DecoderDev& d, int l, const Inst<T>* tab, int nb
   }
   if constexpr (std::is_same<T, float>::value && NCB <= 2) {
     if (cfg.mr == 4) {
-      k_bwd_hidden<T, TW, NCB, 4, false, 4><<<dim3(d.wp[l] / 64, (nb + 3) / 4), 256 * tall_ks<TW>::v, 0, s>>>(la, tab,
+      k_bwd_hidden<T, TW, NCB, 4, false, 4><<<dim3(d.wp[l] / 64, (nb + 3) / 4), 256 * tall_ks<TW, NCB, 4>::v, 0, s>>>(la, tab,
                                                                                                             nb);
       return;
     }
     if (cfg.mr == 2) {
-      k_bwd_hidden<T, TW, NCB, 4, false, 2><<<dim3(d.wp[l] / 32, (nb + 3) / 4), 256 * tall_ks<TW>::v, 0, s>>>(la, tab,
+      k_bwd_hidden<T, TW, NCB, 4, false, 2><<<dim3(d.wp[l] / 32, (nb + 3) / 4), 256 * tall_ks<TW, NCB, 2>::v, 0, s>>>(la, tab,
                                                                                                             nb);
       return;
     }
