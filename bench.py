@@ -40,8 +40,8 @@ PHASE_KERNEL = dict(dec_hidden="k_fwd_hidden", dec_out="k_fwd_out", bwd_out="k_b
 # factors a plain 512 MiB device copy gives), averaged over one pass of the
 # phase; see profiles/k_fwd_hidden_bar10k_fp32_pmc.md.  They hold only for the
 # kernel sources they were taken on: with any other sources traffic is null.
-MEASURED_TRAFFIC = dict(k_fwd_hidden=1649436, k_bwd_hidden=965621, k_fwd_out=6217984, k_bwd_out=5785600)
-MEASURED_TRAFFIC_SOURCES = "e858add721056d8f"
+MEASURED_TRAFFIC = dict(k_fwd_hidden=1634304, k_bwd_hidden=972676, k_fwd_out=6220032, k_bwd_out=5776384)
+MEASURED_TRAFFIC_SOURCES = "74f3584eaa7a3f1b"
 KERNEL_SOURCES = ("paper_2102_11026_amd/csrc/decoder.hip", "paper_2102_11026_amd/csrc/nmr_internal.h")
 
 
